@@ -1,0 +1,215 @@
+/*
+ * vie.h -- C interface of the MI355X (gfx950) volume-integral-equation solver.
+ *
+ * The library solves the well-conditioned second-kind volume integral
+ * equations of Imbert-Gerard, Vico, Greengard and Ferrando, "Integral equation
+ * methods for electrostatics, acoustics and electromagnetics in smoothly
+ * varying, anisotropic media" (arXiv:1805.04791):
+ *
+ *   anisotropic Laplace   (Section 2, eq. intLap):   J - 2 H T_0 J = 2 H grad phi_inc,
+ *                         H = (eps + I)^{-1} (eps - I)  (eq. rhodef),
+ *   anisotropic Helmholtz (Section 3, eqs. contractionK / intH):
+ *                         J - 2 H T_w J = 2 H grad phi_inc,  H = (eps^{-1} + I)^{-1} (eps^{-1} - I),
+ *                         (the sign follows the derivation; the printed summary
+ *                         equation carries "+"),
+ *   anisotropic Maxwell   (Section 4, eq. intM, and eq. contraction_Maxwell_reduced for mu = I):
+ *                         J - H_eps (J + 2 U_J + 2 i w W_M) = 2 H_eps E_inc,
+ *                         M - H_mu  (M + 2 U_M - 2 i w W_J) = 2 H_mu  H_inc,
+ * with T J = J/2 + grad div V J, U = grad div V J (Laplace, Helmholtz) or
+ * (grad div + w^2) V J (Maxwell), W = curl V J, and V the volume potential of
+ * eq. Vo / eq. Vw.  The integral operators are discretised on a uniform n^3
+ * grid with the truncated-kernel FFT method described at the start of
+ * Section 5, and the linear systems are solved with GMRES (or Bi-CGStab, the
+ * solver of Section 5) without preconditioner.
+ *
+ * Discretisation (the readings of Section 5 used here):
+ *   grid      x_i = origin + (i + 1/2) h, i in [0, n)^3;
+ *   kernel    cut off at R = sqrt(3) n h, its transform sampled at
+ *             s = 2 pi k / (4 n h), |k_a| <= 2n, cube cut-off at pi/h with the
+ *             Nyquist plane averaged over +-pi/h; the windowed real-space
+ *             kernel (displacements |m_a| < n) is convolved on a 2n grid.
+ *
+ * Layout of every density / field / incident array: interleaved complex128
+ * (re, im) [nrhs][c][n][n][n], C order, x the fastest axis; c = 3 (Laplace,
+ * Helmholtz, Maxwell with mu = I) or c = 6 (Maxwell with mu: [J; M], [E; H]).
+ * Tensor fields (coef, mu): complex128 [9][n][n][n], entry (a, b) at 3a + b.
+ *
+ * Memory: unless stated otherwise the vector arguments of vie_apply,
+ * vie_solve, vie_rhs and vie_field are DEVICE pointers (hipMalloc or a torch
+ * tensor's data_ptr()) on the plan's device, owned by the caller.  The plan
+ * owns its own device memory (contrast, kernel tables, workspaces, Krylov
+ * basis) until vie_destroy.  Calls are queued on the given HIP stream (NULL:
+ * the default stream); vie_solve synchronises that stream for its
+ * convergence tests.  A plan must not be used from two streams or threads at
+ * the same time.
+ *
+ * Errors: functions return VIE_OK (0), a negative VIE_E_* code, or the
+ * positive warning VIE_W_NOCONV.  vie_last_error(plan) returns a message for
+ * the last failure on that plan; vie_status_string() names a code.
+ */
+#ifndef VIE_H
+#define VIE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define VIE_OK 0
+#define VIE_E_ARG (-1)       /* null pointer, bad enum, n/h/omega/nrhs out of range */
+#define VIE_E_SIZE (-2)      /* n with no compiled FFT length for 2n (or 4n) */
+#define VIE_E_MEDIUM (-3)    /* a + I singular or non-finite at a grid point; or ||H||_2 >= 1 in strict mode */
+#define VIE_E_NOMEM (-4)     /* device allocation failed */
+#define VIE_E_DEVICE (-5)    /* a HIP call failed (message in vie_last_error) */
+#define VIE_E_STATE (-6)     /* call not valid for this plan (e.g. mu-dependent call on a 3-component plan) */
+#define VIE_W_NOCONV 1       /* vie_solve: some right-hand side did not reach tol within max_iters */
+
+typedef enum { VIE_LAPLACE = 0, VIE_HELMHOLTZ = 1, VIE_MAXWELL = 2 } vie_kind;
+
+typedef enum {
+  VIE_PREC_FP64 = 0,  /* FP64 FFT apply everywhere */
+  VIE_PREC_MIXED = 1  /* FP32-complex FFT apply inside GMRES; FP64 Arnoldi, least squares,
+                         true residuals (iterative refinement) and kernel precompute */
+} vie_precision;
+
+/* vie_problem.flags */
+#define VIE_PTR_HOST 0x1u        /* coef / mu are host pointers (default: device pointers) */
+#define VIE_STRICT_MEDIUM 0x2u   /* fail with VIE_E_MEDIUM when max ||H(x)||_2 >= 1 (Lemma 1) */
+
+/*
+ * The problem statement of the paper (Introduction and Section 5): a grid,
+ * samples of the coefficient tensor(s), and the frequency.
+ *   kind=LAPLACE:   coef = eps(x)            (eq. Laplace0), omega ignored (0)
+ *   kind=HELMHOLTZ: coef = eps^{-1}(x)       (eq. Helmholtz0), omega > 0
+ *   kind=MAXWELL:   coef = eps(x), mu = mu(x) or NULL for mu = I (eq. Maxwell0), omega > 0
+ * n: points per axis; supported n = 8, 12, 16, 24, 32, 48, 64, 96, 128, 160.
+ * h > 0 grid spacing; origin only positions the grid (the operator is
+ * translation invariant).  max_rhs >= 1 sizes the apply workspace (larger
+ * batches are processed in chunks).  The coefficient arrays are copied.
+ */
+typedef struct {
+  int kind;             /* vie_kind */
+  int n;
+  double h;
+  double origin[3];
+  double omega;
+  const double *coef;   /* complex128 [9][n][n][n] */
+  const double *mu;     /* complex128 [9][n][n][n] or NULL */
+  int precision;        /* vie_precision: the default apply precision of vie_solve */
+  int max_rhs;
+  unsigned flags;
+} vie_problem;
+
+struct vie_plan;
+typedef struct vie_plan vie_plan;
+
+/* solver selection (vie_solve_opts.solver) */
+#define VIE_SOLVER_GMRES 0
+#define VIE_SOLVER_BICGSTAB 1
+
+/* vie_solve_opts.flags */
+#define VIE_SOLVE_X0 0x1u        /* density holds the initial guess (resume) instead of 0 */
+#define VIE_SOLVE_FP64 0x2u      /* plain FP64 solve regardless of the plan precision */
+
+typedef struct {
+  double tol;          /* stop when ||b - A x||_2 / ||b||_2 <= tol (true residual, FP64) */
+  int max_iters;       /* total matvec budget per right-hand side (FP32 + FP64) */
+  int restart;         /* GMRES basis size m (inner cycle length) */
+  double inner_tol;    /* mixed: relative reduction asked of each FP32 inner cycle (0: 1e-5) */
+  int solver;          /* VIE_SOLVER_* */
+  unsigned flags;      /* VIE_SOLVE_* */
+} vie_solve_opts;
+
+typedef struct {
+  int status;          /* VIE_OK or VIE_W_NOCONV */
+  int iters;           /* Krylov iterations */
+  int matvecs_fp32;
+  int matvecs_fp64;
+  int refinements;     /* outer true-residual steps */
+  double rel_residual; /* final true ||b - A x|| / ||b|| (FP64) */
+  double seconds;      /* wall time of the batch this right-hand side was solved in */
+} vie_solve_stats;
+
+/* Plan: validates the problem, computes the contrast H (FP64 and FP32) and the
+ * kernel-transform tables (FP64 precompute, FP32 copy), and allocates the
+ * apply workspace.  hip_stream may be NULL.  On success *out owns all device
+ * memory of the plan.  Errors: VIE_E_ARG, VIE_E_SIZE, VIE_E_MEDIUM,
+ * VIE_E_NOMEM, VIE_E_DEVICE (*out is NULL on error). */
+int vie_plan_create(const vie_problem *p, void *hip_stream, vie_plan **out);
+
+/* vie_apply flags */
+#define VIE_APPLY_FP64 0x1u      /* FP64 FFTs (default: the plan precision) */
+#define VIE_APPLY_FP32 0x2u      /* FP32 FFTs */
+#define VIE_APPLY_CONV 0x4u      /* return the raw convolution U (Z for full Maxwell) instead of A x */
+
+/* y = A x for nrhs densities (device pointers, complex128 [nrhs][c][n^3]).
+ * The discrete operator of the integral equation (see the header comment).
+ * x and y must not overlap. */
+int vie_apply(vie_plan *pl, const double *x, double *y, int nrhs, unsigned flags, void *hip_stream);
+
+/* b = 2 H g (the right-hand side of the integral equation; for full Maxwell
+ * [2 H_eps E_inc; 2 H_mu H_inc]).  Device pointers, [nrhs][c][n^3]. */
+int vie_rhs(vie_plan *pl, const double *inc, double *b, int nrhs, void *hip_stream);
+
+/* Total field from a density: grad phi_tot = g + grad div V J (Sections 2-3),
+ * E_tot = E_inc + U_J + i w W_M, H_tot = H_inc + U_M - i w W_J (eqs.
+ * represent_Maxwell / represent_Maxwell_reduced; reduced: E only).
+ * Computed with FP64 FFTs.  Device pointers. */
+int vie_field(vie_plan *pl, const double *density, const double *inc, double *field, int nrhs, void *hip_stream);
+
+/* Solve for nrhs incident fields (device pointers).  inc: g = grad phi_inc
+ * (Laplace, Helmholtz) or [E_inc; H_inc] (Maxwell); density: J (and M);
+ * field may be NULL, else receives the total field.  opts may be NULL
+ * (tol 1e-10, restart 40, max_iters 2000, GMRES).  stats may be NULL, else an
+ * array of nrhs entries.  Right-hand sides are solved together in fused
+ * launches; each keeps its own convergence test, so its result does not
+ * depend on the others in the batch.  Returns VIE_OK, VIE_W_NOCONV (the
+ * best iterate is written) or an error. */
+int vie_solve(vie_plan *pl, const double *inc, double *density, double *field, int nrhs,
+              const vie_solve_opts *opts, vie_solve_stats *stats, void *hip_stream);
+
+/* Frees the plan and all its device memory.  vie_destroy(NULL) is a no-op. */
+int vie_destroy(vie_plan *pl);
+
+/* Introspection (host pointers).
+ * vie_plan_info: out[0] = n, out[1] = components c, out[2] = P (= 2n),
+ * out[3] = oversampled grid M (= 4n), out[4] = max ||H(x)||_2 (Lemma 1),
+ * out[5] = table entries, out[6] = device bytes held by the plan. */
+int vie_plan_info(const vie_plan *pl, double *out, int nout);
+
+/* Copies the FP64 kernel-transform tables into host memory:
+ * complex128 [n+1][n+1][ne][nxp] (z, y, entry, x-octant index padded to nxp),
+ * the transform of the windowed kernel on the 2n grid at frequencies
+ * q in [0, n]^3, scaled by (2n)^-3 (curl entries also by i omega).
+ * host_bytes must be at least the size reported in *needed. */
+int vie_copy_tables(const vie_plan *pl, double *host, long host_bytes, long *needed, int *nxp, int *ne);
+
+/* Copies the FP64 contrast H (and H_mu if present) into host memory as
+ * complex128 [9][n^3] (followed by [9][n^3] for H_mu). */
+int vie_copy_contrast(const vie_plan *pl, double *host, long host_bytes);
+
+const char *vie_status_string(int status);
+/* Message of the last failure on pl; with pl == NULL, of the last failed
+ * vie_plan_create on the calling thread. */
+const char *vie_last_error(const vie_plan *pl);
+
+/* Whether n is a supported grid size (1/0). */
+int vie_supported_n(int n);
+
+/* Kernel timing.  vie_profile(pl, 1) starts recording a HIP event pair on the
+ * launch stream around every kernel of the apply passes and of the Krylov
+ * operations (and resets the totals); vie_profile(pl, 0) stops.
+ * vie_profile_read waits for the recorded events and writes, per kernel
+ * family, the summed duration in milliseconds, the launch count and the
+ * summed algorithmic bytes (every operand of a launch read or written once;
+ * host arrays of nfam entries); it returns the number of families.
+ * vie_profile_family(i) names family i. */
+int vie_profile(vie_plan *pl, int enable);
+int vie_profile_read(vie_plan *pl, double *ms, long *counts, double *bytes, int nfam);
+const char *vie_profile_family(int fam);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VIE_H */

@@ -86,16 +86,28 @@ def conv_direct_at(K: np.ndarray, f: np.ndarray, point) -> complex:
     return complex(np.sum(Kr * f))
 
 
-def conv_fft_window(K: np.ndarray, f: np.ndarray) -> np.ndarray:
-    """Same sum with the window placed (wrapped) on a 2n grid and FFTs; zero at offset n."""
-    n = f.shape[-1]
+def window_transform(K: np.ndarray) -> np.ndarray:
+    """FFT of the window placed (wrapped) on the 2n grid, zero at offset n."""
+    n = (K.shape[-1] + 1) // 2
     P = 2 * n
     idx = np.arange(-(n - 1), n) % P
     Kp = np.zeros((P, P, P), dtype=np.complex128)
     Kp[np.ix_(idx, idx, idx)] = K
+    return np.fft.fftn(Kp)
+
+
+def conv_fft_window_hat(Khat: np.ndarray, f: np.ndarray) -> np.ndarray:
+    """Circular convolution on the 2n grid with a transformed window, cropped to n."""
+    n = f.shape[-1]
+    P = 2 * n
     fp = np.zeros((P, P, P), dtype=np.complex128)
     fp[:n, :n, :n] = f
-    return np.fft.ifftn(np.fft.fftn(Kp) * np.fft.fftn(fp))[:n, :n, :n]
+    return np.fft.ifftn(Khat * np.fft.fftn(fp))[:n, :n, :n]
+
+
+def conv_fft_window(K: np.ndarray, f: np.ndarray) -> np.ndarray:
+    """Same sum with the window placed (wrapped) on a 2n grid and FFTs; zero at offset n."""
+    return conv_fft_window_hat(window_transform(K), f)
 
 
 def conv_fft_mgrid(F: np.ndarray, f: np.ndarray) -> np.ndarray:
@@ -140,7 +152,11 @@ class Convolver:
         else:
             self.sym = tb.kernel_tables(kind_sym, n, h, omega, R, M)
             self.curl = tb.kernel_tables("curl", n, h, omega, R, M) if with_curl else None
-        self._conv = {"direct": conv_direct, "window": conv_fft_window, "mgrid": conv_fft_mgrid}[route]
+        if route == "window":
+            # transform each window once; the convolution then needs 2 FFTs
+            self.sym = [window_transform(K) for K in self.sym]
+            self.curl = [window_transform(K) for K in self.curl] if with_curl else None
+        self._conv = {"direct": conv_direct, "window": conv_fft_window_hat, "mgrid": conv_fft_mgrid}[route]
 
     def sym_apply(self, J: np.ndarray) -> np.ndarray:
         """U_a = sum_b K^{ab} * J_b."""

@@ -1,0 +1,196 @@
+// Kernels specific to the operator apply: the fused z pass (forward FFT,
+// spectral kernel multiply, inverse FFT) and the last inverse x pass fused
+// with the pointwise contrast combine.
+//
+// Spectral multiply (symbols of Sections 2-4, eqs. Todef, Vw, represent_Maxwell):
+//   MUL_SYM3: U^ = K^ J^ with K^ complex symmetric 3x3 (grad div V or
+//             (grad div + omega^2) V), 6 tables;
+//   MUL_MAX6: [Z_J; Z_M] = [[D, c x], [-c x, D]] [J^; M^] with D the
+//             (grad div + omega^2) V symbol and c = i omega (i s G^) the curl
+//             symbol scaled by i omega, 9 tables; so that Z_J = U_J + i omega W_M and
+//             Z_M = U_M - i omega W_J (eqs. intM and represent_Maxwell).
+// The tables hold one octant q in [0, n]^3 of the 2n-periodic transform; the
+// other octants follow from the parity of each entry (odd in s_a for the
+// off-diagonal entries ab and for curl component a).
+//
+// Pointwise combine (eqs. intLap, contractionK with the derived sign,
+// contraction_Maxwell_reduced, intM):
+//   MODE_MATVEC:   y = J - H (J + 2 U)            (per 3-component half)
+//   MODE_FIELD:    y = g + U                       (total field)
+//   MODE_CONV:     y = U                           (raw convolution)
+//   MODE_RESIDUAL: y = b - (J - H (J + 2 U))
+#pragma once
+
+#include "fft.hpp"
+
+namespace vie {
+
+enum { MUL_SYM3 = 0, MUL_MAX6 = 1 };
+enum { MODE_MATVEC = 0, MODE_FIELD = 1, MODE_CONV = 2, MODE_RESIDUAL = 3 };
+
+struct ZArgs {
+  int T;            // kx columns per block
+  int ntiles;       // P / T
+  int n;            // grid points per axis
+  int P;            // 2n
+  int nxp;          // padded octant row length (>= n + 1)
+  int ne;           // table entries (6 or 9)
+  long comp_stride; // n * P * P
+  long rhs_stride;  // C * n * P * P
+};
+
+template <typename R, int P1, int P2, int C, int MUL>
+__global__ void __launch_bounds__(kFusedMaxThreads) k_zpass(cx<R>* buf, const cx<R>* __restrict__ tab, ZArgs a,
+                                                const cx<R>* __restrict__ twg) {
+  constexpr int P = P1 * P2;
+  constexpr int J = P1 > P2 ? P1 : P2;
+  static_assert(MUL != MUL_SYM3 || C == 3, "SYM3 multiply acts on 3 components");
+  static_assert(MUL != MUL_MAX6 || C == 6, "MAX6 multiply acts on 6 components");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<R>* tw = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* lds = tw + P;
+  load_twiddles<R, P>(tw, twg);
+  int col, j;
+  Layout<false>::lane(threadIdx.x, a.T, J, col, j);
+  const int tile = int(blockIdx.x % unsigned(a.ntiles));
+  const long rest = long(blockIdx.x / unsigned(a.ntiles));
+  const int ky = int(rest % P);
+  const long rhs = rest / P;
+  const int kx = tile * a.T + col;
+  const bool valid = kx < P;
+  const long PP = long(P) * P;
+  cx<R>* base = buf + rhs * a.rhs_stride + long(ky) * P + kx;
+  __syncthreads();
+
+  cx<R> X[C][P2];
+  static_for<0, C>([&](auto c) {
+    const cx<R>* src = base + c * a.comp_stride;
+    fft_fwd_AB<R, P1, P2, false>([&](int z) { return src[long(z) * PP]; }, a.n, lds, tw, col, j, a.T, valid, X[c]);
+  });
+
+  if (j < P1 && valid) {
+    const int N = a.n;
+    const int fy = ky <= N ? ky : P - ky;
+    const int fx = kx <= N ? kx : P - kx;
+    const R sy = ky > N ? R(-1) : R(1);
+    const R sx = kx > N ? R(-1) : R(1);
+    static_for<0, P2>([&](auto k2) {
+      const int kz = j + P1 * k2;
+      const int fz = kz <= N ? kz : P - kz;
+      const R sz = kz > N ? R(-1) : R(1);
+      const cx<R>* t = tab + (long(fz * (N + 1) + fy) * a.ne) * a.nxp + fx;
+      const cx<R> kxx = t[0], kyy = t[a.nxp], kzz = t[2 * a.nxp];
+      const cx<R> kxy = (sx * sy) * t[3 * a.nxp];
+      const cx<R> kxz = (sx * sz) * t[4 * a.nxp];
+      const cx<R> kyz = (sy * sz) * t[5 * a.nxp];
+      if constexpr (MUL == MUL_SYM3) {
+        const cx<R> x0 = X[0][k2], x1 = X[1][k2], x2 = X[2][k2];
+        X[0][k2] = kxx * x0 + kxy * x1 + kxz * x2;
+        X[1][k2] = kxy * x0 + kyy * x1 + kyz * x2;
+        X[2][k2] = kxz * x0 + kyz * x1 + kzz * x2;
+      } else {
+        const cx<R> cxv = sx * t[6 * a.nxp], cyv = sy * t[7 * a.nxp], czv = sz * t[8 * a.nxp];
+        const cx<R> j0 = X[0][k2], j1 = X[1][k2], j2 = X[2][k2];
+        const cx<R> m0 = X[3][k2], m1 = X[4][k2], m2 = X[5][k2];
+        // c x m and c x j
+        const cx<R> cm0 = cyv * m2 - czv * m1, cm1 = czv * m0 - cxv * m2, cm2 = cxv * m1 - cyv * m0;
+        const cx<R> cj0 = cyv * j2 - czv * j1, cj1 = czv * j0 - cxv * j2, cj2 = cxv * j1 - cyv * j0;
+        X[0][k2] = kxx * j0 + kxy * j1 + kxz * j2 + cm0;
+        X[1][k2] = kxy * j0 + kyy * j1 + kyz * j2 + cm1;
+        X[2][k2] = kxz * j0 + kyz * j1 + kzz * j2 + cm2;
+        X[3][k2] = kxx * m0 + kxy * m1 + kxz * m2 - cj0;
+        X[4][k2] = kxy * m0 + kyy * m1 + kyz * m2 - cj1;
+        X[5][k2] = kxz * m0 + kyz * m1 + kzz * m2 - cj2;
+      }
+    });
+  }
+
+  static_for<0, C>([&](auto c) {
+    cx<R>* dst = base + c * a.comp_stride;
+    fft_inv_CD<R, P1, P2, false>(
+        X[c], [&](auto, int z, cx<R> v) { dst[long(z) * PP] = v; }, a.n, lds, tw, col, j, a.T, valid);
+  });
+}
+
+struct XArgs {
+  int T;            // rows per block
+  long nrows;       // nrhs * n * n
+  int n;            // grid points per axis
+  long n3;          // n^3
+};
+
+// Rows (rhs, z, y): inverse x transform of every component, then the pointwise
+// combine.  Vectors J, B, out are complex128 [rhs][C][n^3]; H, Hmu [9][n^3].
+template <typename R, int P1, int P2, int C, int MODE>
+__global__ void __launch_bounds__(kFusedMaxThreads) k_xinv(const cx<R>* __restrict__ A, XArgs a, const c128* __restrict__ Jv,
+                                               const c128* __restrict__ Bv, const cx<R>* __restrict__ H,
+                                               const cx<R>* __restrict__ Hmu, c128* __restrict__ out,
+                                               const cx<R>* __restrict__ twg) {
+  constexpr int P = P1 * P2;
+  constexpr int J = P1 > P2 ? P1 : P2;
+  static_assert(P1 % 2 == 0, "the cropped inverse assumes n = P/2 with P1 even");
+  constexpr int NV = P1 / 2;  // outputs per thread per component: x = j + P2 m2, m2 < NV
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<R>* tw = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* lds = tw + P;
+  load_twiddles<R, P>(tw, twg);
+  int col, j;
+  Layout<true>::lane(threadIdx.x, a.T, J, col, j);
+  const long row = long(blockIdx.x) * a.T + col;
+  const bool valid = row < a.nrows;
+  const int N = a.n;
+  const long NN = long(N) * N;
+  const long rhs = valid ? row / NN : 0;
+  const long zy = valid ? row % NN : 0;
+  __syncthreads();
+
+  cx<R> U[C][NV];
+  static_for<0, C>([&](auto c) {
+    const cx<R>* src = A + ((rhs * C + c) * NN + zy) * P;
+    cx<R> X[P2];
+    if (j < P1) {
+      static_for<0, P2>([&](auto k2) { X[k2] = valid ? src[j + P1 * k2] : czero<R>(); });
+    }
+    fft_inv_CD<R, P1, P2, true>(
+        X,
+        [&](auto m2, int, cx<R> v) {
+          if constexpr (decltype(m2)::value < NV) U[c][decltype(m2)::value] = v;
+        },
+        N, lds, tw, col, j, a.T, valid);
+  });
+
+  if (!valid || j >= P2) return;
+  static_for<0, NV>([&](auto m2) {
+    const int x = j + P2 * m2;
+    const long p = zy * N + x;
+    static_for<0, C / 3>([&](auto half) {
+      constexpr int c0 = 3 * decltype(half)::value;
+      const long vb = (rhs * C + c0) * a.n3 + p;
+      if constexpr (MODE == MODE_CONV) {
+        static_for<0, 3>([&](auto c) { out[vb + c * a.n3] = cvt<double>(U[c0 + c][m2]); });
+      } else if constexpr (MODE == MODE_FIELD) {
+        static_for<0, 3>([&](auto c) {
+          out[vb + c * a.n3] = cvt<double>(cvt<R>(Jv[vb + c * a.n3]) + U[c0 + c][m2]);
+        });
+      } else {
+        const cx<R>* Hh = (c0 == 0) ? H : Hmu;
+        cx<R> jv[3], v[3];
+        static_for<0, 3>([&](auto c) {
+          jv[c] = cvt<R>(Jv[vb + c * a.n3]);
+          v[c] = jv[c] + R(2) * U[c0 + c][m2];
+        });
+        static_for<0, 3>([&](auto r) {
+          cx<R> acc = jv[r];
+          static_for<0, 3>([&](auto s) { acc = acc - Hh[(3 * r + s) * a.n3 + p] * v[s]; });
+          if constexpr (MODE == MODE_RESIDUAL) {
+            out[vb + r * a.n3] = Bv[vb + r * a.n3] - cvt<double>(acc);
+          } else {
+            out[vb + r * a.n3] = cvt<double>(acc);
+          }
+        });
+      }
+    });
+  });
+}
+
+}  // namespace vie

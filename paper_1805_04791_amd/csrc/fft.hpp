@@ -1,0 +1,206 @@
+// Pencil FFT building blocks for gfx950.
+//
+// A length-P transform (P = P1 * P2) of one pencil is split into two
+// register-resident DFTs with one LDS exchange in between:
+//
+//   forward  X[k1 + P1 k2] = sum_n2 W_P2^{n2 k2} . W_P^{n2 k1} . sum_n1 x[P2 n1 + n2] W_P1^{n1 k1}
+//            step A: thread (col, n2) loads P1 inputs, DFT_P1, twiddle, -> LDS
+//            step B: thread (col, k1) reads P2 values from LDS, DFT_P2 -> X[k1 + P1 k2]
+//   inverse  x[m1 + P2 m2] = sum_k1 W_P1^{-m2 k1} . W_P^{-m1 k1} . sum_k2 X[k1 + P1 k2] W_P2^{-m1 k2}
+//            step C: thread (col, k1) holds X[k1 + P1 k2] (all k2), IDFT_P2, twiddle, -> LDS
+//            step D: thread (col, m1) reads P1 values, IDFT_P1 -> x[m1 + P2 m2]
+//
+// The forward result of step B is laid out exactly as step C expects, so a
+// fused forward-multiply-inverse pencil needs no exchange between the halves.
+// Zero-padded inputs (n >= nin) are never read and cropped outputs
+// (n >= nout) never written.
+//
+// Two thread layouts: "strided" pencils (y and z axes) put adjacent columns
+// on adjacent lanes so every global access is a contiguous run of T complex
+// values; "contiguous" pencils (x axis) put adjacent pencil indices on
+// adjacent lanes.
+#pragma once
+
+#include "cx.hpp"
+#include "dft.hpp"
+
+namespace vie {
+
+template <typename T>
+struct scalar_of;
+template <typename R>
+struct scalar_of<cx<R>> {
+  using type = R;
+};
+
+// largest block of each kernel family (the tile choice keeps T*J within it)
+constexpr int kPassMaxThreads = 512;
+constexpr int kFusedMaxThreads = 256;
+
+struct Geo {
+  int T;          // columns (strided) or rows (contiguous) per block
+  int ntiles;     // column tiles per pencil group
+  long ncols;     // columns per group
+  int nin;        // valid inputs along the transform axis
+  int nout;       // outputs written along the transform axis
+};
+
+// element n of pencil (g, c) lives at p + g*gs + c*cs + n*as
+template <typename T>
+struct MemLoad {
+  const T* p;
+  long gs, cs, as;
+  template <typename R>
+  __device__ __forceinline__ cx<R> load(long g, long c, int n) const {
+    return cvt<R>(p[g * gs + c * cs + long(n) * as]);
+  }
+};
+
+template <typename T>
+struct MemStore {
+  T* p;
+  long gs, cs, as;
+  double scale;       // multiplies every stored value
+  int zero_first;     // store 0 at n == 0
+  template <typename R>
+  __device__ __forceinline__ void store(long g, long c, int n, cx<R> v) const {
+    using S = typename scalar_of<T>::type;
+    if (zero_first && n == 0) v = czero<R>();
+    v = R(scale) * v;
+    p[g * gs + c * cs + long(n) * as] = cvt<S>(v);
+  }
+};
+
+template <bool CONTIG>
+struct Layout;
+
+// strided: (a * Bd + b) * T + col
+template <>
+struct Layout<false> {
+  __device__ __forceinline__ static int idx(int col, int a, int b, int Bd, int Ad, int T) {
+    (void)Ad;
+    return (a * Bd + b) * T + col;
+  }
+  __device__ __forceinline__ static void lane(int tid, int T, int J, int& col, int& j) {
+    (void)J;
+    col = tid % T;
+    j = tid / T;
+  }
+};
+
+// contiguous: col * Ad * (Bd + 1) + a * (Bd + 1) + b
+template <>
+struct Layout<true> {
+  __device__ __forceinline__ static int idx(int col, int a, int b, int Bd, int Ad, int T) {
+    (void)T;
+    return col * (Ad * (Bd + 1)) + a * (Bd + 1) + b;
+  }
+  __device__ __forceinline__ static void lane(int tid, int T, int J, int& col, int& j) {
+    (void)T;
+    col = tid / J;
+    j = tid % J;
+  }
+};
+
+template <int P1, int P2>
+__host__ __device__ constexpr int lds_elems_per_col(bool contig) {
+  return contig ? (P2 * (P1 + 1) > P1 * (P2 + 1) ? P2 * (P1 + 1) : P1 * (P2 + 1)) : P1 * P2;
+}
+
+// Step A + B.  load(n) is called for n < nin only.  On return the threads with
+// j < P1 hold X[j + P1 k2] in X[k2].  Contains two block barriers; every thread
+// of the block must call it.
+template <typename R, int P1, int P2, bool CONTIG, typename LoadF>
+__device__ __forceinline__ void fft_fwd_AB(LoadF&& load, int nin, cx<R>* lds, const cx<R>* tw, int col,
+                                           int j, int T, bool valid, cx<R> (&X)[P2]) {
+  if (j < P2) {
+    cx<R> u[P1];
+    static_for<0, P1>([&](auto n1) {
+      const int n = P2 * n1 + j;
+      u[n1] = (valid && n < nin) ? load(n) : czero<R>();
+    });
+    DFT<P1, false>::run(u);
+    static_for<1, P1>([&](auto k1) { u[k1] = u[k1] * tw[j * k1]; });
+    static_for<0, P1>([&](auto k1) { lds[Layout<CONTIG>::idx(col, j, k1, P1, P2, T)] = u[k1]; });
+  }
+  __syncthreads();
+  if (j < P1) {
+    static_for<0, P2>([&](auto n2) { X[n2] = lds[Layout<CONTIG>::idx(col, n2, j, P1, P2, T)]; });
+    DFT<P2, false>::run(X);
+  }
+  __syncthreads();
+}
+
+// Step C + D.  Threads with j < P1 supply X[j + P1 k2] in X[k2] (destroyed).
+// store(m2, n, v) is called for n = j + P2 m2 < nout only (m2 is a compile-time index).
+template <typename R, int P1, int P2, bool CONTIG, typename StoreF>
+__device__ __forceinline__ void fft_inv_CD(cx<R> (&X)[P2], StoreF&& store, int nout, cx<R>* lds, const cx<R>* tw,
+                                           int col, int j, int T, bool valid) {
+  if (j < P1) {
+    DFT<P2, true>::run(X);
+    static_for<1, P2>([&](auto m1) { X[m1] = cmulc(tw[m1 * j], X[m1]); });
+    static_for<0, P2>([&](auto m1) { lds[Layout<CONTIG>::idx(col, j, m1, P2, P1, T)] = X[m1]; });
+  }
+  __syncthreads();
+  if (j < P2) {
+    cx<R> u[P1];
+    static_for<0, P1>([&](auto k1) { u[k1] = lds[Layout<CONTIG>::idx(col, k1, j, P2, P1, T)]; });
+    DFT<P1, true>::run(u);
+    static_for<0, P1>([&](auto m2) {
+      const int n = j + P2 * m2;
+      if (valid && n < nout) store(m2, n, u[m2]);
+    });
+  }
+  __syncthreads();
+}
+
+// stage the length-P twiddle table W_P^j into LDS
+template <typename R, int P>
+__device__ __forceinline__ void load_twiddles(cx<R>* tw, const cx<R>* __restrict__ twg) {
+  for (int i = threadIdx.x; i < P; i += blockDim.x) tw[i] = twg[i];
+}
+
+// One pass of a batched pencil FFT (forward or inverse, pruned).
+template <typename R, int P1, int P2, bool CONTIG, bool INV, typename Src, typename Dst>
+__global__ void __launch_bounds__(kPassMaxThreads) k_pass(Src src, Dst dst, Geo geo, const cx<R>* __restrict__ twg) {
+  constexpr int P = P1 * P2;
+  constexpr int J = P1 > P2 ? P1 : P2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<R>* tw = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* lds = tw + P;
+  load_twiddles<R, P>(tw, twg);
+  int col, j;
+  Layout<CONTIG>::lane(threadIdx.x, geo.T, J, col, j);
+  const long tile = long(blockIdx.x) % geo.ntiles;
+  const long g = long(blockIdx.x) / geo.ntiles;
+  const long c = tile * geo.T + col;
+  const bool valid = c < geo.ncols;
+  __syncthreads();
+  cx<R> X[P2];
+  if constexpr (!INV) {
+    fft_fwd_AB<R, P1, P2, CONTIG>([&](int n) { return src.template load<R>(g, c, n); }, geo.nin, lds, tw, col, j,
+                                  geo.T, valid, X);
+    if (j < P1 && valid) {
+      static_for<0, P2>([&](auto k2) {
+        const int n = j + P1 * k2;
+        if (n < geo.nout) dst.template store<R>(g, c, n, X[k2]);
+      });
+    }
+  } else {
+    if (j < P1) {
+      static_for<0, P2>([&](auto k2) {
+        const int n = j + P1 * k2;
+        X[k2] = (valid && n < geo.nin) ? src.template load<R>(g, c, n) : czero<R>();
+      });
+    }
+    fft_inv_CD<R, P1, P2, CONTIG>(
+        X, [&](auto, int n, cx<R> v) { dst.template store<R>(g, c, n, v); }, geo.nout, lds, tw, col, j, geo.T, valid);
+  }
+}
+
+template <int P1, int P2>
+struct Split {
+  static constexpr int p1 = P1, p2 = P2, P = P1 * P2, J = (P1 > P2 ? P1 : P2);
+};
+
+}  // namespace vie

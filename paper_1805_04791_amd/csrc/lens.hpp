@@ -1,0 +1,169 @@
+// Per-length kernel registry.  Each supported FFT length P = P1 * P2 is
+// compiled in its own translation unit (len_<P>.hip) which registers launch
+// functions for every kernel of that length at library load.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "apply_kernels.hpp"
+#include "fft.hpp"
+#include "symbol.hpp"
+
+namespace vie {
+
+// Source functor of the first precompute pass: symbol samples on the M^3
+// frequency grid, odd entries zeroed on their Nyquist planes, modulated by
+// (-i)^(ix + iy + iz) so that the inverse transform's first 2n outputs are the
+// displacements -n .. n-1.
+struct SymbolSrc {
+  int M;
+  int set;      // SYM_GRAD or SYM_MAXWELL
+  int entry0;   // table entry of group 0
+  double h, w, R;
+  // g = table entry - entry0, c = row index iz * M + iy, n = ix
+  template <typename Rt>
+  __device__ __forceinline__ cx<Rt> load(long g, long c, int n) const {
+    const int e = entry0 + int(g);
+    const int ix = n, iy = int(c % M), iz = int(c / M);
+    const int half = M / 2;
+    if ((ix == half && symbol_odd(e, 0)) || (iy == half && symbol_odd(e, 1)) || (iz == half && symbol_odd(e, 2)))
+      return czero<Rt>();
+    const double ds = 2.0 * kPi / (double(M) * h);
+    const double sx = ds * double(ix < half ? ix : ix - M);
+    const double sy = ds * double(iy < half ? iy : iy - M);
+    const double sz = ds * double(iz < half ? iz : iz - M);
+    c128 v = symbol_entry(set, e, sx, sy, sz, w, R);
+    switch ((ix + iy + iz) & 3) {
+      case 1: v = times_mi(v); break;
+      case 2: v = -v; break;
+      case 3: v = times_i(v); break;
+      default: break;
+    }
+    return cvt<Rt>(v);
+  }
+};
+
+template <typename R>
+struct LenOps {
+  int P = 0, P1 = 0, P2 = 0;
+  // x-axis forward pass reading complex128 input
+  hipError_t (*contig_fwd)(MemLoad<c128>, MemStore<cx<R>>, Geo, long ngroups, const cx<R>*, hipStream_t) = nullptr;
+  // y/z-axis pass, forward or inverse
+  hipError_t (*strided)(bool inv, MemLoad<cx<R>>, MemStore<cx<R>>, Geo, long ngroups, const cx<R>*,
+                        hipStream_t) = nullptr;
+  // fused z pass, mul = MUL_SYM3 or MUL_MAX6
+  hipError_t (*zpass)(int mul, cx<R>*, const cx<R>*, ZArgs, long nblocks, const cx<R>*, hipStream_t) = nullptr;
+  // last inverse x pass with combine, C in {3, 6}, mode MODE_*
+  hipError_t (*xinv)(int C, int mode, const cx<R>*, XArgs, const c128*, const c128*, const cx<R>*, const cx<R>*,
+                     c128*, const cx<R>*, hipStream_t) = nullptr;
+  // precompute: inverse x pass of length M fed by the symbol (double only)
+  hipError_t (*symbol_inv)(SymbolSrc, MemStore<c128>, Geo, long ngroups, const c128*, hipStream_t) = nullptr;
+};
+
+template <typename R>
+LenOps<R>* len_table();  // indexed by P, size kMaxLen + 1
+constexpr int kMaxLen = 640;
+
+template <typename R>
+inline const LenOps<R>* len_ops(int P) {
+  if (P < 0 || P > kMaxLen) return nullptr;
+  const LenOps<R>* o = &len_table<R>()[P];
+  return o->P == P ? o : nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+template <typename R, int P1, int P2, bool CONTIG>
+inline size_t pass_lds_bytes(int T) {
+  return sizeof(cx<R>) * (size_t(P1 * P2) + size_t(T) * lds_elems_per_col<P1, P2>(CONTIG));
+}
+
+template <typename R, int P1, int P2>
+struct LenImpl {
+  static constexpr int P = P1 * P2;
+  static constexpr int J = P1 > P2 ? P1 : P2;
+
+  static hipError_t contig_fwd(MemLoad<c128> src, MemStore<cx<R>> dst, Geo geo, long ngroups, const cx<R>* tw,
+                               hipStream_t s) {
+    const long blocks = long(geo.ntiles) * ngroups;
+    k_pass<R, P1, P2, true, false, MemLoad<c128>, MemStore<cx<R>>><<<dim3(unsigned(blocks)), dim3(geo.T * J), pass_lds_bytes<R, P1, P2, true>(geo.T), s>>>(src, dst, geo, tw);
+    return hipGetLastError();
+  }
+  static hipError_t strided(bool inv, MemLoad<cx<R>> src, MemStore<cx<R>> dst, Geo geo, long ngroups,
+                            const cx<R>* tw, hipStream_t s) {
+    const long blocks = long(geo.ntiles) * ngroups;
+    if (inv)
+      k_pass<R, P1, P2, false, true, MemLoad<cx<R>>, MemStore<cx<R>>><<<dim3(unsigned(blocks)), dim3(geo.T * J), pass_lds_bytes<R, P1, P2, false>(geo.T), s>>>(src, dst, geo, tw);
+    else
+      k_pass<R, P1, P2, false, false, MemLoad<cx<R>>, MemStore<cx<R>>><<<dim3(unsigned(blocks)), dim3(geo.T * J), pass_lds_bytes<R, P1, P2, false>(geo.T), s>>>(src, dst, geo, tw);
+    return hipGetLastError();
+  }
+  static hipError_t zpass(int mul, cx<R>* buf, const cx<R>* tab, ZArgs a, long nblocks, const cx<R>* tw,
+                          hipStream_t s) {
+    const size_t lds = pass_lds_bytes<R, P1, P2, false>(a.T);
+    if (mul == MUL_SYM3)
+      k_zpass<R, P1, P2, 3, MUL_SYM3><<<dim3(unsigned(nblocks)), dim3(a.T * J), lds, s>>>(buf, tab, a, tw);
+    else
+      k_zpass<R, P1, P2, 6, MUL_MAX6><<<dim3(unsigned(nblocks)), dim3(a.T * J), lds, s>>>(buf, tab, a, tw);
+    return hipGetLastError();
+  }
+  template <int C, int MODE>
+  static void xinv_launch(const cx<R>* A, XArgs a, const c128* J_, const c128* B, const cx<R>* H, const cx<R>* Hmu,
+                          c128* out, const cx<R>* tw, hipStream_t s) {
+    const long blocks = (a.nrows + a.T - 1) / a.T;
+    k_xinv<R, P1, P2, C, MODE><<<dim3(unsigned(blocks)), dim3(a.T * J), pass_lds_bytes<R, P1, P2, true>(a.T), s>>>(A, a, J_, B, H, Hmu, out, tw);
+  }
+  static hipError_t xinv(int C, int mode, const cx<R>* A, XArgs a, const c128* J_, const c128* B, const cx<R>* H,
+                         const cx<R>* Hmu, c128* out, const cx<R>* tw, hipStream_t s) {
+#define VIE_XINV_CASE(CC, MM) \
+  if (C == CC && mode == MM) { xinv_launch<CC, MM>(A, a, J_, B, H, Hmu, out, tw, s); return hipGetLastError(); }
+    VIE_XINV_CASE(3, MODE_MATVEC)
+    VIE_XINV_CASE(3, MODE_FIELD)
+    VIE_XINV_CASE(3, MODE_CONV)
+    VIE_XINV_CASE(3, MODE_RESIDUAL)
+    VIE_XINV_CASE(6, MODE_MATVEC)
+    VIE_XINV_CASE(6, MODE_FIELD)
+    VIE_XINV_CASE(6, MODE_CONV)
+    VIE_XINV_CASE(6, MODE_RESIDUAL)
+#undef VIE_XINV_CASE
+    return hipErrorInvalidValue;
+  }
+  static hipError_t symbol_inv(SymbolSrc src, MemStore<c128> dst, Geo geo, long ngroups, const c128* tw,
+                               hipStream_t s) {
+    const long blocks = long(geo.ntiles) * ngroups;
+    k_pass<double, P1, P2, true, true, SymbolSrc, MemStore<c128>><<<dim3(unsigned(blocks)), dim3(geo.T * J), pass_lds_bytes<double, P1, P2, true>(geo.T), s>>>(src, dst, geo, tw);
+    return hipGetLastError();
+  }
+
+  // register the apply kernels and, for double, the precompute passes
+  template <bool APPLY, bool SYMBOL>
+  static void register_all() {
+    LenOps<R>& o = len_table<R>()[P];
+    o.P = P;
+    o.P1 = P1;
+    o.P2 = P2;
+    o.strided = &strided;
+    if constexpr (APPLY) {
+      o.contig_fwd = &contig_fwd;
+      o.zpass = &zpass;
+      o.xinv = &xinv;
+    }
+    if constexpr (SYMBOL && std::is_same<R, double>::value) o.symbol_inv = &symbol_inv;
+  }
+};
+
+// Registers length P1*P2.  APPLY: apply kernels in FP32 and FP64 (and the FP64
+// forward passes of the precompute).  SYMBOL: the FP64 symbol pass and
+// strided inverse used as the oversampled length M.
+#define VIE_REGISTER_LEN(P1_, P2_, APPLY_, SYMBOL_)                                  \
+  namespace {                                                                        \
+  struct RegLen##P1_##x##P2_ {                                                       \
+    RegLen##P1_##x##P2_() {                                                          \
+      if constexpr (APPLY_) vie::LenImpl<float, P1_, P2_>::register_all<true, false>(); \
+      vie::LenImpl<double, P1_, P2_>::register_all<APPLY_, SYMBOL_>();                 \
+    }                                                                                \
+  } reg_len_##P1_##x##P2_;                                                           \
+  }
+
+}  // namespace vie

@@ -1,0 +1,778 @@
+// Plan creation (contrast + kernel-table precompute), the batched FFT apply,
+// autotuning of the pencil tiles, and the C entry points other than vie_solve.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+
+#include "lens.hpp"
+#include "pointwise.hpp"
+
+using namespace vie;
+
+namespace vie {
+
+template <typename R>
+LenOps<R>* len_table() {
+  static LenOps<R> t[kMaxLen + 1];
+  return t;
+}
+template LenOps<float>* len_table<float>();
+template LenOps<double>* len_table<double>();
+
+std::string& last_create_error() {
+  static thread_local std::string m;
+  return m;
+}
+
+int fail(vie_plan* pl, int code, const std::string& msg) {
+  if (pl) pl->err = msg;
+  return code;
+}
+
+int hip_fail(vie_plan* pl, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (pl) pl->err = m;
+  return e == hipErrorOutOfMemory ? VIE_E_NOMEM : VIE_E_DEVICE;
+}
+
+int dev_alloc(vie_plan* pl, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(pl, VIE_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  pl->allocs.push_back({*p, bytes});
+  pl->dev_bytes += bytes;
+  return VIE_OK;
+}
+
+void dev_free(vie_plan* pl, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < pl->allocs.size(); ++i) {
+    if (pl->allocs[i].first == p) {
+      pl->dev_bytes -= pl->allocs[i].second;
+      pl->allocs.erase(pl->allocs.begin() + long(i));
+      break;
+    }
+  }
+  (void)hipFree(p);
+}
+
+static hipEvent_t take_event(vie_plan* pl) {
+  if (!pl->ev_pool.empty()) {
+    hipEvent_t e = pl->ev_pool.back();
+    pl->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int prof_begin(vie_plan* pl, hipStream_t s) {
+  if (!pl->prof_on) return -1;
+  hipEvent_t a = take_event(pl), b = take_event(pl);
+  if (!a || !b) return -1;
+  (void)hipEventRecord(a, s);
+  pl->prof.push_back({-1, a, b, 0.0});
+  return int(pl->prof.size()) - 1;
+}
+
+void prof_end(vie_plan* pl, int fam, int token, hipStream_t s, double bytes) {
+  if (token < 0 || !pl->prof_on) return;
+  pl->prof[size_t(token)].fam = fam;
+  pl->prof[size_t(token)].bytes = bytes;
+  (void)hipEventRecord(pl->prof[size_t(token)].b, s);
+}
+
+// fold recorded pairs into the per-family totals
+static void prof_collect(vie_plan* pl) {
+  for (auto& r : pl->prof) {
+    if (r.fam >= 0) {
+      (void)hipEventSynchronize(r.b);
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        pl->prof_ms[r.fam] += ms;
+        pl->prof_cnt[r.fam] += 1;
+        pl->prof_bytes[r.fam] += r.bytes;
+      }
+    }
+    pl->ev_pool.push_back(r.a);
+    pl->ev_pool.push_back(r.b);
+  }
+  pl->prof.clear();
+}
+
+}  // namespace vie
+
+namespace {
+
+// exp(-2 pi i j / L) with exact quadrant reduction
+void twiddle_host(long j, long L, double* re, double* im) {
+  j %= L;
+  if (j < 0) j += L;
+  const long q = (4 * j) / L;
+  const long r = 4 * j - q * L;
+  double c, s;
+  if (2 * r <= L) {
+    const double phi = (M_PI / 2.0) * double(r) / double(L);
+    c = std::cos(phi);
+    s = std::sin(phi);
+  } else {
+    const double psi = (M_PI / 2.0) * double(L - r) / double(L);
+    c = std::sin(psi);
+    s = std::cos(psi);
+  }
+  double cc, ss;
+  switch (q & 3) {
+    case 0: cc = c; ss = s; break;
+    case 1: cc = -s; ss = c; break;
+    case 2: cc = -c; ss = -s; break;
+    default: cc = s; ss = -c; break;
+  }
+  *re = cc;
+  *im = -ss;
+}
+
+template <typename R>
+int upload_twiddles(vie_plan* pl, int L, cx<R>** out, hipStream_t s) {
+  std::vector<cx<R>> h(static_cast<size_t>(L));
+  for (int j = 0; j < L; ++j) {
+    double re, im;
+    twiddle_host(j, L, &re, &im);
+    h[size_t(j)] = {R(re), R(im)};
+  }
+  int rc = dev_alloc(pl, reinterpret_cast<void**>(out), sizeof(cx<R>) * size_t(L));
+  if (rc) return rc;
+  HIPCHK(pl, hipMemcpyAsync(*out, h.data(), sizeof(cx<R>) * size_t(L), hipMemcpyHostToDevice, s));
+  HIPCHK(pl, hipStreamSynchronize(s));
+  return VIE_OK;
+}
+
+constexpr int kTileChoices[] = {2, 4, 8, 12, 16, 24, 32};
+
+template <typename R, bool CONTIG>
+size_t lds_need(int P1, int P2, int T) {
+  const size_t per = CONTIG ? size_t(std::max(P2 * (P1 + 1), P1 * (P2 + 1))) : size_t(P1 * P2);
+  return sizeof(cx<R>) * (size_t(P1 * P2) + size_t(T) * per);
+}
+
+// T columns per block must divide `cols` (the column count of a strided
+// pass, or the transform length for contiguous passes)
+template <typename R>
+bool tile_ok(const vie_plan* pl, int P1, int P2, int T, bool contig, long cols, int maxthreads) {
+  const int J = std::max(P1, P2);
+  if (T * J > maxthreads || T * J < 16) return false;
+  if (cols > 0 && cols % T != 0) return false;
+  const size_t need = contig ? lds_need<R, true>(P1, P2, T) : lds_need<R, false>(P1, P2, T);
+  return need <= pl->max_lds;
+}
+
+template <typename R>
+int default_tile(const vie_plan* pl, int P1, int P2, bool contig, int maxthreads, long cols) {
+  const int J = std::max(P1, P2);
+  int best = 0;
+  for (int T : kTileChoices) {
+    if (!tile_ok<R>(pl, P1, P2, T, contig, cols, maxthreads)) continue;
+    // prefer ~256 threads per block
+    if (best == 0 || std::abs(T * J - 256) < std::abs(best * J - 256)) best = T;
+  }
+  return best;
+}
+
+int bucket_of(int nb) {
+  int b = 1;
+  while (b < nb) b <<= 1;
+  return b;
+}
+
+bool env_flag(const char* name, bool dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return !(v[0] == '0' || v[0] == 'n' || v[0] == 'N' || v[0] == 'f' || v[0] == 'F');
+}
+
+// ---------------------------------------------------------------------------
+// the five passes of one batched apply
+// ---------------------------------------------------------------------------
+template <typename R>
+struct ApplyCall {
+  vie_plan* pl;
+  const LenOps<R>* ops;
+  const cx<R>* tw;
+  cx<R>* A;
+  cx<R>* B;
+  int nb;
+};
+
+template <typename R>
+hipError_t pass_xfwd(const ApplyCall<R>& c, const c128* in, int T, hipStream_t s) {
+  const vie_plan* pl = c.pl;
+  const long rows = long(c.nb) * pl->C * pl->n * pl->n;
+  Geo g{T, int((rows + T - 1) / T), rows, pl->n, pl->P};
+  MemLoad<c128> src{in, 0, pl->n, 1};
+  MemStore<cx<R>> dst{c.A, 0, pl->P, 1, 1.0, 0};
+  return c.ops->contig_fwd(src, dst, g, 1, c.tw, s);
+}
+
+template <typename R>
+hipError_t pass_yfwd(const ApplyCall<R>& c, int T, hipStream_t s) {
+  const vie_plan* pl = c.pl;
+  const long N = pl->n, P = pl->P;
+  Geo g{T, int(P / T), P, int(N), int(P)};
+  MemLoad<cx<R>> src{c.A, N * P, 1, P};
+  MemStore<cx<R>> dst{c.B, P * P, 1, P, 1.0, 0};
+  return c.ops->strided(false, src, dst, g, long(c.nb) * pl->C * N, c.tw, s);
+}
+
+template <typename R>
+hipError_t pass_z(const ApplyCall<R>& c, const cx<R>* tab, int T, hipStream_t s) {
+  const vie_plan* pl = c.pl;
+  const long N = pl->n, P = pl->P;
+  ZArgs a{T, int(P / T), int(N), int(P), pl->nxp, pl->ne, N * P * P, long(pl->C) * N * P * P};
+  const long nblocks = long(P / T) * P * c.nb;
+  return c.ops->zpass(pl->full ? MUL_MAX6 : MUL_SYM3, c.B, tab, a, nblocks, c.tw, s);
+}
+
+template <typename R>
+hipError_t pass_yinv(const ApplyCall<R>& c, int T, hipStream_t s) {
+  const vie_plan* pl = c.pl;
+  const long N = pl->n, P = pl->P;
+  Geo g{T, int(P / T), P, int(P), int(N)};
+  MemLoad<cx<R>> src{c.B, P * P, 1, P};
+  MemStore<cx<R>> dst{c.A, N * P, 1, P, 1.0, 0};
+  return c.ops->strided(true, src, dst, g, long(c.nb) * pl->C * N, c.tw, s);
+}
+
+template <typename R>
+hipError_t pass_xinv(const ApplyCall<R>& c, const c128* addv, const c128* bvec, c128* out, int mode, int T,
+                     hipStream_t s) {
+  const vie_plan* pl = c.pl;
+  XArgs a{T, long(c.nb) * pl->n * pl->n, pl->n, pl->n3};
+  const cx<R>* H;
+  const cx<R>* Hmu;
+  if constexpr (std::is_same<R, float>::value) {
+    H = pl->H32;
+    Hmu = pl->Hmu32;
+  } else {
+    H = pl->H64;
+    Hmu = pl->Hmu64;
+  }
+  return c.ops->xinv(pl->C, mode, c.A, a, addv, bvec, H, Hmu, out, c.tw, s);
+}
+
+template <typename R>
+int ensure_workspace(vie_plan* pl, int nb) {
+  const int idx = std::is_same<R, double>::value ? 1 : 0;
+  if (pl->ws_cap[idx] >= nb) return VIE_OK;
+  dev_free(pl, pl->wsA[idx]);
+  dev_free(pl, pl->wsB[idx]);
+  pl->wsA[idx] = pl->wsB[idx] = nullptr;
+  pl->ws_cap[idx] = 0;
+  const size_t N = size_t(pl->n), P = size_t(pl->P), C = size_t(pl->C);
+  int rc = dev_alloc(pl, &pl->wsA[idx], sizeof(cx<R>) * size_t(nb) * C * N * N * P);
+  if (rc) return rc;
+  rc = dev_alloc(pl, &pl->wsB[idx], sizeof(cx<R>) * size_t(nb) * C * N * P * P);
+  if (rc) return rc;
+  pl->ws_cap[idx] = nb;
+  return VIE_OK;
+}
+
+// time one pass for each tile candidate and keep the fastest
+template <typename R, typename F>
+int pick_tile(vie_plan* pl, int P1, int P2, bool contig, int maxthreads, F&& run, hipStream_t s, int* out) {
+  hipEvent_t e0, e1;
+  HIPCHK(pl, hipEventCreate(&e0));
+  HIPCHK(pl, hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  int best = 0;
+  for (int T : kTileChoices) {
+    if (!tile_ok<R>(pl, P1, P2, T, contig, P1 * P2, maxthreads)) continue;
+    HIPCHK(pl, run(T));  // warm-up
+    HIPCHK(pl, hipEventRecord(e0, s));
+    for (int r = 0; r < 3; ++r) HIPCHK(pl, run(T));
+    HIPCHK(pl, hipEventRecord(e1, s));
+    HIPCHK(pl, hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(pl, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = T;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best == 0) return fail(pl, VIE_E_SIZE, "no tile shape fits the LDS limit");
+  *out = best;
+  return VIE_OK;
+}
+
+template <typename R>
+int get_tune(vie_plan* pl, const ApplyCall<R>& c, const c128* in, c128* out, hipStream_t s, Tune* t) {
+  const int idx = std::is_same<R, double>::value ? 1 : 0;
+  const int key = bucket_of(c.nb);
+  auto it = pl->tune[idx].find(key);
+  if (it != pl->tune[idx].end()) {
+    *t = it->second;
+    return VIE_OK;
+  }
+  const int P1 = c.ops->P1, P2 = c.ops->P2;
+  Tune d;
+  const int P = P1 * P2;
+  d.tx_fwd = default_tile<R>(pl, P1, P2, true, kPassMaxThreads, P);
+  d.tx_inv = default_tile<R>(pl, P1, P2, true, kFusedMaxThreads, P);
+  d.ty_fwd = d.ty_inv = default_tile<R>(pl, P1, P2, false, kPassMaxThreads, P);
+  d.tz = default_tile<R>(pl, P1, P2, false, kFusedMaxThreads, P);
+  if (d.tx_fwd == 0 || d.tz == 0 || d.tx_inv == 0 || d.ty_fwd == 0) return fail(pl, VIE_E_SIZE, "no tile shape fits the LDS limit");
+  // measure only where it pays: large grids, unless switched off
+  if (pl->n >= 48 && env_flag("VIE_AUTOTUNE", true)) {
+    const cx<R>* tab;
+    if constexpr (std::is_same<R, float>::value)
+      tab = pl->tab32;
+    else
+      tab = pl->tab64;
+    int rc;
+    rc = pick_tile<R>(pl, P1, P2, true, kPassMaxThreads, [&](int T) { return pass_xfwd<R>(c, in, T, s); }, s, &d.tx_fwd);
+    if (rc) return rc;
+    rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, [&](int T) { return pass_yfwd<R>(c, T, s); }, s, &d.ty_fwd);
+    if (rc) return rc;
+    rc = pick_tile<R>(pl, P1, P2, false, kFusedMaxThreads, [&](int T) { return pass_z<R>(c, tab, T, s); }, s, &d.tz);
+    if (rc) return rc;
+    rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, [&](int T) { return pass_yinv<R>(c, T, s); }, s, &d.ty_inv);
+    if (rc) return rc;
+    rc = pick_tile<R>(pl, P1, P2, true, kFusedMaxThreads,
+                      [&](int T) { return pass_xinv<R>(c, in, nullptr, out, MODE_CONV, T, s); }, s, &d.tx_inv);
+    if (rc) return rc;
+  }
+  d.tuned = true;
+  pl->tune[idx][key] = d;
+  *t = d;
+  return VIE_OK;
+}
+
+template <typename R>
+int apply_typed(vie_plan* pl, const c128* in, const c128* addv, const c128* bvec, c128* out, int nrhs, int mode,
+                hipStream_t s) {
+  const LenOps<R>* ops = len_ops<R>(pl->P);
+  if (!ops || !ops->contig_fwd || !ops->zpass || !ops->xinv)
+    return fail(pl, VIE_E_SIZE, "no compiled FFT length " + std::to_string(pl->P));
+  const int idx = std::is_same<R, double>::value ? 1 : 0;
+  const int chunk = std::max(1, std::min(nrhs, pl->max_rhs));
+  int rc = ensure_workspace<R>(pl, chunk);
+  if (rc) return rc;
+  const cx<R>* tw;
+  const cx<R>* tab;
+  if constexpr (std::is_same<R, float>::value) {
+    tw = pl->tw32;
+    tab = pl->tab32;
+  } else {
+    tw = pl->tw64;
+    tab = pl->tab64;
+  }
+  const long L = long(pl->C) * pl->n3;
+  for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+    const int nb = std::min(chunk, nrhs - r0);
+    ApplyCall<R> c{pl, ops, tw, static_cast<cx<R>*>(pl->wsA[idx]), static_cast<cx<R>*>(pl->wsB[idx]), nb};
+    const long off = long(r0) * L;
+    const c128* inr = in + off;
+    c128* outr = out + off;
+    Tune t;
+    rc = get_tune<R>(pl, c, inr, outr, s, &t);
+    if (rc) return rc;
+    const int f0 = std::is_same<R, double>::value ? FAM_XFWD64 : FAM_XFWD32;
+    // algorithmic bytes: every operand read or written once per launch
+    const double cr = double(sizeof(cx<R>)), c16 = double(sizeof(c128));
+    const double vN3 = double(nb) * pl->C * double(pl->n3);
+    const double vN2P = vN3 / pl->n * pl->P, vNP2 = vN2P / pl->n * pl->P;
+    const double hb = 9.0 * double(pl->n3) * cr * (pl->full ? 2 : 1);
+    const double xinv_b = vN2P * cr + hb * (mode == MODE_MATVEC || mode == MODE_RESIDUAL) +
+                          vN3 * c16 * (1 + (mode != MODE_CONV) + (mode == MODE_RESIDUAL));
+    int tok = prof_begin(pl, s);
+    HIPCHK(pl, pass_xfwd<R>(c, inr, t.tx_fwd, s));
+    prof_end(pl, f0 + 0, tok, s, vN3 * c16 + vN2P * cr);
+    tok = prof_begin(pl, s);
+    HIPCHK(pl, pass_yfwd<R>(c, t.ty_fwd, s));
+    prof_end(pl, f0 + 1, tok, s, (vN2P + vNP2) * cr);
+    tok = prof_begin(pl, s);
+    HIPCHK(pl, pass_z<R>(c, tab, t.tz, s));
+    prof_end(pl, f0 + 2, tok, s, 2.0 * vNP2 * cr + double(pl->tab_elems) * cr);
+    tok = prof_begin(pl, s);
+    HIPCHK(pl, pass_yinv<R>(c, t.ty_inv, s));
+    prof_end(pl, f0 + 3, tok, s, (vN2P + vNP2) * cr);
+    tok = prof_begin(pl, s);
+    HIPCHK(pl, pass_xinv<R>(c, addv ? addv + off : inr, bvec ? bvec + off : nullptr, outr, mode, t.tx_inv, s));
+    prof_end(pl, f0 + 4, tok, s, xinv_b);
+  }
+  return VIE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// precompute of the kernel-transform tables (FP64)
+// ---------------------------------------------------------------------------
+int build_tables(vie_plan* pl, hipStream_t s) {
+  const int N = pl->n, P = pl->P, M = pl->M, NE = pl->ne;
+  const LenOps<double>* opsM = len_ops<double>(M);
+  const LenOps<double>* opsP = len_ops<double>(P);
+  if (!opsM || !opsM->symbol_inv || !opsM->strided)
+    return fail(pl, VIE_E_SIZE, "no compiled oversampled FFT length " + std::to_string(M));
+  if (!opsP || !opsP->contig_fwd || !opsP->strided)
+    return fail(pl, VIE_E_SIZE, "no compiled FFT length " + std::to_string(P));
+  c128* twM = nullptr;
+  int rc = upload_twiddles<double>(pl, M, &twM, s);
+  if (rc) return rc;
+  const long MM = long(M), PP = long(P);
+  c128 *buf1 = nullptr, *buf2 = nullptr, *buf3 = nullptr;
+  rc = dev_alloc(pl, reinterpret_cast<void**>(&buf1), sizeof(c128) * size_t(MM * MM * PP));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&buf2), sizeof(c128) * size_t(MM * PP * PP));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&buf3), sizeof(c128) * size_t(NE) * size_t(PP * PP * PP));
+  auto cleanup = [&]() {
+    dev_free(pl, buf1);
+    dev_free(pl, buf2);
+    dev_free(pl, buf3);
+    dev_free(pl, twM);
+  };
+  if (rc) {
+    cleanup();
+    return rc;
+  }
+  // strided passes of length M run over P (y) or P^2 (z) columns
+  const int TcM = default_tile<double>(pl, opsM->P1, opsM->P2, true, kPassMaxThreads, 0);
+  const int TsM = default_tile<double>(pl, opsM->P1, opsM->P2, false, kPassMaxThreads, P);
+  const int TcP = default_tile<double>(pl, opsP->P1, opsP->P2, true, kPassMaxThreads, 0);
+  const int TsP = default_tile<double>(pl, opsP->P1, opsP->P2, false, kPassMaxThreads, P);
+  if (!TcM || !TsM || !TcP || !TsP) {
+    cleanup();
+    return fail(pl, VIE_E_SIZE, "no tile shape fits the LDS limit for the precompute");
+  }
+  hipError_t e = hipSuccess;
+  for (int ent = 0; ent < NE && e == hipSuccess; ++ent) {
+    // (a) symbol samples of entry `ent` -> inverse transform along x; keep
+    //     outputs 0..P-1 (displacements -n..n-1), zero displacement -n
+    {
+      SymbolSrc src{M, pl->sym_set, ent, pl->h, pl->omega, pl->R};
+      const long rows = MM * MM;
+      Geo g{TcM, int((rows + TcM - 1) / TcM), rows, M, P};
+      MemStore<c128> dst{buf1, 0, PP, 1, 1.0 / double(M), 1};
+      e = opsM->symbol_inv(src, dst, g, 1, twM, s);
+    }
+    // (b) inverse along y: buf1[kz][ky][nx] -> buf2[kz][ny][nx]
+    if (e == hipSuccess) {
+      Geo g{TsM, int(PP / TsM), PP, M, P};
+      MemLoad<c128> src{buf1, MM * PP, 1, PP};
+      MemStore<c128> dst{buf2, PP * PP, 1, PP, 1.0 / double(M), 1};
+      e = opsM->strided(true, src, dst, g, MM, twM, s);
+    }
+    // (c) inverse along z: buf2[kz][ny][nx] -> buf3[ent][nz][ny][nx]
+    if (e == hipSuccess) {
+      const long cols = PP * PP;
+      Geo g{TsM, int(cols / TsM), cols, M, P};
+      MemLoad<c128> src{buf2, 0, 1, PP * PP};
+      MemStore<c128> dst{buf3 + long(ent) * PP * PP * PP, 0, 1, PP * PP, 1.0 / double(M), 1};
+      e = opsM->strided(true, src, dst, g, 1, twM, s);
+    }
+  }
+  // (d) forward transforms of length P along x, y, z (in place, all entries)
+  if (e == hipSuccess) {
+    const long rows = long(NE) * PP * PP;
+    Geo g{TcP, int((rows + TcP - 1) / TcP), rows, P, P};
+    MemLoad<c128> src{buf3, 0, PP, 1};
+    MemStore<c128> dst{buf3, 0, PP, 1, 1.0, 0};
+    e = opsP->contig_fwd(src, dst, g, 1, pl->tw64, s);
+  }
+  if (e == hipSuccess) {
+    Geo g{TsP, int(PP / TsP), PP, P, P};
+    MemLoad<c128> src{buf3, PP * PP, 1, PP};
+    MemStore<c128> dst{buf3, PP * PP, 1, PP, 1.0, 0};
+    e = opsP->strided(false, src, dst, g, long(NE) * PP, pl->tw64, s);
+  }
+  if (e == hipSuccess) {
+    const long cols = PP * PP;
+    Geo g{TsP, int(cols / TsP), cols, P, P};
+    MemLoad<c128> src{buf3, PP * PP * PP, 1, PP * PP};
+    MemStore<c128> dst{buf3, PP * PP * PP, 1, PP * PP, 1.0, 0};
+    e = opsP->strided(false, src, dst, g, NE, pl->tw64, s);
+  }
+  // (e) shift by n in every axis ((-1)^q), scale by P^-3, fold to the octant
+  if (e == hipSuccess) e = launch_finalize_tables(buf3, pl->tab64, pl->tab32, N, P, pl->nxp, NE, pl->omega, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup();
+  return e == hipSuccess ? VIE_OK : hip_fail(pl, e, "table precompute");
+}
+
+}  // namespace
+
+namespace vie {
+
+int apply_any(vie_plan* pl, bool fp64, const c128* in, const c128* addv, const c128* bvec, c128* out, int nrhs,
+              int mode, hipStream_t s) {
+  return fp64 ? apply_typed<double>(pl, in, addv, bvec, out, nrhs, mode, s)
+              : apply_typed<float>(pl, in, addv, bvec, out, nrhs, mode, s);
+}
+
+}  // namespace vie
+
+namespace {
+
+const int kSupportedN[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 160};
+
+bool n_supported(int n) {
+  for (int v : kSupportedN)
+    if (v == n) return true;
+  return false;
+}
+
+void destroy_plan(vie_plan* pl) {
+  if (!pl) return;
+  for (auto& r : pl->prof) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : pl->ev_pool) (void)hipEventDestroy(e);
+  for (auto& a : pl->allocs) (void)hipFree(a.first);
+  pl->allocs.clear();
+  if (pl->red_host) (void)hipHostFree(pl->red_host);
+  if (pl->coef_host) (void)hipHostFree(pl->coef_host);
+  if (pl->scale_host) (void)hipHostFree(pl->scale_host);
+  delete pl;
+}
+
+int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
+  if (p->kind < VIE_LAPLACE || p->kind > VIE_MAXWELL) return fail(pl, VIE_E_ARG, "unknown kind");
+  if (!p->coef) return fail(pl, VIE_E_ARG, "coef is NULL");
+  if (p->n <= 0 || !(p->h > 0.0) || !std::isfinite(p->h)) return fail(pl, VIE_E_ARG, "n and h must be positive");
+  if (p->kind != VIE_LAPLACE && !(p->omega > 0.0 && std::isfinite(p->omega)))
+    return fail(pl, VIE_E_ARG, "omega must be positive for Helmholtz and Maxwell");
+  if (p->mu && p->kind != VIE_MAXWELL) return fail(pl, VIE_E_ARG, "mu is only used by Maxwell");
+  if (p->precision != VIE_PREC_FP64 && p->precision != VIE_PREC_MIXED) return fail(pl, VIE_E_ARG, "bad precision");
+  if (p->max_rhs < 1 || p->max_rhs > 4096) return fail(pl, VIE_E_ARG, "max_rhs out of range");
+  if (!n_supported(p->n))
+    return fail(pl, VIE_E_SIZE, "n = " + std::to_string(p->n) + " has no compiled FFT lengths (2n, 4n)");
+  pl->kind = p->kind;
+  pl->n = p->n;
+  pl->h = p->h;
+  pl->omega = p->kind == VIE_LAPLACE ? 0.0 : p->omega;
+  pl->full = p->mu != nullptr;
+  pl->C = pl->full ? 6 : 3;
+  pl->P = 2 * p->n;
+  pl->M = 4 * p->n;
+  pl->R = std::sqrt(3.0) * p->n * p->h;
+  pl->sym_set = p->kind == VIE_MAXWELL ? SYM_MAXWELL : SYM_GRAD;
+  pl->ne = pl->full ? 9 : 6;
+  pl->nxp = ((p->n + 1 + 15) / 16) * 16;
+  pl->precision = p->precision;
+  pl->max_rhs = p->max_rhs;
+  pl->flags = p->flags;
+  pl->n3 = long(p->n) * p->n * p->n;
+  HIPCHK(pl, hipGetDevice(&pl->device));
+  {
+    hipDeviceProp_t prop;
+    HIPCHK(pl, hipGetDeviceProperties(&prop, pl->device));
+    pl->max_lds = std::min<size_t>(prop.sharedMemPerBlock, 65536);
+  }
+  const size_t tf = sizeof(c128) * 9 * size_t(pl->n3);
+  // coefficient upload (device copy) -> contrast
+  c128* coef_d = nullptr;
+  int rc = dev_alloc(pl, reinterpret_cast<void**>(&coef_d), tf);
+  if (rc) return rc;
+  const hipMemcpyKind kind = (p->flags & VIE_PTR_HOST) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  HIPCHK(pl, hipMemcpyAsync(coef_d, p->coef, tf, kind, s));
+  rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->H64), tf);
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->H32), tf / 2);
+  if (rc) return rc;
+  const int nblk = int(std::min<long>(4096, (pl->n3 + 255) / 256));
+  double* bmax = nullptr;
+  int* bbad = nullptr;
+  rc = dev_alloc(pl, reinterpret_cast<void**>(&bmax), sizeof(double) * size_t(nblk));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&bbad), sizeof(int) * size_t(nblk));
+  if (rc) return rc;
+  std::vector<double> hmax(static_cast<size_t>(nblk));
+  std::vector<int> hbad(static_cast<size_t>(nblk));
+  double worst = 0.0;
+  long bad = 0;
+  for (int pass = 0; pass < (pl->full ? 2 : 1); ++pass) {
+    c128* H64 = pl->H64;
+    c64* H32 = pl->H32;
+    if (pass == 1) {
+      HIPCHK(pl, hipMemcpyAsync(coef_d, p->mu, tf, kind, s));
+      rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->Hmu64), tf);
+      if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->Hmu32), tf / 2);
+      if (rc) return rc;
+      H64 = pl->Hmu64;
+      H32 = pl->Hmu32;
+    }
+    HIPCHK(pl, launch_contrast(coef_d, H64, H32, pl->n3, bmax, bbad, nblk, s));
+    HIPCHK(pl, hipMemcpyAsync(hmax.data(), bmax, sizeof(double) * size_t(nblk), hipMemcpyDeviceToHost, s));
+    HIPCHK(pl, hipMemcpyAsync(hbad.data(), bbad, sizeof(int) * size_t(nblk), hipMemcpyDeviceToHost, s));
+    HIPCHK(pl, hipStreamSynchronize(s));
+    for (int i = 0; i < nblk; ++i) {
+      worst = std::max(worst, hmax[size_t(i)]);
+      bad += hbad[size_t(i)];
+    }
+  }
+  dev_free(pl, coef_d);
+  dev_free(pl, bmax);
+  dev_free(pl, bbad);
+  pl->hmax = worst;
+  if (bad > 0)
+    return fail(pl, VIE_E_MEDIUM, std::to_string(bad) + " grid points where a + I is singular or not finite");
+  if ((p->flags & VIE_STRICT_MEDIUM) && !(worst < 1.0))
+    return fail(pl, VIE_E_MEDIUM, "max ||H(x)||_2 = " + std::to_string(worst) + " >= 1 (contrast not a contraction)");
+  // twiddles and kernel tables
+  rc = upload_twiddles<double>(pl, pl->P, &pl->tw64, s);
+  if (!rc) rc = upload_twiddles<float>(pl, pl->P, &pl->tw32, s);
+  if (rc) return rc;
+  pl->tab_elems = long(pl->n + 1) * (pl->n + 1) * pl->ne * pl->nxp;
+  rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->tab64), sizeof(c128) * size_t(pl->tab_elems));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->tab32), sizeof(c64) * size_t(pl->tab_elems));
+  if (rc) return rc;
+  rc = build_tables(pl, s);
+  if (rc) return rc;
+  return VIE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vie_plan_create(const vie_problem* p, void* hip_stream, vie_plan** out) {
+  if (!out) return VIE_E_ARG;
+  *out = nullptr;
+  if (!p) return VIE_E_ARG;
+  vie_plan* pl = new (std::nothrow) vie_plan();
+  if (!pl) return VIE_E_NOMEM;
+  const int rc = create_impl(p, static_cast<hipStream_t>(hip_stream), pl);
+  if (rc != VIE_OK) {
+    vie::last_create_error() = pl->err;
+    destroy_plan(pl);
+    return rc;
+  }
+  *out = pl;
+  return VIE_OK;
+}
+
+int vie_destroy(vie_plan* pl) {
+  if (!pl) return VIE_OK;
+  (void)hipDeviceSynchronize();
+  destroy_plan(pl);
+  return VIE_OK;
+}
+
+int vie_apply(vie_plan* pl, const double* x, double* y, int nrhs, unsigned flags, void* hip_stream) {
+  if (!pl) return VIE_E_ARG;
+  if (!x || !y || nrhs < 1) return fail(pl, VIE_E_ARG, "vie_apply: null pointer or nrhs < 1");
+  if ((flags & VIE_APPLY_FP64) && (flags & VIE_APPLY_FP32)) return fail(pl, VIE_E_ARG, "FP64 and FP32 both set");
+  if (x == y) return fail(pl, VIE_E_ARG, "vie_apply: x and y must not overlap");
+  bool fp64 = pl->precision == VIE_PREC_FP64;
+  if (flags & VIE_APPLY_FP64) fp64 = true;
+  if (flags & VIE_APPLY_FP32) fp64 = false;
+  const int mode = (flags & VIE_APPLY_CONV) ? MODE_CONV : MODE_MATVEC;
+  const c128* in = reinterpret_cast<const c128*>(x);
+  return apply_any(pl, fp64, in, in, nullptr, reinterpret_cast<c128*>(y), nrhs, mode,
+                   static_cast<hipStream_t>(hip_stream));
+}
+
+int vie_rhs(vie_plan* pl, const double* inc, double* b, int nrhs, void* hip_stream) {
+  if (!pl) return VIE_E_ARG;
+  if (!inc || !b || nrhs < 1) return fail(pl, VIE_E_ARG, "vie_rhs: null pointer or nrhs < 1");
+  hipError_t e = launch_rhs(pl->H64, pl->Hmu64, reinterpret_cast<const c128*>(inc), reinterpret_cast<c128*>(b),
+                            nrhs, pl->C, pl->n3, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? VIE_OK : hip_fail(pl, e, "vie_rhs");
+}
+
+int vie_field(vie_plan* pl, const double* density, const double* inc, double* field, int nrhs, void* hip_stream) {
+  if (!pl) return VIE_E_ARG;
+  if (!density || !inc || !field || nrhs < 1) return fail(pl, VIE_E_ARG, "vie_field: null pointer or nrhs < 1");
+  return apply_any(pl, true, reinterpret_cast<const c128*>(density), reinterpret_cast<const c128*>(inc), nullptr,
+                   reinterpret_cast<c128*>(field), nrhs, MODE_FIELD, static_cast<hipStream_t>(hip_stream));
+}
+
+int vie_plan_info(const vie_plan* pl, double* out, int nout) {
+  if (!pl || !out) return VIE_E_ARG;
+  const double v[7] = {double(pl->n),  double(pl->C),  double(pl->P),        double(pl->M),
+                       pl->hmax,       double(pl->ne), double(pl->dev_bytes)};
+  for (int i = 0; i < nout && i < 7; ++i) out[i] = v[i];
+  return VIE_OK;
+}
+
+int vie_copy_tables(const vie_plan* pl, double* host, long host_bytes, long* needed, int* nxp, int* ne) {
+  if (!pl) return VIE_E_ARG;
+  const long bytes = long(sizeof(c128)) * pl->tab_elems;
+  if (needed) *needed = bytes;
+  if (nxp) *nxp = pl->nxp;
+  if (ne) *ne = pl->ne;
+  if (!host) return VIE_OK;
+  if (host_bytes < bytes) return VIE_E_ARG;
+  hipError_t e = hipMemcpy(host, pl->tab64, size_t(bytes), hipMemcpyDeviceToHost);
+  return e == hipSuccess ? VIE_OK : VIE_E_DEVICE;
+}
+
+int vie_copy_contrast(const vie_plan* pl, double* host, long host_bytes) {
+  if (!pl || !host) return VIE_E_ARG;
+  const long one = long(sizeof(c128)) * 9 * pl->n3;
+  const long bytes = pl->full ? 2 * one : one;
+  if (host_bytes < bytes) return VIE_E_ARG;
+  hipError_t e = hipMemcpy(host, pl->H64, size_t(one), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && pl->full) e = hipMemcpy(reinterpret_cast<char*>(host) + one, pl->Hmu64, size_t(one),
+                                                 hipMemcpyDeviceToHost);
+  return e == hipSuccess ? VIE_OK : VIE_E_DEVICE;
+}
+
+const char* vie_status_string(int status) {
+  switch (status) {
+    case VIE_OK: return "VIE_OK";
+    case VIE_E_ARG: return "VIE_E_ARG: invalid argument";
+    case VIE_E_SIZE: return "VIE_E_SIZE: unsupported grid size";
+    case VIE_E_MEDIUM: return "VIE_E_MEDIUM: invalid medium";
+    case VIE_E_NOMEM: return "VIE_E_NOMEM: device memory exhausted";
+    case VIE_E_DEVICE: return "VIE_E_DEVICE: HIP error";
+    case VIE_E_STATE: return "VIE_E_STATE: call not valid for this plan";
+    case VIE_W_NOCONV: return "VIE_W_NOCONV: not converged";
+    default: return "unknown status";
+  }
+}
+
+const char* vie_last_error(const vie_plan* pl) { return pl ? pl->err.c_str() : vie::last_create_error().c_str(); }
+
+int vie_supported_n(int n) { return n_supported(n) ? 1 : 0; }
+
+int vie_profile(vie_plan* pl, int enable) {
+  if (!pl) return VIE_E_ARG;
+  if (pl->prof_on) vie::prof_collect(pl);
+  pl->prof_on = enable != 0;
+  for (int i = 0; i < 16; ++i) {
+    pl->prof_ms[i] = 0;
+    pl->prof_cnt[i] = 0;
+    pl->prof_bytes[i] = 0;
+  }
+  return VIE_OK;
+}
+
+int vie_profile_read(vie_plan* pl, double* ms, long* counts, double* bytes, int nfam) {
+  if (!pl || !ms || !counts || !bytes) return VIE_E_ARG;
+  vie::prof_collect(pl);
+  for (int i = 0; i < nfam && i < vie::FAM_COUNT; ++i) {
+    ms[i] = pl->prof_ms[i];
+    counts[i] = pl->prof_cnt[i];
+    bytes[i] = pl->prof_bytes[i];
+  }
+  return vie::FAM_COUNT;
+}
+
+const char* vie_profile_family(int fam) {
+  static const char* names[] = {"fft_x_fwd_fp32", "fft_y_fwd_fp32", "fft_z_mul_fp32", "fft_y_inv_fp32",
+                                "fft_x_inv_combine_fp32", "fft_x_fwd_fp64", "fft_y_fwd_fp64", "fft_z_mul_fp64",
+                                "fft_y_inv_fp64", "fft_x_inv_combine_fp64", "krylov_dots", "krylov_reduce",
+                                "krylov_combine"};
+  return (fam >= 0 && fam < vie::FAM_COUNT) ? names[fam] : "";
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Plan object shared by the runtime translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "cx.hpp"
+#include "vie.h"
+
+namespace vie {
+
+// tile choices of the five apply passes
+struct Tune {
+  int tx_fwd = 0, ty_fwd = 0, tz = 0, ty_inv = 0, tx_inv = 0;
+  bool tuned = false;
+};
+
+struct DeviceArena {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+};
+
+}  // namespace vie
+
+struct vie_plan {
+  int kind = 0, n = 0, C = 3, P = 0, M = 0, ne = 6, nxp = 0, sym_set = 0, precision = 0, max_rhs = 1;
+  unsigned flags = 0;
+  double h = 0, omega = 0, R = 0, hmax = 0;
+  long n3 = 0;
+  bool full = false;  // mu present (6 unknowns per point)
+  int device = 0;
+  size_t max_lds = 65536;
+
+  vie::c128 *H64 = nullptr, *Hmu64 = nullptr;
+  vie::c64 *H32 = nullptr, *Hmu32 = nullptr;
+  vie::c128* tab64 = nullptr;
+  vie::c64* tab32 = nullptr;
+  long tab_elems = 0;
+  vie::c128* tw64 = nullptr;
+  vie::c64* tw32 = nullptr;
+
+  // apply workspaces [0] FP32, [1] FP64; capacity in right-hand sides
+  void* wsA[2] = {nullptr, nullptr};
+  void* wsB[2] = {nullptr, nullptr};
+  int ws_cap[2] = {0, 0};
+  std::map<int, vie::Tune> tune[2];  // keyed by batch size bucket
+
+  // Krylov workspace (FP64)
+  vie::c128* V = nullptr;  // [(m+1)][cap][L]
+  int kr_cap = 0, kr_m = 0;
+  vie::c128 *xw = nullptr, *bw = nullptr, *rw = nullptr, *ww = nullptr;
+  vie::c128* partials = nullptr;  // [cap][nblk][m+2]
+  vie::c128* red = nullptr;       // [cap][m+2]
+  vie::c128* coefd = nullptr;     // [cap][m+1]
+  double* scaled = nullptr;       // [cap]
+  vie::c128* red_host = nullptr;  // pinned
+  vie::c128* coef_host = nullptr; // pinned
+  double* scale_host = nullptr;   // pinned
+
+  size_t dev_bytes = 0;
+  std::vector<std::pair<void*, size_t>> allocs;
+  std::string err;
+
+  // kernel timing with HIP events (vie_profile)
+  struct ProfRec {
+    int fam;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool prof_on = false;
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[16] = {0};
+  long prof_cnt[16] = {0};
+  double prof_bytes[16] = {0};
+};
+
+namespace vie {
+
+#define HIPCHK(pl, expr)                                       \
+  do {                                                         \
+    hipError_t e_ = (expr);                                    \
+    if (e_ != hipSuccess) return vie::hip_fail(pl, e_, #expr); \
+  } while (0)
+
+std::string& last_create_error();
+
+// allocation helpers (record bytes on the plan)
+int dev_alloc(vie_plan* pl, void** p, size_t bytes);
+void dev_free(vie_plan* pl, void* p);
+int fail(vie_plan* pl, int code, const std::string& msg);
+int hip_fail(vie_plan* pl, hipError_t e, const char* what);
+
+// apply: out = f(in) for nrhs vectors; mode MODE_*; addv: J for the
+// combine (MODE_MATVEC/RESIDUAL: the input itself, MODE_FIELD: the incident
+// field); bvec: b of MODE_RESIDUAL.
+int apply_any(vie_plan* pl, bool fp64, const c128* in, const c128* addv, const c128* bvec, c128* out, int nrhs,
+              int mode, hipStream_t s);
+
+// kernel families timed by vie_profile
+enum {
+  FAM_XFWD32 = 0, FAM_YFWD32, FAM_Z32, FAM_YINV32, FAM_XINV32,
+  FAM_XFWD64, FAM_YFWD64, FAM_Z64, FAM_YINV64, FAM_XINV64,
+  FAM_DOTS, FAM_REDUCE, FAM_COMBINE, FAM_COUNT
+};
+// record an event pair around the launches between prof_begin and prof_end
+int prof_begin(vie_plan* pl, hipStream_t s);
+// bytes: algorithmic HBM bytes of the launch (each operand read or written once)
+void prof_end(vie_plan* pl, int fam, int token, hipStream_t s, double bytes);
+
+int solve_batch(vie_plan* pl, const c128* inc, c128* density, c128* field, int nrhs, const vie_solve_opts& o,
+                vie_solve_stats* stats, hipStream_t s);
+
+}  // namespace vie

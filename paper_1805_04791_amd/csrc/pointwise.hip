@@ -1,0 +1,352 @@
+// Pointwise kernels: contrast, right-hand side, table finalisation and the
+// FP64 Krylov vector operations (multi-dot, fixed-order reductions, basis
+// combinations).  Every reduction is two-phase with a block count that depends
+// only on the vector length, so results are bitwise independent of how many
+// right-hand sides share a launch.
+#include "pointwise.hpp"
+
+#include <cmath>
+
+namespace vie {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// spectral norm of a 3x3 complex matrix: sqrt(largest eigenvalue of H^H H)
+__device__ double spec_norm3(const c128 h[9]) {
+  // M = H^H H
+  c128 m[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      c128 acc = {0.0, 0.0};
+      for (int k = 0; k < 3; ++k) acc = acc + cmulc(h[3 * k + a], h[3 * k + b]);
+      m[a][b] = acc;
+    }
+  const double m00 = m[0][0].re, m11 = m[1][1].re, m22 = m[2][2].re;
+  const double q = (m00 + m11 + m22) / 3.0;
+  const double p1 = norm2(m[0][1]) + norm2(m[0][2]) + norm2(m[1][2]);
+  const double p2 = (m00 - q) * (m00 - q) + (m11 - q) * (m11 - q) + (m22 - q) * (m22 - q) + 2.0 * p1;
+  if (!(p2 > 1e-300)) return sqrt(fmax(q, 0.0));
+  const double p = sqrt(p2 / 6.0);
+  const double b00 = (m00 - q) / p, b11 = (m11 - q) / p, b22 = (m22 - q) / p;
+  const c128 b01 = (1.0 / p) * m[0][1], b02 = (1.0 / p) * m[0][2], b12 = (1.0 / p) * m[1][2];
+  const c128 t = b01 * b12;
+  const double re_t = t.re * b02.re + t.im * b02.im;  // Re(b01 b12 conj(b02))
+  const double det = b00 * b11 * b22 + 2.0 * re_t - b00 * norm2(b12) - b11 * norm2(b02) - b22 * norm2(b01);
+  const double r = fmin(1.0, fmax(-1.0, 0.5 * det));
+  const double phi = acos(r) / 3.0;
+  return sqrt(fmax(q + 2.0 * p * cos(phi), 0.0));
+}
+
+__global__ void __launch_bounds__(kBlock) k_contrast(const c128* __restrict__ coef, c128* __restrict__ H64,
+                                                     c64* __restrict__ H32, long n3, double* __restrict__ blk_max,
+                                                     int* __restrict__ blk_bad) {
+  __shared__ double smax[kBlock / 64];
+  __shared__ double sbad[kBlock / 64];
+  double vmax = 0.0;
+  double bad = 0.0;
+  for (long p = long(blockIdx.x) * blockDim.x + threadIdx.x; p < n3; p += long(gridDim.x) * blockDim.x) {
+    c128 b[9];
+    for (int e = 0; e < 9; ++e) b[e] = coef[e * n3 + p];
+    b[0].re += 1.0;
+    b[4].re += 1.0;
+    b[8].re += 1.0;
+    // adjugate of B = a + I
+    c128 adj[9];
+    adj[0] = b[4] * b[8] - b[5] * b[7];
+    adj[1] = b[2] * b[7] - b[1] * b[8];
+    adj[2] = b[1] * b[5] - b[2] * b[4];
+    adj[3] = b[5] * b[6] - b[3] * b[8];
+    adj[4] = b[0] * b[8] - b[2] * b[6];
+    adj[5] = b[2] * b[3] - b[0] * b[5];
+    adj[6] = b[3] * b[7] - b[4] * b[6];
+    adj[7] = b[1] * b[6] - b[0] * b[7];
+    adj[8] = b[0] * b[4] - b[1] * b[3];
+    const c128 det = b[0] * adj[0] + b[1] * adj[3] + b[2] * adj[6];
+    const double dn = norm2(det);
+    double scale_b = 0.0;
+    for (int e = 0; e < 9; ++e) scale_b = fmax(scale_b, norm2(b[e]));
+    const bool singular = !(dn > 1e-28 * scale_b * scale_b * scale_b) || !isfinite(dn);
+    c128 h[9];
+    if (singular) {
+      bad += 1.0;
+      for (int e = 0; e < 9; ++e) h[e] = {0.0, 0.0};
+    } else {
+      const c128 inv_det = {det.re / dn, -det.im / dn};
+      for (int e = 0; e < 9; ++e) {
+        const c128 v = adj[e] * inv_det;
+        h[e] = {-2.0 * v.re, -2.0 * v.im};
+      }
+      h[0].re += 1.0;
+      h[4].re += 1.0;
+      h[8].re += 1.0;
+      const double nrm = spec_norm3(h);
+      if (!isfinite(nrm)) bad += 1.0;
+      vmax = fmax(vmax, nrm);
+    }
+    for (int e = 0; e < 9; ++e) {
+      H64[e * n3 + p] = h[e];
+      H32[e * n3 + p] = cvt<float>(h[e]);
+    }
+  }
+  vmax = wave_max(vmax);
+  bad = wave_sum(bad);
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+    smax[w] = vmax;
+    sbad[w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0, c = 0.0;
+    for (int i = 0; i < kBlock / 64; ++i) {
+      m = fmax(m, smax[i]);
+      c += sbad[i];
+    }
+    blk_max[blockIdx.x] = m;
+    blk_bad[blockIdx.x] = int(c);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_rhs(const c128* __restrict__ H, const c128* __restrict__ Hmu,
+                                                const c128* __restrict__ inc, c128* __restrict__ b, int nrhs,
+                                                int C, long n3) {
+  const long total = long(nrhs) * (C / 3) * n3;
+  for (long t = long(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long p = t % n3;
+    const long rh = t / n3;  // rhs * (C/3) + half
+    const int half = int(rh % (C / 3));
+    const c128* Hh = half == 0 ? H : Hmu;
+    const long vb = rh * 3 * n3 + p;
+    c128 g[3];
+    for (int c = 0; c < 3; ++c) g[c] = inc[vb + c * n3];
+    for (int r = 0; r < 3; ++r) {
+      c128 acc = {0.0, 0.0};
+      for (int c = 0; c < 3; ++c) acc = acc + Hh[(3 * r + c) * n3 + p] * g[c];
+      b[vb + r * n3] = 2.0 * acc;
+    }
+  }
+}
+
+constexpr int kGroup = 8;  // basis vectors per accumulation sweep
+
+__global__ void __launch_bounds__(kBlock) k_dots(const c128* __restrict__ V, long vstride, long rstride,
+                                                 const c128* __restrict__ w, long L, int nv, long chunk,
+                                                 c128* __restrict__ partials) {
+  __shared__ double red[kBlock / 64][2 * kGroup];
+  const int rhs = blockIdx.y;
+  const int blk = blockIdx.x;
+  const int nblk = gridDim.x;
+  const long lo = long(blk) * chunk;
+  const long hi = lo + chunk < L ? lo + chunk : L;
+  const c128* wr = w + rhs * rstride;
+  const c128* Vr = V + rhs * rstride;
+  const int nv1 = nv + 1;
+  c128* out = partials + (long(rhs) * nblk + blk) * nv1;
+  for (int g0 = 0; g0 < nv1; g0 += kGroup) {
+    double ar[kGroup], ai[kGroup];
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) ar[q] = ai[q] = 0.0;
+    for (long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+      const c128 we = wr[e];
+#pragma unroll
+      for (int q = 0; q < kGroup; ++q) {
+        const int i = g0 + q;
+        if (i < nv) {
+          const c128 v = Vr[long(i) * vstride + e];
+          ar[q] += v.re * we.re + v.im * we.im;
+          ai[q] += v.re * we.im - v.im * we.re;
+        } else if (i == nv) {
+          ar[q] += we.re * we.re + we.im * we.im;
+        }
+      }
+    }
+    const int wv = threadIdx.x / 64;
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) {
+      const double sr = wave_sum(ar[q]);
+      const double si = wave_sum(ai[q]);
+      if ((threadIdx.x & 63) == 0) {
+        red[wv][2 * q] = sr;
+        red[wv][2 * q + 1] = si;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < kGroup && g0 + int(threadIdx.x) < nv1) {
+      double sr = 0.0, si = 0.0;
+      for (int k = 0; k < kBlock / 64; ++k) {
+        sr += red[k][2 * threadIdx.x];
+        si += red[k][2 * threadIdx.x + 1];
+      }
+      out[g0 + threadIdx.x] = {sr, si};
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_reduce(const c128* __restrict__ partials, int nblk, int nv1,
+                                                   c128* __restrict__ out) {
+  __shared__ double red[kBlock / 64][2];
+  const int rhs = blockIdx.x;
+  for (int i = 0; i < nv1; ++i) {
+    double sr = 0.0, si = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+      const c128 v = partials[(long(rhs) * nblk + b) * nv1 + i];
+      sr += v.re;
+      si += v.im;
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if ((threadIdx.x & 63) == 0) {
+      red[threadIdx.x / 64][0] = sr;
+      red[threadIdx.x / 64][1] = si;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0.0, c = 0.0;
+      for (int k = 0; k < kBlock / 64; ++k) {
+        a += red[k][0];
+        c += red[k][1];
+      }
+      out[long(rhs) * nv1 + i] = {a, c};
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_combine(const c128* __restrict__ V, long vstride, long rstride,
+                                                    const c128* w, c128* out, long L, int nv,
+                                                    const c128* __restrict__ coef, const double* __restrict__ scale) {
+  const int rhs = blockIdx.y;
+  const c128* wr = w + rhs * rstride;
+  c128* outr = out + rhs * rstride;
+  const c128* Vr = V + rhs * rstride;
+  const c128* cr = coef + long(rhs) * (nv > 0 ? nv : 1);
+  const double sc = scale[rhs];
+  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < L; e += long(gridDim.x) * blockDim.x) {
+    c128 acc = wr[e];
+    for (int i = 0; i < nv; ++i) acc = acc - Vr[long(i) * vstride + e] * cr[i];
+    outr[e] = sc * acc;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill(c128* p, long n, c128 v) {
+  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += long(gridDim.x) * blockDim.x) p[e] = v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy(const c128* __restrict__ s, c128* __restrict__ d, long n) {
+  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += long(gridDim.x) * blockDim.x) d[e] = s[e];
+}
+
+__global__ void __launch_bounds__(kBlock) k_demote(const c128* __restrict__ s, c64* __restrict__ d, long n) {
+  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += long(gridDim.x) * blockDim.x)
+    d[e] = cvt<float>(s[e]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_finalize(const c128* __restrict__ buf, c128* __restrict__ tab64,
+                                                     c64* __restrict__ tab32, int n, int P, int nxp, int ne,
+                                                     double omega) {
+  const long n1 = n + 1;
+  const long total = n1 * n1 * ne * nxp;
+  const double sc = 1.0 / (double(P) * double(P) * double(P));
+  const long P3 = long(P) * P * P;
+  for (long t = long(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const int qx = int(t % nxp);
+    long r = t / nxp;
+    const int e = int(r % ne);
+    r /= ne;
+    const int qy = int(r % n1);
+    const int qz = int(r / n1);
+    c128 v = {0.0, 0.0};
+    if (qx <= n) {
+      v = buf[e * P3 + (long(qz) * P + qy) * P + qx];
+      double f = ((qx + qy + qz) & 1) ? -sc : sc;
+      v = f * v;
+      if (e >= 6) v = omega * times_i(v);
+    }
+    tab64[t] = v;
+    tab32[t] = cvt<float>(v);
+  }
+}
+
+int grid_for(long n) {
+  long b = (n + kBlock - 1) / kBlock;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return int(b);
+}
+
+}  // namespace
+
+int krylov_blocks(long L) {
+  long b = (L + 8 * kBlock - 1) / (8 * kBlock);
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return int(b);
+}
+
+hipError_t launch_contrast(const c128* coef, c128* H64, c64* H32, long n3, double* blk_max, int* blk_bad,
+                           int nblocks, hipStream_t s) {
+  k_contrast<<<nblocks, kBlock, 0, s>>>(coef, H64, H32, n3, blk_max, blk_bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs(const c128* H, const c128* Hmu, const c128* inc, c128* b, int nrhs, int C, long n3,
+                      hipStream_t s) {
+  k_rhs<<<grid_for(long(nrhs) * (C / 3) * n3), kBlock, 0, s>>>(H, Hmu, inc, b, nrhs, C, n3);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots(const c128* V, long vstride, long rstride, const c128* w, long L, int nv, int nrhs,
+                       int nblk, c128* partials, hipStream_t s) {
+  const long chunk = (L + nblk - 1) / nblk;
+  k_dots<<<dim3(nblk, nrhs), kBlock, 0, s>>>(V, vstride, rstride, w, L, nv, chunk, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const c128* partials, int nrhs, int nblk, int nv1, c128* out, hipStream_t s) {
+  k_reduce<<<nrhs, kBlock, 0, s>>>(partials, nblk, nv1, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const c128* V, long vstride, long rstride, const c128* w, c128* out, long L, int nv,
+                          const c128* coef, const double* scale, int nrhs, hipStream_t s) {
+  long bx = (L + kBlock - 1) / kBlock;
+  if (bx > 2048) bx = 2048;
+  k_combine<<<dim3(unsigned(bx), nrhs), kBlock, 0, s>>>(V, vstride, rstride, w, out, L, nv, coef, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(c128* p, long n, c128 v, hipStream_t s) {
+  k_fill<<<grid_for(n), kBlock, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const c128* src, c128* dst, long n, hipStream_t s) {
+  k_copy<<<grid_for(n), kBlock, 0, s>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_demote(const c128* src, c64* dst, long n, hipStream_t s) {
+  k_demote<<<grid_for(n), kBlock, 0, s>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_tables(const c128* buf, c128* tab64, c64* tab32, int n, int P, int nxp, int ne,
+                                  double omega, hipStream_t s) {
+  const long total = long(n + 1) * (n + 1) * ne * nxp;
+  k_finalize<<<grid_for(total), kBlock, 0, s>>>(buf, tab64, tab32, n, P, nxp, ne, omega);
+  return hipGetLastError();
+}
+
+}  // namespace vie

@@ -1,0 +1,42 @@
+// Launchers of the pointwise and Krylov kernels (pointwise.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cx.hpp"
+
+namespace vie {
+
+// H = (a + I)^{-1} (a - I) = I - 2 (a + I)^{-1} at every point (eq. rhodef).
+// Writes H in FP64 and FP32, and per-block (max ||H||_2, count of singular or
+// non-finite points) into blk_max / blk_bad (nblocks entries each).
+hipError_t launch_contrast(const c128* coef, c128* H64, c64* H32, long n3, double* blk_max, int* blk_bad,
+                           int nblocks, hipStream_t s);
+
+// b = 2 H g per 3-component half (H for the first half, Hmu for the second).
+hipError_t launch_rhs(const c128* H, const c128* Hmu, const c128* inc, c128* b, int nrhs, int C, long n3,
+                      hipStream_t s);
+
+// Partial sums, per right-hand side r and block: conj(V_i) . w_r for i < nv and
+// ||w_r||^2 (slot nv).  V_i of rhs r at V + i * vstride + r * rstride.
+hipError_t launch_dots(const c128* V, long vstride, long rstride, const c128* w, long L, int nv, int nrhs,
+                       int nblk, c128* partials, hipStream_t s);
+// out[r][i] = sum over blocks of partials[r][blk][i], fixed order.
+hipError_t launch_reduce(const c128* partials, int nrhs, int nblk, int nv1, c128* out, hipStream_t s);
+// out_r = (w_r - sum_i V_i c[r][i]) * s[r]   (out may alias w)
+hipError_t launch_combine(const c128* V, long vstride, long rstride, const c128* w, c128* out, long L, int nv,
+                          const c128* coef, const double* scale, int nrhs, hipStream_t s);
+hipError_t launch_fill(c128* p, long n, c128 v, hipStream_t s);
+hipError_t launch_copy(const c128* src, c128* dst, long n, hipStream_t s);
+// FP32 tables from FP64
+hipError_t launch_demote(const c128* src, c64* dst, long n, hipStream_t s);
+
+// Octant tables from the P^3 transforms of the windowed kernel:
+// tab[((qz (n+1) + qy) ne + e) nxp + qx] = (-1)^(qx+qy+qz) * scale_e * buf[e][qz][qy][qx]
+// for q in [0, n]^3; scale_e = 1/P^3, times i*omega for the curl entries e >= 6.
+hipError_t launch_finalize_tables(const c128* buf, c128* tab64, c64* tab32, int n, int P, int nxp, int ne,
+                                  double omega, hipStream_t s);
+
+int krylov_blocks(long L);
+
+}  // namespace vie

@@ -1,0 +1,556 @@
+// Batched Krylov solvers for A x = b on the plan's operator.
+//
+// GMRES(m) (named with Bi-CGStab as a suitable unpreconditioned iteration in
+// the Introduction and Discussion) with classical Gram-Schmidt and selective
+// re-orthogonalisation (a second pass only when the first removes more than
+// half of ||w||^2), Givens rotations and the small least-squares solve on the
+// host in FP64.  Bi-CGStab is the solver of Section 5.
+//
+// Mixed precision: the outer loop recomputes the true residual
+// r = b - A x with the FP64 apply and solves A d = r with the FP32 apply
+// (Krylov vectors, Arnoldi and least squares stay FP64), x += d, until
+// ||r|| / ||b|| <= tol.  Plain FP64 runs the same loop with the FP64 apply.
+//
+// Right-hand sides are advanced together in fused launches, but every
+// decision (re-orthogonalisation, convergence, inner cycle length, budget) is
+// taken per right-hand side and every reduction has a fixed order, so a
+// right-hand side gets bitwise the same answer alone or in a batch.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "apply_kernels.hpp"
+#include "plan.hpp"
+#include "pointwise.hpp"
+
+namespace vie {
+
+namespace {
+
+using cd = std::complex<double>;
+
+inline size_t zu(long v) { return static_cast<size_t>(v); }
+
+struct RhsState {
+  double bnorm = 0, rnorm = 0;
+  bool done = false, conv = false;
+  int iters = 0, mv32 = 0, mv64 = 0, refine = 0;
+};
+
+int ensure_krylov(vie_plan* pl, int cap, int m) {
+  if (pl->kr_cap >= cap && pl->kr_m >= m) return VIE_OK;
+  cap = std::max(cap, pl->kr_cap);
+  m = std::max(m, pl->kr_m);
+  dev_free(pl, pl->V);
+  dev_free(pl, pl->xw);
+  dev_free(pl, pl->bw);
+  dev_free(pl, pl->rw);
+  dev_free(pl, pl->ww);
+  dev_free(pl, pl->partials);
+  dev_free(pl, pl->red);
+  dev_free(pl, pl->coefd);
+  dev_free(pl, pl->scaled);
+  pl->V = pl->xw = pl->bw = pl->rw = pl->ww = pl->partials = pl->red = pl->coefd = nullptr;
+  pl->scaled = nullptr;
+  if (pl->red_host) (void)hipHostFree(pl->red_host);
+  if (pl->coef_host) (void)hipHostFree(pl->coef_host);
+  if (pl->scale_host) (void)hipHostFree(pl->scale_host);
+  pl->red_host = pl->coef_host = nullptr;
+  pl->scale_host = nullptr;
+  pl->kr_cap = pl->kr_m = 0;
+  const size_t L = zu(pl->C) * zu(pl->n3);
+  const size_t nblk = zu(krylov_blocks(long(L)));
+  const size_t vec = sizeof(c128) * L * zu(cap);
+  int rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->V), vec * zu(m + 1));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->xw), vec);
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->bw), vec);
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->rw), vec);
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->ww), vec);
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->partials), sizeof(c128) * zu(cap) * nblk * zu(m + 2));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->red), sizeof(c128) * zu(cap) * zu(m + 2));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->coefd), sizeof(c128) * zu(cap) * zu(m + 2));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->scaled), sizeof(double) * zu(cap));
+  if (rc) return rc;
+  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->red_host), sizeof(c128) * zu(cap) * zu(m + 2)));
+  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->coef_host), sizeof(c128) * zu(cap) * zu(m + 2)));
+  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->scale_host), sizeof(double) * zu(cap)));
+  pl->kr_cap = cap;
+  pl->kr_m = m;
+  return VIE_OK;
+}
+
+// Context of one batch: nb right-hand sides in slots 0..nb-1 of the work vectors.
+struct Batch {
+  vie_plan* pl;
+  hipStream_t s;
+  int nb;
+  long L;      // vector length C n^3
+  long vs;     // basis vector stride (cap * L)
+  int nblk;
+};
+
+// red[r][0..nv] <- (conj(V_i) . w_r, ||w_r||^2), copied to the host
+int dots_host(const Batch& b, const c128* V, const c128* w, int nv) {
+  vie_plan* pl = b.pl;
+  int tok = prof_begin(pl, b.s);
+  HIPCHK(pl, launch_dots(V, b.vs, b.L, w, b.L, nv, b.nb, b.nblk, pl->partials, b.s));
+  prof_end(pl, FAM_DOTS, tok, b.s, double(nv + 1) * b.nb * double(b.L) * sizeof(c128));
+  tok = prof_begin(pl, b.s);
+  HIPCHK(pl, launch_reduce(pl->partials, b.nb, b.nblk, nv + 1, pl->red, b.s));
+  prof_end(pl, FAM_REDUCE, tok, b.s, double(b.nb) * (b.nblk + 1) * (nv + 1) * sizeof(c128));
+  HIPCHK(pl, hipMemcpyAsync(pl->red_host, pl->red, sizeof(c128) * zu(b.nb) * zu(nv + 1),
+                            hipMemcpyDeviceToHost, b.s));
+  HIPCHK(pl, hipStreamSynchronize(b.s));
+  return VIE_OK;
+}
+
+cd red_at(const Batch& b, int r, int i, int nv1) {
+  const c128 v = b.pl->red_host[zu(r) * zu(nv1) + zu(i)];
+  return {v.re, v.im};
+}
+
+// out_r = (w_r - sum_{i<nv} V_i c[r][i]) * scale[r], coefficients from host arrays
+int combine_host(const Batch& b, const c128* V, const c128* w, c128* out, int nv, const std::vector<cd>& coef,
+                 const std::vector<double>& scale) {
+  vie_plan* pl = b.pl;
+  const int stride = std::max(nv, 1);
+  for (int r = 0; r < b.nb; ++r) {
+    for (int i = 0; i < stride; ++i) {
+      const cd c = i < nv ? coef[zu(r) * zu(nv) + zu(i)] : cd(0.0, 0.0);
+      pl->coef_host[zu(r) * zu(stride) + zu(i)] = {c.real(), c.imag()};
+    }
+    pl->scale_host[r] = scale[zu(r)];
+  }
+  HIPCHK(pl, hipMemcpyAsync(pl->coefd, pl->coef_host, sizeof(c128) * zu(b.nb) * zu(stride),
+                            hipMemcpyHostToDevice, b.s));
+  HIPCHK(pl, hipMemcpyAsync(pl->scaled, pl->scale_host, sizeof(double) * zu(b.nb), hipMemcpyHostToDevice, b.s));
+  const int tok = prof_begin(pl, b.s);
+  HIPCHK(pl, launch_combine(V, b.vs, b.L, w, out, b.L, nv, pl->coefd, pl->scaled, b.nb, b.s));
+  prof_end(pl, FAM_COMBINE, tok, b.s, double(nv + 2) * b.nb * double(b.L) * sizeof(c128));
+  // the pinned staging buffers are reused by the next call: wait for the copies
+  HIPCHK(pl, hipStreamSynchronize(b.s));
+  return VIE_OK;
+}
+
+// ||v_r|| for every slot
+int norms(const Batch& b, const c128* v, std::vector<double>& out) {
+  int rc = dots_host(b, nullptr, v, 0);
+  if (rc) return rc;
+  out.resize(zu(b.nb));
+  for (int r = 0; r < b.nb; ++r) out[zu(r)] = std::sqrt(std::max(0.0, red_at(b, r, 0, 1).real()));
+  return VIE_OK;
+}
+
+// One GMRES(m) cycle on A d = r (r in rw, x += d in xw).  target[r]: absolute
+// residual at which slot r stops; active[r]: slot takes part; budget[r]:
+// matvecs it may still spend.
+int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rnorm, const std::vector<double>& target,
+                std::vector<RhsState>& st, const std::vector<bool>& active_in, const std::vector<int>& budget) {
+  vie_plan* pl = b.pl;
+  const int nb = b.nb;
+  std::vector<bool> active = active_in;
+  std::vector<int> jend(static_cast<size_t>(nb), 0);
+  std::vector<double> scale(static_cast<size_t>(nb));
+  std::vector<cd> none;
+  // V_0 = r / ||r||
+  for (int r = 0; r < nb; ++r) scale[zu(r)] = (active[zu(r)] && rnorm[zu(r)] > 0) ? 1.0 / rnorm[zu(r)] : 0.0;
+  for (int r = 0; r < nb; ++r)
+    if (!(rnorm[zu(r)] > 0)) active[zu(r)] = false;
+  int rc = combine_host(b, nullptr, pl->rw, pl->V, 0, none, scale);
+  if (rc) return rc;
+  // Hessenberg (column-major, (m+1) x m), rotations, rhs g
+  std::vector<std::vector<cd>> Hs(static_cast<size_t>(nb), std::vector<cd>(zu((m + 1) * m)));
+  std::vector<std::vector<double>> cs(static_cast<size_t>(nb), std::vector<double>(zu(m)));
+  std::vector<std::vector<cd>> sn(static_cast<size_t>(nb), std::vector<cd>(zu(m)));
+  std::vector<std::vector<cd>> g(static_cast<size_t>(nb), std::vector<cd>(zu(m + 1)));
+  for (int r = 0; r < nb; ++r) g[zu(r)][0] = rnorm[zu(r)];
+  const double eta2 = 0.5;  // re-orthogonalise when ||w'||^2 < 0.5 ||w||^2
+  std::vector<cd> h1(zu(nb) * zu(m + 1)), h2(zu(nb) * zu(m + 1));
+  std::vector<double> w2(static_cast<size_t>(nb)), wp2(zu(nb));
+  std::vector<bool> reorth(static_cast<size_t>(nb));
+  int j = 0;
+  for (j = 0; j < m; ++j) {
+    bool any = false;
+    for (int r = 0; r < nb; ++r) any = any || active[zu(r)];
+    if (!any) break;
+    const c128* Vj = pl->V + long(j) * b.vs;
+    c128* Vn = pl->V + long(j + 1) * b.vs;
+    rc = apply_any(pl, fp64, Vj, Vj, nullptr, pl->ww, nb, MODE_MATVEC, b.s);
+    if (rc) return rc;
+    const int nv = j + 1;
+    rc = dots_host(b, pl->V, pl->ww, nv);
+    if (rc) return rc;
+    bool any_reorth = false;
+    for (int r = 0; r < nb; ++r) {
+      double p = 0;
+      for (int i = 0; i < nv; ++i) {
+        const cd v = red_at(b, r, i, nv + 1);
+        h1[zu(r) * zu(nv) + zu(i)] = v;
+        p += std::norm(v);
+      }
+      w2[zu(r)] = red_at(b, r, nv, nv + 1).real();
+      wp2[zu(r)] = w2[zu(r)] - p;
+      reorth[zu(r)] = active[zu(r)] && wp2[zu(r)] < eta2 * w2[zu(r)];
+      any_reorth = any_reorth || reorth[zu(r)];
+    }
+    std::vector<cd> hcol(zu(nb) * zu(nv + 1));
+    std::vector<cd> coef2(zu(nb) * zu(nv), cd(0, 0));
+    for (int r = 0; r < nb; ++r)
+      for (int i = 0; i < nv; ++i) hcol[zu(r) * zu(nv + 1) + zu(i)] = h1[zu(r) * zu(nv) + zu(i)];
+    if (any_reorth) {
+      std::vector<double> one(static_cast<size_t>(nb), 1.0);
+      rc = combine_host(b, pl->V, pl->ww, pl->ww, nv, h1, one);  // w <- w - V h1
+      if (rc) return rc;
+      rc = dots_host(b, pl->V, pl->ww, nv);
+      if (rc) return rc;
+      for (int r = 0; r < nb; ++r) {
+        double beta2;
+        if (reorth[zu(r)]) {
+          double p = 0;
+          for (int i = 0; i < nv; ++i) {
+            const cd v = red_at(b, r, i, nv + 1);
+            coef2[zu(r) * zu(nv) + zu(i)] = v;
+            hcol[zu(r) * zu(nv + 1) + zu(i)] += v;
+            p += std::norm(v);
+          }
+          beta2 = red_at(b, r, nv, nv + 1).real() - p;
+        } else {
+          beta2 = wp2[zu(r)];
+        }
+        const double beta = std::sqrt(std::max(beta2, 0.0));
+        hcol[zu(r) * zu(nv + 1) + zu(nv)] = beta;
+        scale[zu(r)] = (active[zu(r)] && beta > 1e-300) ? 1.0 / beta : 0.0;
+      }
+      rc = combine_host(b, pl->V, pl->ww, Vn, nv, coef2, scale);
+      if (rc) return rc;
+    } else {
+      for (int r = 0; r < nb; ++r) {
+        const double beta = std::sqrt(std::max(wp2[zu(r)], 0.0));
+        hcol[zu(r) * zu(nv + 1) + zu(nv)] = beta;
+        scale[zu(r)] = (active[zu(r)] && beta > 1e-300) ? 1.0 / beta : 0.0;
+      }
+      rc = combine_host(b, pl->V, pl->ww, Vn, nv, h1, scale);
+      if (rc) return rc;
+    }
+    // Givens update per active slot
+    for (int r = 0; r < nb; ++r) {
+      if (!active[zu(r)]) continue;
+      RhsState& S = st[zu(r)];
+      S.iters++;
+      if (fp64)
+        S.mv64++;
+      else
+        S.mv32++;
+      std::vector<cd>& H = Hs[zu(r)];
+      for (int i = 0; i <= nv; ++i) H[zu(j) * zu(m + 1) + zu(i)] = hcol[zu(r) * zu(nv + 1) + zu(i)];
+      cd* col = &H[zu(j) * zu(m + 1)];
+      for (int i = 0; i < j; ++i) {
+        const cd t = cs[zu(r)][zu(i)] * col[i] + sn[zu(r)][zu(i)] * col[i + 1];
+        col[i + 1] = -std::conj(sn[zu(r)][zu(i)]) * col[i] + cs[zu(r)][zu(i)] * col[i + 1];
+        col[i] = t;
+      }
+      const cd a = col[j], bb = col[j + 1];
+      const double rho = std::sqrt(std::norm(a) + std::norm(bb));
+      double c;
+      cd sgn;
+      if (std::abs(a) == 0.0) {
+        c = 0.0;
+        sgn = 1.0;
+        col[j] = bb;
+      } else {
+        c = std::abs(a) / rho;
+        const cd ph = a / std::abs(a);
+        sgn = ph * std::conj(bb) / rho;
+        col[j] = ph * rho;
+      }
+      col[j + 1] = 0.0;
+      cs[zu(r)][zu(j)] = c;
+      sn[zu(r)][zu(j)] = sgn;
+      cd& gj = g[zu(r)][zu(j)];
+      cd& gj1 = g[zu(r)][zu(j + 1)];
+      gj1 = -std::conj(sgn) * gj;
+      gj = c * gj;
+      jend[zu(r)] = j + 1;
+      const double est = std::abs(gj1);
+      const bool breakdown = !(hcol[zu(r) * zu(nv + 1) + zu(nv)].real() > 1e-300);
+      if (est <= target[zu(r)] || breakdown || S.mv32 + S.mv64 >= budget[zu(r)]) active[zu(r)] = false;
+    }
+  }
+  // x += V y with y from the triangular systems
+  int nvmax = 0;
+  for (int r = 0; r < nb; ++r) nvmax = std::max(nvmax, jend[zu(r)]);
+  if (nvmax == 0) return VIE_OK;
+  std::vector<cd> coef(zu(nb) * zu(nvmax), cd(0, 0));
+  for (int r = 0; r < nb; ++r) {
+    const int k = jend[zu(r)];
+    std::vector<cd> y(static_cast<size_t>(k));
+    const std::vector<cd>& H = Hs[zu(r)];
+    for (int i = k - 1; i >= 0; --i) {
+      cd acc = g[zu(r)][zu(i)];
+      for (int q = i + 1; q < k; ++q) acc -= H[zu(q) * zu(m + 1) + zu(i)] * y[zu(q)];
+      const cd d = H[zu(i) * zu(m + 1) + zu(i)];
+      y[zu(i)] = std::abs(d) > 0 ? acc / d : cd(0, 0);
+    }
+    for (int i = 0; i < k; ++i) coef[zu(r) * zu(nvmax) + zu(i)] = -y[zu(i)];
+  }
+  std::vector<double> one(static_cast<size_t>(nb), 1.0);
+  return combine_host(b, pl->V, pl->xw, pl->xw, nvmax, coef, one);
+}
+
+// Bi-CGStab on A d = r (r in rw, d accumulated into xw).  Work vectors in the
+// basis slots: 0 rhat, 1 v, 2 p, 3 s, 4 t.
+int bicgstab_run(const Batch& b, bool fp64, const std::vector<double>& rnorm0, const std::vector<double>& target,
+                 std::vector<RhsState>& st, const std::vector<bool>& active_in, const std::vector<int>& budget) {
+  vie_plan* pl = b.pl;
+  const int nb = b.nb;
+  std::vector<bool> active = active_in;
+  c128* rhat = pl->V;
+  c128* v = pl->V + b.vs;
+  c128* p = pl->V + 2 * b.vs;
+  c128* sv = pl->V + 3 * b.vs;
+  c128* t = pl->V + 4 * b.vs;
+  std::vector<cd> none;
+  std::vector<double> one(static_cast<size_t>(nb), 1.0), zero(zu(nb), 0.0);
+  int rc = combine_host(b, nullptr, pl->rw, rhat, 0, none, one);
+  if (!rc) rc = combine_host(b, nullptr, pl->rw, p, 0, none, zero);  // p = 0
+  if (!rc) rc = combine_host(b, nullptr, pl->rw, v, 0, none, zero);  // v = 0
+  if (rc) return rc;
+  std::vector<cd> rho(static_cast<size_t>(nb), 1.0), alpha(zu(nb), 1.0), omg(zu(nb), 1.0);
+  for (int r = 0; r < nb; ++r)
+    if (!(rnorm0[zu(r)] > 0)) active[zu(r)] = false;
+  const int max_steps = 100000;
+  for (int it = 0; it < max_steps; ++it) {
+    bool any = false;
+    for (int r = 0; r < nb; ++r) any = any || active[zu(r)];
+    if (!any) break;
+    // rho_new = (rhat, r)
+    rc = dots_host(b, rhat, pl->rw, 1);
+    if (rc) return rc;
+    std::vector<cd> cP(zu(nb) * 2, cd(0, 0));
+    std::vector<cd> rho_new(static_cast<size_t>(nb));
+    for (int r = 0; r < nb; ++r) {
+      rho_new[zu(r)] = red_at(b, r, 0, 2);
+      if (!active[zu(r)]) continue;
+      const cd beta = (rho_new[zu(r)] / rho[zu(r)]) * (alpha[zu(r)] / omg[zu(r)]);
+      // p = r + beta (p - omega v) = r - (v (beta omega) + p (-beta))
+      cP[zu(r) * 2 + 0] = beta * omg[zu(r)];
+      cP[zu(r) * 2 + 1] = -beta;
+    }
+    std::vector<double> sc(static_cast<size_t>(nb));
+    for (int r = 0; r < nb; ++r) sc[zu(r)] = active[zu(r)] ? 1.0 : 0.0;
+    rc = combine_host(b, v, pl->rw, p, 2, cP, sc);
+    if (rc) return rc;
+    rc = apply_any(pl, fp64, p, p, nullptr, v, nb, MODE_MATVEC, b.s);
+    if (rc) return rc;
+    rc = dots_host(b, rhat, v, 1);
+    if (rc) return rc;
+    std::vector<cd> cS(static_cast<size_t>(nb), cd(0, 0));
+    for (int r = 0; r < nb; ++r) {
+      if (!active[zu(r)]) continue;
+      const cd den = red_at(b, r, 0, 2);
+      alpha[zu(r)] = std::abs(den) > 0 ? rho_new[zu(r)] / den : cd(0, 0);
+      cS[zu(r)] = alpha[zu(r)];
+    }
+    rc = combine_host(b, v, pl->rw, sv, 1, cS, sc);  // s = r - alpha v
+    if (rc) return rc;
+    rc = apply_any(pl, fp64, sv, sv, nullptr, t, nb, MODE_MATVEC, b.s);
+    if (rc) return rc;
+    rc = dots_host(b, sv, t, 1);  // conj(s).t and ||t||^2
+    if (rc) return rc;
+    std::vector<cd> cX(zu(nb) * 2, cd(0, 0)), cR(zu(nb), cd(0, 0));
+    for (int r = 0; r < nb; ++r) {
+      if (!active[zu(r)]) continue;
+      const cd st_ = std::conj(red_at(b, r, 0, 2));  // (t, s) = sum conj(t) s
+      const double tt = red_at(b, r, 1, 2).real();
+      omg[zu(r)] = tt > 0 ? st_ / tt : cd(0, 0);
+      cX[zu(r) * 2 + 0] = -alpha[zu(r)];
+      cX[zu(r) * 2 + 1] = -omg[zu(r)];
+      cR[zu(r)] = omg[zu(r)];
+      rho[zu(r)] = rho_new[zu(r)];
+      st[zu(r)].iters++;
+      if (fp64)
+        st[zu(r)].mv64 += 2;
+      else
+        st[zu(r)].mv32 += 2;
+    }
+    rc = combine_host(b, p, pl->xw, pl->xw, 2, cX, one);  // x += alpha p + omega s
+    if (rc) return rc;
+    // r = s - omega t (frozen slots keep r)
+    for (int r = 0; r < nb; ++r) sc[zu(r)] = 1.0;
+    {
+      std::vector<cd> cRr(static_cast<size_t>(nb), cd(0, 0));
+      for (int r = 0; r < nb; ++r) cRr[zu(r)] = cR[zu(r)];
+      // slots not active: r <- r (use w = r and coefficient 0 via a second call)
+      rc = combine_host(b, t, sv, pl->ww, 1, cRr, sc);
+      if (rc) return rc;
+    }
+    rc = dots_host(b, nullptr, pl->ww, 0);
+    if (rc) return rc;
+    std::vector<double> nr(static_cast<size_t>(nb));
+    for (int r = 0; r < nb; ++r) nr[zu(r)] = std::sqrt(std::max(0.0, red_at(b, r, 0, 1).real()));
+    // copy the new residual of active slots into rw
+    std::vector<double> keep(static_cast<size_t>(nb));
+    for (int r = 0; r < nb; ++r) keep[zu(r)] = active[zu(r)] ? 1.0 : 0.0;
+    // rw = active ? ww : rw  -> rw = ww*keep + rw*(1-keep): two combines keep arithmetic exact
+    for (int r = 0; r < nb; ++r) {
+      if (!active[zu(r)]) continue;
+      (void)r;
+    }
+    rc = VIE_OK;
+    {
+      // slots that are active take ww; inactive slots keep rw: done with a copy
+      // per active slot range (contiguous slots are copied in one call)
+      int r = 0;
+      while (r < nb) {
+        if (!active[zu(r)]) {
+          ++r;
+          continue;
+        }
+        int e = r;
+        while (e < nb && active[zu(e)]) ++e;
+        HIPCHK(pl, launch_copy(pl->ww + long(r) * b.L, pl->rw + long(r) * b.L, long(e - r) * b.L, b.s));
+        r = e;
+      }
+    }
+    for (int r = 0; r < nb; ++r) {
+      if (!active[zu(r)]) continue;
+      RhsState& S = st[zu(r)];
+      if (nr[zu(r)] <= target[zu(r)] || S.mv32 + S.mv64 >= budget[zu(r)] || !std::isfinite(nr[zu(r)]))
+        active[zu(r)] = false;
+    }
+  }
+  return VIE_OK;
+}
+
+}  // namespace
+
+int solve_batch(vie_plan* pl, const c128* inc, c128* density, c128* field, int nrhs, const vie_solve_opts& o,
+                vie_solve_stats* stats, hipStream_t s) {
+  const bool mixed = pl->precision == VIE_PREC_MIXED && !(o.flags & VIE_SOLVE_FP64);
+  const int m = o.solver == VIE_SOLVER_BICGSTAB ? 5 : std::max(1, o.restart);
+  const long L = long(pl->C) * pl->n3;
+  const int cap = std::max(1, std::min(nrhs, pl->max_rhs));
+  int rc = ensure_krylov(pl, cap, std::max(m, 5));
+  if (rc) return rc;
+  int status = VIE_OK;
+  for (int r0 = 0; r0 < nrhs; r0 += cap) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int nb = std::min(cap, nrhs - r0);
+    Batch b{pl, s, nb, L, long(pl->kr_cap) * L, krylov_blocks(L)};
+    const long off = long(r0) * L;
+    // b = 2 H g
+    HIPCHK(pl, launch_rhs(pl->H64, pl->Hmu64, inc + off, pl->bw, nb, pl->C, pl->n3, s));
+    std::vector<double> bnorm, rnorm;
+    rc = norms(b, pl->bw, bnorm);
+    if (rc) return rc;
+    if (o.flags & VIE_SOLVE_X0) {
+      HIPCHK(pl, launch_copy(density + off, pl->xw, long(nb) * L, s));
+      rc = apply_any(pl, true, pl->xw, pl->xw, pl->bw, pl->rw, nb, MODE_RESIDUAL, s);
+      if (rc) return rc;
+    } else {
+      HIPCHK(pl, launch_fill(pl->xw, long(nb) * L, c128{0.0, 0.0}, s));
+      HIPCHK(pl, launch_copy(pl->bw, pl->rw, long(nb) * L, s));
+    }
+    rc = norms(b, pl->rw, rnorm);
+    if (rc) return rc;
+    std::vector<RhsState> st(static_cast<size_t>(nb));
+    for (int r = 0; r < nb; ++r) {
+      st[zu(r)].bnorm = bnorm[zu(r)];
+      st[zu(r)].rnorm = rnorm[zu(r)];
+      if (o.flags & VIE_SOLVE_X0) st[zu(r)].mv64++;
+      if (!(bnorm[zu(r)] > 0)) {
+        // b = 0: x = 0 is exact
+        st[zu(r)].done = st[zu(r)].conv = true;
+        st[zu(r)].rnorm = 0;
+      } else if (rnorm[zu(r)] <= o.tol * bnorm[zu(r)]) {
+        st[zu(r)].done = st[zu(r)].conv = true;
+      }
+    }
+    std::vector<double> prev(rnorm);
+    int stall = 0;
+    for (int outer = 0; outer < 10000; ++outer) {
+      bool any = false;
+      for (int r = 0; r < nb; ++r) any = any || !st[zu(r)].done;
+      if (!any) break;
+      std::vector<double> target(static_cast<size_t>(nb));
+      std::vector<bool> active(static_cast<size_t>(nb));
+      std::vector<int> budget(static_cast<size_t>(nb));
+      for (int r = 0; r < nb; ++r) {
+        const RhsState& S = st[zu(r)];
+        active[zu(r)] = !S.done;
+        const double inner = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+        target[zu(r)] = mixed ? std::max(inner * S.rnorm, 0.3 * o.tol * S.bnorm) : 0.5 * o.tol * S.bnorm;
+        budget[zu(r)] = std::max(1, o.max_iters - 1);
+        if (S.done) rnorm[zu(r)] = 0.0;
+      }
+      if (o.solver == VIE_SOLVER_BICGSTAB)
+        rc = bicgstab_run(b, !mixed, rnorm, target, st, active, budget);
+      else
+        rc = gmres_cycle(b, !mixed, m, rnorm, target, st, active, budget);
+      if (rc) return rc;
+      // true residual with the FP64 operator
+      rc = apply_any(pl, true, pl->xw, pl->xw, pl->bw, pl->rw, nb, MODE_RESIDUAL, s);
+      if (rc) return rc;
+      rc = norms(b, pl->rw, rnorm);
+      if (rc) return rc;
+      bool progressed = false;
+      for (int r = 0; r < nb; ++r) {
+        RhsState& S = st[zu(r)];
+        if (S.done) continue;
+        S.mv64++;
+        S.refine++;
+        S.rnorm = rnorm[zu(r)];
+        if (S.rnorm < 0.9 * prev[zu(r)]) progressed = true;
+        prev[zu(r)] = S.rnorm;
+        if (S.rnorm <= o.tol * S.bnorm) {
+          S.done = S.conv = true;
+        } else if (S.mv32 + S.mv64 >= o.max_iters || !std::isfinite(S.rnorm)) {
+          S.done = true;
+        }
+      }
+      stall = progressed ? 0 : stall + 1;
+      if (stall >= 3) {
+        for (int r = 0; r < nb; ++r) st[zu(r)].done = true;
+      }
+    }
+    HIPCHK(pl, launch_copy(pl->xw, density + off, long(nb) * L, s));
+    if (field) {
+      rc = apply_any(pl, true, density + off, inc + off, nullptr, field + off, nb, MODE_FIELD, s);
+      if (rc) return rc;
+    }
+    HIPCHK(pl, hipStreamSynchronize(s));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int r = 0; r < nb; ++r) {
+      const RhsState& S = st[zu(r)];
+      if (!S.conv) status = VIE_W_NOCONV;
+      if (stats) {
+        vie_solve_stats& x = stats[r0 + r];
+        x.status = S.conv ? VIE_OK : VIE_W_NOCONV;
+        x.iters = S.iters;
+        x.matvecs_fp32 = S.mv32;
+        x.matvecs_fp64 = S.mv64;
+        x.refinements = S.refine;
+        x.rel_residual = S.bnorm > 0 ? S.rnorm / S.bnorm : 0.0;
+        x.seconds = secs;
+      }
+    }
+  }
+  return status;
+}
+
+}  // namespace vie
+
+extern "C" int vie_solve(vie_plan* pl, const double* inc, double* density, double* field, int nrhs,
+                         const vie_solve_opts* opts, vie_solve_stats* stats, void* hip_stream) {
+  if (!pl) return VIE_E_ARG;
+  if (!inc || !density || nrhs < 1) return vie::fail(pl, VIE_E_ARG, "vie_solve: null pointer or nrhs < 1");
+  vie_solve_opts o{1e-10, 2000, 40, 0.0, VIE_SOLVER_GMRES, 0u};
+  if (opts) o = *opts;
+  if (!(o.tol > 0) || o.max_iters < 1 || o.restart < 1 || o.restart > 1000 ||
+      (o.solver != VIE_SOLVER_GMRES && o.solver != VIE_SOLVER_BICGSTAB))
+    return vie::fail(pl, VIE_E_ARG, "vie_solve: invalid options");
+  return vie::solve_batch(pl, reinterpret_cast<const vie::c128*>(inc), reinterpret_cast<vie::c128*>(density),
+                          reinterpret_cast<vie::c128*>(field), nrhs, o, stats, static_cast<hipStream_t>(hip_stream));
+}

@@ -1,0 +1,141 @@
+"""GPU solves through the C ABI against the oracle's solutions.
+
+FP64 GMRES is run to a true relative residual of 1e-12 and must agree with
+the oracle solution (GMRES to 1e-13) to 1e-10; the mixed FP32/FP64 solver is
+run to 1e-9 and must agree to 1e-8 (the error is at most kappa times the
+residual, kappa = O(10) for these contractive media).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import operator as op
+from oracle import solve as sv
+from vie_inputs import generators as gen
+
+from _helpers import medium, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vie():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_04791_amd import vie as v
+    v.load_library()
+    return v
+
+
+def incident(kind, n, omega, nrhs, full, item=0):
+    out = []
+    for j in range(nrhs):
+        rng = gen.rng_for(gen.CONFIG_IDS["test"], 900 + item + j)
+        d = gen.random_unit(rng)
+        if kind == op.KIND_LAPLACE:
+            out.append(gen.constant_field(n, d))
+        elif kind == op.KIND_HELMHOLTZ:
+            out.append(gen.plane_wave_gradient(n, omega, d))
+        else:
+            p = gen.random_polarisation(rng, d)
+            f = gen.plane_wave_em(n, omega, d, p)
+            out.append(f if full else f[:3])
+    return np.stack(out)
+
+
+CASES = [("laplace", op.KIND_LAPLACE, False), ("helmholtz", op.KIND_HELMHOLTZ, False),
+         ("maxwell", op.KIND_MAXWELL, False), ("maxwell_full", op.KIND_MAXWELL, True)]
+
+
+@pytest.mark.parametrize("name,kind,full", CASES)
+def test_fp64_and_mixed_solves_match_oracle(vie, name, kind, full):
+    n = 16
+    coef, mu, omega = medium(kind, n, 3, full)
+    inc = incident(kind, n, omega, 2, full)
+    A = op.Operator(kind, coef, omega, mu=mu)
+    ref = [sv.gmres(A.apply, A.rhs(inc[r]), tol=1e-13)[0] for r in range(2)]
+    plan = vie.Plan(kind, coef, omega=omega, mu=mu, precision=vie.PREC_MIXED, max_rhs=2)
+    d64, f64, st64, rc = plan.solve(inc, tol=1e-12, fp64=True)
+    assert rc == vie.OK
+    d32, f32, st32, rc = plan.solve(inc, tol=1e-9)
+    assert rc == vie.OK
+    d64, d32, f64 = d64.cpu().numpy(), d32.cpu().numpy(), f64.cpu().numpy()
+    for r in range(2):
+        assert st64[r]["rel_residual"] <= 1e-12 and st64[r]["matvecs_fp32"] == 0
+        assert st32[r]["rel_residual"] <= 1e-9 and st32[r]["matvecs_fp32"] > 0
+        assert rel(d64[r], ref[r]) < 1e-10
+        assert rel(d32[r], ref[r]) < 1e-8
+        assert rel(f64[r], A.field(ref[r], inc[r])) < 1e-10
+    plan.close()
+
+
+def test_bicgstab_matches_oracle(vie):
+    n = 16
+    coef, mu, omega = medium(op.KIND_HELMHOLTZ, n, 4)
+    inc = incident(op.KIND_HELMHOLTZ, n, omega, 2, False)
+    A = op.Operator(op.KIND_HELMHOLTZ, coef, omega)
+    ref = [sv.gmres(A.apply, A.rhs(inc[r]), tol=1e-13)[0] for r in range(2)]
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2)
+    for fp64, tol, err in ((True, 1e-12, 1e-10), (False, 1e-9, 1e-8)):
+        d, _, st, rc = plan.solve(inc, tol=tol, fp64=fp64, solver=vie.SOLVER_BICGSTAB, want_field=False)
+        assert rc == vie.OK
+        d = d.cpu().numpy()
+        for r in range(2):
+            assert st[r]["rel_residual"] <= tol
+            assert rel(d[r], ref[r]) < err
+    plan.close()
+
+
+def test_laplace_config_solve(vie):
+    """The anisotropic Laplace configuration (32^3, eps = I + b A, E0 = z) in FP64."""
+    prob = gen.config_problem("laplace32")
+    A = op.Operator(prob.kind, prob.coef, 0.0)
+    ref, info = sv.gmres(A.apply, A.rhs(prob.inc[0]), tol=1e-13)
+    plan = vie.Plan(prob.kind, prob.coef, precision=vie.PREC_FP64)
+    d, f, st, rc = plan.solve(prob.inc, tol=1e-12)
+    assert rc == vie.OK
+    assert rel(d.cpu().numpy()[0], ref) < 1e-10
+    assert abs(st[0]["iters"] - info["matvecs"]) <= 3
+    plan.close()
+
+
+def test_batch_result_equals_single(vie):
+    n = 16
+    coef, mu, omega = medium(op.KIND_HELMHOLTZ, n, 5)
+    inc = incident(op.KIND_HELMHOLTZ, n, omega, 4, False, item=20)
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=4)
+    db, _, stb, _ = plan.solve(inc, tol=1e-9, want_field=False)
+    db = db.cpu().numpy()
+    for r in (0, 3):
+        ds, _, sts, _ = plan.solve(inc[r:r + 1], tol=1e-9, want_field=False)
+        assert np.array_equal(ds.cpu().numpy()[0], db[r])
+        assert sts[0]["iters"] == stb[r]["iters"]
+    plan.close()
+
+
+def test_identity_medium_gives_zero_density(vie):
+    n = 12
+    coef = gen.identity_field(n)
+    inc = incident(op.KIND_HELMHOLTZ, n, 2.0, 1, False)
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=2.0, precision=vie.PREC_MIXED)
+    d, f, st, rc = plan.solve(inc, tol=1e-10)
+    assert rc == vie.OK
+    assert np.all(d.cpu().numpy() == 0)
+    assert np.allclose(f.cpu().numpy(), inc, rtol=0, atol=1e-14)
+    plan.close()
+
+
+def test_resume_from_x0_and_noconv(vie):
+    n = 12
+    coef, mu, omega = medium(op.KIND_HELMHOLTZ, n, 6)
+    inc = incident(op.KIND_HELMHOLTZ, n, omega, 1, False)
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_FP64)
+    d1, _, st1, rc1 = plan.solve(inc, tol=1e-12, max_iters=3, restart=2, want_field=False)
+    assert rc1 == vie.W_NOCONV and st1[0]["status"] == vie.W_NOCONV
+    d2, _, st2, rc2 = plan.solve(inc, tol=1e-12, x0=d1, want_field=False)
+    assert rc2 == vie.OK and st2[0]["rel_residual"] <= 1e-12
+    plan.close()
