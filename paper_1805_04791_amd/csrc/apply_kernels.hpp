@@ -37,13 +37,20 @@ struct ZArgs {
   int ne;           // table entries (6 or 9)
   long comp_stride; // n * P * P
   long rhs_stride;  // C * n * P * P
+  int nb;           // right-hand sides in the launch
 };
 
+// Block order: blocks are dealt round-robin to the 8 XCDs (block b runs on
+// XCD b % 8).  The nb right-hand sides of one (ky, kx-tile) slice read the
+// same table slice, so they are given consecutive launch slots on one XCD and
+// the slice is re-read from that XCD's L2.  Requires (P / T) * P % 8 == 0.
 template <typename R, int P1, int P2, int C, int MUL>
-__global__ void __launch_bounds__(kFusedMaxThreads) k_zpass(cx<R>* buf, const cx<R>* __restrict__ tab, ZArgs a,
-                                                const cx<R>* __restrict__ twg) {
+__global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* buf, const cx<R>* __restrict__ tab, ZArgs a,
+                                                            const cx<R>* __restrict__ twg) {
   constexpr int P = P1 * P2;
   constexpr int J = P1 > P2 ? P1 : P2;
+  constexpr int H1 = P1 / 2;  // z < n = P/2  <=>  n1 < P1/2 for z = P2 n1 + j
+  static_assert(P1 % 2 == 0, "pruned z input assumes P1 even");
   static_assert(MUL != MUL_SYM3 || C == 3, "SYM3 multiply acts on 3 components");
   static_assert(MUL != MUL_MAX6 || C == 6, "MAX6 multiply acts on 6 components");
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -52,20 +59,42 @@ __global__ void __launch_bounds__(kFusedMaxThreads) k_zpass(cx<R>* buf, const cx
   load_twiddles<R, P>(tw, twg);
   int col, j;
   Layout<false>::lane(threadIdx.x, a.T, J, col, j);
-  const int tile = int(blockIdx.x % unsigned(a.ntiles));
-  const long rest = long(blockIdx.x / unsigned(a.ntiles));
-  const int ky = int(rest % P);
-  const long rhs = rest / P;
+  const unsigned xcd = blockIdx.x % 8u;
+  const unsigned k = blockIdx.x / 8u;
+  const long slice = long(k / unsigned(a.nb)) * 8 + xcd;
+  const long rhs = long(k % unsigned(a.nb));
+  const int tile = int(slice % a.ntiles);
+  const int ky = int(slice / a.ntiles);
   const int kx = tile * a.T + col;
   const bool valid = kx < P;
   const long PP = long(P) * P;
   cx<R>* base = buf + rhs * a.rhs_stride + long(ky) * P + kx;
+
+  // kUpfront: all inputs of the block in flight at once
+  constexpr int CU = kUpfront ? C : 1;
+  cx<R> in[CU][H1];
+  auto load_comp = [&](int c, cx<R>(&dst)[H1]) {
+    const cx<R>* src = base + c * a.comp_stride;
+    static_for<0, H1>([&](auto n1) {
+      dst[n1] = (valid && j < P2) ? src[long(P2 * n1 + j) * PP] : czero<R>();
+    });
+  };
+  if constexpr (kUpfront) static_for<0, C>([&](auto c) { load_comp(c, in[c]); });
   __syncthreads();
+  ThreadTw<R, P1, P2, kRegTwiddles<R>> twr;
+  twr.init(tw, j);
 
   cx<R> X[C][P2];
   static_for<0, C>([&](auto c) {
-    const cx<R>* src = base + c * a.comp_stride;
-    fft_fwd_AB<R, P1, P2, false>([&](int z) { return src[long(z) * PP]; }, a.n, lds, tw, col, j, a.T, valid, X[c]);
+    if constexpr (!kUpfront) load_comp(c, in[0]);
+    cx<R> u[P1];
+    static_for<0, P1>([&](auto n1) {
+      if constexpr (decltype(n1)::value < H1)
+        u[n1] = in[kUpfront ? int(c) : 0][n1];
+      else
+        u[n1] = czero<R>();
+    });
+    fft_fwd_core<R, P1, P2, false>(u, twr, lds, col, j, a.T, X[c]);
   });
 
   if (j < P1 && valid) {
@@ -108,7 +137,7 @@ __global__ void __launch_bounds__(kFusedMaxThreads) k_zpass(cx<R>* buf, const cx
   static_for<0, C>([&](auto c) {
     cx<R>* dst = base + c * a.comp_stride;
     fft_inv_CD<R, P1, P2, false>(
-        X[c], [&](auto, int z, cx<R> v) { dst[long(z) * PP] = v; }, a.n, lds, tw, col, j, a.T, valid);
+        X[c], [&](auto, int z, cx<R> v) { dst[long(z) * PP] = v; }, a.n, lds, twr, col, j, a.T, valid);
   });
 }
 
@@ -122,7 +151,7 @@ struct XArgs {
 // Rows (rhs, z, y): inverse x transform of every component, then the pointwise
 // combine.  Vectors J, B, out are complex128 [rhs][C][n^3]; H, Hmu [9][n^3].
 template <typename R, int P1, int P2, int C, int MODE>
-__global__ void __launch_bounds__(kFusedMaxThreads) k_xinv(const cx<R>* __restrict__ A, XArgs a, const c128* __restrict__ Jv,
+__global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R>* __restrict__ A, XArgs a, const c128* __restrict__ Jv,
                                                const c128* __restrict__ Bv, const cx<R>* __restrict__ H,
                                                const cx<R>* __restrict__ Hmu, c128* __restrict__ out,
                                                const cx<R>* __restrict__ twg) {
@@ -142,21 +171,28 @@ __global__ void __launch_bounds__(kFusedMaxThreads) k_xinv(const cx<R>* __restri
   const long NN = long(N) * N;
   const long rhs = valid ? row / NN : 0;
   const long zy = valid ? row % NN : 0;
+
+  // kUpfront: all spectral inputs of the row in flight at once
+  constexpr int CU = kUpfront ? C : 1;
+  cx<R> X[CU][P2];
+  auto load_comp = [&](int c, cx<R>(&dst)[P2]) {
+    const cx<R>* src = A + ((rhs * C + c) * NN + zy) * P;
+    static_for<0, P2>([&](auto k2) { dst[k2] = (valid && j < P1) ? src[j + P1 * k2] : czero<R>(); });
+  };
+  if constexpr (kUpfront) static_for<0, C>([&](auto c) { load_comp(c, X[c]); });
   __syncthreads();
+  ThreadTw<R, P1, P2, kRegTwiddles<R>> twr;
+  twr.init(tw, j);
 
   cx<R> U[C][NV];
   static_for<0, C>([&](auto c) {
-    const cx<R>* src = A + ((rhs * C + c) * NN + zy) * P;
-    cx<R> X[P2];
-    if (j < P1) {
-      static_for<0, P2>([&](auto k2) { X[k2] = valid ? src[j + P1 * k2] : czero<R>(); });
-    }
+    if constexpr (!kUpfront) load_comp(c, X[0]);
     fft_inv_CD<R, P1, P2, true>(
-        X,
+        X[kUpfront ? int(c) : 0],
         [&](auto m2, int, cx<R> v) {
           if constexpr (decltype(m2)::value < NV) U[c][decltype(m2)::value] = v;
         },
-        N, lds, tw, col, j, a.T, valid);
+        N, lds, twr, col, j, a.T, valid);
   });
 
   if (!valid || j >= P2) return;

@@ -33,9 +33,24 @@ struct scalar_of<cx<R>> {
   using type = R;
 };
 
+// Kernel variants.  kUpfront: the fused z / x-inverse passes issue the loads
+// of all components before the first transform (more bytes in flight, more
+// VGPRs).  kRegTwiddles<R>: per-thread twiddles held in registers.
+#ifndef VIE_ZVAR
+#define VIE_ZVAR 1
+#endif
+constexpr bool kUpfront = (VIE_ZVAR & 1) != 0;
+template <typename R>
+constexpr bool kRegTwiddles = (VIE_ZVAR & 2) != 0 && sizeof(R) == 4;
+
 // largest block of each kernel family (the tile choice keeps T*J within it)
 constexpr int kPassMaxThreads = 512;
-constexpr int kFusedMaxThreads = 256;
+constexpr int kFusedMaxThreads = 512;
+// the FP64 six-component kernels need every register a wave can hold
+template <typename R, int C>
+constexpr int fused_max_threads() {
+  return (sizeof(R) == 8 && C == 6) ? 256 : kFusedMaxThreads;
+}
 
 struct Geo {
   int T;          // columns (strided) or rows (contiguous) per block
@@ -74,12 +89,14 @@ struct MemStore {
 template <bool CONTIG>
 struct Layout;
 
-// strided: (a * Bd + b) * T + col
+// strided: (a * (Bd + 1) + b) * T + col.  The extra slot per a-row shifts the
+// pencil groups a, a+1 of one half-wave by T elements so that their
+// contiguous T-column runs fall into different LDS banks.
 template <>
 struct Layout<false> {
   __device__ __forceinline__ static int idx(int col, int a, int b, int Bd, int Ad, int T) {
     (void)Ad;
-    return (a * Bd + b) * T + col;
+    return (a * (Bd + 1) + b) * T + col;
   }
   __device__ __forceinline__ static void lane(int tid, int T, int J, int& col, int& j) {
     (void)J;
@@ -104,23 +121,52 @@ struct Layout<true> {
 
 template <int P1, int P2>
 __host__ __device__ constexpr int lds_elems_per_col(bool contig) {
-  return contig ? (P2 * (P1 + 1) > P1 * (P2 + 1) ? P2 * (P1 + 1) : P1 * (P2 + 1)) : P1 * P2;
+  (void)contig;
+  return P2 * (P1 + 1) > P1 * (P2 + 1) ? P2 * (P1 + 1) : P1 * (P2 + 1);
 }
 
-// Step A + B.  load(n) is called for n < nin only.  On return the threads with
-// j < P1 hold X[j + P1 k2] in X[k2].  Contains two block barriers; every thread
-// of the block must call it.
-template <typename R, int P1, int P2, bool CONTIG, typename LoadF>
-__device__ __forceinline__ void fft_fwd_AB(LoadF&& load, int nin, cx<R>* lds, const cx<R>* tw, int col,
-                                           int j, int T, bool valid, cx<R> (&X)[P2]) {
+// Twiddles W_P^{j i} of thread j.  Step A multiplies by W_P^{n2 k1} (n2 = j,
+// k1 < P1) and step C by W_P^{-m1 k1} (k1 = j, m1 < P2 <= P1); j i < P in both.
+// REG: the P1 values are copied to registers once per block (fewer LDS reads,
+// more VGPRs); otherwise they are read from the LDS table when needed.
+template <typename R, int P1, int P2, bool REG>
+struct ThreadTw {
+  static constexpr int P = P1 * P2;
+  cx<R> r[REG ? P1 : 1];
+  const cx<R>* t;
+  int j;
+  __device__ __forceinline__ void init(const cx<R>* tw, int jj) {
+    t = tw;
+    j = jj;
+    if constexpr (REG) static_for<0, P1>([&](auto i) { r[i] = tw[(jj * i) % P]; });
+  }
+  template <int I>
+  __device__ __forceinline__ cx<R> get() const {
+    if constexpr (REG)
+      return r[I];
+    else
+      return t[j * I];
+  }
+};
+
+// Inputs of step A for thread j (< P2): u[n1] = x[P2 n1 + j], zero for n >= nin.
+template <typename R, int P1, int P2, typename LoadF>
+__device__ __forceinline__ void fft_load(LoadF&& load, int nin, int j, bool valid, cx<R> (&u)[P1]) {
+  static_for<0, P1>([&](auto n1) {
+    const int n = P2 * n1 + j;
+    u[n1] = (valid && j < P2 && n < nin) ? load(n) : czero<R>();
+  });
+}
+
+// Step A + B from preloaded inputs u (destroyed).  On return the threads with
+// j < P1 hold X[j + P1 k2] in X[k2].  Two block barriers: every thread of the
+// block must call it.
+template <typename R, int P1, int P2, bool CONTIG, typename TW>
+__device__ __forceinline__ void fft_fwd_core(cx<R> (&u)[P1], const TW& twr, cx<R>* lds, int col, int j, int T,
+                                             cx<R> (&X)[P2]) {
   if (j < P2) {
-    cx<R> u[P1];
-    static_for<0, P1>([&](auto n1) {
-      const int n = P2 * n1 + j;
-      u[n1] = (valid && n < nin) ? load(n) : czero<R>();
-    });
     DFT<P1, false>::run(u);
-    static_for<1, P1>([&](auto k1) { u[k1] = u[k1] * tw[j * k1]; });
+    static_for<1, P1>([&](auto k1) { u[k1] = u[k1] * twr.template get<decltype(k1)::value>(); });
     static_for<0, P1>([&](auto k1) { lds[Layout<CONTIG>::idx(col, j, k1, P1, P2, T)] = u[k1]; });
   }
   __syncthreads();
@@ -131,14 +177,23 @@ __device__ __forceinline__ void fft_fwd_AB(LoadF&& load, int nin, cx<R>* lds, co
   __syncthreads();
 }
 
+// Step A + B with the loads done here.
+template <typename R, int P1, int P2, bool CONTIG, typename LoadF, typename TW>
+__device__ __forceinline__ void fft_fwd_AB(LoadF&& load, int nin, cx<R>* lds, const TW& twr, int col, int j,
+                                           int T, bool valid, cx<R> (&X)[P2]) {
+  cx<R> u[P1];
+  fft_load<R, P1, P2>(load, nin, j, valid, u);
+  fft_fwd_core<R, P1, P2, CONTIG>(u, twr, lds, col, j, T, X);
+}
+
 // Step C + D.  Threads with j < P1 supply X[j + P1 k2] in X[k2] (destroyed).
 // store(m2, n, v) is called for n = j + P2 m2 < nout only (m2 is a compile-time index).
-template <typename R, int P1, int P2, bool CONTIG, typename StoreF>
-__device__ __forceinline__ void fft_inv_CD(cx<R> (&X)[P2], StoreF&& store, int nout, cx<R>* lds, const cx<R>* tw,
+template <typename R, int P1, int P2, bool CONTIG, typename StoreF, typename TW>
+__device__ __forceinline__ void fft_inv_CD(cx<R> (&X)[P2], StoreF&& store, int nout, cx<R>* lds, const TW& twr,
                                            int col, int j, int T, bool valid) {
   if (j < P1) {
     DFT<P2, true>::run(X);
-    static_for<1, P2>([&](auto m1) { X[m1] = cmulc(tw[m1 * j], X[m1]); });
+    static_for<1, P2>([&](auto m1) { X[m1] = cmulc(twr.template get<decltype(m1)::value>(), X[m1]); });
     static_for<0, P2>([&](auto m1) { lds[Layout<CONTIG>::idx(col, j, m1, P2, P1, T)] = X[m1]; });
   }
   __syncthreads();
@@ -175,11 +230,14 @@ __global__ void __launch_bounds__(kPassMaxThreads) k_pass(Src src, Dst dst, Geo 
   const long g = long(blockIdx.x) / geo.ntiles;
   const long c = tile * geo.T + col;
   const bool valid = c < geo.ncols;
+  cx<R> u[P1];
+  if constexpr (!INV) fft_load<R, P1, P2>([&](int n) { return src.template load<R>(g, c, n); }, geo.nin, j, valid, u);
   __syncthreads();
+  ThreadTw<R, P1, P2, kRegTwiddles<R>> twr;
+  twr.init(tw, j);
   cx<R> X[P2];
   if constexpr (!INV) {
-    fft_fwd_AB<R, P1, P2, CONTIG>([&](int n) { return src.template load<R>(g, c, n); }, geo.nin, lds, tw, col, j,
-                                  geo.T, valid, X);
+    fft_fwd_core<R, P1, P2, CONTIG>(u, twr, lds, col, j, geo.T, X);
     if (j < P1 && valid) {
       static_for<0, P2>([&](auto k2) {
         const int n = j + P1 * k2;
@@ -194,7 +252,7 @@ __global__ void __launch_bounds__(kPassMaxThreads) k_pass(Src src, Dst dst, Geo 
       });
     }
     fft_inv_CD<R, P1, P2, CONTIG>(
-        X, [&](auto, int n, cx<R> v) { dst.template store<R>(g, c, n, v); }, geo.nout, lds, tw, col, j, geo.T, valid);
+        X, [&](auto, int n, cx<R> v) { dst.template store<R>(g, c, n, v); }, geo.nout, lds, twr, col, j, geo.T, valid);
   }
 }
 

@@ -162,17 +162,24 @@ constexpr int kTileChoices[] = {2, 4, 8, 12, 16, 24, 32};
 
 template <typename R, bool CONTIG>
 size_t lds_need(int P1, int P2, int T) {
-  const size_t per = CONTIG ? size_t(std::max(P2 * (P1 + 1), P1 * (P2 + 1))) : size_t(P1 * P2);
+  const size_t per = size_t(std::max(P2 * (P1 + 1), P1 * (P2 + 1)));  // both layouts pad one slot per row
   return sizeof(cx<R>) * (size_t(P1 * P2) + size_t(T) * per);
 }
 
 // T columns per block must divide `cols` (the column count of a strided
 // pass, or the transform length for contiguous passes)
+// Strided passes read and write runs of T consecutive complex values per row;
+// a run shorter than a 128-byte cache line makes neighbouring tiles, which
+// run on different XCDs, fetch the same line twice, so T * sizeof >= 128 B
+// whenever the column count allows it.
 template <typename R>
-bool tile_ok(const vie_plan* pl, int P1, int P2, int T, bool contig, long cols, int maxthreads) {
+bool tile_ok(const vie_plan* pl, int P1, int P2, int T, bool contig, long cols, int maxthreads,
+             bool full_lines = true) {
   const int J = std::max(P1, P2);
   if (T * J > maxthreads || T * J < 16) return false;
   if (cols > 0 && cols % T != 0) return false;
+  const int full = int(128 / sizeof(cx<R>));
+  if (full_lines && !contig && T < full && (cols <= 0 || cols >= full)) return false;
   const size_t need = contig ? lds_need<R, true>(P1, P2, T) : lds_need<R, false>(P1, P2, T);
   return need <= pl->max_lds;
 }
@@ -180,13 +187,16 @@ bool tile_ok(const vie_plan* pl, int P1, int P2, int T, bool contig, long cols, 
 template <typename R>
 int default_tile(const vie_plan* pl, int P1, int P2, bool contig, int maxthreads, long cols) {
   const int J = std::max(P1, P2);
-  int best = 0;
-  for (int T : kTileChoices) {
-    if (!tile_ok<R>(pl, P1, P2, T, contig, cols, maxthreads)) continue;
-    // prefer ~256 threads per block
-    if (best == 0 || std::abs(T * J - 256) < std::abs(best * J - 256)) best = T;
+  for (int strict = 1; strict >= 0; --strict) {
+    int best = 0;
+    for (int T : kTileChoices) {
+      if (!tile_ok<R>(pl, P1, P2, T, contig, cols, maxthreads, strict != 0)) continue;
+      // prefer ~256 threads per block
+      if (best == 0 || std::abs(T * J - 256) < std::abs(best * J - 256)) best = T;
+    }
+    if (best) return best;
   }
-  return best;
+  return 0;
 }
 
 int bucket_of(int nb) {
@@ -238,7 +248,7 @@ template <typename R>
 hipError_t pass_z(const ApplyCall<R>& c, const cx<R>* tab, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
   const long N = pl->n, P = pl->P;
-  ZArgs a{T, int(P / T), int(N), int(P), pl->nxp, pl->ne, N * P * P, long(pl->C) * N * P * P};
+  ZArgs a{T, int(P / T), int(N), int(P), pl->nxp, pl->ne, N * P * P, long(pl->C) * N * P * P, c.nb};
   const long nblocks = long(P / T) * P * c.nb;
   return c.ops->zpass(pl->full ? MUL_MAX6 : MUL_SYM3, c.B, tab, a, nblocks, c.tw, s);
 }
@@ -295,8 +305,10 @@ int pick_tile(vie_plan* pl, int P1, int P2, bool contig, int maxthreads, F&& run
   HIPCHK(pl, hipEventCreate(&e1));
   float best_ms = 1e30f;
   int best = 0;
+  bool any_full = false;
+  for (int T : kTileChoices) any_full = any_full || tile_ok<R>(pl, P1, P2, T, contig, P1 * P2, maxthreads, true);
   for (int T : kTileChoices) {
-    if (!tile_ok<R>(pl, P1, P2, T, contig, P1 * P2, maxthreads)) continue;
+    if (!tile_ok<R>(pl, P1, P2, T, contig, P1 * P2, maxthreads, any_full)) continue;
     HIPCHK(pl, run(T));  // warm-up
     HIPCHK(pl, hipEventRecord(e0, s));
     for (int r = 0; r < 3; ++r) HIPCHK(pl, run(T));
@@ -329,9 +341,10 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const c128* in, c128* out, hip
   Tune d;
   const int P = P1 * P2;
   d.tx_fwd = default_tile<R>(pl, P1, P2, true, kPassMaxThreads, P);
-  d.tx_inv = default_tile<R>(pl, P1, P2, true, kFusedMaxThreads, P);
+  const int fmax = (sizeof(R) == 8 && pl->C == 6) ? 256 : kFusedMaxThreads;
+  d.tx_inv = default_tile<R>(pl, P1, P2, true, fmax, P);
   d.ty_fwd = d.ty_inv = default_tile<R>(pl, P1, P2, false, kPassMaxThreads, P);
-  d.tz = default_tile<R>(pl, P1, P2, false, kFusedMaxThreads, P);
+  d.tz = default_tile<R>(pl, P1, P2, false, fmax, P);
   if (d.tx_fwd == 0 || d.tz == 0 || d.tx_inv == 0 || d.ty_fwd == 0) return fail(pl, VIE_E_SIZE, "no tile shape fits the LDS limit");
   // measure only where it pays: large grids, unless switched off
   if (pl->n >= 48 && env_flag("VIE_AUTOTUNE", true)) {
@@ -345,15 +358,18 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const c128* in, c128* out, hip
     if (rc) return rc;
     rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, [&](int T) { return pass_yfwd<R>(c, T, s); }, s, &d.ty_fwd);
     if (rc) return rc;
-    rc = pick_tile<R>(pl, P1, P2, false, kFusedMaxThreads, [&](int T) { return pass_z<R>(c, tab, T, s); }, s, &d.tz);
+    rc = pick_tile<R>(pl, P1, P2, false, fmax, [&](int T) { return pass_z<R>(c, tab, T, s); }, s, &d.tz);
     if (rc) return rc;
     rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, [&](int T) { return pass_yinv<R>(c, T, s); }, s, &d.ty_inv);
     if (rc) return rc;
-    rc = pick_tile<R>(pl, P1, P2, true, kFusedMaxThreads,
+    rc = pick_tile<R>(pl, P1, P2, true, fmax,
                       [&](int T) { return pass_xinv<R>(c, in, nullptr, out, MODE_CONV, T, s); }, s, &d.tx_inv);
     if (rc) return rc;
   }
   d.tuned = true;
+  if (env_flag("VIE_DEBUG", false))
+    std::fprintf(stderr, "[vie] tiles P=%d fp%d nb=%d: xfwd %d yfwd %d z %d yinv %d xinv %d\n", pl->P,
+                 int(8 * sizeof(R)), c.nb, d.tx_fwd, d.ty_fwd, d.tz, d.ty_inv, d.tx_inv);
   pl->tune[idx][key] = d;
   *t = d;
   return VIE_OK;

@@ -2,9 +2,12 @@
 //
 // GMRES(m) (named with Bi-CGStab as a suitable unpreconditioned iteration in
 // the Introduction and Discussion) with classical Gram-Schmidt and selective
-// re-orthogonalisation (a second pass only when the first removes more than
-// half of ||w||^2), Givens rotations and the small least-squares solve on the
-// host in FP64.  Bi-CGStab is the solver of Section 5.
+// re-orthogonalisation, Givens rotations and the small least-squares solve on
+// the host in FP64.  A classical pass loses orthogonality roughly like
+// eps (||r_0|| / ||r_j||)^2, so a second pass is made once the cycle's residual
+// estimate has dropped below 1e-6 ||r_0||, or when the first pass cancels all
+// but 1e-4 of ||w||^2.  FP32 inner cycles of the mixed solver stop above that
+// level and run single-pass.  Bi-CGStab is the solver of Section 5.
 //
 // Mixed precision: the outer loop recomputes the true residual
 // r = b - A x with the FP64 apply and solves A d = r with the FP32 apply
@@ -166,7 +169,8 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
   std::vector<std::vector<cd>> sn(static_cast<size_t>(nb), std::vector<cd>(zu(m)));
   std::vector<std::vector<cd>> g(static_cast<size_t>(nb), std::vector<cd>(zu(m + 1)));
   for (int r = 0; r < nb; ++r) g[zu(r)][0] = rnorm[zu(r)];
-  const double eta2 = 0.5;  // re-orthogonalise when ||w'||^2 < 0.5 ||w||^2
+  const double eta2 = 1e-4;   // re-orthogonalise when ||w'||^2 < 1e-4 ||w||^2 ...
+  const double deep = 1e-6;   // ... or once |g_j| < 1e-6 ||r_0||
   std::vector<cd> h1(zu(nb) * zu(m + 1)), h2(zu(nb) * zu(m + 1));
   std::vector<double> w2(static_cast<size_t>(nb)), wp2(zu(nb));
   std::vector<bool> reorth(static_cast<size_t>(nb));
@@ -192,7 +196,8 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
       }
       w2[zu(r)] = red_at(b, r, nv, nv + 1).real();
       wp2[zu(r)] = w2[zu(r)] - p;
-      reorth[zu(r)] = active[zu(r)] && wp2[zu(r)] < eta2 * w2[zu(r)];
+      const bool converged_far = std::abs(g[zu(r)][zu(j)]) < deep * rnorm[zu(r)];
+      reorth[zu(r)] = active[zu(r)] && (wp2[zu(r)] < eta2 * w2[zu(r)] || converged_far);
       any_reorth = any_reorth || reorth[zu(r)];
     }
     std::vector<cd> hcol(zu(nb) * zu(nv + 1));
