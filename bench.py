@@ -50,10 +50,12 @@ def cpu_baseline(n: int, omega: float, matvecs_per_solve: float, budget_s: float
     A.apply(prob.inc[0])
     mv = time.perf_counter() - t0
     solve_s = mv * matvecs_per_solve
-    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one FP64 matvec of the oracle at {n}^3 ({mv:.2f} s, numpy pocketfft, "
-                       f"single thread; table setup {setup:.1f} s excluded) x {matvecs_per_solve:.0f} "
-                       f"matvecs per solve (the GPU FP64 GMRES count)"),
+    from oracle import tables as tb
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": tb.WORKERS, "kind": "oracle",
+            "sample": (f"one FP64 matvec of the oracle at {n}^3 ({mv:.2f} s; scipy.fft with "
+                       f"{tb.WORKERS} workers, the rest single-threaded numpy; table setup {setup:.1f} s "
+                       f"not counted) x {matvecs_per_solve:.1f} matvecs per solve (the GPU FP64 "
+                       f"GMRES count for the same right-hand sides)"),
             "matvec_s": mv, "setup_s": setup}
 
 

@@ -174,7 +174,8 @@ int vie_destroy(vie_plan *pl);
 /* Introspection (host pointers).
  * vie_plan_info: out[0] = n, out[1] = components c, out[2] = P (= 2n),
  * out[3] = oversampled grid M (= 4n), out[4] = max ||H(x)||_2 (Lemma 1),
- * out[5] = table entries, out[6] = device bytes held by the plan. */
+ * out[5] = table entries, out[6] = device bytes held by the plan,
+ * out[7] = applies replayed from captured hipGraphs so far. */
 int vie_plan_info(const vie_plan *pl, double *out, int nout);
 
 /* Copies the FP64 kernel-transform tables into host memory:
@@ -195,6 +196,13 @@ const char *vie_last_error(const vie_plan *pl);
 
 /* Whether n is a supported grid size (1/0). */
 int vie_supported_n(int n);
+
+/* Upper estimate of the device bytes a plan of this size holds at its peak
+ * (the larger of: the kernel-table precompute, or the plan plus apply
+ * workspaces and a Krylov basis of `restart` vectors for batches of
+ * nrhs_batch right-hand sides).  Host-only; -1 on bad arguments.  Used for
+ * admission control by callers that share one GPU among many plans. */
+long vie_footprint_bytes(int kind, int n, int full, int nrhs_batch, int restart);
 
 /* Kernel timing.  vie_profile(pl, 1) starts recording a HIP event pair on the
  * launch stream around every kernel of the apply passes and of the Krylov

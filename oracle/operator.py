@@ -93,7 +93,7 @@ def window_transform(K: np.ndarray) -> np.ndarray:
     idx = np.arange(-(n - 1), n) % P
     Kp = np.zeros((P, P, P), dtype=np.complex128)
     Kp[np.ix_(idx, idx, idx)] = K
-    return np.fft.fftn(Kp)
+    return tb.fftn(Kp)
 
 
 def conv_fft_window_hat(Khat: np.ndarray, f: np.ndarray) -> np.ndarray:
@@ -102,7 +102,7 @@ def conv_fft_window_hat(Khat: np.ndarray, f: np.ndarray) -> np.ndarray:
     P = 2 * n
     fp = np.zeros((P, P, P), dtype=np.complex128)
     fp[:n, :n, :n] = f
-    return np.fft.ifftn(Khat * np.fft.fftn(fp))[:n, :n, :n]
+    return tb.ifftn(Khat * tb.fftn(fp))[:n, :n, :n]
 
 
 def conv_fft_window(K: np.ndarray, f: np.ndarray) -> np.ndarray:
@@ -116,7 +116,7 @@ def conv_fft_mgrid(F: np.ndarray, f: np.ndarray) -> np.ndarray:
     M = F.shape[0]
     fp = np.zeros((M, M, M), dtype=np.complex128)
     fp[:n, :n, :n] = f
-    return np.fft.ifftn(F * np.fft.fftn(fp))[:n, :n, :n]
+    return tb.ifftn(F * tb.fftn(fp))[:n, :n, :n]
 
 
 # ----------------------------------------------------------------------------

@@ -75,25 +75,38 @@ def ghat(s, omega: float, R: float) -> np.ndarray:
     return out
 
 
-def symbol_grad(sx, sy, sz, omega: float, R: float):
-    """Entries (xx, yy, zz, xy, xz, yz) of -s s^T G^ (grad div V)."""
+def _g(sx, sy, sz, omega, R, g):
+    return ghat(np.sqrt(sx * sx + sy * sy + sz * sz), omega, R) if g is None else g
+
+
+def symbol_grad(sx, sy, sz, omega: float, R: float, g=None, entries=None):
+    """Entries (xx, yy, zz, xy, xz, yz) of -s s^T G^ (grad div V).
+
+    g: G^(|s|) when already known; entries: indices of the entries wanted."""
     s = (sx, sy, sz)
-    g = ghat(np.sqrt(sx * sx + sy * sy + sz * sz), omega, R)
-    return [-(s[a] * s[b]) * g for (a, b) in SYM_ENTRIES]
+    g = _g(sx, sy, sz, omega, R, g)
+    idx = range(6) if entries is None else entries
+    return [-(s[SYM_ENTRIES[e][0]] * s[SYM_ENTRIES[e][1]]) * g for e in idx]
 
 
-def symbol_maxwell_D(sx, sy, sz, omega: float, R: float):
+def symbol_maxwell_D(sx, sy, sz, omega: float, R: float, g=None, entries=None):
     """Entries (xx, yy, zz, xy, xz, yz) of (omega^2 I - s s^T) G^."""
     s = (sx, sy, sz)
-    g = ghat(np.sqrt(sx * sx + sy * sy + sz * sz), omega, R)
-    return [((omega * omega if a == b else 0.0) - s[a] * s[b]) * g for (a, b) in SYM_ENTRIES]
+    g = _g(sx, sy, sz, omega, R, g)
+    idx = range(6) if entries is None else entries
+    out = []
+    for e in idx:
+        a, b = SYM_ENTRIES[e]
+        out.append(((omega * omega if a == b else 0.0) - s[a] * s[b]) * g)
+    return out
 
 
-def symbol_curl(sx, sy, sz, omega: float, R: float):
+def symbol_curl(sx, sy, sz, omega: float, R: float, g=None, entries=None):
     """The vector i s_b G^ (b = x, y, z): curl V m has symbol (i s G^) x m."""
     s = (sx, sy, sz)
-    g = ghat(np.sqrt(sx * sx + sy * sy + sz * sz), omega, R)
-    return [1j * s[b] * g for b in range(3)]
+    g = _g(sx, sy, sz, omega, R, g)
+    idx = range(3) if entries is None else entries
+    return [1j * s[b] * g for b in idx]
 
 
 def symbol_set(kind: str):

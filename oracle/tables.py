@@ -27,10 +27,23 @@ from __future__ import annotations
 
 import itertools
 import math
+import os
 
 import numpy as np
+import scipy.fft
 
 from . import symbol as sym
+
+# scipy's pocketfft with every host core the process may use (capped at 16)
+WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def fftn(a):
+    return scipy.fft.fftn(a, workers=WORKERS)
+
+
+def ifftn(a):
+    return scipy.fft.ifftn(a, workers=WORKERS)
 
 
 def default_R(n: int, h: float) -> float:
@@ -46,37 +59,48 @@ def freq_integers(M: int) -> np.ndarray:
     return np.fft.fftfreq(M, d=1.0 / M).round().astype(np.int64)
 
 
-def sampled_symbol(kind: str, n: int, h: float, omega: float, R: float = None, M: int = None):
+def sampled_symbol(kind: str, n: int, h: float, omega: float, R: float = None, M: int = None,
+                   entries=None):
     """Samples of the symbol entries on the M^3 frequency grid, Nyquist planes averaged.
 
-    Returns a list of complex arrays [M][M][M] in FFT order.
+    Returns a list of complex arrays [M][M][M] in FFT order (only the listed
+    entries when ``entries`` is given).
     """
+    return list(iter_sampled_symbol(kind, n, h, omega, R, M, entries))
+
+
+def iter_sampled_symbol(kind: str, n: int, h: float, omega: float, R: float = None, M: int = None,
+                        entries=None):
+    """Yields the sampled entries one at a time; G^(|s|) is evaluated once."""
     R = default_R(n, h) if R is None else R
     M = default_M(n) if M is None else M
     fn = sym.symbol_set(kind)
+    nent = 3 if kind == "curl" else 6
+    entries = list(range(nent)) if entries is None else list(entries)
     k = freq_integers(M)
     s1 = 2.0 * math.pi * k / (M * h)
     nyq1 = k == -(M // 2)
     SZ, SY, SX = np.meshgrid(s1, s1, s1, indexing="ij")
+    g = sym.ghat(np.sqrt(SX * SX + SY * SY + SZ * SZ), omega, R)
     NZ, NY, NX = np.meshgrid(nyq1, nyq1, nyq1, indexing="ij")
     nyq = (NX, NY, NZ)
-    count = NX.astype(np.int64) + NY + NZ
-    out = [np.array(e, dtype=np.complex128) for e in fn(SX, SY, SZ, omega, R)]
+    scale = 1.0 / (2.0 ** (NX.astype(np.int64) + NY + NZ))
+    # points on Nyquist planes, and the symbol there at every sign choice of those axes
+    flips = []
     for r in (1, 2, 3):
         for T in itertools.combinations(range(3), r):
             mask = np.logical_and.reduce([nyq[a] for a in T])
-            if not mask.any():
-                continue
-            comp = [SX[mask].copy(), SY[mask].copy(), SZ[mask].copy()]
-            for a in T:
-                comp[a] = -comp[a]          # -pi/h -> +pi/h
-            vals = fn(comp[0], comp[1], comp[2], omega, R)
-            for e in range(len(out)):
-                out[e][mask] += vals[e]
-    scale = 1.0 / (2.0 ** count)
-    for e in range(len(out)):
-        out[e] *= scale
-    return out
+            if mask.any():
+                comp = [SX[mask].copy(), SY[mask].copy(), SZ[mask].copy()]
+                for a in T:
+                    comp[a] = -comp[a]          # -pi/h -> +pi/h
+                flips.append((mask, comp))
+    for e in entries:
+        F = np.array(fn(SX, SY, SZ, omega, R, g=g, entries=[e])[0], dtype=np.complex128)
+        for mask, comp in flips:
+            F[mask] += fn(comp[0], comp[1], comp[2], omega, R, entries=[e])[0]
+        F *= scale
+        yield F
 
 
 def window_indices(n: int, M: int) -> np.ndarray:
@@ -89,12 +113,13 @@ def kernel_tables(kind: str, n: int, h: float, omega: float, R: float = None, M:
     Returns a list of arrays [(2n-1)]^3 indexed by m + n - 1 (axes z, y, x).
     """
     M = default_M(n) if M is None else M
-    samples = sampled_symbol(kind, n, h, omega, R, M)
     idx = window_indices(n, M)
     tabs = []
-    for F in samples:
-        K = np.fft.ifftn(F)              # M^{-3} sum_k F_k exp(+2 pi i k m / M)
+    for F in iter_sampled_symbol(kind, n, h, omega, R, M):   # one M^3 entry at a time
+        K = ifftn(F)                     # M^{-3} sum_k F_k exp(+2 pi i k m / M)
+        del F
         tabs.append(np.ascontiguousarray(K[np.ix_(idx, idx, idx)]))
+        del K
     return tabs
 
 

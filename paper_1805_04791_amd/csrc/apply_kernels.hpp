@@ -146,6 +146,8 @@ struct XArgs {
   long nrows;       // nrhs * n * n
   int n;            // grid points per axis
   long n3;          // n^3
+  int nb;           // right-hand sides in the launch
+  int xcd_order;    // 1: row tiles of all right-hand sides back-to-back per XCD
 };
 
 // Rows (rhs, z, y): inverse x transform of every component, then the pointwise
@@ -165,10 +167,19 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
   load_twiddles<R, P>(tw, twg);
   int col, j;
   Layout<true>::lane(threadIdx.x, a.T, J, col, j);
-  const long row = long(blockIdx.x) * a.T + col;
-  const bool valid = row < a.nrows;
   const int N = a.n;
   const long NN = long(N) * N;
+  // xcd_order: block b runs on XCD b % 8; the nb right-hand sides of one
+  // (z, y) row tile share H, so they take consecutive slots on one XCD
+  long tile_id = blockIdx.x;
+  if (a.xcd_order) {
+    const unsigned xcd = blockIdx.x % 8u, k = blockIdx.x / 8u;
+    const long slice = long(k / unsigned(a.nb)) * 8 + xcd;
+    const long r = long(k % unsigned(a.nb));
+    tile_id = r * (NN / a.T) + slice;
+  }
+  const long row = tile_id * a.T + col;
+  const bool valid = row < a.nrows;
   const long rhs = valid ? row / NN : 0;
   const long zy = valid ? row % NN : 0;
 

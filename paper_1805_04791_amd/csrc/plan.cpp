@@ -267,7 +267,9 @@ template <typename R>
 hipError_t pass_xinv(const ApplyCall<R>& c, const c128* addv, const c128* bvec, c128* out, int mode, int T,
                      hipStream_t s) {
   const vie_plan* pl = c.pl;
-  XArgs a{T, long(c.nb) * pl->n * pl->n, pl->n, pl->n3};
+  const long NN = long(pl->n) * pl->n;
+  const int xcd = (NN % T == 0) && ((NN / T) % 8 == 0) ? 1 : 0;
+  XArgs a{T, long(c.nb) * NN, pl->n, pl->n3, c.nb, xcd};
   const cx<R>* H;
   const cx<R>* Hmu;
   if constexpr (std::is_same<R, float>::value) {
@@ -284,6 +286,7 @@ template <typename R>
 int ensure_workspace(vie_plan* pl, int nb) {
   const int idx = std::is_same<R, double>::value ? 1 : 0;
   if (pl->ws_cap[idx] >= nb) return VIE_OK;
+  clear_graphs(pl);  // captured applies hold the old workspace pointers
   dev_free(pl, pl->wsA[idx]);
   dev_free(pl, pl->wsB[idx]);
   pl->wsA[idx] = pl->wsB[idx] = nullptr;
@@ -534,6 +537,52 @@ int apply_any(vie_plan* pl, bool fp64, const c128* in, const c128* addv, const c
               : apply_typed<float>(pl, in, addv, bvec, out, nrhs, mode, s);
 }
 
+void clear_graphs(vie_plan* pl) {
+  for (auto& kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+  pl->graphs.clear();
+}
+
+int apply_graph(vie_plan* pl, bool fp64, const c128* in, const c128* addv, const c128* bvec, c128* out, int nrhs,
+                int mode, hipStream_t s) {
+  const int idx = fp64 ? 1 : 0;
+  // eager when capture is off, while timing kernels, for chunked batches, or
+  // before the first apply of this batch size (tiling and workspace set up)
+  if (!pl->use_graphs || pl->prof_on || nrhs > pl->max_rhs || pl->ws_cap[idx] < nrhs ||
+      pl->tune[idx].find(bucket_of(nrhs)) == pl->tune[idx].end())
+    return apply_any(pl, fp64, in, addv, bvec, out, nrhs, mode, s);
+  if (!pl->gstream) {
+    HIPCHK(pl, hipStreamCreateWithFlags(&pl->gstream, hipStreamNonBlocking));
+    HIPCHK(pl, hipEventCreateWithFlags(&pl->gev_in, hipEventDisableTiming));
+    HIPCHK(pl, hipEventCreateWithFlags(&pl->gev_out, hipEventDisableTiming));
+  }
+  vie_plan::GraphKey key{idx, mode, nrhs, in, addv, bvec, out};
+  auto it = pl->graphs.find(key);
+  if (it == pl->graphs.end()) {
+    if (pl->graphs.size() >= 512) clear_graphs(pl);
+    hipGraph_t g = nullptr;
+    HIPCHK(pl, hipStreamBeginCapture(pl->gstream, hipStreamCaptureModeRelaxed));
+    const int rc = apply_any(pl, fp64, in, addv, bvec, out, nrhs, mode, pl->gstream);
+    const hipError_t ec = hipStreamEndCapture(pl->gstream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ec != hipSuccess) return hip_fail(pl, ec, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return hip_fail(pl, ei, "hipGraphInstantiate");
+    it = pl->graphs.emplace(key, ex).first;
+  }
+  HIPCHK(pl, hipEventRecord(pl->gev_in, s));
+  HIPCHK(pl, hipStreamWaitEvent(pl->gstream, pl->gev_in, 0));
+  HIPCHK(pl, hipGraphLaunch(it->second, pl->gstream));
+  HIPCHK(pl, hipEventRecord(pl->gev_out, pl->gstream));
+  HIPCHK(pl, hipStreamWaitEvent(s, pl->gev_out, 0));
+  pl->graph_launches++;
+  return VIE_OK;
+}
+
 }  // namespace vie
 
 namespace {
@@ -548,6 +597,11 @@ bool n_supported(int n) {
 
 void destroy_plan(vie_plan* pl) {
   if (!pl) return;
+  vie::clear_graphs(pl);
+  if (pl->gstream) (void)hipStreamSynchronize(pl->gstream);
+  if (pl->gev_in) (void)hipEventDestroy(pl->gev_in);
+  if (pl->gev_out) (void)hipEventDestroy(pl->gev_out);
+  if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
   for (auto& r : pl->prof) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -588,6 +642,7 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   pl->max_rhs = p->max_rhs;
   pl->flags = p->flags;
   pl->n3 = long(p->n) * p->n * p->n;
+  pl->use_graphs = env_flag("VIE_GRAPHS", true);
   HIPCHK(pl, hipGetDevice(&pl->device));
   {
     hipDeviceProp_t prop;
@@ -713,9 +768,9 @@ int vie_field(vie_plan* pl, const double* density, const double* inc, double* fi
 
 int vie_plan_info(const vie_plan* pl, double* out, int nout) {
   if (!pl || !out) return VIE_E_ARG;
-  const double v[7] = {double(pl->n),  double(pl->C),  double(pl->P),        double(pl->M),
-                       pl->hmax,       double(pl->ne), double(pl->dev_bytes)};
-  for (int i = 0; i < nout && i < 7; ++i) out[i] = v[i];
+  const double v[8] = {double(pl->n),  double(pl->C),  double(pl->P),         double(pl->M),
+                       pl->hmax,       double(pl->ne), double(pl->dev_bytes), double(pl->graph_launches)};
+  for (int i = 0; i < nout && i < 8; ++i) out[i] = v[i];
   return VIE_OK;
 }
 
@@ -759,6 +814,24 @@ const char* vie_status_string(int status) {
 const char* vie_last_error(const vie_plan* pl) { return pl ? pl->err.c_str() : vie::last_create_error().c_str(); }
 
 int vie_supported_n(int n) { return n_supported(n) ? 1 : 0; }
+
+long vie_footprint_bytes(int kind, int n, int full, int nrhs_batch, int restart) {
+  if (n <= 0 || nrhs_batch < 1 || restart < 1) return -1;
+  const double n3 = double(n) * n * n, P = 2.0 * n, M = 4.0 * n;
+  const double C = full ? 6 : 3, ne = full ? 9 : 6;
+  const double nxp = double(((n + 1 + 15) / 16) * 16);
+  (void)kind;
+  double b = 0;
+  b += (full ? 2 : 1) * 9 * n3 * (16 + 8);                       // H in FP64 and FP32
+  b += double(n + 1) * (n + 1) * ne * nxp * (16 + 8);            // octant tables
+  const double precompute = (M * M * P + M * P * P + ne * P * P * P) * 16 + 9 * n3 * 16;
+  const double nb = nrhs_batch;
+  const double ws = nb * C * (double(n) * n * P + double(n) * P * P);  // apply workspace elements
+  b += ws * (8 + 16);                                             // FP32 and FP64 workspaces
+  const double L = C * n3;
+  b += (double(restart) + 1 + 4) * nb * L * 16;                   // Krylov basis + x, b, r, w
+  return long(std::max(b, precompute + b - ws * 24 - (double(restart) + 5) * nb * L * 16));
+}
 
 int vie_profile(vie_plan* pl, int enable) {
   if (!pl) return VIE_E_ARG;

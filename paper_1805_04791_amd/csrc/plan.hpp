@@ -65,6 +65,25 @@ struct vie_plan {
   std::vector<std::pair<void*, size_t>> allocs;
   std::string err;
 
+  // captured applies: key (fp64, mode, nb, in, addv, bvec, out) -> graph
+  struct GraphKey {
+    int fp64, mode, nb;
+    const void *in, *addv, *bvec, *out;
+    bool operator<(const GraphKey& o) const {
+      return std::tie(fp64, mode, nb, in, addv, bvec, out) < std::tie(o.fp64, o.mode, o.nb, o.in, o.addv, o.bvec, o.out);
+    }
+  };
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  hipStream_t gstream = nullptr;
+  hipEvent_t gev_in = nullptr, gev_out = nullptr;
+  bool use_graphs = true;
+  long graph_launches = 0;
+
+  // pinned staging slots of the basis coefficients (two, used alternately)
+  long sync_count = 0;
+  long stage_epoch[2] = {-1, -1};
+  int stage_next = 0;
+
   // kernel timing with HIP events (vie_profile)
   struct ProfRec {
     int fam;
@@ -100,6 +119,11 @@ int hip_fail(vie_plan* pl, hipError_t e, const char* what);
 // field); bvec: b of MODE_RESIDUAL.
 int apply_any(vie_plan* pl, bool fp64, const c128* in, const c128* addv, const c128* bvec, c128* out, int nrhs,
               int mode, hipStream_t s);
+// the same through a captured hipGraph replayed on the plan's stream (solver
+// calls with stable pointers); falls back to apply_any when capture is off
+int apply_graph(vie_plan* pl, bool fp64, const c128* in, const c128* addv, const c128* bvec, c128* out, int nrhs,
+                int mode, hipStream_t s);
+void clear_graphs(vie_plan* pl);
 
 // kernel families timed by vie_profile
 enum {

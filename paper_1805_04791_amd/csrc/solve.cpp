@@ -44,6 +44,7 @@ struct RhsState {
 
 int ensure_krylov(vie_plan* pl, int cap, int m) {
   if (pl->kr_cap >= cap && pl->kr_m >= m) return VIE_OK;
+  HIPCHK(pl, hipDeviceSynchronize());  // pending copies may still read the old staging buffers
   cap = std::max(cap, pl->kr_cap);
   m = std::max(m, pl->kr_m);
   dev_free(pl, pl->V);
@@ -73,12 +74,13 @@ int ensure_krylov(vie_plan* pl, int cap, int m) {
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->ww), vec);
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->partials), sizeof(c128) * zu(cap) * nblk * zu(m + 2));
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->red), sizeof(c128) * zu(cap) * zu(m + 2));
-  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->coefd), sizeof(c128) * zu(cap) * zu(m + 2));
-  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->scaled), sizeof(double) * zu(cap));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->coefd), 2 * sizeof(c128) * zu(cap) * zu(m + 2));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->scaled), 2 * sizeof(double) * zu(cap));
   if (rc) return rc;
   HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->red_host), sizeof(c128) * zu(cap) * zu(m + 2)));
-  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->coef_host), sizeof(c128) * zu(cap) * zu(m + 2)));
-  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->scale_host), sizeof(double) * zu(cap)));
+  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->coef_host), 2 * sizeof(c128) * zu(cap) * zu(m + 2)));
+  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->scale_host), 2 * sizeof(double) * zu(cap)));
+  pl->stage_epoch[0] = pl->stage_epoch[1] = -1;
   pl->kr_cap = cap;
   pl->kr_m = m;
   return VIE_OK;
@@ -106,6 +108,7 @@ int dots_host(const Batch& b, const c128* V, const c128* w, int nv) {
   HIPCHK(pl, hipMemcpyAsync(pl->red_host, pl->red, sizeof(c128) * zu(b.nb) * zu(nv + 1),
                             hipMemcpyDeviceToHost, b.s));
   HIPCHK(pl, hipStreamSynchronize(b.s));
+  pl->sync_count++;
   return VIE_OK;
 }
 
@@ -119,21 +122,32 @@ int combine_host(const Batch& b, const c128* V, const c128* w, c128* out, int nv
                  const std::vector<double>& scale) {
   vie_plan* pl = b.pl;
   const int stride = std::max(nv, 1);
+  // two staging slots used alternately; a slot is rewritten only after the
+  // stream has been synchronised since its copies were queued
+  const int slot = pl->stage_next;
+  pl->stage_next ^= 1;
+  if (pl->stage_epoch[slot] == pl->sync_count) {
+    HIPCHK(pl, hipStreamSynchronize(b.s));
+    pl->sync_count++;
+  }
+  pl->stage_epoch[slot] = pl->sync_count;
+  const size_t half_c = zu(pl->kr_cap) * zu(pl->kr_m + 2);
+  c128* ch = pl->coef_host + zu(slot) * half_c;
+  double* sh = pl->scale_host + zu(slot) * zu(pl->kr_cap);
+  c128* cdv = pl->coefd + zu(slot) * half_c;
+  double* sdv = pl->scaled + zu(slot) * zu(pl->kr_cap);
   for (int r = 0; r < b.nb; ++r) {
     for (int i = 0; i < stride; ++i) {
       const cd c = i < nv ? coef[zu(r) * zu(nv) + zu(i)] : cd(0.0, 0.0);
-      pl->coef_host[zu(r) * zu(stride) + zu(i)] = {c.real(), c.imag()};
+      ch[zu(r) * zu(stride) + zu(i)] = {c.real(), c.imag()};
     }
-    pl->scale_host[r] = scale[zu(r)];
+    sh[r] = scale[zu(r)];
   }
-  HIPCHK(pl, hipMemcpyAsync(pl->coefd, pl->coef_host, sizeof(c128) * zu(b.nb) * zu(stride),
-                            hipMemcpyHostToDevice, b.s));
-  HIPCHK(pl, hipMemcpyAsync(pl->scaled, pl->scale_host, sizeof(double) * zu(b.nb), hipMemcpyHostToDevice, b.s));
+  HIPCHK(pl, hipMemcpyAsync(cdv, ch, sizeof(c128) * zu(b.nb) * zu(stride), hipMemcpyHostToDevice, b.s));
+  HIPCHK(pl, hipMemcpyAsync(sdv, sh, sizeof(double) * zu(b.nb), hipMemcpyHostToDevice, b.s));
   const int tok = prof_begin(pl, b.s);
-  HIPCHK(pl, launch_combine(V, b.vs, b.L, w, out, b.L, nv, pl->coefd, pl->scaled, b.nb, b.s));
+  HIPCHK(pl, launch_combine(V, b.vs, b.L, w, out, b.L, nv, cdv, sdv, b.nb, b.s));
   prof_end(pl, FAM_COMBINE, tok, b.s, double(nv + 2) * b.nb * double(b.L) * sizeof(c128));
-  // the pinned staging buffers are reused by the next call: wait for the copies
-  HIPCHK(pl, hipStreamSynchronize(b.s));
   return VIE_OK;
 }
 
@@ -181,7 +195,7 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
     if (!any) break;
     const c128* Vj = pl->V + long(j) * b.vs;
     c128* Vn = pl->V + long(j + 1) * b.vs;
-    rc = apply_any(pl, fp64, Vj, Vj, nullptr, pl->ww, nb, MODE_MATVEC, b.s);
+    rc = apply_graph(pl, fp64, Vj, Vj, nullptr, pl->ww, nb, MODE_MATVEC, b.s);
     if (rc) return rc;
     const int nv = j + 1;
     rc = dots_host(b, pl->V, pl->ww, nv);
@@ -347,7 +361,7 @@ int bicgstab_run(const Batch& b, bool fp64, const std::vector<double>& rnorm0, c
     for (int r = 0; r < nb; ++r) sc[zu(r)] = active[zu(r)] ? 1.0 : 0.0;
     rc = combine_host(b, v, pl->rw, p, 2, cP, sc);
     if (rc) return rc;
-    rc = apply_any(pl, fp64, p, p, nullptr, v, nb, MODE_MATVEC, b.s);
+    rc = apply_graph(pl, fp64, p, p, nullptr, v, nb, MODE_MATVEC, b.s);
     if (rc) return rc;
     rc = dots_host(b, rhat, v, 1);
     if (rc) return rc;
@@ -360,7 +374,7 @@ int bicgstab_run(const Batch& b, bool fp64, const std::vector<double>& rnorm0, c
     }
     rc = combine_host(b, v, pl->rw, sv, 1, cS, sc);  // s = r - alpha v
     if (rc) return rc;
-    rc = apply_any(pl, fp64, sv, sv, nullptr, t, nb, MODE_MATVEC, b.s);
+    rc = apply_graph(pl, fp64, sv, sv, nullptr, t, nb, MODE_MATVEC, b.s);
     if (rc) return rc;
     rc = dots_host(b, sv, t, 1);  // conj(s).t and ||t||^2
     if (rc) return rc;
@@ -496,7 +510,7 @@ int solve_batch(vie_plan* pl, const c128* inc, c128* density, c128* field, int n
         rc = gmres_cycle(b, !mixed, m, rnorm, target, st, active, budget);
       if (rc) return rc;
       // true residual with the FP64 operator
-      rc = apply_any(pl, true, pl->xw, pl->xw, pl->bw, pl->rw, nb, MODE_RESIDUAL, s);
+      rc = apply_graph(pl, true, pl->xw, pl->xw, pl->bw, pl->rw, nb, MODE_RESIDUAL, s);
       if (rc) return rc;
       rc = norms(b, pl->rw, rnorm);
       if (rc) return rc;

@@ -56,7 +56,8 @@ class SolveStats(ctypes.Structure):
 
 EXPORTS = ["vie_plan_create", "vie_apply", "vie_rhs", "vie_field", "vie_solve", "vie_destroy",
            "vie_plan_info", "vie_copy_tables", "vie_copy_contrast", "vie_status_string",
-           "vie_last_error", "vie_supported_n", "vie_profile", "vie_profile_read", "vie_profile_family"]
+           "vie_last_error", "vie_supported_n", "vie_profile", "vie_profile_read", "vie_profile_family",
+           "vie_footprint_bytes"]
 
 _lib = None
 
@@ -90,6 +91,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                    ctypes.POINTER(cd), ci]
     L.vie_profile_family.argtypes = [ci]
     L.vie_profile_family.restype = ctypes.c_char_p
+    L.vie_footprint_bytes.argtypes = [ci, ci, ci, ci, ci]
+    L.vie_footprint_bytes.restype = ctypes.c_long
     for name in ("vie_plan_create", "vie_apply", "vie_rhs", "vie_field", "vie_solve", "vie_destroy",
                  "vie_plan_info", "vie_copy_tables", "vie_copy_contrast", "vie_supported_n",
                  "vie_profile", "vie_profile_read"):
@@ -121,6 +124,12 @@ def _device_c128(x, device):
 
 def supported_n(n: int) -> bool:
     return bool(load_library().vie_supported_n(int(n)))
+
+
+def footprint_bytes(kind: int, n: int, full: bool, nrhs_batch: int, restart: int) -> int:
+    """Peak device bytes of a plan of this size (host-only estimate)."""
+    return int(load_library().vie_footprint_bytes(int(kind), int(n), 1 if full else 0, int(nrhs_batch),
+                                                  int(restart)))
 
 
 class Plan:
@@ -228,9 +237,9 @@ class Plan:
         return dens, fld, [s.as_dict() for s in st], rc
 
     def info(self) -> dict:
-        out = (ctypes.c_double * 7)()
-        self._check(self.lib.vie_plan_info(self._h, out, 7), "vie_plan_info")
-        keys = ["n", "ncomp", "P", "M", "max_contrast_norm", "table_entries", "device_bytes"]
+        out = (ctypes.c_double * 8)()
+        self._check(self.lib.vie_plan_info(self._h, out, 8), "vie_plan_info")
+        keys = ["n", "ncomp", "P", "M", "max_contrast_norm", "table_entries", "device_bytes", "graph_launches"]
         return dict(zip(keys, list(out)))
 
     def tables(self) -> np.ndarray:

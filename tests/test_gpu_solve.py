@@ -139,3 +139,27 @@ def test_resume_from_x0_and_noconv(vie):
     d2, _, st2, rc2 = plan.solve(inc, tol=1e-12, x0=d1, want_field=False)
     assert rc2 == vie.OK and st2[0]["rel_residual"] <= 1e-12
     plan.close()
+
+
+def test_graph_replay_equals_eager(vie, monkeypatch):
+    """Solver applies replayed from captured hipGraphs give bitwise the eager
+    results, over several solves (replays) with eager work in between."""
+    n = 24
+    coef, mu, omega = medium(op.KIND_HELMHOLTZ, n, 7)
+    inc = incident(op.KIND_HELMHOLTZ, n, omega, 3, False, item=40)
+    monkeypatch.setenv("VIE_GRAPHS", "0")
+    eager = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
+    monkeypatch.setenv("VIE_GRAPHS", "1")
+    graph = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
+    ref, _, _, _ = eager.solve(inc, tol=1e-10, want_field=False)
+    ref = ref.cpu().numpy()
+    for rep in range(3):
+        d, _, st, rc = graph.solve(inc, tol=1e-10, want_field=False)
+        assert rc == vie.OK
+        assert np.array_equal(d.cpu().numpy(), ref)
+        x = gen.random_density((1, 3, n, n, n), gen.rng_for(gen.CONFIG_IDS["test"], 50 + rep))
+        graph.apply(x, vie.APPLY_FP32)          # eager work between replays
+    assert graph.info()["graph_launches"] > 0
+    assert eager.info()["graph_launches"] == 0
+    eager.close()
+    graph.close()

@@ -1,0 +1,107 @@
+"""Serving loop: admission by footprint (CPU) and results alone == in the mix (GPU)."""
+
+import threading
+
+import numpy as np
+import pytest
+
+from paper_1805_04791_amd.serving import Admission, PlanCache, Request
+
+
+def test_admission_never_overcommits():
+    adm = Admission(100)
+    sizes = [30, 50, 40, 20, 60, 10, 90, 5]
+    inflight = []
+    peak = [0]
+    lock = threading.Lock()
+
+    def run(sz):
+        with adm.lock:
+            while not adm.fits(sz):
+                adm.lock.wait()
+            adm.take(sz)
+        with lock:
+            inflight.append(sz)
+            peak[0] = max(peak[0], sum(inflight))
+        with lock:
+            inflight.remove(sz)
+        adm.give(sz)
+
+    ts = [threading.Thread(target=run, args=(s,)) for s in sizes]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert adm.used == 0
+    assert adm.peak <= 100 and peak[0] <= 100
+
+
+def test_admission_admits_oversized_request_alone():
+    adm = Admission(100)
+    assert adm.fits(150)          # an empty device takes anything
+    adm.take(150)
+    assert not adm.fits(1)
+    adm.give(150)
+    assert adm.fits(1)
+
+
+def test_plan_cache_lru_and_checkout():
+    closed = []
+
+    class P:
+        def __init__(self, k):
+            self.k = k
+
+        def close(self):
+            closed.append(self.k)
+
+    c = PlanCache(2)
+    for k in "abc":
+        c.put(k, P(k))
+    assert closed == ["a"]
+    p = c.get("b")
+    assert p.k == "b" and c.get("b") is None     # checked out: not shared
+    c.put("b", p)
+    assert c.hits == 1 and c.misses == 1
+
+
+def test_request_key_from_medium():
+    coef = np.zeros((9, 4, 4, 4), dtype=np.complex128)
+    a = Request(0, 1, 4, 2.0, 1, coef=coef, inc=np.zeros((1, 3, 4, 4, 4), complex)).materialise()
+    b = Request(1, 1, 4, 2.0, 1, coef=coef.copy(), inc=np.zeros((1, 3, 4, 4, 4), complex)).materialise()
+    coef2 = coef.copy()
+    coef2[0, 0, 0, 0] = 1
+    c = Request(2, 1, 4, 2.0, 1, coef=coef2, inc=np.zeros((1, 3, 4, 4, 4), complex)).materialise()
+    assert a.key == b.key != c.key
+
+
+@pytest.mark.gpu
+def test_results_alone_equal_results_in_the_mix():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_04791_amd.serving import Server, requests_from_generator
+    reqs = requests_from_generator(10, rate=1e6, grids=(16, 24, 32), max_rhs=4)
+    # two requests share a medium (and so a plan) to exercise merged batches
+    dup = requests_from_generator(1, rate=1e6, grids=(16, 24, 32), max_rhs=4)[0]
+    dup.id, dup.key, dup.make = 99, reqs[0].key, reqs[0].make
+    dup.kind, dup.n, dup.omega, dup.nrhs = reqs[0].kind, reqs[0].n, reqs[0].omega, reqs[0].nrhs
+    alone = {}
+    for r in reqs:
+        srv = Server(workers=1)
+        res = srv.run(lambda r=r: [Request(r.id, r.kind, r.n, r.omega, r.nrhs, key=r.key, make=r.make)],
+                      realtime=False)
+        assert not srv.errors, srv.errors
+        alone[r.id] = res[0].density
+    srv = Server(workers=3)
+    mix = srv.run(lambda: [Request(r.id, r.kind, r.n, r.omega, r.nrhs, key=r.key, make=r.make)
+                           for r in reqs + [dup]], realtime=False)
+    assert not srv.errors, srv.errors
+    assert len(mix) == len(reqs) + 1
+    for res in mix:
+        ref = alone[0 if res.id == 99 else res.id]
+        err = np.linalg.norm(res.density - ref) / np.linalg.norm(ref)
+        assert err <= 1e-8, (res.id, err)
+        assert all(s["status"] == 0 and s["rel_residual"] <= 1e-9 for s in res.stats)
+    s = srv.summary(mix)
+    assert s["max_inflight"] >= 1 and s["rhs_converged"] == s["rhs_solved"]
