@@ -75,6 +75,11 @@ typedef enum {
 /* vie_problem.flags */
 #define VIE_PTR_HOST 0x1u        /* coef / mu are host pointers (default: device pointers) */
 #define VIE_STRICT_MEDIUM 0x2u   /* fail with VIE_E_MEDIUM when max ||H(x)||_2 >= 1 (Lemma 1) */
+#define VIE_NO_GRAPHS 0x4u       /* never replay solver applies from captured hipGraphs.  Capture
+                                    (on by default; VIE_GRAPHS=0 in the environment also turns it
+                                    off) forbids, in every thread of the process, HIP calls that
+                                    allocate, free or synchronise the device; hosts whose other
+                                    threads make such calls while a plan solves set this flag. */
 
 /*
  * The problem statement of the paper (Introduction and Section 5): a grid,
@@ -163,19 +168,29 @@ int vie_field(vie_plan *pl, const double *density, const double *inc, double *fi
  * (tol 1e-10, restart 40, max_iters 2000, GMRES).  stats may be NULL, else an
  * array of nrhs entries.  Right-hand sides are solved together in fused
  * launches; each keeps its own convergence test, so its result does not
- * depend on the others in the batch.  Returns VIE_OK, VIE_W_NOCONV (the
- * best iterate is written) or an error. */
+ * depend on the others in the batch.  The unknowns are the points of the
+ * bounding box of supp(H) (vie_plan_info): the integral equation forces
+ * J = 0 where H = 0, and density is written as exactly 0 there; with
+ * VIE_SOLVE_X0 only the box part of the initial density is used.  Returns
+ * VIE_OK, VIE_W_NOCONV (the best iterate is written) or an error. */
 int vie_solve(vie_plan *pl, const double *inc, double *density, double *field, int nrhs,
               const vie_solve_opts *opts, vie_solve_stats *stats, void *hip_stream);
 
-/* Frees the plan and all its device memory.  vie_destroy(NULL) is a no-op. */
+/* Synchronises the stream of the plan's latest call, then frees the plan and
+ * all its device memory.  Work on other streams that uses the plan must have
+ * completed.  vie_destroy(NULL) is a no-op. */
 int vie_destroy(vie_plan *pl);
 
 /* Introspection (host pointers).
  * vie_plan_info: out[0] = n, out[1] = components c, out[2] = P (= 2n),
  * out[3] = oversampled grid M (= 4n), out[4] = max ||H(x)||_2 (Lemma 1),
  * out[5] = table entries, out[6] = device bytes held by the plan,
- * out[7] = applies replayed from captured hipGraphs so far. */
+ * out[7] = applies replayed from captured hipGraphs so far,
+ * out[8..10] = corner (x0, y0, z0) and out[11..13] = extent (bx, by, bz) of
+ * the box the solver works on: the bounding box of the points where H (or
+ * H_mu) is non-zero, outside which the density vanishes (a single point if
+ * H = 0 everywhere; the whole grid when VIE_BOX=0 is set in the
+ * environment at plan creation). */
 int vie_plan_info(const vie_plan *pl, double *out, int nout);
 
 /* Copies the FP64 kernel-transform tables into host memory:

@@ -31,13 +31,14 @@ enum { MODE_MATVEC = 0, MODE_FIELD = 1, MODE_CONV = 2, MODE_RESIDUAL = 3 };
 struct ZArgs {
   int T;            // kx columns per block
   int ntiles;       // P / T
-  int n;            // grid points per axis
+  int n;            // grid points per axis (the tables' octant is [0, n])
   int P;            // 2n
   int nxp;          // padded octant row length (>= n + 1)
   int ne;           // table entries (6 or 9)
   long comp_stride; // n * P * P
   long rhs_stride;  // C * n * P * P
   int nb;           // right-hand sides in the launch
+  int nz;           // z extent of the data (n, or the support box): inputs z < nz, outputs z < nz
 };
 
 // Block order: blocks are dealt round-robin to the 8 XCDs (block b runs on
@@ -76,7 +77,8 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
   auto load_comp = [&](int c, cx<R>(&dst)[H1]) {
     const cx<R>* src = base + c * a.comp_stride;
     static_for<0, H1>([&](auto n1) {
-      dst[n1] = (valid && j < P2) ? src[long(P2 * n1 + j) * PP] : czero<R>();
+      const int z = P2 * n1 + j;
+      dst[n1] = (valid && j < P2 && z < a.nz) ? src[long(z) * PP] : czero<R>();
     });
   };
   if constexpr (kUpfront) static_for<0, C>([&](auto c) { load_comp(c, in[c]); });
@@ -137,21 +139,25 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
   static_for<0, C>([&](auto c) {
     cx<R>* dst = base + c * a.comp_stride;
     fft_inv_CD<R, P1, P2, false>(
-        X[c], [&](auto, int z, cx<R> v) { dst[long(z) * PP] = v; }, a.n, lds, twr, col, j, a.T, valid);
+        X[c], [&](auto, int z, cx<R> v) { dst[long(z) * PP] = v; }, a.nz, lds, twr, col, j, a.T, valid);
   });
 }
 
 struct XArgs {
   int T;            // rows per block
-  long nrows;       // nrhs * n * n
-  int n;            // grid points per axis
+  long nrows;       // nrhs * bz * by
+  int n;            // grid points per axis (layout of H)
   long n3;          // n^3
   int nb;           // right-hand sides in the launch
   int xcd_order;    // 1: row tiles of all right-hand sides back-to-back per XCD
+  int bx, by, bz;   // extent of the data box (n, n, n for the whole grid)
+  int x0, y0, z0;   // its corner in the grid
+  long vn3;         // bx * by * bz: points per component of the vectors
 };
 
-// Rows (rhs, z, y): inverse x transform of every component, then the pointwise
-// combine.  Vectors J, B, out are complex128 [rhs][C][n^3]; H, Hmu [9][n^3].
+// Rows (rhs, z, y) of the data box: inverse x transform of every component,
+// then the pointwise combine.  Vectors J, B, out are complex128
+// [rhs][C][bz][by][bx]; H, Hmu [9][n^3] on the whole grid.
 template <typename R, int P1, int P2, int C, int MODE>
 __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R>* __restrict__ A, XArgs a, const c128* __restrict__ Jv,
                                                const c128* __restrict__ Bv, const cx<R>* __restrict__ H,
@@ -159,8 +165,8 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
                                                const cx<R>* __restrict__ twg) {
   constexpr int P = P1 * P2;
   constexpr int J = P1 > P2 ? P1 : P2;
-  static_assert(P1 % 2 == 0, "the cropped inverse assumes n = P/2 with P1 even");
-  constexpr int NV = P1 / 2;  // outputs per thread per component: x = j + P2 m2, m2 < NV
+  static_assert(P1 % 2 == 0, "the cropped inverse assumes bx <= P/2 with P1 even");
+  constexpr int NV = P1 / 2;  // outputs per thread per component: x = j + P2 m2 < bx <= P/2
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<R>* tw = reinterpret_cast<cx<R>*>(smem_raw);
   cx<R>* lds = tw + P;
@@ -168,7 +174,7 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
   int col, j;
   Layout<true>::lane(threadIdx.x, a.T, J, col, j);
   const int N = a.n;
-  const long NN = long(N) * N;
+  const long NN = long(a.bz) * a.by;  // rows per right-hand side
   // xcd_order: block b runs on XCD b % 8; the nb right-hand sides of one
   // (z, y) row tile share H, so they take consecutive slots on one XCD
   long tile_id = blockIdx.x;
@@ -182,6 +188,7 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
   const bool valid = row < a.nrows;
   const long rhs = valid ? row / NN : 0;
   const long zy = valid ? row % NN : 0;
+  const long hrow = (long(a.z0) + zy / a.by) * N + (a.y0 + zy % a.by);  // (z, y) in the grid
 
   // kUpfront: all spectral inputs of the row in flight at once
   constexpr int CU = kUpfront ? C : 1;
@@ -203,36 +210,39 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
         [&](auto m2, int, cx<R> v) {
           if constexpr (decltype(m2)::value < NV) U[c][decltype(m2)::value] = v;
         },
-        N, lds, twr, col, j, a.T, valid);
+        a.bx, lds, twr, col, j, a.T, valid);
   });
 
   if (!valid || j >= P2) return;
+  const long vs = a.vn3;
   static_for<0, NV>([&](auto m2) {
     const int x = j + P2 * m2;
-    const long p = zy * N + x;
+    if (x >= a.bx) return;
+    const long p = zy * a.bx + x;             // point in the vectors' box layout
+    const long ph = hrow * N + (a.x0 + x);    // the same point in the grid (H)
     static_for<0, C / 3>([&](auto half) {
       constexpr int c0 = 3 * decltype(half)::value;
-      const long vb = (rhs * C + c0) * a.n3 + p;
+      const long vb = (rhs * C + c0) * vs + p;
       if constexpr (MODE == MODE_CONV) {
-        static_for<0, 3>([&](auto c) { out[vb + c * a.n3] = cvt<double>(U[c0 + c][m2]); });
+        static_for<0, 3>([&](auto c) { out[vb + c * vs] = cvt<double>(U[c0 + c][m2]); });
       } else if constexpr (MODE == MODE_FIELD) {
         static_for<0, 3>([&](auto c) {
-          out[vb + c * a.n3] = cvt<double>(cvt<R>(Jv[vb + c * a.n3]) + U[c0 + c][m2]);
+          out[vb + c * vs] = cvt<double>(cvt<R>(Jv[vb + c * vs]) + U[c0 + c][m2]);
         });
       } else {
         const cx<R>* Hh = (c0 == 0) ? H : Hmu;
         cx<R> jv[3], v[3];
         static_for<0, 3>([&](auto c) {
-          jv[c] = cvt<R>(Jv[vb + c * a.n3]);
+          jv[c] = cvt<R>(Jv[vb + c * vs]);
           v[c] = jv[c] + R(2) * U[c0 + c][m2];
         });
         static_for<0, 3>([&](auto r) {
           cx<R> acc = jv[r];
-          static_for<0, 3>([&](auto s) { acc = acc - Hh[(3 * r + s) * a.n3 + p] * v[s]; });
+          static_for<0, 3>([&](auto s) { acc = acc - Hh[(3 * r + s) * a.n3 + ph] * v[s]; });
           if constexpr (MODE == MODE_RESIDUAL) {
-            out[vb + r * a.n3] = Bv[vb + r * a.n3] - cvt<double>(acc);
+            out[vb + r * vs] = Bv[vb + r * vs] - cvt<double>(acc);
           } else {
-            out[vb + r * a.n3] = cvt<double>(acc);
+            out[vb + r * vs] = cvt<double>(acc);
           }
         });
       }

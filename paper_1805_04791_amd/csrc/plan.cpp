@@ -41,7 +41,13 @@ int hip_fail(vie_plan* pl, hipError_t e, const char* what) {
   return e == hipErrorOutOfMemory ? VIE_E_NOMEM : VIE_E_DEVICE;
 }
 
+std::recursive_mutex& hip_mutex() {
+  static std::recursive_mutex m;
+  return m;
+}
+
 int dev_alloc(vie_plan* pl, void** p, size_t bytes) {
+  std::lock_guard<std::recursive_mutex> lk(hip_mutex());
   *p = nullptr;
   if (bytes == 0) bytes = 256;
   hipError_t e = hipMalloc(p, bytes);
@@ -57,6 +63,7 @@ int dev_alloc(vie_plan* pl, void** p, size_t bytes) {
 
 void dev_free(vie_plan* pl, void* p) {
   if (!p) return;
+  std::lock_guard<std::recursive_mutex> lk(hip_mutex());
   for (size_t i = 0; i < pl->allocs.size(); ++i) {
     if (pl->allocs[i].first == p) {
       pl->dev_bytes -= pl->allocs[i].second;
@@ -222,54 +229,59 @@ struct ApplyCall {
   cx<R>* A;
   cx<R>* B;
   int nb;
+  Geom g;
 };
 
+// x forward: rows (rhs, c, z, y) of the box, bx samples -> P
 template <typename R>
 hipError_t pass_xfwd(const ApplyCall<R>& c, const c128* in, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long rows = long(c.nb) * pl->C * pl->n * pl->n;
-  Geo g{T, int((rows + T - 1) / T), rows, pl->n, pl->P};
-  MemLoad<c128> src{in, 0, pl->n, 1};
+  const long rows = long(c.nb) * pl->C * c.g.bz * c.g.by;
+  Geo g{T, int((rows + T - 1) / T), rows, c.g.bx, pl->P};
+  MemLoad<c128> src{in, 0, c.g.bx, 1};
   MemStore<cx<R>> dst{c.A, 0, pl->P, 1, 1.0, 0};
   return c.ops->contig_fwd(src, dst, g, 1, c.tw, s);
 }
 
+// y forward: A [rhs][c][bz][by][P] -> B [rhs][c][bz][P][P]
 template <typename R>
 hipError_t pass_yfwd(const ApplyCall<R>& c, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long N = pl->n, P = pl->P;
-  Geo g{T, int(P / T), P, int(N), int(P)};
-  MemLoad<cx<R>> src{c.A, N * P, 1, P};
+  const long P = pl->P, by = c.g.by;
+  Geo g{T, int(P / T), P, int(by), int(P)};
+  MemLoad<cx<R>> src{c.A, by * P, 1, P};
   MemStore<cx<R>> dst{c.B, P * P, 1, P, 1.0, 0};
-  return c.ops->strided(false, src, dst, g, long(c.nb) * pl->C * N, c.tw, s);
+  return c.ops->strided(false, src, dst, g, long(c.nb) * pl->C * c.g.bz, c.tw, s);
 }
 
 template <typename R>
 hipError_t pass_z(const ApplyCall<R>& c, const cx<R>* tab, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long N = pl->n, P = pl->P;
-  ZArgs a{T, int(P / T), int(N), int(P), pl->nxp, pl->ne, N * P * P, long(pl->C) * N * P * P, c.nb};
+  const long N = pl->n, P = pl->P, bz = c.g.bz;
+  ZArgs a{T, int(P / T), int(N), int(P), pl->nxp, pl->ne, bz * P * P, long(pl->C) * bz * P * P, c.nb, int(bz)};
   const long nblocks = long(P / T) * P * c.nb;
   return c.ops->zpass(pl->full ? MUL_MAX6 : MUL_SYM3, c.B, tab, a, nblocks, c.tw, s);
 }
 
+// y inverse: B -> A, outputs y < by
 template <typename R>
 hipError_t pass_yinv(const ApplyCall<R>& c, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long N = pl->n, P = pl->P;
-  Geo g{T, int(P / T), P, int(P), int(N)};
+  const long P = pl->P, by = c.g.by;
+  Geo g{T, int(P / T), P, int(P), int(by)};
   MemLoad<cx<R>> src{c.B, P * P, 1, P};
-  MemStore<cx<R>> dst{c.A, N * P, 1, P, 1.0, 0};
-  return c.ops->strided(true, src, dst, g, long(c.nb) * pl->C * N, c.tw, s);
+  MemStore<cx<R>> dst{c.A, by * P, 1, P, 1.0, 0};
+  return c.ops->strided(true, src, dst, g, long(c.nb) * pl->C * c.g.bz, c.tw, s);
 }
 
 template <typename R>
 hipError_t pass_xinv(const ApplyCall<R>& c, const c128* addv, const c128* bvec, c128* out, int mode, int T,
                      hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long NN = long(pl->n) * pl->n;
+  const long NN = long(c.g.bz) * c.g.by;
   const int xcd = (NN % T == 0) && ((NN / T) % 8 == 0) ? 1 : 0;
-  XArgs a{T, long(c.nb) * NN, pl->n, pl->n3, c.nb, xcd};
+  XArgs a{T,        long(c.nb) * NN, pl->n,  pl->n3,  c.nb,    xcd,     c.g.bx,
+          c.g.by,   c.g.bz,          c.g.x0, c.g.y0,  c.g.z0,  c.g.vn3()};
   const cx<R>* H;
   const cx<R>* Hmu;
   if constexpr (std::is_same<R, float>::value) {
@@ -331,10 +343,12 @@ int pick_tile(vie_plan* pl, int P1, int P2, bool contig, int maxthreads, F&& run
   return VIE_OK;
 }
 
+int tune_key(int nb, const Geom& g) { return bucket_of(nb) + (g.id << 20); }
+
 template <typename R>
 int get_tune(vie_plan* pl, const ApplyCall<R>& c, const c128* in, c128* out, hipStream_t s, Tune* t) {
   const int idx = std::is_same<R, double>::value ? 1 : 0;
-  const int key = bucket_of(c.nb);
+  const int key = tune_key(c.nb, c.g);
   auto it = pl->tune[idx].find(key);
   if (it != pl->tune[idx].end()) {
     *t = it->second;
@@ -371,16 +385,16 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const c128* in, c128* out, hip
   }
   d.tuned = true;
   if (env_flag("VIE_DEBUG", false))
-    std::fprintf(stderr, "[vie] tiles P=%d fp%d nb=%d: xfwd %d yfwd %d z %d yinv %d xinv %d\n", pl->P,
-                 int(8 * sizeof(R)), c.nb, d.tx_fwd, d.ty_fwd, d.tz, d.ty_inv, d.tx_inv);
+    std::fprintf(stderr, "[vie] tiles P=%d fp%d nb=%d box %dx%dx%d: xfwd %d yfwd %d z %d yinv %d xinv %d\n", pl->P,
+                 int(8 * sizeof(R)), c.nb, c.g.bx, c.g.by, c.g.bz, d.tx_fwd, d.ty_fwd, d.tz, d.ty_inv, d.tx_inv);
   pl->tune[idx][key] = d;
   *t = d;
   return VIE_OK;
 }
 
 template <typename R>
-int apply_typed(vie_plan* pl, const c128* in, const c128* addv, const c128* bvec, c128* out, int nrhs, int mode,
-                hipStream_t s) {
+int apply_typed(vie_plan* pl, const Geom& geom, const c128* in, const c128* addv, const c128* bvec, c128* out,
+                int nrhs, int mode, hipStream_t s) {
   const LenOps<R>* ops = len_ops<R>(pl->P);
   if (!ops || !ops->contig_fwd || !ops->zpass || !ops->xinv)
     return fail(pl, VIE_E_SIZE, "no compiled FFT length " + std::to_string(pl->P));
@@ -397,10 +411,10 @@ int apply_typed(vie_plan* pl, const c128* in, const c128* addv, const c128* bvec
     tw = pl->tw64;
     tab = pl->tab64;
   }
-  const long L = long(pl->C) * pl->n3;
+  const long L = long(pl->C) * geom.vn3();
   for (int r0 = 0; r0 < nrhs; r0 += chunk) {
     const int nb = std::min(chunk, nrhs - r0);
-    ApplyCall<R> c{pl, ops, tw, static_cast<cx<R>*>(pl->wsA[idx]), static_cast<cx<R>*>(pl->wsB[idx]), nb};
+    ApplyCall<R> c{pl, ops, tw, static_cast<cx<R>*>(pl->wsA[idx]), static_cast<cx<R>*>(pl->wsB[idx]), nb, geom};
     const long off = long(r0) * L;
     const c128* inr = in + off;
     c128* outr = out + off;
@@ -410,9 +424,9 @@ int apply_typed(vie_plan* pl, const c128* in, const c128* addv, const c128* bvec
     const int f0 = std::is_same<R, double>::value ? FAM_XFWD64 : FAM_XFWD32;
     // algorithmic bytes: every operand read or written once per launch
     const double cr = double(sizeof(cx<R>)), c16 = double(sizeof(c128));
-    const double vN3 = double(nb) * pl->C * double(pl->n3);
-    const double vN2P = vN3 / pl->n * pl->P, vNP2 = vN2P / pl->n * pl->P;
-    const double hb = 9.0 * double(pl->n3) * cr * (pl->full ? 2 : 1);
+    const double vN3 = double(nb) * pl->C * double(geom.vn3());
+    const double vN2P = vN3 / geom.bx * pl->P, vNP2 = vN2P / geom.by * pl->P;
+    const double hb = 9.0 * double(geom.vn3()) * cr * (pl->full ? 2 : 1);
     const double xinv_b = vN2P * cr + hb * (mode == MODE_MATVEC || mode == MODE_RESIDUAL) +
                           vN3 * c16 * (1 + (mode != MODE_CONV) + (mode == MODE_RESIDUAL));
     int tok = prof_begin(pl, s);
@@ -531,10 +545,10 @@ int build_tables(vie_plan* pl, hipStream_t s) {
 
 namespace vie {
 
-int apply_any(vie_plan* pl, bool fp64, const c128* in, const c128* addv, const c128* bvec, c128* out, int nrhs,
-              int mode, hipStream_t s) {
-  return fp64 ? apply_typed<double>(pl, in, addv, bvec, out, nrhs, mode, s)
-              : apply_typed<float>(pl, in, addv, bvec, out, nrhs, mode, s);
+int apply_any(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
+              c128* out, int nrhs, int mode, hipStream_t s) {
+  return fp64 ? apply_typed<double>(pl, g, in, addv, bvec, out, nrhs, mode, s)
+              : apply_typed<float>(pl, g, in, addv, bvec, out, nrhs, mode, s);
 }
 
 void clear_graphs(vie_plan* pl) {
@@ -542,35 +556,36 @@ void clear_graphs(vie_plan* pl) {
   pl->graphs.clear();
 }
 
-int apply_graph(vie_plan* pl, bool fp64, const c128* in, const c128* addv, const c128* bvec, c128* out, int nrhs,
-                int mode, hipStream_t s) {
+int apply_graph(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
+                c128* out, int nrhs, int mode, hipStream_t s) {
   const int idx = fp64 ? 1 : 0;
   // eager when capture is off, while timing kernels, for chunked batches, or
   // before the first apply of this batch size (tiling and workspace set up)
   if (!pl->use_graphs || pl->prof_on || nrhs > pl->max_rhs || pl->ws_cap[idx] < nrhs ||
-      pl->tune[idx].find(bucket_of(nrhs)) == pl->tune[idx].end())
-    return apply_any(pl, fp64, in, addv, bvec, out, nrhs, mode, s);
+      pl->tune[idx].find(tune_key(nrhs, g)) == pl->tune[idx].end())
+    return apply_any(pl, g, fp64, in, addv, bvec, out, nrhs, mode, s);
   if (!pl->gstream) {
     HIPCHK(pl, hipStreamCreateWithFlags(&pl->gstream, hipStreamNonBlocking));
     HIPCHK(pl, hipEventCreateWithFlags(&pl->gev_in, hipEventDisableTiming));
     HIPCHK(pl, hipEventCreateWithFlags(&pl->gev_out, hipEventDisableTiming));
   }
-  vie_plan::GraphKey key{idx, mode, nrhs, in, addv, bvec, out};
+  vie_plan::GraphKey key{idx, mode, nrhs, g.id, in, addv, bvec, out};
   auto it = pl->graphs.find(key);
   if (it == pl->graphs.end()) {
     if (pl->graphs.size() >= 512) clear_graphs(pl);
-    hipGraph_t g = nullptr;
+    std::lock_guard<std::recursive_mutex> lk(hip_mutex());
+    hipGraph_t graph = nullptr;
     HIPCHK(pl, hipStreamBeginCapture(pl->gstream, hipStreamCaptureModeRelaxed));
-    const int rc = apply_any(pl, fp64, in, addv, bvec, out, nrhs, mode, pl->gstream);
-    const hipError_t ec = hipStreamEndCapture(pl->gstream, &g);
+    const int rc = apply_any(pl, g, fp64, in, addv, bvec, out, nrhs, mode, pl->gstream);
+    const hipError_t ec = hipStreamEndCapture(pl->gstream, &graph);
     if (rc) {
-      if (g) (void)hipGraphDestroy(g);
+      if (graph) (void)hipGraphDestroy(graph);
       return rc;
     }
     if (ec != hipSuccess) return hip_fail(pl, ec, "hipStreamEndCapture");
     hipGraphExec_t ex = nullptr;
-    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
+    const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
     if (ei != hipSuccess) return hip_fail(pl, ei, "hipGraphInstantiate");
     it = pl->graphs.emplace(key, ex).first;
   }
@@ -597,6 +612,7 @@ bool n_supported(int n) {
 
 void destroy_plan(vie_plan* pl) {
   if (!pl) return;
+  std::lock_guard<std::recursive_mutex> lk(hip_mutex());
   vie::clear_graphs(pl);
   if (pl->gstream) (void)hipStreamSynchronize(pl->gstream);
   if (pl->gev_in) (void)hipEventDestroy(pl->gev_in);
@@ -642,7 +658,8 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   pl->max_rhs = p->max_rhs;
   pl->flags = p->flags;
   pl->n3 = long(p->n) * p->n * p->n;
-  pl->use_graphs = env_flag("VIE_GRAPHS", true);
+  pl->use_graphs = env_flag("VIE_GRAPHS", true) && !(p->flags & VIE_NO_GRAPHS);
+  pl->last_stream = s;
   HIPCHK(pl, hipGetDevice(&pl->device));
   {
     hipDeviceProp_t prop;
@@ -662,13 +679,17 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   const int nblk = int(std::min<long>(4096, (pl->n3 + 255) / 256));
   double* bmax = nullptr;
   int* bbad = nullptr;
+  int* bbox = nullptr;
   rc = dev_alloc(pl, reinterpret_cast<void**>(&bmax), sizeof(double) * size_t(nblk));
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&bbad), sizeof(int) * size_t(nblk));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&bbox), sizeof(int) * 6 * size_t(nblk));
   if (rc) return rc;
   std::vector<double> hmax(static_cast<size_t>(nblk));
   std::vector<int> hbad(static_cast<size_t>(nblk));
+  std::vector<int> hbox(static_cast<size_t>(6 * nblk));
   double worst = 0.0;
   long bad = 0;
+  int lo[3] = {p->n, p->n, p->n}, hi[3] = {-1, -1, -1};
   for (int pass = 0; pass < (pl->full ? 2 : 1); ++pass) {
     c128* H64 = pl->H64;
     c64* H32 = pl->H32;
@@ -680,18 +701,32 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
       H64 = pl->Hmu64;
       H32 = pl->Hmu32;
     }
-    HIPCHK(pl, launch_contrast(coef_d, H64, H32, pl->n3, bmax, bbad, nblk, s));
+    HIPCHK(pl, launch_contrast(coef_d, H64, H32, pl->n, bmax, bbad, bbox, nblk, s));
     HIPCHK(pl, hipMemcpyAsync(hmax.data(), bmax, sizeof(double) * size_t(nblk), hipMemcpyDeviceToHost, s));
     HIPCHK(pl, hipMemcpyAsync(hbad.data(), bbad, sizeof(int) * size_t(nblk), hipMemcpyDeviceToHost, s));
+    HIPCHK(pl, hipMemcpyAsync(hbox.data(), bbox, sizeof(int) * 6 * size_t(nblk), hipMemcpyDeviceToHost, s));
     HIPCHK(pl, hipStreamSynchronize(s));
     for (int i = 0; i < nblk; ++i) {
       worst = std::max(worst, hmax[size_t(i)]);
       bad += hbad[size_t(i)];
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], hbox[size_t(6 * i + 2 * a)]);
+        hi[a] = std::max(hi[a], hbox[size_t(6 * i + 2 * a + 1)]);
+      }
     }
   }
   dev_free(pl, coef_d);
   dev_free(pl, bmax);
   dev_free(pl, bbad);
+  dev_free(pl, bbox);
+  // whole grid and the bounding box of supp(H) (a single point if H vanishes)
+  pl->grid = Geom{p->n, p->n, p->n, 0, 0, 0, 0};
+  if (hi[0] < 0) {
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = 0;
+  }
+  pl->box = Geom{hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1, lo[0], lo[1], lo[2], 1};
+  pl->use_box = env_flag("VIE_BOX", true);
+  if (!pl->use_box) pl->box = pl->grid;
   pl->hmax = worst;
   if (bad > 0)
     return fail(pl, VIE_E_MEDIUM, std::to_string(bad) + " grid points where a + I is singular or not finite");
@@ -732,7 +767,7 @@ int vie_plan_create(const vie_problem* p, void* hip_stream, vie_plan** out) {
 
 int vie_destroy(vie_plan* pl) {
   if (!pl) return VIE_OK;
-  (void)hipDeviceSynchronize();
+  (void)hipStreamSynchronize(pl->last_stream);
   destroy_plan(pl);
   return VIE_OK;
 }
@@ -742,35 +777,41 @@ int vie_apply(vie_plan* pl, const double* x, double* y, int nrhs, unsigned flags
   if (!x || !y || nrhs < 1) return fail(pl, VIE_E_ARG, "vie_apply: null pointer or nrhs < 1");
   if ((flags & VIE_APPLY_FP64) && (flags & VIE_APPLY_FP32)) return fail(pl, VIE_E_ARG, "FP64 and FP32 both set");
   if (x == y) return fail(pl, VIE_E_ARG, "vie_apply: x and y must not overlap");
+  pl->last_stream = static_cast<hipStream_t>(hip_stream);
   bool fp64 = pl->precision == VIE_PREC_FP64;
   if (flags & VIE_APPLY_FP64) fp64 = true;
   if (flags & VIE_APPLY_FP32) fp64 = false;
   const int mode = (flags & VIE_APPLY_CONV) ? MODE_CONV : MODE_MATVEC;
   const c128* in = reinterpret_cast<const c128*>(x);
-  return apply_any(pl, fp64, in, in, nullptr, reinterpret_cast<c128*>(y), nrhs, mode,
+  return apply_any(pl, pl->grid, fp64, in, in, nullptr, reinterpret_cast<c128*>(y), nrhs, mode,
                    static_cast<hipStream_t>(hip_stream));
 }
 
 int vie_rhs(vie_plan* pl, const double* inc, double* b, int nrhs, void* hip_stream) {
   if (!pl) return VIE_E_ARG;
   if (!inc || !b || nrhs < 1) return fail(pl, VIE_E_ARG, "vie_rhs: null pointer or nrhs < 1");
+  pl->last_stream = static_cast<hipStream_t>(hip_stream);
   hipError_t e = launch_rhs(pl->H64, pl->Hmu64, reinterpret_cast<const c128*>(inc), reinterpret_cast<c128*>(b),
-                            nrhs, pl->C, pl->n3, static_cast<hipStream_t>(hip_stream));
+                            nrhs, pl->C, box_of(pl->grid, pl->n), static_cast<hipStream_t>(hip_stream));
   return e == hipSuccess ? VIE_OK : hip_fail(pl, e, "vie_rhs");
 }
 
 int vie_field(vie_plan* pl, const double* density, const double* inc, double* field, int nrhs, void* hip_stream) {
   if (!pl) return VIE_E_ARG;
   if (!density || !inc || !field || nrhs < 1) return fail(pl, VIE_E_ARG, "vie_field: null pointer or nrhs < 1");
-  return apply_any(pl, true, reinterpret_cast<const c128*>(density), reinterpret_cast<const c128*>(inc), nullptr,
-                   reinterpret_cast<c128*>(field), nrhs, MODE_FIELD, static_cast<hipStream_t>(hip_stream));
+  pl->last_stream = static_cast<hipStream_t>(hip_stream);
+  return apply_any(pl, pl->grid, true, reinterpret_cast<const c128*>(density),
+                   reinterpret_cast<const c128*>(inc), nullptr, reinterpret_cast<c128*>(field), nrhs, MODE_FIELD,
+                   static_cast<hipStream_t>(hip_stream));
 }
 
 int vie_plan_info(const vie_plan* pl, double* out, int nout) {
   if (!pl || !out) return VIE_E_ARG;
-  const double v[8] = {double(pl->n),  double(pl->C),  double(pl->P),         double(pl->M),
-                       pl->hmax,       double(pl->ne), double(pl->dev_bytes), double(pl->graph_launches)};
-  for (int i = 0; i < nout && i < 8; ++i) out[i] = v[i];
+  const double v[14] = {double(pl->n),         double(pl->C),      double(pl->P),      double(pl->M),
+                        pl->hmax,              double(pl->ne),     double(pl->dev_bytes),
+                        double(pl->graph_launches), double(pl->box.x0), double(pl->box.y0), double(pl->box.z0),
+                        double(pl->box.bx),    double(pl->box.by), double(pl->box.bz)};
+  for (int i = 0; i < nout && i < 14; ++i) out[i] = v[i];
   return VIE_OK;
 }
 

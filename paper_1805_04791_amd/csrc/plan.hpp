@@ -4,14 +4,26 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
 
 #include "cx.hpp"
+#include "pointwise.hpp"
 #include "vie.h"
 
 namespace vie {
+
+// Extent of the data an apply works on: the whole grid, or the bounding box
+// of the support of H (the Krylov vectors vanish outside it exactly).
+struct Geom {
+  int bx = 0, by = 0, bz = 0;
+  int x0 = 0, y0 = 0, z0 = 0;
+  int id = 0;  // 0 whole grid, 1 support box
+  long vn3() const { return long(bx) * by * bz; }
+};
+inline Box box_of(const Geom& g, int n) { return Box{n, g.bx, g.by, g.bz, g.x0, g.y0, g.z0}; }
 
 // tile choices of the five apply passes
 struct Tune {
@@ -32,6 +44,9 @@ struct vie_plan {
   double h = 0, omega = 0, R = 0, hmax = 0;
   long n3 = 0;
   bool full = false;  // mu present (6 unknowns per point)
+  vie::Geom grid, box;  // whole grid; bounding box of supp(H) (of H and H_mu)
+  bool use_box = true;
+  hipStream_t last_stream = nullptr;  // stream of the latest call (synchronised by vie_destroy)
   int device = 0;
   size_t max_lds = 65536;
 
@@ -67,10 +82,11 @@ struct vie_plan {
 
   // captured applies: key (fp64, mode, nb, in, addv, bvec, out) -> graph
   struct GraphKey {
-    int fp64, mode, nb;
+    int fp64, mode, nb, geom;
     const void *in, *addv, *bvec, *out;
     bool operator<(const GraphKey& o) const {
-      return std::tie(fp64, mode, nb, in, addv, bvec, out) < std::tie(o.fp64, o.mode, o.nb, o.in, o.addv, o.bvec, o.out);
+      return std::tie(fp64, mode, nb, geom, in, addv, bvec, out) <
+             std::tie(o.fp64, o.mode, o.nb, o.geom, o.in, o.addv, o.bvec, o.out);
     }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -117,12 +133,18 @@ int hip_fail(vie_plan* pl, hipError_t e, const char* what);
 // apply: out = f(in) for nrhs vectors; mode MODE_*; addv: J for the
 // combine (MODE_MATVEC/RESIDUAL: the input itself, MODE_FIELD: the incident
 // field); bvec: b of MODE_RESIDUAL.
-int apply_any(vie_plan* pl, bool fp64, const c128* in, const c128* addv, const c128* bvec, c128* out, int nrhs,
-              int mode, hipStream_t s);
+// Serialises the library's stream captures with its allocations, frees and
+// synchronisations, which HIP forbids while any stream of the process is
+// being captured.
+std::recursive_mutex& hip_mutex();
+
+// Vectors are laid out on geometry g ([rhs][C][bz][by][bx]).
+int apply_any(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
+              c128* out, int nrhs, int mode, hipStream_t s);
 // the same through a captured hipGraph replayed on the plan's stream (solver
 // calls with stable pointers); falls back to apply_any when capture is off
-int apply_graph(vie_plan* pl, bool fp64, const c128* in, const c128* addv, const c128* bvec, c128* out, int nrhs,
-                int mode, hipStream_t s);
+int apply_graph(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
+                c128* out, int nrhs, int mode, hipStream_t s);
 void clear_graphs(vie_plan* pl);
 
 // kernel families timed by vie_profile

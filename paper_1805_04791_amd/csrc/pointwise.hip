@@ -21,6 +21,14 @@ __device__ __forceinline__ double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
+__device__ __forceinline__ int wave_imin(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_imax(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
 
 // spectral norm of a 3x3 complex matrix: sqrt(largest eigenvalue of H^H H)
 __device__ double spec_norm3(const c128 h[9]) {
@@ -48,13 +56,19 @@ __device__ double spec_norm3(const c128 h[9]) {
   return sqrt(fmax(q + 2.0 * p * cos(phi), 0.0));
 }
 
+// H = I - 2 (a + I)^{-1}, the block maximum of ||H(x)||_2, the count of
+// singular points and the bounding box (x, y, z min/max) of the points where
+// H has a non-zero entry.
 __global__ void __launch_bounds__(kBlock) k_contrast(const c128* __restrict__ coef, c128* __restrict__ H64,
-                                                     c64* __restrict__ H32, long n3, double* __restrict__ blk_max,
-                                                     int* __restrict__ blk_bad) {
+                                                     c64* __restrict__ H32, int n, double* __restrict__ blk_max,
+                                                     int* __restrict__ blk_bad, int* __restrict__ blk_box) {
   __shared__ double smax[kBlock / 64];
   __shared__ double sbad[kBlock / 64];
+  __shared__ int sbox[kBlock / 64][6];
+  const long n3 = long(n) * n * n;
   double vmax = 0.0;
   double bad = 0.0;
+  int lo[3] = {n, n, n}, hi[3] = {-1, -1, -1};
   for (long p = long(blockIdx.x) * blockDim.x + threadIdx.x; p < n3; p += long(gridDim.x) * blockDim.x) {
     c128 b[9];
     for (int e = 0; e < 9; ++e) b[e] = coef[e * n3 + p];
@@ -94,47 +108,109 @@ __global__ void __launch_bounds__(kBlock) k_contrast(const c128* __restrict__ co
       if (!isfinite(nrm)) bad += 1.0;
       vmax = fmax(vmax, nrm);
     }
+    bool nz = false;
     for (int e = 0; e < 9; ++e) {
       H64[e * n3 + p] = h[e];
       H32[e * n3 + p] = cvt<float>(h[e]);
+      nz = nz || h[e].re != 0.0 || h[e].im != 0.0;
+    }
+    if (nz) {
+      const int q[3] = {int(p % n), int((p / n) % n), int(p / (long(n) * n))};
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = min(lo[a], q[a]);
+        hi[a] = max(hi[a], q[a]);
+      }
     }
   }
   vmax = wave_max(vmax);
   bad = wave_sum(bad);
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = wave_imin(lo[a]);
+    hi[a] = wave_imax(hi[a]);
+  }
   const int w = threadIdx.x / 64;
   if ((threadIdx.x & 63) == 0) {
     smax[w] = vmax;
     sbad[w] = bad;
+    for (int a = 0; a < 3; ++a) {
+      sbox[w][2 * a] = lo[a];
+      sbox[w][2 * a + 1] = hi[a];
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = 0.0, c = 0.0;
+    int b[6] = {n, -1, n, -1, n, -1};
     for (int i = 0; i < kBlock / 64; ++i) {
       m = fmax(m, smax[i]);
       c += sbad[i];
+      for (int a = 0; a < 3; ++a) {
+        b[2 * a] = min(b[2 * a], sbox[i][2 * a]);
+        b[2 * a + 1] = max(b[2 * a + 1], sbox[i][2 * a + 1]);
+      }
     }
     blk_max[blockIdx.x] = m;
     blk_bad[blockIdx.x] = int(c);
+    for (int i = 0; i < 6; ++i) blk_box[6 * blockIdx.x + i] = b[i];
   }
 }
 
+// grid index of box point p (box layout [bz][by][bx])
+__device__ __forceinline__ long box_to_grid(long p, const Box& g) {
+  const long x = p % g.bx, y = (p / g.bx) % g.by, z = p / (long(g.bx) * g.by);
+  return ((z + g.z0) * g.n + (y + g.y0)) * g.n + (x + g.x0);
+}
+
+// b = 2 H g on the box; g on the whole grid [rhs][C][n^3], b in box layout
 __global__ void __launch_bounds__(kBlock) k_rhs(const c128* __restrict__ H, const c128* __restrict__ Hmu,
                                                 const c128* __restrict__ inc, c128* __restrict__ b, int nrhs,
-                                                int C, long n3) {
-  const long total = long(nrhs) * (C / 3) * n3;
+                                                int C, Box g) {
+  const long vn3 = long(g.bx) * g.by * g.bz;
+  const long n3 = long(g.n) * g.n * g.n;
+  const long total = long(nrhs) * (C / 3) * vn3;
   for (long t = long(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
-    const long p = t % n3;
-    const long rh = t / n3;  // rhs * (C/3) + half
+    const long p = t % vn3;
+    const long rh = t / vn3;  // rhs * (C/3) + half
     const int half = int(rh % (C / 3));
     const c128* Hh = half == 0 ? H : Hmu;
-    const long vb = rh * 3 * n3 + p;
-    c128 g[3];
-    for (int c = 0; c < 3; ++c) g[c] = inc[vb + c * n3];
+    const long ph = box_to_grid(p, g);
+    const long vb = rh * 3 * vn3 + p;
+    const long gb = rh * 3 * n3 + ph;
+    c128 v[3];
+    for (int c = 0; c < 3; ++c) v[c] = inc[gb + c * n3];
     for (int r = 0; r < 3; ++r) {
       c128 acc = {0.0, 0.0};
-      for (int c = 0; c < 3; ++c) acc = acc + Hh[(3 * r + c) * n3 + p] * g[c];
-      b[vb + r * n3] = 2.0 * acc;
+      for (int c = 0; c < 3; ++c) acc = acc + Hh[(3 * r + c) * n3 + ph] * v[c];
+      b[vb + r * vn3] = 2.0 * acc;
     }
+  }
+}
+
+// box <- grid (gather) for nv = nrhs * C components
+__global__ void __launch_bounds__(kBlock) k_gather(const c128* __restrict__ full, c128* __restrict__ box, long nv,
+                                                   Box g) {
+  const long vn3 = long(g.bx) * g.by * g.bz;
+  const long n3 = long(g.n) * g.n * g.n;
+  const long total = nv * vn3;
+  for (long t = long(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long p = t % vn3, c = t / vn3;
+    box[t] = full[c * n3 + box_to_grid(p, g)];
+  }
+}
+
+// grid <- box with zeros outside the box (scatter), over the whole grid
+__global__ void __launch_bounds__(kBlock) k_scatter(const c128* __restrict__ box, c128* __restrict__ full, long nv,
+                                                    Box g) {
+  const long vn3 = long(g.bx) * g.by * g.bz;
+  const long n3 = long(g.n) * g.n * g.n;
+  const long total = nv * n3;
+  for (long t = long(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long ph = t % n3, c = t / n3;
+    const int x = int(ph % g.n) - g.x0, y = int((ph / g.n) % g.n) - g.y0, z = int(ph / (long(g.n) * g.n)) - g.z0;
+    c128 v = {0.0, 0.0};
+    if (x >= 0 && x < g.bx && y >= 0 && y < g.by && z >= 0 && z < g.bz)
+      v = box[c * vn3 + (long(z) * g.by + y) * g.bx + x];
+    full[t] = v;
   }
 }
 
@@ -295,15 +371,25 @@ int krylov_blocks(long L) {
   return int(b);
 }
 
-hipError_t launch_contrast(const c128* coef, c128* H64, c64* H32, long n3, double* blk_max, int* blk_bad,
-                           int nblocks, hipStream_t s) {
-  k_contrast<<<nblocks, kBlock, 0, s>>>(coef, H64, H32, n3, blk_max, blk_bad);
+hipError_t launch_contrast(const c128* coef, c128* H64, c64* H32, int n, double* blk_max, int* blk_bad,
+                           int* blk_box, int nblocks, hipStream_t s) {
+  k_contrast<<<nblocks, kBlock, 0, s>>>(coef, H64, H32, n, blk_max, blk_bad, blk_box);
   return hipGetLastError();
 }
 
-hipError_t launch_rhs(const c128* H, const c128* Hmu, const c128* inc, c128* b, int nrhs, int C, long n3,
+hipError_t launch_rhs(const c128* H, const c128* Hmu, const c128* inc, c128* b, int nrhs, int C, const Box& g,
                       hipStream_t s) {
-  k_rhs<<<grid_for(long(nrhs) * (C / 3) * n3), kBlock, 0, s>>>(H, Hmu, inc, b, nrhs, C, n3);
+  k_rhs<<<grid_for(long(nrhs) * (C / 3) * g.bx * g.by * g.bz), kBlock, 0, s>>>(H, Hmu, inc, b, nrhs, C, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const c128* full, c128* box, long nv, const Box& g, hipStream_t s) {
+  k_gather<<<grid_for(nv * g.bx * g.by * g.bz), kBlock, 0, s>>>(full, box, nv, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const c128* box, c128* full, long nv, const Box& g, hipStream_t s) {
+  k_scatter<<<grid_for(nv * g.n * g.n * g.n), kBlock, 0, s>>>(box, full, nv, g);
   return hipGetLastError();
 }
 

@@ -7,15 +7,30 @@
 
 namespace vie {
 
-// H = (a + I)^{-1} (a - I) = I - 2 (a + I)^{-1} at every point (eq. rhodef).
-// Writes H in FP64 and FP32, and per-block (max ||H||_2, count of singular or
-// non-finite points) into blk_max / blk_bad (nblocks entries each).
-hipError_t launch_contrast(const c128* coef, c128* H64, c64* H32, long n3, double* blk_max, int* blk_bad,
-                           int nblocks, hipStream_t s);
+// A box of the n^3 grid: extent (bx, by, bz), corner (x0, y0, z0).  Box
+// vectors are laid out [bz][by][bx] per component.
+struct Box {
+  int n;
+  int bx, by, bz;
+  int x0, y0, z0;
+};
 
-// b = 2 H g per 3-component half (H for the first half, Hmu for the second).
-hipError_t launch_rhs(const c128* H, const c128* Hmu, const c128* inc, c128* b, int nrhs, int C, long n3,
+// H = (a + I)^{-1} (a - I) = I - 2 (a + I)^{-1} at every point (eq. rhodef).
+// Writes H in FP64 and FP32, and per block: max ||H||_2 (blk_max), the count
+// of singular or non-finite points (blk_bad) and the bounding box of the
+// points where H != 0 (blk_box[6 b ..] = xmin, xmax, ymin, ymax, zmin, zmax;
+// min = n, max = -1 for a block without such points).
+hipError_t launch_contrast(const c128* coef, c128* H64, c64* H32, int n, double* blk_max, int* blk_bad,
+                           int* blk_box, int nblocks, hipStream_t s);
+
+// b = 2 H g per 3-component half (H for the first half, Hmu for the second),
+// at the points of box g: inc on the whole grid [nrhs][C][n^3], b in box layout.
+hipError_t launch_rhs(const c128* H, const c128* Hmu, const c128* inc, c128* b, int nrhs, int C, const Box& g,
                       hipStream_t s);
+// box[v] <- full[v] restricted to the box, v < nv components
+hipError_t launch_gather(const c128* full, c128* box, long nv, const Box& g, hipStream_t s);
+// full[v] <- box[v] inside the box, 0 outside, v < nv components
+hipError_t launch_scatter(const c128* box, c128* full, long nv, const Box& g, hipStream_t s);
 
 // Partial sums, per right-hand side r and block: conj(V_i) . w_r for i < nv and
 // ||w_r||^2 (slot nv).  V_i of rhs r at V + i * vstride + r * rstride.

@@ -42,9 +42,12 @@ struct RhsState {
   int iters = 0, mv32 = 0, mv64 = 0, refine = 0;
 };
 
-int ensure_krylov(vie_plan* pl, int cap, int m) {
+int ensure_krylov(vie_plan* pl, int cap, int m, hipStream_t s) {
   if (pl->kr_cap >= cap && pl->kr_m >= m) return VIE_OK;
-  HIPCHK(pl, hipDeviceSynchronize());  // pending copies may still read the old staging buffers
+  // pending copies may still read the old staging buffers
+  HIPCHK(pl, hipStreamSynchronize(s));
+  if (pl->gstream) HIPCHK(pl, hipStreamSynchronize(pl->gstream));
+  std::lock_guard<std::recursive_mutex> lk(hip_mutex());
   cap = std::max(cap, pl->kr_cap);
   m = std::max(m, pl->kr_m);
   dev_free(pl, pl->V);
@@ -64,7 +67,7 @@ int ensure_krylov(vie_plan* pl, int cap, int m) {
   pl->red_host = pl->coef_host = nullptr;
   pl->scale_host = nullptr;
   pl->kr_cap = pl->kr_m = 0;
-  const size_t L = zu(pl->C) * zu(pl->n3);
+  const size_t L = zu(pl->C) * zu(pl->box.vn3());  // vectors live on the support box
   const size_t nblk = zu(krylov_blocks(long(L)));
   const size_t vec = sizeof(c128) * L * zu(cap);
   int rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->V), vec * zu(m + 1));
@@ -91,7 +94,7 @@ struct Batch {
   vie_plan* pl;
   hipStream_t s;
   int nb;
-  long L;      // vector length C n^3
+  long L;      // vector length C bx by bz (the support box)
   long vs;     // basis vector stride (cap * L)
   int nblk;
 };
@@ -195,7 +198,7 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
     if (!any) break;
     const c128* Vj = pl->V + long(j) * b.vs;
     c128* Vn = pl->V + long(j + 1) * b.vs;
-    rc = apply_graph(pl, fp64, Vj, Vj, nullptr, pl->ww, nb, MODE_MATVEC, b.s);
+    rc = apply_graph(pl, pl->box, fp64, Vj, Vj, nullptr, pl->ww, nb, MODE_MATVEC, b.s);
     if (rc) return rc;
     const int nv = j + 1;
     rc = dots_host(b, pl->V, pl->ww, nv);
@@ -361,7 +364,7 @@ int bicgstab_run(const Batch& b, bool fp64, const std::vector<double>& rnorm0, c
     for (int r = 0; r < nb; ++r) sc[zu(r)] = active[zu(r)] ? 1.0 : 0.0;
     rc = combine_host(b, v, pl->rw, p, 2, cP, sc);
     if (rc) return rc;
-    rc = apply_graph(pl, fp64, p, p, nullptr, v, nb, MODE_MATVEC, b.s);
+    rc = apply_graph(pl, pl->box, fp64, p, p, nullptr, v, nb, MODE_MATVEC, b.s);
     if (rc) return rc;
     rc = dots_host(b, rhat, v, 1);
     if (rc) return rc;
@@ -374,7 +377,7 @@ int bicgstab_run(const Batch& b, bool fp64, const std::vector<double>& rnorm0, c
     }
     rc = combine_host(b, v, pl->rw, sv, 1, cS, sc);  // s = r - alpha v
     if (rc) return rc;
-    rc = apply_graph(pl, fp64, sv, sv, nullptr, t, nb, MODE_MATVEC, b.s);
+    rc = apply_graph(pl, pl->box, fp64, sv, sv, nullptr, t, nb, MODE_MATVEC, b.s);
     if (rc) return rc;
     rc = dots_host(b, sv, t, 1);  // conj(s).t and ||t||^2
     if (rc) return rc;
@@ -449,24 +452,28 @@ int solve_batch(vie_plan* pl, const c128* inc, c128* density, c128* field, int n
                 vie_solve_stats* stats, hipStream_t s) {
   const bool mixed = pl->precision == VIE_PREC_MIXED && !(o.flags & VIE_SOLVE_FP64);
   const int m = o.solver == VIE_SOLVER_BICGSTAB ? 5 : std::max(1, o.restart);
-  const long L = long(pl->C) * pl->n3;
+  // Outside supp(H) the equation gives J = 0 exactly, so the unknowns are
+  // the points of the bounding box of supp(H); U is needed only there too.
+  const long L = long(pl->C) * pl->box.vn3();
+  const long Lg = long(pl->C) * pl->n3;
+  const Box box = box_of(pl->box, pl->n);
   const int cap = std::max(1, std::min(nrhs, pl->max_rhs));
-  int rc = ensure_krylov(pl, cap, std::max(m, 5));
+  int rc = ensure_krylov(pl, cap, std::max(m, 5), s);
   if (rc) return rc;
   int status = VIE_OK;
   for (int r0 = 0; r0 < nrhs; r0 += cap) {
     const auto t0 = std::chrono::steady_clock::now();
     const int nb = std::min(cap, nrhs - r0);
     Batch b{pl, s, nb, L, long(pl->kr_cap) * L, krylov_blocks(L)};
-    const long off = long(r0) * L;
+    const long off = long(r0) * Lg;
     // b = 2 H g
-    HIPCHK(pl, launch_rhs(pl->H64, pl->Hmu64, inc + off, pl->bw, nb, pl->C, pl->n3, s));
+    HIPCHK(pl, launch_rhs(pl->H64, pl->Hmu64, inc + off, pl->bw, nb, pl->C, box, s));
     std::vector<double> bnorm, rnorm;
     rc = norms(b, pl->bw, bnorm);
     if (rc) return rc;
     if (o.flags & VIE_SOLVE_X0) {
-      HIPCHK(pl, launch_copy(density + off, pl->xw, long(nb) * L, s));
-      rc = apply_any(pl, true, pl->xw, pl->xw, pl->bw, pl->rw, nb, MODE_RESIDUAL, s);
+      HIPCHK(pl, launch_gather(density + off, pl->xw, long(nb) * pl->C, box, s));
+      rc = apply_any(pl, pl->box, true, pl->xw, pl->xw, pl->bw, pl->rw, nb, MODE_RESIDUAL, s);
       if (rc) return rc;
     } else {
       HIPCHK(pl, launch_fill(pl->xw, long(nb) * L, c128{0.0, 0.0}, s));
@@ -510,7 +517,7 @@ int solve_batch(vie_plan* pl, const c128* inc, c128* density, c128* field, int n
         rc = gmres_cycle(b, !mixed, m, rnorm, target, st, active, budget);
       if (rc) return rc;
       // true residual with the FP64 operator
-      rc = apply_graph(pl, true, pl->xw, pl->xw, pl->bw, pl->rw, nb, MODE_RESIDUAL, s);
+      rc = apply_graph(pl, pl->box, true, pl->xw, pl->xw, pl->bw, pl->rw, nb, MODE_RESIDUAL, s);
       if (rc) return rc;
       rc = norms(b, pl->rw, rnorm);
       if (rc) return rc;
@@ -534,9 +541,9 @@ int solve_batch(vie_plan* pl, const c128* inc, c128* density, c128* field, int n
         for (int r = 0; r < nb; ++r) st[zu(r)].done = true;
       }
     }
-    HIPCHK(pl, launch_copy(pl->xw, density + off, long(nb) * L, s));
+    HIPCHK(pl, launch_scatter(pl->xw, density + off, long(nb) * pl->C, box, s));
     if (field) {
-      rc = apply_any(pl, true, density + off, inc + off, nullptr, field + off, nb, MODE_FIELD, s);
+      rc = apply_any(pl, pl->grid, true, density + off, inc + off, nullptr, field + off, nb, MODE_FIELD, s);
       if (rc) return rc;
     }
     HIPCHK(pl, hipStreamSynchronize(s));
@@ -565,6 +572,7 @@ extern "C" int vie_solve(vie_plan* pl, const double* inc, double* density, doubl
                          const vie_solve_opts* opts, vie_solve_stats* stats, void* hip_stream) {
   if (!pl) return VIE_E_ARG;
   if (!inc || !density || nrhs < 1) return vie::fail(pl, VIE_E_ARG, "vie_solve: null pointer or nrhs < 1");
+  pl->last_stream = static_cast<hipStream_t>(hip_stream);
   vie_solve_opts o{1e-10, 2000, 40, 0.0, VIE_SOLVER_GMRES, 0u};
   if (opts) o = *opts;
   if (!(o.tol > 0) || o.max_iters < 1 || o.restart < 1 || o.restart > 1000 ||

@@ -232,8 +232,10 @@ class Server:
                     r = sel[0]
                     plan = self.cache.get(r.key)
                     if plan is None:
+                        # worker threads allocate and synchronise while others
+                        # solve, which stream capture would forbid
                         plan = vie.Plan(r.kind, r.coef, omega=r.omega, mu=r.mu, precision=self.precision,
-                                        max_rhs=self.max_batch, stream=stream)
+                                        max_rhs=self.max_batch, stream=stream, graphs=False)
                     inc = np.concatenate([q.inc for q in sel])
                     dens, _, stats, rc = plan.solve(inc, tol=min(q.tol for q in sel), restart=self.restart,
                                                     want_field=False, stream=stream)

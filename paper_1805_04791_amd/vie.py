@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libvie.so")
 
 LAPLACE, HELMHOLTZ, MAXWELL = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
-PTR_HOST, STRICT_MEDIUM = 0x1, 0x2
+PTR_HOST, STRICT_MEDIUM, NO_GRAPHS = 0x1, 0x2, 0x4
 APPLY_FP64, APPLY_FP32, APPLY_CONV = 0x1, 0x2, 0x4
 SOLVER_GMRES, SOLVER_BICGSTAB = 0, 1
 SOLVE_X0, SOLVE_FP64 = 0x1, 0x2
@@ -141,7 +141,7 @@ class Plan:
 
     def __init__(self, kind: int, coef, omega: float = 0.0, mu=None, h: Optional[float] = None,
                  precision: int = PREC_MIXED, max_rhs: int = 1, strict: bool = False,
-                 device: str = "cuda", stream=None):
+                 device: str = "cuda", stream=None, graphs: bool = True):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the volume-integral-equation library runs on MI355X only")
@@ -163,7 +163,7 @@ class Plan:
         p.mu = mu_d.data_ptr() if mu_d is not None else None
         p.precision = int(precision)
         p.max_rhs = int(max_rhs)
-        p.flags = STRICT_MEDIUM if strict else 0
+        p.flags = (STRICT_MEDIUM if strict else 0) | (0 if graphs else NO_GRAPHS)
         handle = ctypes.c_void_p()
         rc = self.lib.vie_plan_create(ctypes.byref(p), _stream_ptr(stream), ctypes.byref(handle))
         if rc != OK:
@@ -237,10 +237,13 @@ class Plan:
         return dens, fld, [s.as_dict() for s in st], rc
 
     def info(self) -> dict:
-        out = (ctypes.c_double * 8)()
-        self._check(self.lib.vie_plan_info(self._h, out, 8), "vie_plan_info")
-        keys = ["n", "ncomp", "P", "M", "max_contrast_norm", "table_entries", "device_bytes", "graph_launches"]
-        return dict(zip(keys, list(out)))
+        out = (ctypes.c_double * 14)()
+        self._check(self.lib.vie_plan_info(self._h, out, 14), "vie_plan_info")
+        keys = ["n", "ncomp", "P", "M", "max_contrast_norm", "table_entries", "device_bytes", "graph_launches",
+                "box_x0", "box_y0", "box_z0", "box_nx", "box_ny", "box_nz"]
+        d = dict(zip(keys, list(out)))
+        d["box"] = tuple(int(d.pop(k)) for k in keys[8:])
+        return d
 
     def tables(self) -> np.ndarray:
         """FP64 octant tables as complex128 [n+1][n+1][ne][nxp]."""

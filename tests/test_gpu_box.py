@@ -1,0 +1,182 @@
+"""Support-box restriction of the solver (GPU, through the C ABI).
+
+Where H(x) = 0 the integral equation reads J(x) = 0, so the solver keeps its
+unknowns on the bounding box of supp(H) only.  These tests check that the box
+the library finds is exactly the bounding box of the oracle contrast's
+support, that solves on ragged, off-centre boxes agree with the oracle's
+full-grid solution, that the density is exactly zero outside the box, and
+that a box solve agrees with the whole-grid solve.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import operator as op
+from oracle import solve as sv
+from vie_inputs import generators as gen
+
+from _helpers import medium, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vie():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_04791_amd import vie as v
+    v.load_library()
+    return v
+
+
+def masked(coef, mask):
+    """I + mask (coef - I): the medium restricted to where mask = 1."""
+    eye = np.eye(3, dtype=np.complex128).reshape(9, 1, 1, 1)
+    return eye + mask[None] * (coef - eye)
+
+
+def support_box(*Hs):
+    """(x0, y0, z0, bx, by, bz) of the points where any H has a non-zero entry."""
+    nz = np.zeros(Hs[0].shape[-3:], dtype=bool)
+    for H in Hs:
+        nz |= np.any(H.reshape(9, *H.shape[-3:]) != 0, axis=0)
+    if not nz.any():
+        return (0, 0, 0, 1, 1, 1)
+    zs, ys, xs = np.nonzero(nz)
+    return (int(xs.min()), int(ys.min()), int(zs.min()),
+            int(xs.max() - xs.min() + 1), int(ys.max() - ys.min() + 1), int(zs.max() - zs.min() + 1))
+
+
+def plane_waves(n, omega, count, item):
+    out = []
+    for j in range(count):
+        d = gen.random_unit(gen.rng_for(gen.CONFIG_IDS["test"], 700 + item + j))
+        out.append(gen.plane_wave_gradient(n, omega, d))
+    return np.stack(out)
+
+
+def em_waves(n, omega, count, item, full):
+    out = []
+    for j in range(count):
+        rng = gen.rng_for(gen.CONFIG_IDS["test"], 750 + item + j)
+        d = gen.random_unit(rng)
+        f = gen.plane_wave_em(n, omega, d, gen.random_polarisation(rng, d))
+        out.append(f if full else f[:3])
+    return np.stack(out)
+
+
+def offcentre_mask(n):
+    X, Y, Z = gen.grid_coords(n)
+    return ((X > 0.1) & (Y < 0.3)).astype(np.float64)
+
+
+def test_box_is_support_bounding_box(vie):
+    n = 24
+    coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 11)
+    X, Y, Z = gen.grid_coords(n)
+    cases = [coef, masked(coef, offcentre_mask(n)), masked(coef, ((X < -0.5) & (Z > 0.2)).astype(float)),
+             gen.identity_field(n)]
+    for c in cases:
+        plan = vie.Plan(op.KIND_HELMHOLTZ, c, omega=omega, precision=vie.PREC_MIXED)
+        assert plan.info()["box"] == support_box(op.contrast(c)), plan.info()["box"]
+        plan.close()
+
+
+def test_box_union_of_eps_and_mu_supports(vie):
+    n = 16
+    eps, mu, omega = medium(op.KIND_MAXWELL, n, 12, full=True)
+    X, Y, Z = gen.grid_coords(n)
+    eps = masked(eps, (Z > 0.0).astype(float))
+    mu = masked(mu, (X < -0.2).astype(float))
+    plan = vie.Plan(op.KIND_MAXWELL, eps, omega=omega, mu=mu, precision=vie.PREC_MIXED)
+    assert plan.info()["box"] == support_box(op.contrast(eps), op.contrast(mu))
+    plan.close()
+
+
+@pytest.mark.parametrize("n", [16, 24])
+def test_offcentre_box_solve_matches_oracle(vie, n):
+    coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 13)
+    coef = masked(coef, offcentre_mask(n))
+    inc = plane_waves(n, omega, 2, 0)
+    A = op.Operator(op.KIND_HELMHOLTZ, coef, omega)
+    ref = [sv.gmres(A.apply, A.rhs(inc[r]), tol=1e-13)[0] for r in range(2)]
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2)
+    x0, y0, z0, bx, by, bz = plan.info()["box"]
+    assert (bx, by, bz) != (n, n, n)
+    inside = np.zeros((n, n, n), dtype=bool)
+    inside[z0:z0 + bz, y0:y0 + by, x0:x0 + bx] = True
+    for fp64, tol, err in ((True, 1e-12, 1e-10), (False, 1e-9, 1e-8)):
+        d, f, st, rc = plan.solve(inc, tol=tol, fp64=fp64)
+        assert rc == vie.OK
+        d, f = d.cpu().numpy(), f.cpu().numpy()
+        for r in range(2):
+            assert st[r]["rel_residual"] <= tol
+            assert rel(d[r], ref[r]) < err
+            assert np.all(d[r][:, ~inside] == 0)
+            assert rel(f[r], A.field(ref[r], inc[r])) < err
+    plan.close()
+
+
+def test_offcentre_box_full_maxwell_matches_oracle(vie):
+    n = 16
+    eps, mu, omega = medium(op.KIND_MAXWELL, n, 14, full=True)
+    X, Y, Z = gen.grid_coords(n)
+    eps = masked(eps, (Y > -0.3).astype(float))
+    mu = masked(mu, (Y > 0.2).astype(float))
+    inc = em_waves(n, omega, 2, 0, True)
+    A = op.Operator(op.KIND_MAXWELL, eps, omega, mu=mu)
+    ref = [sv.gmres(A.apply, A.rhs(inc[r]), tol=1e-13)[0] for r in range(2)]
+    plan = vie.Plan(op.KIND_MAXWELL, eps, omega=omega, mu=mu, precision=vie.PREC_MIXED, max_rhs=2)
+    d, _, st, rc = plan.solve(inc, tol=1e-12, fp64=True, want_field=False)
+    assert rc == vie.OK
+    d = d.cpu().numpy()
+    for r in range(2):
+        assert rel(d[r], ref[r]) < 1e-10
+    plan.close()
+
+
+def test_box_solve_equals_whole_grid_solve(vie, monkeypatch):
+    n = 24
+    coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 15)
+    inc = plane_waves(n, omega, 3, 10)
+    monkeypatch.setenv("VIE_BOX", "0")
+    whole = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
+    monkeypatch.delenv("VIE_BOX")
+    boxed = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
+    assert whole.info()["box"] == (0, 0, 0, n, n, n)
+    assert boxed.info()["box"] != (0, 0, 0, n, n, n)
+    for fp64, tol, err in ((True, 1e-12, 1e-10), (False, 1e-10, 1e-9)):
+        dw, _, sw, _ = whole.solve(inc, tol=tol, fp64=fp64, want_field=False)
+        db, _, sb, _ = boxed.solve(inc, tol=tol, fp64=fp64, want_field=False)
+        dw, db = dw.cpu().numpy(), db.cpu().numpy()
+        for r in range(3):
+            assert rel(db[r], dw[r]) < err
+            assert abs(sb[r]["iters"] - sw[r]["iters"]) <= 2
+    whole.close()
+    boxed.close()
+
+
+def test_x0_outside_box_is_ignored(vie):
+    """A warm start is restricted to the box: values outside it cannot
+    change the solution (the equation fixes J = 0 there)."""
+    n = 16
+    coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 16)
+    coef = masked(coef, offcentre_mask(n))
+    inc = plane_waves(n, omega, 1, 20)
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_FP64)
+    d1, _, _, _ = plan.solve(inc, tol=1e-12, max_iters=4, restart=4, want_field=False)
+    d1 = d1.cpu().numpy()
+    x0, y0, z0, bx, by, bz = plan.info()["box"]
+    junk = d1.copy()
+    outside = np.ones((n, n, n), dtype=bool)
+    outside[z0:z0 + bz, y0:y0 + by, x0:x0 + bx] = False
+    junk[:, :, outside] = 1e3
+    da, _, sa, _ = plan.solve(inc, tol=1e-12, x0=d1, want_field=False)
+    db, _, sb, _ = plan.solve(inc, tol=1e-12, x0=junk, want_field=False)
+    assert np.array_equal(da.cpu().numpy(), db.cpu().numpy())
+    assert sa[0]["iters"] == sb[0]["iters"]
+    plan.close()
