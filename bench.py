@@ -29,6 +29,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MI355X_HBM_PEAK_GBS = 8000.0
+# Vector ALU peak reachable by this build: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flops (FMA) x 2.4 GHz.  FP64 and FP32 alike: the published 157.3 TFLOP/s
+# FP32 figure counts packed (two-per-lane) FP32 instructions, which the
+# library is compiled without.
+MI355X_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 METRIC = "solves/s to 1e-8 rel err (128³ Helmholtz), mixed vs FP64; p50/p99 latency"
 
 
@@ -72,6 +77,9 @@ def main(argv=None):
     ap.add_argument("--latency-solves", type=int, default=8, help="single-RHS mixed solves for p50/p99")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run a plain fp32 copy kernel (x * 1.0) over this many MiB, three times, "
+                         "as the reference for hardware byte counters")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -87,6 +95,15 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if args.calibrate_copy_mib > 0:
+        src = torch.ones(args.calibrate_copy_mib * 2 ** 18, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] calibration copy: {args.calibrate_copy_mib} MiB read and written, 3 times",
+              file=sys.stderr, flush=True)
     n, B = args.n, args.nrhs
     omega = 8.0 * math.pi * n / 128.0 if n != 128 else 8.0 * math.pi
     prob = gen.helmholtz_problem(n, omega, "helmholtz128", nrhs=B)
@@ -150,13 +167,30 @@ def main(argv=None):
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
 
-    # ---- roofline of the dominant kernel family (HIP events, algorithmic bytes)
-    fam, (ms, cnt, by) = max(prof.items(), key=lambda kv: kv[1][0])
-    achieved = by / (ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": fam, "achieved": achieved, "peak": MI355X_HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / MI355X_HBM_PEAK_GBS, "traffic": None,
-            "avg_launch_us": 1e3 * ms / cnt, "bytes_per_launch": by / cnt}
-    breakdown = {k: {"ms": v[0], "launches": v[1], "GB/s": v[2] / (v[0] * 1e-3) / 1e9 if v[0] > 0 else None}
+    # ---- roofline of the dominant kernel family (HIP events, algorithmic
+    # bytes and nominal flops): ALU-bound when its arithmetic intensity is
+    # above the ridge point peak_flops / peak_bandwidth
+    fam, (ms, cnt, by, fl) = max(prof.items(), key=lambda kv: kv[1][0])
+    ridge = MI355X_VALU_PEAK_TFLOPS * 1e12 / (MI355X_HBM_PEAK_GBS * 1e9)
+    alu = fl / by > ridge
+    # HBM bytes per launch from the committed counter summary of this kernel
+    # and workload, if the device sources are unchanged since it was taken
+    from paper_1805_04791_amd import profiling
+    tr = profiling.read_traffic(os.path.join(ROOT, "profiles", f"{fam}.helmholtz{n}.traffic.md"))
+    digest = profiling.source_digest()
+    traffic = tr[0] if tr is not None and tr[2] == digest else None
+    if alu:
+        achieved, peak, unit = fl / (ms * 1e-3) / 1e12, MI355X_VALU_PEAK_TFLOPS, "TFLOP/s"
+    else:
+        achieved, peak, unit = by / (ms * 1e-3) / 1e9, MI355X_HBM_PEAK_GBS, "GB/s"
+    roof = {"bound": "alu" if alu else "hbm", "kernel": fam, "achieved": achieved, "peak": peak,
+            "unit": unit, "frac": achieved / peak, "traffic": traffic,
+            "avg_launch_us": 1e3 * ms / cnt, "bytes_per_launch": by / cnt, "flops_per_launch": fl / cnt,
+            "flop_per_byte": fl / by, "ridge_flop_per_byte": ridge,
+            "hbm_GBs": by / (ms * 1e-3) / 1e9, "source_digest": digest}
+    breakdown = {k: {"ms": v[0], "launches": v[1],
+                     "GB/s": v[2] / (v[0] * 1e-3) / 1e9 if v[0] > 0 else None,
+                     "TFLOP/s": v[3] / (v[0] * 1e-3) / 1e12 if v[0] > 0 else None}
                  for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
 
     cpu = None

@@ -223,12 +223,16 @@ long vie_footprint_bytes(int kind, int n, int full, int nrhs_batch, int restart)
  * launch stream around every kernel of the apply passes and of the Krylov
  * operations (and resets the totals); vie_profile(pl, 0) stops.
  * vie_profile_read waits for the recorded events and writes, per kernel
- * family, the summed duration in milliseconds, the launch count and the
- * summed algorithmic bytes (every operand of a launch read or written once;
- * host arrays of nfam entries); it returns the number of families.
+ * family, the summed duration in milliseconds, the launch count, the
+ * summed algorithmic bytes (every operand of a launch read or written once)
+ * and the summed nominal flops (5 L log2 L per transformed pencil of length
+ * L, 66 per frequency point for the 3x3 multiply and 216 for the 6x6 Maxwell
+ * block, 72 per point and 3-component half for the combine, 8 per complex
+ * multiply-add of the Krylov operations); host arrays of nfam entries, flops
+ * may be NULL.  It returns the number of families.
  * vie_profile_family(i) names family i. */
 int vie_profile(vie_plan *pl, int enable);
-int vie_profile_read(vie_plan *pl, double *ms, long *counts, double *bytes, int nfam);
+int vie_profile_read(vie_plan *pl, double *ms, long *counts, double *bytes, double *flops, int nfam);
 const char *vie_profile_family(int fam);
 
 #ifdef __cplusplus

@@ -90,14 +90,15 @@ int prof_begin(vie_plan* pl, hipStream_t s) {
   hipEvent_t a = take_event(pl), b = take_event(pl);
   if (!a || !b) return -1;
   (void)hipEventRecord(a, s);
-  pl->prof.push_back({-1, a, b, 0.0});
+  pl->prof.push_back({-1, a, b, 0.0, 0.0});
   return int(pl->prof.size()) - 1;
 }
 
-void prof_end(vie_plan* pl, int fam, int token, hipStream_t s, double bytes) {
+void prof_end(vie_plan* pl, int fam, int token, hipStream_t s, double bytes, double flops) {
   if (token < 0 || !pl->prof_on) return;
   pl->prof[size_t(token)].fam = fam;
   pl->prof[size_t(token)].bytes = bytes;
+  pl->prof[size_t(token)].flops = flops;
   (void)hipEventRecord(pl->prof[size_t(token)].b, s);
 }
 
@@ -111,6 +112,7 @@ static void prof_collect(vie_plan* pl) {
         pl->prof_ms[r.fam] += ms;
         pl->prof_cnt[r.fam] += 1;
         pl->prof_bytes[r.fam] += r.bytes;
+        pl->prof_flops[r.fam] += r.flops;
       }
     }
     pl->ev_pool.push_back(r.a);
@@ -363,8 +365,24 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const c128* in, c128* out, hip
   d.ty_fwd = d.ty_inv = default_tile<R>(pl, P1, P2, false, kPassMaxThreads, P);
   d.tz = default_tile<R>(pl, P1, P2, false, fmax, P);
   if (d.tx_fwd == 0 || d.tz == 0 || d.tx_inv == 0 || d.ty_fwd == 0) return fail(pl, VIE_E_SIZE, "no tile shape fits the LDS limit");
-  // measure only where it pays: large grids, unless switched off
-  if (pl->n >= 48 && env_flag("VIE_AUTOTUNE", true)) {
+  // VIE_TILES="xfwd,yfwd,z,yinv,xinv" pins the tiles of this FFT length and
+  // precision (profiling runs that must repeat a measured launch shape)
+  const char* pin = std::getenv(sizeof(R) == 8 ? "VIE_TILES_FP64" : "VIE_TILES");
+  int pt[5];
+  if (pin && std::sscanf(pin, "%d,%d,%d,%d,%d", &pt[0], &pt[1], &pt[2], &pt[3], &pt[4]) == 5) {
+    const bool ok = tile_ok<R>(pl, P1, P2, pt[0], true, P, kPassMaxThreads, false) &&
+                    tile_ok<R>(pl, P1, P2, pt[1], false, P, kPassMaxThreads, false) &&
+                    tile_ok<R>(pl, P1, P2, pt[2], false, P, fmax, false) &&
+                    tile_ok<R>(pl, P1, P2, pt[3], false, P, kPassMaxThreads, false) &&
+                    tile_ok<R>(pl, P1, P2, pt[4], true, P, fmax, false);
+    if (!ok) return fail(pl, VIE_E_ARG, std::string("tiles pinned by the environment do not fit: ") + pin);
+    d.tx_fwd = pt[0];
+    d.ty_fwd = pt[1];
+    d.tz = pt[2];
+    d.ty_inv = pt[3];
+    d.tx_inv = pt[4];
+  } else if (pl->n >= 48 && env_flag("VIE_AUTOTUNE", true)) {
+    // measure only where it pays: large grids, unless switched off
     const cx<R>* tab;
     if constexpr (std::is_same<R, float>::value)
       tab = pl->tab32;
@@ -429,21 +447,29 @@ int apply_typed(vie_plan* pl, const Geom& geom, const c128* in, const c128* addv
     const double hb = 9.0 * double(geom.vn3()) * cr * (pl->full ? 2 : 1);
     const double xinv_b = vN2P * cr + hb * (mode == MODE_MATVEC || mode == MODE_RESIDUAL) +
                           vN3 * c16 * (1 + (mode != MODE_CONV) + (mode == MODE_RESIDUAL));
+    // nominal flops: 5 P log2 P per transformed pencil of length P; 66 per
+    // frequency point for the 3x3 multiply (216 for the 6x6 Maxwell block);
+    // 72 per point and 3-component half for the combine
+    const double P = pl->P, fft_row = 5.0 * P * std::log2(P);
+    const double rows_x = vN3 / geom.bx, rows_y = vN2P / geom.by, rows_z = vNP2 / geom.bz;
+    const double pts = double(nb) * P * P * P;
+    const double mul_f = (pl->full ? 216.0 : 66.0) * pts;
+    const double comb_f = (mode == MODE_CONV) ? 0.0 : 72.0 * vN3 / 3.0;
     int tok = prof_begin(pl, s);
     HIPCHK(pl, pass_xfwd<R>(c, inr, t.tx_fwd, s));
-    prof_end(pl, f0 + 0, tok, s, vN3 * c16 + vN2P * cr);
+    prof_end(pl, f0 + 0, tok, s, vN3 * c16 + vN2P * cr, rows_x * fft_row);
     tok = prof_begin(pl, s);
     HIPCHK(pl, pass_yfwd<R>(c, t.ty_fwd, s));
-    prof_end(pl, f0 + 1, tok, s, (vN2P + vNP2) * cr);
+    prof_end(pl, f0 + 1, tok, s, (vN2P + vNP2) * cr, rows_y * fft_row);
     tok = prof_begin(pl, s);
     HIPCHK(pl, pass_z<R>(c, tab, t.tz, s));
-    prof_end(pl, f0 + 2, tok, s, 2.0 * vNP2 * cr + double(pl->tab_elems) * cr);
+    prof_end(pl, f0 + 2, tok, s, 2.0 * vNP2 * cr + double(pl->tab_elems) * cr, 2.0 * rows_z * fft_row + mul_f);
     tok = prof_begin(pl, s);
     HIPCHK(pl, pass_yinv<R>(c, t.ty_inv, s));
-    prof_end(pl, f0 + 3, tok, s, (vN2P + vNP2) * cr);
+    prof_end(pl, f0 + 3, tok, s, (vN2P + vNP2) * cr, rows_y * fft_row);
     tok = prof_begin(pl, s);
     HIPCHK(pl, pass_xinv<R>(c, addv ? addv + off : inr, bvec ? bvec + off : nullptr, outr, mode, t.tx_inv, s));
-    prof_end(pl, f0 + 4, tok, s, xinv_b);
+    prof_end(pl, f0 + 4, tok, s, xinv_b, rows_x * fft_row + comb_f);
   }
   return VIE_OK;
 }
@@ -882,17 +908,19 @@ int vie_profile(vie_plan* pl, int enable) {
     pl->prof_ms[i] = 0;
     pl->prof_cnt[i] = 0;
     pl->prof_bytes[i] = 0;
+    pl->prof_flops[i] = 0;
   }
   return VIE_OK;
 }
 
-int vie_profile_read(vie_plan* pl, double* ms, long* counts, double* bytes, int nfam) {
+int vie_profile_read(vie_plan* pl, double* ms, long* counts, double* bytes, double* flops, int nfam) {
   if (!pl || !ms || !counts || !bytes) return VIE_E_ARG;
   vie::prof_collect(pl);
   for (int i = 0; i < nfam && i < vie::FAM_COUNT; ++i) {
     ms[i] = pl->prof_ms[i];
     counts[i] = pl->prof_cnt[i];
     bytes[i] = pl->prof_bytes[i];
+    if (flops) flops[i] = pl->prof_flops[i];
   }
   return vie::FAM_COUNT;
 }

@@ -104,7 +104,7 @@ struct vie_plan {
   struct ProfRec {
     int fam;
     hipEvent_t a, b;
-    double bytes;
+    double bytes, flops;
   };
   bool prof_on = false;
   std::vector<ProfRec> prof;
@@ -112,6 +112,7 @@ struct vie_plan {
   double prof_ms[16] = {0};
   long prof_cnt[16] = {0};
   double prof_bytes[16] = {0};
+  double prof_flops[16] = {0};
 };
 
 namespace vie {
@@ -156,7 +157,7 @@ enum {
 // record an event pair around the launches between prof_begin and prof_end
 int prof_begin(vie_plan* pl, hipStream_t s);
 // bytes: algorithmic HBM bytes of the launch (each operand read or written once)
-void prof_end(vie_plan* pl, int fam, int token, hipStream_t s, double bytes);
+void prof_end(vie_plan* pl, int fam, int token, hipStream_t s, double bytes, double flops = 0.0);
 
 int solve_batch(vie_plan* pl, const c128* inc, c128* density, c128* field, int nrhs, const vie_solve_opts& o,
                 vie_solve_stats* stats, hipStream_t s);

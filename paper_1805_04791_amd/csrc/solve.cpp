@@ -104,7 +104,8 @@ int dots_host(const Batch& b, const c128* V, const c128* w, int nv) {
   vie_plan* pl = b.pl;
   int tok = prof_begin(pl, b.s);
   HIPCHK(pl, launch_dots(V, b.vs, b.L, w, b.L, nv, b.nb, b.nblk, pl->partials, b.s));
-  prof_end(pl, FAM_DOTS, tok, b.s, double(nv + 1) * b.nb * double(b.L) * sizeof(c128));
+  prof_end(pl, FAM_DOTS, tok, b.s, double(nv + 1) * b.nb * double(b.L) * sizeof(c128),
+           (8.0 * nv + 4.0) * b.nb * double(b.L));
   tok = prof_begin(pl, b.s);
   HIPCHK(pl, launch_reduce(pl->partials, b.nb, b.nblk, nv + 1, pl->red, b.s));
   prof_end(pl, FAM_REDUCE, tok, b.s, double(b.nb) * (b.nblk + 1) * (nv + 1) * sizeof(c128));
@@ -150,7 +151,8 @@ int combine_host(const Batch& b, const c128* V, const c128* w, c128* out, int nv
   HIPCHK(pl, hipMemcpyAsync(sdv, sh, sizeof(double) * zu(b.nb), hipMemcpyHostToDevice, b.s));
   const int tok = prof_begin(pl, b.s);
   HIPCHK(pl, launch_combine(V, b.vs, b.L, w, out, b.L, nv, cdv, sdv, b.nb, b.s));
-  prof_end(pl, FAM_COMBINE, tok, b.s, double(nv + 2) * b.nb * double(b.L) * sizeof(c128));
+  prof_end(pl, FAM_COMBINE, tok, b.s, double(nv + 2) * b.nb * double(b.L) * sizeof(c128),
+           (8.0 * nv + 2.0) * b.nb * double(b.L));
   return VIE_OK;
 }
 

@@ -88,7 +88,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.vie_supported_n.argtypes = [ci]
     L.vie_profile.argtypes = [vp, ci]
     L.vie_profile_read.argtypes = [vp, ctypes.POINTER(cd), ctypes.POINTER(ctypes.c_long),
-                                   ctypes.POINTER(cd), ci]
+                                   ctypes.POINTER(cd), ctypes.POINTER(cd), ci]
     L.vie_profile_family.argtypes = [ci]
     L.vie_profile_family.restype = ctypes.c_char_p
     L.vie_footprint_bytes.argtypes = [ci, ci, ci, ci, ci]
@@ -269,15 +269,16 @@ class Plan:
         self._check(self.lib.vie_profile(self._h, 1 if enable else 0), "vie_profile")
 
     def profile_read(self) -> dict:
-        """{family: (total ms, launches, algorithmic bytes)} since profile(True)."""
+        """{family: (total ms, launches, algorithmic bytes, nominal flops)} since profile(True)."""
         ms = (ctypes.c_double * 16)()
         cnt = (ctypes.c_long * 16)()
         by = (ctypes.c_double * 16)()
-        nf = self._check(self.lib.vie_profile_read(self._h, ms, cnt, by, 16), "vie_profile_read")
+        fl = (ctypes.c_double * 16)()
+        nf = self._check(self.lib.vie_profile_read(self._h, ms, cnt, by, fl, 16), "vie_profile_read")
         out = {}
         for i in range(nf):
             if cnt[i]:
-                out[self.lib.vie_profile_family(i).decode()] = (ms[i], cnt[i], by[i])
+                out[self.lib.vie_profile_family(i).decode()] = (ms[i], cnt[i], by[i], fl[i])
         return out
 
     def close(self):
