@@ -146,8 +146,10 @@ int vie_plan_create(const vie_problem *p, void *hip_stream, vie_plan **out);
 #define VIE_APPLY_FP64 0x1u      /* FP64 FFTs (default: the plan precision) */
 #define VIE_APPLY_FP32 0x2u      /* FP32 FFTs */
 #define VIE_APPLY_CONV 0x4u      /* return the raw convolution U (Z for full Maxwell) instead of A x */
+#define VIE_APPLY_C64 0x8u       /* x and y are complex64 (float pairs); FP32 matvec only */
 
-/* y = A x for nrhs densities (device pointers, complex128 [nrhs][c][n^3]).
+/* y = A x for nrhs densities (device pointers, complex128 [nrhs][c][n^3], or
+ * complex64 with VIE_APPLY_C64; x and y are passed as double* either way).
  * The discrete operator of the integral equation (see the header comment).
  * x and y must not overlap. */
 int vie_apply(vie_plan *pl, const double *x, double *y, int nrhs, unsigned flags, void *hip_stream);

@@ -156,13 +156,15 @@ struct XArgs {
 };
 
 // Rows (rhs, z, y) of the data box: inverse x transform of every component,
-// then the pointwise combine.  Vectors J, B, out are complex128
-// [rhs][C][bz][by][bx]; H, Hmu [9][n^3] on the whole grid.
-template <typename R, int P1, int P2, int C, int MODE>
-__global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R>* __restrict__ A, XArgs a, const c128* __restrict__ Jv,
+// then the pointwise combine.  Vectors J, B, out are [rhs][C][bz][by][bx],
+// J and out stored as TV (complex128, or complex64 for the FP32 Krylov basis
+// of the mixed solver), B as complex128; H, Hmu [9][n^3] on the whole grid.
+template <typename R, int P1, int P2, int C, int MODE, typename TV = c128>
+__global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R>* __restrict__ A, XArgs a, const TV* __restrict__ Jv,
                                                const c128* __restrict__ Bv, const cx<R>* __restrict__ H,
-                                               const cx<R>* __restrict__ Hmu, c128* __restrict__ out,
+                                               const cx<R>* __restrict__ Hmu, TV* __restrict__ out,
                                                const cx<R>* __restrict__ twg) {
+  using S = decltype(TV::re);
   constexpr int P = P1 * P2;
   constexpr int J = P1 > P2 ? P1 : P2;
   static_assert(P1 % 2 == 0, "the cropped inverse assumes bx <= P/2 with P1 even");
@@ -224,10 +226,10 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
       constexpr int c0 = 3 * decltype(half)::value;
       const long vb = (rhs * C + c0) * vs + p;
       if constexpr (MODE == MODE_CONV) {
-        static_for<0, 3>([&](auto c) { out[vb + c * vs] = cvt<double>(U[c0 + c][m2]); });
+        static_for<0, 3>([&](auto c) { out[vb + c * vs] = cvt<S>(U[c0 + c][m2]); });
       } else if constexpr (MODE == MODE_FIELD) {
         static_for<0, 3>([&](auto c) {
-          out[vb + c * vs] = cvt<double>(cvt<R>(Jv[vb + c * vs]) + U[c0 + c][m2]);
+          out[vb + c * vs] = cvt<S>(cvt<R>(Jv[vb + c * vs]) + U[c0 + c][m2]);
         });
       } else {
         const cx<R>* Hh = (c0 == 0) ? H : Hmu;
@@ -240,9 +242,9 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
           cx<R> acc = jv[r];
           static_for<0, 3>([&](auto s) { acc = acc - Hh[(3 * r + s) * a.n3 + ph] * v[s]; });
           if constexpr (MODE == MODE_RESIDUAL) {
-            out[vb + r * vs] = Bv[vb + r * vs] - cvt<double>(acc);
+            out[vb + r * vs] = cvt<S>(Bv[vb + r * vs] - cvt<double>(acc));
           } else {
-            out[vb + r * vs] = cvt<double>(acc);
+            out[vb + r * vs] = cvt<S>(acc);
           }
         });
       }

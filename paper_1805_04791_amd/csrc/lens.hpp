@@ -56,6 +56,11 @@ struct LenOps {
   // last inverse x pass with combine, C in {3, 6}, mode MODE_*
   hipError_t (*xinv)(int C, int mode, const cx<R>*, XArgs, const c128*, const c128*, const cx<R>*, const cx<R>*,
                      c128*, const cx<R>*, hipStream_t) = nullptr;
+  // the same two passes with the vectors stored as complex64 (the FP32 Krylov
+  // basis of the mixed solver; float only, MODE_MATVEC only)
+  hipError_t (*contig_fwd_v32)(MemLoad<c64>, MemStore<cx<R>>, Geo, long ngroups, const cx<R>*, hipStream_t) = nullptr;
+  hipError_t (*xinv_v32)(int C, const cx<R>*, XArgs, const c64*, const cx<R>*, const cx<R>*, c64*, const cx<R>*,
+                         hipStream_t) = nullptr;
   // precompute: inverse x pass of length M fed by the symbol (double only)
   hipError_t (*symbol_inv)(SymbolSrc, MemStore<c128>, Geo, long ngroups, const c128*, hipStream_t) = nullptr;
 };
@@ -88,6 +93,23 @@ struct LenImpl {
                                hipStream_t s) {
     const long blocks = long(geo.ntiles) * ngroups;
     k_pass<R, P1, P2, true, false, MemLoad<c128>, MemStore<cx<R>>><<<dim3(unsigned(blocks)), dim3(geo.T * J), pass_lds_bytes<R, P1, P2, true>(geo.T), s>>>(src, dst, geo, tw);
+    return hipGetLastError();
+  }
+  static hipError_t contig_fwd_v32(MemLoad<c64> src, MemStore<cx<R>> dst, Geo geo, long ngroups, const cx<R>* tw,
+                                   hipStream_t s) {
+    const long blocks = long(geo.ntiles) * ngroups;
+    k_pass<R, P1, P2, true, false, MemLoad<c64>, MemStore<cx<R>>><<<dim3(unsigned(blocks)), dim3(geo.T * J), pass_lds_bytes<R, P1, P2, true>(geo.T), s>>>(src, dst, geo, tw);
+    return hipGetLastError();
+  }
+  static hipError_t xinv_v32(int C, const cx<R>* A, XArgs a, const c64* J_, const cx<R>* H, const cx<R>* Hmu,
+                             c64* out, const cx<R>* tw, hipStream_t s) {
+    const long blocks = (a.nrows + a.T - 1) / a.T;
+    if (C == 3)
+      k_xinv<R, P1, P2, 3, MODE_MATVEC, c64><<<dim3(unsigned(blocks)), dim3(a.T * J), pass_lds_bytes<R, P1, P2, true>(a.T), s>>>(A, a, J_, nullptr, H, Hmu, out, tw);
+    else if (C == 6)
+      k_xinv<R, P1, P2, 6, MODE_MATVEC, c64><<<dim3(unsigned(blocks)), dim3(a.T * J), pass_lds_bytes<R, P1, P2, true>(a.T), s>>>(A, a, J_, nullptr, H, Hmu, out, tw);
+    else
+      return hipErrorInvalidValue;
     return hipGetLastError();
   }
   static hipError_t strided(bool inv, MemLoad<cx<R>> src, MemStore<cx<R>> dst, Geo geo, long ngroups,
@@ -148,6 +170,10 @@ struct LenImpl {
       o.contig_fwd = &contig_fwd;
       o.zpass = &zpass;
       o.xinv = &xinv;
+      if constexpr (std::is_same<R, float>::value) {
+        o.contig_fwd_v32 = &contig_fwd_v32;
+        o.xinv_v32 = &xinv_v32;
+      }
     }
     if constexpr (SYMBOL && std::is_same<R, double>::value) o.symbol_inv = &symbol_inv;
   }

@@ -234,15 +234,19 @@ struct ApplyCall {
   Geom g;
 };
 
-// x forward: rows (rhs, c, z, y) of the box, bx samples -> P
-template <typename R>
-hipError_t pass_xfwd(const ApplyCall<R>& c, const c128* in, int T, hipStream_t s) {
+// x forward: rows (rhs, c, z, y) of the box, bx samples -> P; TV is the
+// storage of the input vectors (complex128, or complex64 in FP32 applies)
+template <typename R, typename TV>
+hipError_t pass_xfwd(const ApplyCall<R>& c, const TV* in, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
   const long rows = long(c.nb) * pl->C * c.g.bz * c.g.by;
   Geo g{T, int((rows + T - 1) / T), rows, c.g.bx, pl->P};
-  MemLoad<c128> src{in, 0, c.g.bx, 1};
+  MemLoad<TV> src{in, 0, c.g.bx, 1};
   MemStore<cx<R>> dst{c.A, 0, pl->P, 1, 1.0, 0};
-  return c.ops->contig_fwd(src, dst, g, 1, c.tw, s);
+  if constexpr (std::is_same<TV, c128>::value)
+    return c.ops->contig_fwd(src, dst, g, 1, c.tw, s);
+  else
+    return c.ops->contig_fwd_v32(src, dst, g, 1, c.tw, s);
 }
 
 // y forward: A [rhs][c][bz][by][P] -> B [rhs][c][bz][P][P]
@@ -276,8 +280,8 @@ hipError_t pass_yinv(const ApplyCall<R>& c, int T, hipStream_t s) {
   return c.ops->strided(true, src, dst, g, long(c.nb) * pl->C * c.g.bz, c.tw, s);
 }
 
-template <typename R>
-hipError_t pass_xinv(const ApplyCall<R>& c, const c128* addv, const c128* bvec, c128* out, int mode, int T,
+template <typename R, typename TV>
+hipError_t pass_xinv(const ApplyCall<R>& c, const TV* addv, const c128* bvec, TV* out, int mode, int T,
                      hipStream_t s) {
   const vie_plan* pl = c.pl;
   const long NN = long(c.g.bz) * c.g.by;
@@ -293,7 +297,12 @@ hipError_t pass_xinv(const ApplyCall<R>& c, const c128* addv, const c128* bvec, 
     H = pl->H64;
     Hmu = pl->Hmu64;
   }
-  return c.ops->xinv(pl->C, mode, c.A, a, addv, bvec, H, Hmu, out, c.tw, s);
+  if constexpr (std::is_same<TV, c128>::value) {
+    return c.ops->xinv(pl->C, mode, c.A, a, addv, bvec, H, Hmu, out, c.tw, s);
+  } else {
+    if (mode != MODE_MATVEC) return hipErrorInvalidValue;
+    return c.ops->xinv_v32(pl->C, c.A, a, addv, H, Hmu, out, c.tw, s);
+  }
 }
 
 template <typename R>
@@ -347,8 +356,8 @@ int pick_tile(vie_plan* pl, int P1, int P2, bool contig, int maxthreads, F&& run
 
 int tune_key(int nb, const Geom& g) { return bucket_of(nb) + (g.id << 20); }
 
-template <typename R>
-int get_tune(vie_plan* pl, const ApplyCall<R>& c, const c128* in, c128* out, hipStream_t s, Tune* t) {
+template <typename R, typename TV>
+int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStream_t s, Tune* t) {
   const int idx = std::is_same<R, double>::value ? 1 : 0;
   const int key = tune_key(c.nb, c.g);
   auto it = pl->tune[idx].find(key);
@@ -389,7 +398,7 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const c128* in, c128* out, hip
     else
       tab = pl->tab64;
     int rc;
-    rc = pick_tile<R>(pl, P1, P2, true, kPassMaxThreads, [&](int T) { return pass_xfwd<R>(c, in, T, s); }, s, &d.tx_fwd);
+    rc = pick_tile<R>(pl, P1, P2, true, kPassMaxThreads, [&](int T) { return pass_xfwd<R, TV>(c, in, T, s); }, s, &d.tx_fwd);
     if (rc) return rc;
     rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, [&](int T) { return pass_yfwd<R>(c, T, s); }, s, &d.ty_fwd);
     if (rc) return rc;
@@ -397,8 +406,10 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const c128* in, c128* out, hip
     if (rc) return rc;
     rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, [&](int T) { return pass_yinv<R>(c, T, s); }, s, &d.ty_inv);
     if (rc) return rc;
+    // the raw convolution for complex128 vectors (any J), the matvec for complex64
+    const int xmode = std::is_same<TV, c128>::value ? MODE_CONV : MODE_MATVEC;
     rc = pick_tile<R>(pl, P1, P2, true, fmax,
-                      [&](int T) { return pass_xinv<R>(c, in, nullptr, out, MODE_CONV, T, s); }, s, &d.tx_inv);
+                      [&](int T) { return pass_xinv<R, TV>(c, in, nullptr, out, xmode, T, s); }, s, &d.tx_inv);
     if (rc) return rc;
   }
   d.tuned = true;
@@ -410,12 +421,14 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const c128* in, c128* out, hip
   return VIE_OK;
 }
 
-template <typename R>
-int apply_typed(vie_plan* pl, const Geom& geom, const c128* in, const c128* addv, const c128* bvec, c128* out,
+template <typename R, typename TV>
+int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, const c128* bvec, TV* out,
                 int nrhs, int mode, hipStream_t s) {
   const LenOps<R>* ops = len_ops<R>(pl->P);
   if (!ops || !ops->contig_fwd || !ops->zpass || !ops->xinv)
     return fail(pl, VIE_E_SIZE, "no compiled FFT length " + std::to_string(pl->P));
+  if (!std::is_same<TV, c128>::value && (!ops->contig_fwd_v32 || !ops->xinv_v32))
+    return fail(pl, VIE_E_STATE, "complex64 vectors need the FP32 apply");
   const int idx = std::is_same<R, double>::value ? 1 : 0;
   const int chunk = std::max(1, std::min(nrhs, pl->max_rhs));
   int rc = ensure_workspace<R>(pl, chunk);
@@ -434,19 +447,19 @@ int apply_typed(vie_plan* pl, const Geom& geom, const c128* in, const c128* addv
     const int nb = std::min(chunk, nrhs - r0);
     ApplyCall<R> c{pl, ops, tw, static_cast<cx<R>*>(pl->wsA[idx]), static_cast<cx<R>*>(pl->wsB[idx]), nb, geom};
     const long off = long(r0) * L;
-    const c128* inr = in + off;
-    c128* outr = out + off;
+    const TV* inr = in + off;
+    TV* outr = out + off;
     Tune t;
-    rc = get_tune<R>(pl, c, inr, outr, s, &t);
+    rc = get_tune<R, TV>(pl, c, inr, outr, s, &t);
     if (rc) return rc;
     const int f0 = std::is_same<R, double>::value ? FAM_XFWD64 : FAM_XFWD32;
     // algorithmic bytes: every operand read or written once per launch
-    const double cr = double(sizeof(cx<R>)), c16 = double(sizeof(c128));
+    const double cr = double(sizeof(cx<R>)), c16 = double(sizeof(TV));
     const double vN3 = double(nb) * pl->C * double(geom.vn3());
     const double vN2P = vN3 / geom.bx * pl->P, vNP2 = vN2P / geom.by * pl->P;
     const double hb = 9.0 * double(geom.vn3()) * cr * (pl->full ? 2 : 1);
     const double xinv_b = vN2P * cr + hb * (mode == MODE_MATVEC || mode == MODE_RESIDUAL) +
-                          vN3 * c16 * (1 + (mode != MODE_CONV) + (mode == MODE_RESIDUAL));
+                          vN3 * c16 * (1 + (mode != MODE_CONV)) + vN3 * sizeof(c128) * (mode == MODE_RESIDUAL);
     // nominal flops: 5 P log2 P per transformed pencil of length P; 66 per
     // frequency point for the 3x3 multiply (216 for the 6x6 Maxwell block);
     // 72 per point and 3-component half for the combine
@@ -456,7 +469,7 @@ int apply_typed(vie_plan* pl, const Geom& geom, const c128* in, const c128* addv
     const double mul_f = (pl->full ? 216.0 : 66.0) * pts;
     const double comb_f = (mode == MODE_CONV) ? 0.0 : 72.0 * vN3 / 3.0;
     int tok = prof_begin(pl, s);
-    HIPCHK(pl, pass_xfwd<R>(c, inr, t.tx_fwd, s));
+    HIPCHK(pl, (pass_xfwd<R, TV>(c, inr, t.tx_fwd, s)));
     prof_end(pl, f0 + 0, tok, s, vN3 * c16 + vN2P * cr, rows_x * fft_row);
     tok = prof_begin(pl, s);
     HIPCHK(pl, pass_yfwd<R>(c, t.ty_fwd, s));
@@ -468,7 +481,7 @@ int apply_typed(vie_plan* pl, const Geom& geom, const c128* in, const c128* addv
     HIPCHK(pl, pass_yinv<R>(c, t.ty_inv, s));
     prof_end(pl, f0 + 3, tok, s, (vN2P + vNP2) * cr, rows_y * fft_row);
     tok = prof_begin(pl, s);
-    HIPCHK(pl, pass_xinv<R>(c, addv ? addv + off : inr, bvec ? bvec + off : nullptr, outr, mode, t.tx_inv, s));
+    HIPCHK(pl, (pass_xinv<R, TV>(c, addv ? addv + off : inr, bvec ? bvec + off : nullptr, outr, mode, t.tx_inv, s)));
     prof_end(pl, f0 + 4, tok, s, xinv_b, rows_x * fft_row + comb_f);
   }
   return VIE_OK;
@@ -573,8 +586,12 @@ namespace vie {
 
 int apply_any(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
               c128* out, int nrhs, int mode, hipStream_t s) {
-  return fp64 ? apply_typed<double>(pl, g, in, addv, bvec, out, nrhs, mode, s)
-              : apply_typed<float>(pl, g, in, addv, bvec, out, nrhs, mode, s);
+  return fp64 ? apply_typed<double, c128>(pl, g, in, addv, bvec, out, nrhs, mode, s)
+              : apply_typed<float, c128>(pl, g, in, addv, bvec, out, nrhs, mode, s);
+}
+
+int apply_any(vie_plan* pl, const Geom& g, const c64* in, c64* out, int nrhs, hipStream_t s) {
+  return apply_typed<float, c64>(pl, g, in, in, nullptr, out, nrhs, MODE_MATVEC, s);
 }
 
 void clear_graphs(vie_plan* pl) {
@@ -582,27 +599,31 @@ void clear_graphs(vie_plan* pl) {
   pl->graphs.clear();
 }
 
-int apply_graph(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
-                c128* out, int nrhs, int mode, hipStream_t s) {
+namespace {
+
+// Replays the apply `run(stream)` from a hipGraph captured at its first call
+// with this key; eager when capture is off, while timing kernels, for chunked
+// batches, or before the first apply of this batch size (tiling and
+// workspace set up).
+template <typename F>
+int graph_or_eager(vie_plan* pl, const Geom& g, bool fp64, int nrhs, const vie_plan::GraphKey& key, hipStream_t s,
+                   F&& run) {
   const int idx = fp64 ? 1 : 0;
-  // eager when capture is off, while timing kernels, for chunked batches, or
-  // before the first apply of this batch size (tiling and workspace set up)
   if (!pl->use_graphs || pl->prof_on || nrhs > pl->max_rhs || pl->ws_cap[idx] < nrhs ||
       pl->tune[idx].find(tune_key(nrhs, g)) == pl->tune[idx].end())
-    return apply_any(pl, g, fp64, in, addv, bvec, out, nrhs, mode, s);
+    return run(s);
   if (!pl->gstream) {
     HIPCHK(pl, hipStreamCreateWithFlags(&pl->gstream, hipStreamNonBlocking));
     HIPCHK(pl, hipEventCreateWithFlags(&pl->gev_in, hipEventDisableTiming));
     HIPCHK(pl, hipEventCreateWithFlags(&pl->gev_out, hipEventDisableTiming));
   }
-  vie_plan::GraphKey key{idx, mode, nrhs, g.id, in, addv, bvec, out};
   auto it = pl->graphs.find(key);
   if (it == pl->graphs.end()) {
     if (pl->graphs.size() >= 512) clear_graphs(pl);
     std::lock_guard<std::recursive_mutex> lk(hip_mutex());
     hipGraph_t graph = nullptr;
     HIPCHK(pl, hipStreamBeginCapture(pl->gstream, hipStreamCaptureModeRelaxed));
-    const int rc = apply_any(pl, g, fp64, in, addv, bvec, out, nrhs, mode, pl->gstream);
+    const int rc = run(pl->gstream);
     const hipError_t ec = hipStreamEndCapture(pl->gstream, &graph);
     if (rc) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -622,6 +643,16 @@ int apply_graph(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c1
   HIPCHK(pl, hipStreamWaitEvent(s, pl->gev_out, 0));
   pl->graph_launches++;
   return VIE_OK;
+}
+
+}  // namespace
+
+int apply_graph(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
+                c128* out, int nrhs, int mode, hipStream_t s) {
+  const vie_plan::GraphKey key{fp64 ? 1 : 0, mode, nrhs, g.id, in, addv, bvec, out};
+  return graph_or_eager(pl, g, fp64, nrhs, key, s, [&](hipStream_t st) {
+    return apply_any(pl, g, fp64, in, addv, bvec, out, nrhs, mode, st);
+  });
 }
 
 }  // namespace vie
@@ -808,6 +839,12 @@ int vie_apply(vie_plan* pl, const double* x, double* y, int nrhs, unsigned flags
   if (flags & VIE_APPLY_FP64) fp64 = true;
   if (flags & VIE_APPLY_FP32) fp64 = false;
   const int mode = (flags & VIE_APPLY_CONV) ? MODE_CONV : MODE_MATVEC;
+  if (flags & VIE_APPLY_C64) {
+    if (fp64 || mode != MODE_MATVEC)
+      return fail(pl, VIE_E_ARG, "vie_apply: complex64 vectors need the FP32 matvec (no FP64, no CONV)");
+    return apply_any(pl, pl->grid, reinterpret_cast<const c64*>(x), reinterpret_cast<c64*>(y), nrhs,
+                     static_cast<hipStream_t>(hip_stream));
+  }
   const c128* in = reinterpret_cast<const c128*>(x);
   return apply_any(pl, pl->grid, fp64, in, in, nullptr, reinterpret_cast<c128*>(y), nrhs, mode,
                    static_cast<hipStream_t>(hip_stream));

@@ -216,8 +216,11 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const c128* __restrict__ box
 
 constexpr int kGroup = 8;  // basis vectors per accumulation sweep
 
-__global__ void __launch_bounds__(kBlock) k_dots(const c128* __restrict__ V, long vstride, long rstride,
-                                                 const c128* __restrict__ w, long L, int nv, long chunk,
+// TV, TW: storage of the basis and of w (complex128 or complex64); the
+// products are formed and summed in FP64.
+template <typename TV, typename TW>
+__global__ void __launch_bounds__(kBlock) k_dots(const TV* __restrict__ V, long vstride, long rstride,
+                                                 const TW* __restrict__ w, long L, int nv, long chunk,
                                                  c128* __restrict__ partials) {
   __shared__ double red[kBlock / 64][2 * kGroup];
   const int rhs = blockIdx.y;
@@ -225,8 +228,8 @@ __global__ void __launch_bounds__(kBlock) k_dots(const c128* __restrict__ V, lon
   const int nblk = gridDim.x;
   const long lo = long(blk) * chunk;
   const long hi = lo + chunk < L ? lo + chunk : L;
-  const c128* wr = w + rhs * rstride;
-  const c128* Vr = V + rhs * rstride;
+  const TW* wr = w + rhs * rstride;
+  const TV* Vr = V + rhs * rstride;
   const int nv1 = nv + 1;
   c128* out = partials + (long(rhs) * nblk + blk) * nv1;
   for (int g0 = 0; g0 < nv1; g0 += kGroup) {
@@ -234,12 +237,12 @@ __global__ void __launch_bounds__(kBlock) k_dots(const c128* __restrict__ V, lon
 #pragma unroll
     for (int q = 0; q < kGroup; ++q) ar[q] = ai[q] = 0.0;
     for (long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-      const c128 we = wr[e];
+      const c128 we = cvt<double>(wr[e]);
 #pragma unroll
       for (int q = 0; q < kGroup; ++q) {
         const int i = g0 + q;
         if (i < nv) {
-          const c128 v = Vr[long(i) * vstride + e];
+          const c128 v = cvt<double>(Vr[long(i) * vstride + e]);
           ar[q] += v.re * we.re + v.im * we.im;
           ai[q] += v.re * we.im - v.im * we.re;
         } else if (i == nv) {
@@ -300,19 +303,21 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const c128* __restrict__ part
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_combine(const c128* __restrict__ V, long vstride, long rstride,
-                                                    const c128* w, c128* out, long L, int nv,
+// TV, TW, TO: storage of the basis, of w and of out; arithmetic in FP64.
+template <typename TV, typename TW, typename TO>
+__global__ void __launch_bounds__(kBlock) k_combine(const TV* __restrict__ V, long vstride, long rstride,
+                                                    const TW* w, TO* out, long L, int nv,
                                                     const c128* __restrict__ coef, const double* __restrict__ scale) {
   const int rhs = blockIdx.y;
-  const c128* wr = w + rhs * rstride;
-  c128* outr = out + rhs * rstride;
-  const c128* Vr = V + rhs * rstride;
+  const TW* wr = w + rhs * rstride;
+  TO* outr = out + rhs * rstride;
+  const TV* Vr = V + rhs * rstride;
   const c128* cr = coef + long(rhs) * (nv > 0 ? nv : 1);
   const double sc = scale[rhs];
   for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < L; e += long(gridDim.x) * blockDim.x) {
-    c128 acc = wr[e];
-    for (int i = 0; i < nv; ++i) acc = acc - Vr[long(i) * vstride + e] * cr[i];
-    outr[e] = sc * acc;
+    c128 acc = cvt<double>(wr[e]);
+    for (int i = 0; i < nv; ++i) acc = acc - cvt<double>(Vr[long(i) * vstride + e]) * cr[i];
+    outr[e] = cvt<decltype(TO::re)>(sc * acc);
   }
 }
 
@@ -393,25 +398,35 @@ hipError_t launch_scatter(const c128* box, c128* full, long nv, const Box& g, hi
   return hipGetLastError();
 }
 
-hipError_t launch_dots(const c128* V, long vstride, long rstride, const c128* w, long L, int nv, int nrhs,
-                       int nblk, c128* partials, hipStream_t s) {
+template <typename TV, typename TW>
+hipError_t launch_dots(const TV* V, long vstride, long rstride, const TW* w, long L, int nv, int nrhs, int nblk,
+                       c128* partials, hipStream_t s) {
   const long chunk = (L + nblk - 1) / nblk;
-  k_dots<<<dim3(nblk, nrhs), kBlock, 0, s>>>(V, vstride, rstride, w, L, nv, chunk, partials);
+  k_dots<TV, TW><<<dim3(nblk, nrhs), kBlock, 0, s>>>(V, vstride, rstride, w, L, nv, chunk, partials);
   return hipGetLastError();
 }
+template hipError_t launch_dots<c128, c128>(const c128*, long, long, const c128*, long, int, int, int, c128*,
+                                            hipStream_t);
+
 
 hipError_t launch_reduce(const c128* partials, int nrhs, int nblk, int nv1, c128* out, hipStream_t s) {
   k_reduce<<<nrhs, kBlock, 0, s>>>(partials, nblk, nv1, out);
   return hipGetLastError();
 }
 
-hipError_t launch_combine(const c128* V, long vstride, long rstride, const c128* w, c128* out, long L, int nv,
+template <typename TV, typename TW, typename TO>
+hipError_t launch_combine(const TV* V, long vstride, long rstride, const TW* w, TO* out, long L, int nv,
                           const c128* coef, const double* scale, int nrhs, hipStream_t s) {
   long bx = (L + kBlock - 1) / kBlock;
   if (bx > 2048) bx = 2048;
-  k_combine<<<dim3(unsigned(bx), nrhs), kBlock, 0, s>>>(V, vstride, rstride, w, out, L, nv, coef, scale);
+  k_combine<TV, TW, TO><<<dim3(unsigned(bx), nrhs), kBlock, 0, s>>>(V, vstride, rstride, w, out, L, nv, coef, scale);
   return hipGetLastError();
 }
+#define VIE_COMBINE_INST(TV, TW, TO)                                                                        \
+  template hipError_t launch_combine<TV, TW, TO>(const TV*, long, long, const TW*, TO*, long, int, const c128*, \
+                                                 const double*, int, hipStream_t);
+VIE_COMBINE_INST(c128, c128, c128)
+#undef VIE_COMBINE_INST
 
 hipError_t launch_fill(c128* p, long n, c128 v, hipStream_t s) {
   k_fill<<<grid_for(n), kBlock, 0, s>>>(p, n, v);

@@ -34,12 +34,17 @@ hipError_t launch_scatter(const c128* box, c128* full, long nv, const Box& g, hi
 
 // Partial sums, per right-hand side r and block: conj(V_i) . w_r for i < nv and
 // ||w_r||^2 (slot nv).  V_i of rhs r at V + i * vstride + r * rstride.
-hipError_t launch_dots(const c128* V, long vstride, long rstride, const c128* w, long L, int nv, int nrhs,
-                       int nblk, c128* partials, hipStream_t s);
+// Products and sums in FP64 (vectors complex128; the kernel also reads other
+// storage types, instantiated where used).
+template <typename TV, typename TW>
+hipError_t launch_dots(const TV* V, long vstride, long rstride, const TW* w, long L, int nv, int nrhs, int nblk,
+                       c128* partials, hipStream_t s);
 // out[r][i] = sum over blocks of partials[r][blk][i], fixed order.
 hipError_t launch_reduce(const c128* partials, int nrhs, int nblk, int nv1, c128* out, hipStream_t s);
-// out_r = (w_r - sum_i V_i c[r][i]) * s[r]   (out may alias w)
-hipError_t launch_combine(const c128* V, long vstride, long rstride, const c128* w, c128* out, long L, int nv,
+// out_r = (w_r - sum_i V_i c[r][i]) * s[r]   (out may alias w), in FP64,
+// rounded to the storage of out (instantiated for complex128).
+template <typename TV, typename TW, typename TO>
+hipError_t launch_combine(const TV* V, long vstride, long rstride, const TW* w, TO* out, long L, int nv,
                           const c128* coef, const double* scale, int nrhs, hipStream_t s);
 hipError_t launch_fill(c128* p, long n, c128 v, hipStream_t s);
 hipError_t launch_copy(const c128* src, c128* dst, long n, hipStream_t s);

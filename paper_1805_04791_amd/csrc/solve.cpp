@@ -21,6 +21,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <complex>
 #include <vector>
 
@@ -36,12 +38,22 @@ using cd = std::complex<double>;
 
 inline size_t zu(long v) { return static_cast<size_t>(v); }
 
+// VIE_TRACE=1: one line per GMRES iteration and right-hand side on stderr
+bool trace_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("VIE_TRACE");
+    return v && *v && *v != '0';
+  }();
+  return on;
+}
+
 struct RhsState {
   double bnorm = 0, rnorm = 0;
   bool done = false, conv = false;
   int iters = 0, mv32 = 0, mv64 = 0, refine = 0;
 };
 
+// Work vectors for batches of `cap` right-hand sides and bases of m + 1 vectors.
 int ensure_krylov(vie_plan* pl, int cap, int m, hipStream_t s) {
   if (pl->kr_cap >= cap && pl->kr_m >= m) return VIE_OK;
   // pending copies may still read the old staging buffers
@@ -100,11 +112,12 @@ struct Batch {
 };
 
 // red[r][0..nv] <- (conj(V_i) . w_r, ||w_r||^2), copied to the host
-int dots_host(const Batch& b, const c128* V, const c128* w, int nv) {
+template <typename TV, typename TW>
+int dots_host(const Batch& b, const TV* V, const TW* w, int nv) {
   vie_plan* pl = b.pl;
   int tok = prof_begin(pl, b.s);
   HIPCHK(pl, launch_dots(V, b.vs, b.L, w, b.L, nv, b.nb, b.nblk, pl->partials, b.s));
-  prof_end(pl, FAM_DOTS, tok, b.s, double(nv + 1) * b.nb * double(b.L) * sizeof(c128),
+  prof_end(pl, FAM_DOTS, tok, b.s, (double(nv) * sizeof(TV) + sizeof(TW)) * b.nb * double(b.L),
            (8.0 * nv + 4.0) * b.nb * double(b.L));
   tok = prof_begin(pl, b.s);
   HIPCHK(pl, launch_reduce(pl->partials, b.nb, b.nblk, nv + 1, pl->red, b.s));
@@ -122,7 +135,8 @@ cd red_at(const Batch& b, int r, int i, int nv1) {
 }
 
 // out_r = (w_r - sum_{i<nv} V_i c[r][i]) * scale[r], coefficients from host arrays
-int combine_host(const Batch& b, const c128* V, const c128* w, c128* out, int nv, const std::vector<cd>& coef,
+template <typename TV, typename TW, typename TO>
+int combine_host(const Batch& b, const TV* V, const TW* w, TO* out, int nv, const std::vector<cd>& coef,
                  const std::vector<double>& scale) {
   vie_plan* pl = b.pl;
   const int stride = std::max(nv, 1);
@@ -151,14 +165,14 @@ int combine_host(const Batch& b, const c128* V, const c128* w, c128* out, int nv
   HIPCHK(pl, hipMemcpyAsync(sdv, sh, sizeof(double) * zu(b.nb), hipMemcpyHostToDevice, b.s));
   const int tok = prof_begin(pl, b.s);
   HIPCHK(pl, launch_combine(V, b.vs, b.L, w, out, b.L, nv, cdv, sdv, b.nb, b.s));
-  prof_end(pl, FAM_COMBINE, tok, b.s, double(nv + 2) * b.nb * double(b.L) * sizeof(c128),
+  prof_end(pl, FAM_COMBINE, tok, b.s, (double(nv) * sizeof(TV) + sizeof(TW) + sizeof(TO)) * b.nb * double(b.L),
            (8.0 * nv + 2.0) * b.nb * double(b.L));
   return VIE_OK;
 }
 
 // ||v_r|| for every slot
 int norms(const Batch& b, const c128* v, std::vector<double>& out) {
-  int rc = dots_host(b, nullptr, v, 0);
+  int rc = dots_host(b, static_cast<const c128*>(nullptr), v, 0);
   if (rc) return rc;
   out.resize(zu(b.nb));
   for (int r = 0; r < b.nb; ++r) out[zu(r)] = std::sqrt(std::max(0.0, red_at(b, r, 0, 1).real()));
@@ -168,9 +182,15 @@ int norms(const Batch& b, const c128* v, std::vector<double>& out) {
 // One GMRES(m) cycle on A d = r (r in rw, x += d in xw).  target[r]: absolute
 // residual at which slot r stops; active[r]: slot takes part; budget[r]:
 // matvecs it may still spend.
+// The basis stays complex128 in the FP32 inner cycles too: rounding it to
+// complex64 acts as a unit roundoff of 6e-8 in the classical Gram-Schmidt
+// bound above, and orthogonality is gone once the residual has dropped by
+// about 1e-4, before the inner target of 1e-5.
 int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rnorm, const std::vector<double>& target,
                 std::vector<RhsState>& st, const std::vector<bool>& active_in, const std::vector<int>& budget) {
   vie_plan* pl = b.pl;
+  c128* basis = pl->V;
+  c128* wv = pl->ww;
   const int nb = b.nb;
   std::vector<bool> active = active_in;
   std::vector<int> jend(static_cast<size_t>(nb), 0);
@@ -180,7 +200,7 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
   for (int r = 0; r < nb; ++r) scale[zu(r)] = (active[zu(r)] && rnorm[zu(r)] > 0) ? 1.0 / rnorm[zu(r)] : 0.0;
   for (int r = 0; r < nb; ++r)
     if (!(rnorm[zu(r)] > 0)) active[zu(r)] = false;
-  int rc = combine_host(b, nullptr, pl->rw, pl->V, 0, none, scale);
+  int rc = combine_host(b, static_cast<const c128*>(nullptr), pl->rw, basis, 0, none, scale);
   if (rc) return rc;
   // Hessenberg (column-major, (m+1) x m), rotations, rhs g
   std::vector<std::vector<cd>> Hs(static_cast<size_t>(nb), std::vector<cd>(zu((m + 1) * m)));
@@ -198,12 +218,12 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
     bool any = false;
     for (int r = 0; r < nb; ++r) any = any || active[zu(r)];
     if (!any) break;
-    const c128* Vj = pl->V + long(j) * b.vs;
-    c128* Vn = pl->V + long(j + 1) * b.vs;
-    rc = apply_graph(pl, pl->box, fp64, Vj, Vj, nullptr, pl->ww, nb, MODE_MATVEC, b.s);
+    const c128* Vj = basis + long(j) * b.vs;
+    c128* Vn = basis + long(j + 1) * b.vs;
+    rc = apply_graph(pl, pl->box, fp64, Vj, Vj, nullptr, wv, nb, MODE_MATVEC, b.s);
     if (rc) return rc;
     const int nv = j + 1;
-    rc = dots_host(b, pl->V, pl->ww, nv);
+    rc = dots_host(b, basis, wv, nv);
     if (rc) return rc;
     bool any_reorth = false;
     for (int r = 0; r < nb; ++r) {
@@ -225,9 +245,9 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
       for (int i = 0; i < nv; ++i) hcol[zu(r) * zu(nv + 1) + zu(i)] = h1[zu(r) * zu(nv) + zu(i)];
     if (any_reorth) {
       std::vector<double> one(static_cast<size_t>(nb), 1.0);
-      rc = combine_host(b, pl->V, pl->ww, pl->ww, nv, h1, one);  // w <- w - V h1
+      rc = combine_host(b, basis, wv, wv, nv, h1, one);  // w <- w - V h1
       if (rc) return rc;
-      rc = dots_host(b, pl->V, pl->ww, nv);
+      rc = dots_host(b, basis, wv, nv);
       if (rc) return rc;
       for (int r = 0; r < nb; ++r) {
         double beta2;
@@ -247,7 +267,7 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
         hcol[zu(r) * zu(nv + 1) + zu(nv)] = beta;
         scale[zu(r)] = (active[zu(r)] && beta > 1e-300) ? 1.0 / beta : 0.0;
       }
-      rc = combine_host(b, pl->V, pl->ww, Vn, nv, coef2, scale);
+      rc = combine_host(b, basis, wv, Vn, nv, coef2, scale);
       if (rc) return rc;
     } else {
       for (int r = 0; r < nb; ++r) {
@@ -255,7 +275,7 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
         hcol[zu(r) * zu(nv + 1) + zu(nv)] = beta;
         scale[zu(r)] = (active[zu(r)] && beta > 1e-300) ? 1.0 / beta : 0.0;
       }
-      rc = combine_host(b, pl->V, pl->ww, Vn, nv, h1, scale);
+      rc = combine_host(b, basis, wv, Vn, nv, h1, scale);
       if (rc) return rc;
     }
     // Givens update per active slot
@@ -299,6 +319,10 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
       jend[zu(r)] = j + 1;
       const double est = std::abs(gj1);
       const bool breakdown = !(hcol[zu(r) * zu(nv + 1) + zu(nv)].real() > 1e-300);
+      if (trace_on())
+        std::fprintf(stderr, "[vie] gmres%s rhs %d j %d est/r0 %.3e beta %.3e wp2/w2 %.3e reorth %d\n",
+                     fp64 ? "64" : "32", r, j, est / rnorm[zu(r)], hcol[zu(r) * zu(nv + 1) + zu(nv)].real(),
+                     wp2[zu(r)] / w2[zu(r)], int(reorth[zu(r)]));
       if (est <= target[zu(r)] || breakdown || S.mv32 + S.mv64 >= budget[zu(r)]) active[zu(r)] = false;
     }
   }
@@ -320,7 +344,7 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
     for (int i = 0; i < k; ++i) coef[zu(r) * zu(nvmax) + zu(i)] = -y[zu(i)];
   }
   std::vector<double> one(static_cast<size_t>(nb), 1.0);
-  return combine_host(b, pl->V, pl->xw, pl->xw, nvmax, coef, one);
+  return combine_host(b, static_cast<const c128*>(basis), pl->xw, pl->xw, nvmax, coef, one);
 }
 
 // Bi-CGStab on A d = r (r in rw, d accumulated into xw).  Work vectors in the
@@ -337,9 +361,10 @@ int bicgstab_run(const Batch& b, bool fp64, const std::vector<double>& rnorm0, c
   c128* t = pl->V + 4 * b.vs;
   std::vector<cd> none;
   std::vector<double> one(static_cast<size_t>(nb), 1.0), zero(zu(nb), 0.0);
-  int rc = combine_host(b, nullptr, pl->rw, rhat, 0, none, one);
-  if (!rc) rc = combine_host(b, nullptr, pl->rw, p, 0, none, zero);  // p = 0
-  if (!rc) rc = combine_host(b, nullptr, pl->rw, v, 0, none, zero);  // v = 0
+  const c128* nov = nullptr;
+  int rc = combine_host(b, nov, pl->rw, rhat, 0, none, one);
+  if (!rc) rc = combine_host(b, nov, pl->rw, p, 0, none, zero);  // p = 0
+  if (!rc) rc = combine_host(b, nov, pl->rw, v, 0, none, zero);  // v = 0
   if (rc) return rc;
   std::vector<cd> rho(static_cast<size_t>(nb), 1.0), alpha(zu(nb), 1.0), omg(zu(nb), 1.0);
   for (int r = 0; r < nb; ++r)
@@ -410,7 +435,7 @@ int bicgstab_run(const Batch& b, bool fp64, const std::vector<double>& rnorm0, c
       rc = combine_host(b, t, sv, pl->ww, 1, cRr, sc);
       if (rc) return rc;
     }
-    rc = dots_host(b, nullptr, pl->ww, 0);
+    rc = dots_host(b, nov, pl->ww, 0);
     if (rc) return rc;
     std::vector<double> nr(static_cast<size_t>(nb));
     for (int r = 0; r < nb; ++r) nr[zu(r)] = std::sqrt(std::max(0.0, red_at(b, r, 0, 1).real()));

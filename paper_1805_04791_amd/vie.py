@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libvie.so")
 LAPLACE, HELMHOLTZ, MAXWELL = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 PTR_HOST, STRICT_MEDIUM, NO_GRAPHS = 0x1, 0x2, 0x4
-APPLY_FP64, APPLY_FP32, APPLY_CONV = 0x1, 0x2, 0x4
+APPLY_FP64, APPLY_FP32, APPLY_CONV, APPLY_C64 = 0x1, 0x2, 0x4, 0x8
 SOLVER_GMRES, SOLVER_BICGSTAB = 0, 1
 SOLVE_X0, SOLVE_FP64 = 0x1, 0x2
 
@@ -191,8 +191,11 @@ class Plan:
 
     # -- operations --------------------------------------------------------------
     def apply(self, x, flags: int = 0, stream=None):
+        """y = A x.  With APPLY_C64 the vectors are complex64 (x is converted)."""
         torch = _torch()
         x = self._vec(x)
+        if flags & APPLY_C64:
+            x = x.to(torch.complex64)
         y = torch.empty_like(x)
         self._check(self.lib.vie_apply(self._h, x.data_ptr(), y.data_ptr(), x.shape[0], int(flags),
                                        _stream_ptr(stream)), "vie_apply")

@@ -105,6 +105,24 @@ def test_apply_fp32_matches_oracle(vie, n, name, kind, full):
     plan.close()
 
 
+@pytest.mark.parametrize("n", [16, 24])
+@pytest.mark.parametrize("name,kind,full", KINDS)
+def test_apply_complex64_vectors(vie, n, name, kind, full):
+    """The FP32 matvec on complex64 vectors: the oracle to FP32 accuracy, and
+    the complex128-vector FP32 matvec to the rounding of its output."""
+    plan, oper, *_ = make_plan(vie, kind, n, full, precision=vie.PREC_MIXED)
+    rng = gen.rng_for(gen.CONFIG_IDS["test"], 650 + n)
+    x = gen.random_density((2, oper.ncomp, n, n, n), rng).astype(np.complex64)
+    y32 = plan.apply(x, vie.APPLY_C64)
+    assert y32.dtype == torch.complex64
+    y32 = y32.cpu().numpy()
+    y = plan.apply(x.astype(np.complex128), vie.APPLY_FP32).cpu().numpy()
+    for r in range(2):
+        assert rel(y32[r], oper.apply(x[r].astype(np.complex128))) < 2e-6
+        assert rel(y32[r], y[r]) < 1e-7
+    plan.close()
+
+
 @pytest.mark.parametrize("name,kind,full", KINDS)
 def test_rhs_and_field_match_oracle(vie, name, kind, full):
     n = 16
