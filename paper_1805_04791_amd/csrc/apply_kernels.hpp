@@ -72,7 +72,7 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
   cx<R>* base = buf + rhs * a.rhs_stride + long(ky) * P + kx;
 
   // kUpfront: all inputs of the block in flight at once
-  constexpr int CU = kUpfront ? C : 1;
+  constexpr int CU = kUpfront<R> ? C : 1;
   cx<R> in[CU][H1];
   auto load_comp = [&](int c, cx<R>(&dst)[H1]) {
     const cx<R>* src = base + c * a.comp_stride;
@@ -81,18 +81,18 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
       dst[n1] = (valid && j < P2 && z < a.nz) ? src[long(z) * PP] : czero<R>();
     });
   };
-  if constexpr (kUpfront) static_for<0, C>([&](auto c) { load_comp(c, in[c]); });
+  if constexpr (kUpfront<R>) static_for<0, C>([&](auto c) { load_comp(c, in[c]); });
   __syncthreads();
   ThreadTw<R, P1, P2, kRegTwiddles<R>> twr;
   twr.init(tw, j);
 
   cx<R> X[C][P2];
   static_for<0, C>([&](auto c) {
-    if constexpr (!kUpfront) load_comp(c, in[0]);
+    if constexpr (!kUpfront<R>) load_comp(c, in[0]);
     cx<R> u[P1];
     static_for<0, P1>([&](auto n1) {
       if constexpr (decltype(n1)::value < H1)
-        u[n1] = in[kUpfront ? int(c) : 0][n1];
+        u[n1] = in[kUpfront<R> ? int(c) : 0][n1];
       else
         u[n1] = czero<R>();
     });
@@ -193,22 +193,22 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
   const long hrow = (long(a.z0) + zy / a.by) * N + (a.y0 + zy % a.by);  // (z, y) in the grid
 
   // kUpfront: all spectral inputs of the row in flight at once
-  constexpr int CU = kUpfront ? C : 1;
+  constexpr int CU = kUpfront<R> ? C : 1;
   cx<R> X[CU][P2];
   auto load_comp = [&](int c, cx<R>(&dst)[P2]) {
     const cx<R>* src = A + ((rhs * C + c) * NN + zy) * P;
     static_for<0, P2>([&](auto k2) { dst[k2] = (valid && j < P1) ? src[j + P1 * k2] : czero<R>(); });
   };
-  if constexpr (kUpfront) static_for<0, C>([&](auto c) { load_comp(c, X[c]); });
+  if constexpr (kUpfront<R>) static_for<0, C>([&](auto c) { load_comp(c, X[c]); });
   __syncthreads();
   ThreadTw<R, P1, P2, kRegTwiddles<R>> twr;
   twr.init(tw, j);
 
   cx<R> U[C][NV];
   static_for<0, C>([&](auto c) {
-    if constexpr (!kUpfront) load_comp(c, X[0]);
+    if constexpr (!kUpfront<R>) load_comp(c, X[0]);
     fft_inv_CD<R, P1, P2, true>(
-        X[kUpfront ? int(c) : 0],
+        X[kUpfront<R> ? int(c) : 0],
         [&](auto m2, int, cx<R> v) {
           if constexpr (decltype(m2)::value < NV) U[c][decltype(m2)::value] = v;
         },

@@ -33,23 +33,27 @@ struct scalar_of<cx<R>> {
   using type = R;
 };
 
-// Kernel variants.  kUpfront: the fused z / x-inverse passes issue the loads
-// of all components before the first transform (more bytes in flight, more
-// VGPRs).  kRegTwiddles<R>: per-thread twiddles held in registers.
+// Kernel variants.  kUpfront<R>: the fused z / x-inverse passes issue the
+// loads of all components before the first transform (more bytes in flight,
+// more VGPRs; FP32 only).  kRegTwiddles<R>: per-thread twiddles held in
+// registers.
 #ifndef VIE_ZVAR
 #define VIE_ZVAR 1
 #endif
-constexpr bool kUpfront = (VIE_ZVAR & 1) != 0;
+template <typename R>
+constexpr bool kUpfront = (VIE_ZVAR & 1) != 0 && sizeof(R) == 4;
 template <typename R>
 constexpr bool kRegTwiddles = (VIE_ZVAR & 2) != 0 && sizeof(R) == 4;
 
 // largest block of each kernel family (the tile choice keeps T*J within it)
 constexpr int kPassMaxThreads = 512;
 constexpr int kFusedMaxThreads = 512;
-// the FP64 six-component kernels need every register a wave can hold
+// The FP64 fused kernels hold three (or six) complex128 spectra per thread:
+// at most one wave per SIMD per block, so that a wave may use the whole
+// register file (VGPRs and AGPRs) instead of spilling to memory.
 template <typename R, int C>
 constexpr int fused_max_threads() {
-  return (sizeof(R) == 8 && C == 6) ? 256 : kFusedMaxThreads;
+  return sizeof(R) == 8 ? 256 : kFusedMaxThreads;
 }
 
 struct Geo {

@@ -369,7 +369,7 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStre
   Tune d;
   const int P = P1 * P2;
   d.tx_fwd = default_tile<R>(pl, P1, P2, true, kPassMaxThreads, P);
-  const int fmax = (sizeof(R) == 8 && pl->C == 6) ? 256 : kFusedMaxThreads;
+  const int fmax = pl->C == 6 ? fused_max_threads<R, 6>() : fused_max_threads<R, 3>();
   d.tx_inv = default_tile<R>(pl, P1, P2, true, fmax, P);
   d.ty_fwd = d.ty_inv = default_tile<R>(pl, P1, P2, false, kPassMaxThreads, P);
   d.tz = default_tile<R>(pl, P1, P2, false, fmax, P);
