@@ -170,10 +170,10 @@ int vie_field(vie_plan *pl, const double *density, const double *inc, double *fi
  * (tol 1e-10, restart 40, max_iters 2000, GMRES).  stats may be NULL, else an
  * array of nrhs entries.  Right-hand sides are solved together in fused
  * launches; each keeps its own convergence test, so its result does not
- * depend on the others in the batch.  The unknowns are the points of the
- * bounding box of supp(H) (vie_plan_info): the integral equation forces
- * J = 0 where H = 0, and density is written as exactly 0 there; with
- * VIE_SOLVE_X0 only the box part of the initial density is used.  Returns
+ * depend on the others in the batch.  The unknowns are the support rows of
+ * H (vie_plan_info): the integral equation forces J = 0 where H = 0, and
+ * density is written as exactly 0 outside them; with VIE_SOLVE_X0 only the
+ * initial density on them is used.  Returns
  * VIE_OK, VIE_W_NOCONV (the best iterate is written) or an error. */
 int vie_solve(vie_plan *pl, const double *inc, double *density, double *field, int nrhs,
               const vie_solve_opts *opts, vie_solve_stats *stats, void *hip_stream);
@@ -192,7 +192,10 @@ int vie_destroy(vie_plan *pl);
  * the box the solver works on: the bounding box of the points where H (or
  * H_mu) is non-zero, outside which the density vanishes (a single point if
  * H = 0 everywhere; the whole grid when VIE_BOX=0 is set in the
- * environment at plan creation). */
+ * environment at plan creation), out[14] = the solver's unknown points per
+ * component: in each (z, y) row of the box, the x-interval from the first to
+ * the last point where H (or H_mu) is non-zero (the whole box with
+ * VIE_ROWS=0, the whole grid with VIE_BOX=0). */
 int vie_plan_info(const vie_plan *pl, double *out, int nout);
 
 /* Copies the FP64 kernel-transform tables into host memory:

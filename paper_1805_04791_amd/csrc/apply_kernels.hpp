@@ -152,11 +152,13 @@ struct XArgs {
   int xcd_order;    // 1: row tiles of all right-hand sides back-to-back per XCD
   int bx, by, bz;   // extent of the data box (n, n, n for the whole grid)
   int x0, y0, z0;   // its corner in the grid
-  long vn3;         // bx * by * bz: points per component of the vectors
+  long np;          // points per component of the vectors
+  const int* rows;  // support rows (xa, len, off) per (z, y) row, or null: dense box
 };
 
 // Rows (rhs, z, y) of the data box: inverse x transform of every component,
-// then the pointwise combine.  Vectors J, B, out are [rhs][C][bz][by][bx],
+// then the pointwise combine.  Vectors J, B, out are [rhs][C][np]: the dense
+// box [bz][by][bx], or only the support samples of each row (a.rows),
 // J and out stored as TV (complex128, or complex64 for the FP32 Krylov basis
 // of the mixed solver), B as complex128; H, Hmu [9][n^3] on the whole grid.
 template <typename R, int P1, int P2, int C, int MODE, typename TV = c128>
@@ -216,11 +218,19 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
   });
 
   if (!valid || j >= P2) return;
-  const long vs = a.vn3;
+  const long vs = a.np;
+  // samples x of this row kept in the vectors: [xa, xa + len) at p0 + x
+  int xa = 0, xe = a.bx;
+  long p0 = zy * a.bx;
+  if (a.rows) {
+    xa = a.rows[3 * zy];
+    xe = xa + a.rows[3 * zy + 1];
+    p0 = long(a.rows[3 * zy + 2]) - xa;
+  }
   static_for<0, NV>([&](auto m2) {
     const int x = j + P2 * m2;
-    if (x >= a.bx) return;
-    const long p = zy * a.bx + x;             // point in the vectors' box layout
+    if (x >= a.bx || x < xa || x >= xe) return;
+    const long p = p0 + x;                    // point in the vectors' layout
     const long ph = hrow * N + (a.x0 + x);    // the same point in the grid (H)
     static_for<0, C / 3>([&](auto half) {
       constexpr int c0 = 3 * decltype(half)::value;

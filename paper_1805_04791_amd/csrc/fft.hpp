@@ -64,14 +64,47 @@ struct Geo {
   int nout;       // outputs written along the transform axis
 };
 
+// Sources of a pass: column(g, c) binds pencil (g, c) once per thread; the
+// bound column's load<R>(n) returns element n.
 // element n of pencil (g, c) lives at p + g*gs + c*cs + n*as
 template <typename T>
 struct MemLoad {
   const T* p;
   long gs, cs, as;
-  template <typename R>
-  __device__ __forceinline__ cx<R> load(long g, long c, int n) const {
-    return cvt<R>(p[g * gs + c * cs + long(n) * as]);
+  struct Col {
+    const T* q;
+    long as;
+    template <typename R>
+    __device__ __forceinline__ cx<R> load(int n) const {
+      return cvt<R>(q[long(n) * as]);
+    }
+  };
+  __device__ __forceinline__ Col column(long g, long c) const { return {p + g * gs + c * cs, as}; }
+};
+
+// Rows of a support-compressed vector: row c of the x pass is row r = c % nr
+// (a (z, y) row of the box) of component v = c / nr; the row holds only its
+// samples x in [xa, xa + len), stored at p + v * np + off + (x - xa).
+// rows[3 r .. 3 r + 2] = (xa, len, off).
+// (Row and component indices fit 32 bits: nrhs * C * rows < 2^31.)
+template <typename T>
+struct RowLoad {
+  const T* p;
+  const int* rows;
+  long nr, np;
+  struct Col {
+    const T* q;  // the row's first kept sample (x = xa)
+    int xa, len;
+    template <typename R>
+    __device__ __forceinline__ cx<R> load(int n) const {
+      const int i = n - xa;
+      return (i >= 0 && i < len) ? cvt<R>(q[i]) : czero<R>();
+    }
+  };
+  __device__ __forceinline__ Col column(long, long c) const {
+    const unsigned cu = unsigned(c), nru = unsigned(nr);
+    const unsigned r = cu % nru, v = cu / nru;
+    return {p + long(v) * np + rows[3 * r + 2], rows[3 * r], rows[3 * r + 1]};
   }
 };
 
@@ -235,7 +268,8 @@ __global__ void __launch_bounds__(kPassMaxThreads) k_pass(Src src, Dst dst, Geo 
   const long c = tile * geo.T + col;
   const bool valid = c < geo.ncols;
   cx<R> u[P1];
-  if constexpr (!INV) fft_load<R, P1, P2>([&](int n) { return src.template load<R>(g, c, n); }, geo.nin, j, valid, u);
+  const auto col_src = src.column(g, valid ? c : 0);
+  if constexpr (!INV) fft_load<R, P1, P2>([&](int n) { return col_src.template load<R>(n); }, geo.nin, j, valid, u);
   __syncthreads();
   ThreadTw<R, P1, P2, kRegTwiddles<R>> twr;
   twr.init(tw, j);
@@ -252,7 +286,7 @@ __global__ void __launch_bounds__(kPassMaxThreads) k_pass(Src src, Dst dst, Geo 
     if (j < P1) {
       static_for<0, P2>([&](auto k2) {
         const int n = j + P1 * k2;
-        X[k2] = (valid && n < geo.nin) ? src.template load<R>(g, c, n) : czero<R>();
+        X[k2] = (valid && n < geo.nin) ? col_src.template load<R>(n) : czero<R>();
       });
     }
     fft_inv_CD<R, P1, P2, CONTIG>(

@@ -20,6 +20,15 @@ struct SymbolSrc {
   int set;      // SYM_GRAD or SYM_MAXWELL
   int entry0;   // table entry of group 0
   double h, w, R;
+  struct Col {
+    const SymbolSrc* s;
+    long g, c;
+    template <typename Rt>
+    __device__ __forceinline__ cx<Rt> load(int n) const {
+      return s->template load<Rt>(g, c, n);
+    }
+  };
+  __device__ __forceinline__ Col column(long g, long c) const { return {this, g, c}; }
   // g = table entry - entry0, c = row index iz * M + iy, n = ix
   template <typename Rt>
   __device__ __forceinline__ cx<Rt> load(long g, long c, int n) const {
@@ -56,6 +65,8 @@ struct LenOps {
   // last inverse x pass with combine, C in {3, 6}, mode MODE_*
   hipError_t (*xinv)(int C, int mode, const cx<R>*, XArgs, const c128*, const c128*, const cx<R>*, const cx<R>*,
                      c128*, const cx<R>*, hipStream_t) = nullptr;
+  // x-axis forward pass reading the support rows of complex128 vectors
+  hipError_t (*contig_fwd_rows)(RowLoad<c128>, MemStore<cx<R>>, Geo, long ngroups, const cx<R>*, hipStream_t) = nullptr;
   // the same two passes with the vectors stored as complex64 (the FP32 Krylov
   // basis of the mixed solver; float only, MODE_MATVEC only)
   hipError_t (*contig_fwd_v32)(MemLoad<c64>, MemStore<cx<R>>, Geo, long ngroups, const cx<R>*, hipStream_t) = nullptr;
@@ -93,6 +104,12 @@ struct LenImpl {
                                hipStream_t s) {
     const long blocks = long(geo.ntiles) * ngroups;
     k_pass<R, P1, P2, true, false, MemLoad<c128>, MemStore<cx<R>>><<<dim3(unsigned(blocks)), dim3(geo.T * J), pass_lds_bytes<R, P1, P2, true>(geo.T), s>>>(src, dst, geo, tw);
+    return hipGetLastError();
+  }
+  static hipError_t contig_fwd_rows(RowLoad<c128> src, MemStore<cx<R>> dst, Geo geo, long ngroups,
+                                    const cx<R>* tw, hipStream_t s) {
+    const long blocks = long(geo.ntiles) * ngroups;
+    k_pass<R, P1, P2, true, false, RowLoad<c128>, MemStore<cx<R>>><<<dim3(unsigned(blocks)), dim3(geo.T * J), pass_lds_bytes<R, P1, P2, true>(geo.T), s>>>(src, dst, geo, tw);
     return hipGetLastError();
   }
   static hipError_t contig_fwd_v32(MemLoad<c64> src, MemStore<cx<R>> dst, Geo geo, long ngroups, const cx<R>* tw,
@@ -168,6 +185,7 @@ struct LenImpl {
     o.strided = &strided;
     if constexpr (APPLY) {
       o.contig_fwd = &contig_fwd;
+      o.contig_fwd_rows = &contig_fwd_rows;
       o.zpass = &zpass;
       o.xinv = &xinv;
       if constexpr (std::is_same<R, float>::value) {

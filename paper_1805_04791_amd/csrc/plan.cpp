@@ -239,14 +239,17 @@ struct ApplyCall {
 template <typename R, typename TV>
 hipError_t pass_xfwd(const ApplyCall<R>& c, const TV* in, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long rows = long(c.nb) * pl->C * c.g.bz * c.g.by;
+  const long nr = long(c.g.bz) * c.g.by;
+  const long rows = long(c.nb) * pl->C * nr;
   Geo g{T, int((rows + T - 1) / T), rows, c.g.bx, pl->P};
-  MemLoad<TV> src{in, 0, c.g.bx, 1};
   MemStore<cx<R>> dst{c.A, 0, pl->P, 1, 1.0, 0};
-  if constexpr (std::is_same<TV, c128>::value)
-    return c.ops->contig_fwd(src, dst, g, 1, c.tw, s);
-  else
-    return c.ops->contig_fwd_v32(src, dst, g, 1, c.tw, s);
+  if constexpr (std::is_same<TV, c128>::value) {
+    if (c.g.rows) return c.ops->contig_fwd_rows(RowLoad<c128>{in, c.g.rows, nr, c.g.np}, dst, g, 1, c.tw, s);
+    return c.ops->contig_fwd(MemLoad<c128>{in, 0, c.g.bx, 1}, dst, g, 1, c.tw, s);
+  } else {
+    if (c.g.rows) return hipErrorInvalidValue;
+    return c.ops->contig_fwd_v32(MemLoad<c64>{in, 0, c.g.bx, 1}, dst, g, 1, c.tw, s);
+  }
 }
 
 // y forward: A [rhs][c][bz][by][P] -> B [rhs][c][bz][P][P]
@@ -286,8 +289,8 @@ hipError_t pass_xinv(const ApplyCall<R>& c, const TV* addv, const c128* bvec, TV
   const vie_plan* pl = c.pl;
   const long NN = long(c.g.bz) * c.g.by;
   const int xcd = (NN % T == 0) && ((NN / T) % 8 == 0) ? 1 : 0;
-  XArgs a{T,        long(c.nb) * NN, pl->n,  pl->n3,  c.nb,    xcd,     c.g.bx,
-          c.g.by,   c.g.bz,          c.g.x0, c.g.y0,  c.g.z0,  c.g.vn3()};
+  XArgs a{T,      long(c.nb) * NN, pl->n,  pl->n3, c.nb,   xcd,  c.g.bx,
+          c.g.by, c.g.bz,          c.g.x0, c.g.y0, c.g.z0, c.g.np, c.g.rows};
   const cx<R>* H;
   const cx<R>* Hmu;
   if constexpr (std::is_same<R, float>::value) {
@@ -442,7 +445,7 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     tw = pl->tw64;
     tab = pl->tab64;
   }
-  const long L = long(pl->C) * geom.vn3();
+  const long L = long(pl->C) * geom.np;
   for (int r0 = 0; r0 < nrhs; r0 += chunk) {
     const int nb = std::min(chunk, nrhs - r0);
     ApplyCall<R> c{pl, ops, tw, static_cast<cx<R>*>(pl->wsA[idx]), static_cast<cx<R>*>(pl->wsB[idx]), nb, geom};
@@ -455,16 +458,16 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     const int f0 = std::is_same<R, double>::value ? FAM_XFWD64 : FAM_XFWD32;
     // algorithmic bytes: every operand read or written once per launch
     const double cr = double(sizeof(cx<R>)), c16 = double(sizeof(TV));
-    const double vN3 = double(nb) * pl->C * double(geom.vn3());
-    const double vN2P = vN3 / geom.bx * pl->P, vNP2 = vN2P / geom.by * pl->P;
-    const double hb = 9.0 * double(geom.vn3()) * cr * (pl->full ? 2 : 1);
+    const double vN3 = double(nb) * pl->C * double(geom.np);
+    const double vN2P = double(nb) * pl->C * geom.bz * geom.by * pl->P, vNP2 = vN2P / geom.by * pl->P;
+    const double hb = 9.0 * double(geom.np) * cr * (pl->full ? 2 : 1);
     const double xinv_b = vN2P * cr + hb * (mode == MODE_MATVEC || mode == MODE_RESIDUAL) +
                           vN3 * c16 * (1 + (mode != MODE_CONV)) + vN3 * sizeof(c128) * (mode == MODE_RESIDUAL);
     // nominal flops: 5 P log2 P per transformed pencil of length P; 66 per
     // frequency point for the 3x3 multiply (216 for the 6x6 Maxwell block);
     // 72 per point and 3-component half for the combine
     const double P = pl->P, fft_row = 5.0 * P * std::log2(P);
-    const double rows_x = vN3 / geom.bx, rows_y = vN2P / geom.by, rows_z = vNP2 / geom.bz;
+    const double rows_x = vN2P / P, rows_y = vN2P / geom.by, rows_z = vNP2 / geom.bz;
     const double pts = double(nb) * P * P * P;
     const double mul_f = (pl->full ? 216.0 : 66.0) * pts;
     const double comb_f = (mode == MODE_CONV) ? 0.0 : 72.0 * vN3 / 3.0;
@@ -688,6 +691,33 @@ void destroy_plan(vie_plan* pl) {
   delete pl;
 }
 
+// Support rows of the box: per (z, y) row the x-interval of the points where
+// H (or H_mu) is non-zero; the solver's vectors hold only these points.
+int build_rows(vie_plan* pl, hipStream_t s) {
+  const long nr = long(pl->box.by) * pl->box.bz;
+  int* xalen = nullptr;
+  int rc = dev_alloc(pl, reinterpret_cast<void**>(&xalen), sizeof(int) * 2 * size_t(nr));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->rows_d), sizeof(int) * 3 * size_t(nr));
+  if (rc) return rc;
+  HIPCHK(pl, launch_row_support(pl->H64, pl->full ? pl->Hmu64 : nullptr, box_of(pl->box, pl->n), xalen, s));
+  std::vector<int> h2(size_t(2 * nr)), h3(size_t(3 * nr));
+  HIPCHK(pl, hipMemcpyAsync(h2.data(), xalen, sizeof(int) * h2.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(pl, hipStreamSynchronize(s));
+  long off = 0;
+  for (long r = 0; r < nr; ++r) {
+    h3[size_t(3 * r)] = h2[size_t(2 * r)];
+    h3[size_t(3 * r + 1)] = h2[size_t(2 * r + 1)];
+    h3[size_t(3 * r + 2)] = int(off);
+    off += h2[size_t(2 * r + 1)];
+  }
+  HIPCHK(pl, hipMemcpyAsync(pl->rows_d, h3.data(), sizeof(int) * h3.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(pl, hipStreamSynchronize(s));
+  dev_free(pl, xalen);
+  pl->box.rows = pl->rows_d;
+  pl->box.np = off;
+  return VIE_OK;
+}
+
 int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   if (p->kind < VIE_LAPLACE || p->kind > VIE_MAXWELL) return fail(pl, VIE_E_ARG, "unknown kind");
   if (!p->coef) return fail(pl, VIE_E_ARG, "coef is NULL");
@@ -777,13 +807,19 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   dev_free(pl, bbad);
   dev_free(pl, bbox);
   // whole grid and the bounding box of supp(H) (a single point if H vanishes)
-  pl->grid = Geom{p->n, p->n, p->n, 0, 0, 0, 0};
+  pl->grid = Geom{p->n, p->n, p->n, 0, 0, 0, 0, nullptr, pl->n3};
   if (hi[0] < 0) {
     for (int a = 0; a < 3; ++a) lo[a] = hi[a] = 0;
   }
-  pl->box = Geom{hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1, lo[0], lo[1], lo[2], 1};
+  pl->box = Geom{hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1, lo[0], lo[1], lo[2], 1, nullptr, 0};
+  pl->box.np = long(pl->box.bx) * pl->box.by * pl->box.bz;
   pl->use_box = env_flag("VIE_BOX", true);
-  if (!pl->use_box) pl->box = pl->grid;
+  if (!pl->use_box) {
+    pl->box = pl->grid;
+  } else if (env_flag("VIE_ROWS", true)) {
+    rc = build_rows(pl, s);
+    if (rc) return rc;
+  }
   pl->hmax = worst;
   if (bad > 0)
     return fail(pl, VIE_E_MEDIUM, std::to_string(bad) + " grid points where a + I is singular or not finite");
@@ -870,11 +906,11 @@ int vie_field(vie_plan* pl, const double* density, const double* inc, double* fi
 
 int vie_plan_info(const vie_plan* pl, double* out, int nout) {
   if (!pl || !out) return VIE_E_ARG;
-  const double v[14] = {double(pl->n),         double(pl->C),      double(pl->P),      double(pl->M),
+  const double v[15] = {double(pl->n),         double(pl->C),      double(pl->P),      double(pl->M),
                         pl->hmax,              double(pl->ne),     double(pl->dev_bytes),
                         double(pl->graph_launches), double(pl->box.x0), double(pl->box.y0), double(pl->box.z0),
-                        double(pl->box.bx),    double(pl->box.by), double(pl->box.bz)};
-  for (int i = 0; i < nout && i < 14; ++i) out[i] = v[i];
+                        double(pl->box.bx),    double(pl->box.by), double(pl->box.bz), double(pl->box.np)};
+  for (int i = 0; i < nout && i < 15; ++i) out[i] = v[i];
   return VIE_OK;
 }
 

@@ -20,10 +20,11 @@ namespace vie {
 struct Geom {
   int bx = 0, by = 0, bz = 0;
   int x0 = 0, y0 = 0, z0 = 0;
-  int id = 0;  // 0 whole grid, 1 support box
-  long vn3() const { return long(bx) * by * bz; }
+  int id = 0;                // 0 whole grid, 1 solver geometry
+  const int* rows = nullptr; // support rows (xa, len, off) per (z, y) row; null: dense box
+  long np = 0;               // points per component of the vectors
 };
-inline Box box_of(const Geom& g, int n) { return Box{n, g.bx, g.by, g.bz, g.x0, g.y0, g.z0}; }
+inline Box box_of(const Geom& g, int n) { return Box{n, g.bx, g.by, g.bz, g.x0, g.y0, g.z0, g.rows, g.np}; }
 
 // tile choices of the five apply passes
 struct Tune {
@@ -44,8 +45,9 @@ struct vie_plan {
   double h = 0, omega = 0, R = 0, hmax = 0;
   long n3 = 0;
   bool full = false;  // mu present (6 unknowns per point)
-  vie::Geom grid, box;  // whole grid; bounding box of supp(H) (of H and H_mu)
+  vie::Geom grid, box;  // whole grid; the solver's: bounding box of supp(H) (and H_mu), support rows
   bool use_box = true;
+  int* rows_d = nullptr;  // device (xa, len, off) per (z, y) row of the box
   hipStream_t last_stream = nullptr;  // stream of the latest call (synchronised by vie_destroy)
   int device = 0;
   size_t max_lds = 65536;

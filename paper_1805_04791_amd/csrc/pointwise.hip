@@ -155,13 +155,48 @@ __global__ void __launch_bounds__(kBlock) k_contrast(const c128* __restrict__ co
   }
 }
 
-// grid index of box point p (box layout [bz][by][bx])
-__device__ __forceinline__ long box_to_grid(long p, const Box& g) {
-  const long x = p % g.bx, y = (p / g.bx) % g.by, z = p / (long(g.bx) * g.by);
+// grid index of box point q (dense box order [bz][by][bx])
+__device__ __forceinline__ long box_to_grid(long q, const Box& g) {
+  const long x = q % g.bx, y = (q / g.bx) % g.by, z = q / (long(g.bx) * g.by);
   return ((z + g.z0) * g.n + (y + g.y0)) * g.n + (x + g.x0);
 }
 
-// b = 2 H g on the box; g on the whole grid [rhs][C][n^3], b in box layout
+// index of box point q in the box vectors, or -1 if they do not hold it
+__device__ __forceinline__ long box_to_vec(long q, const Box& g) {
+  if (!g.rows) return q;
+  const long r = q / g.bx;
+  const int i = int(q % g.bx) - g.rows[3 * r];
+  return (i >= 0 && i < g.rows[3 * r + 1]) ? long(g.rows[3 * r + 2]) + i : -1;
+}
+
+__global__ void __launch_bounds__(kBlock) k_row_support(const c128* __restrict__ H, const c128* __restrict__ Hmu,
+                                                        Box g, int* __restrict__ xalen) {
+  const long n3 = long(g.n) * g.n * g.n;
+  const long nr = long(g.by) * g.bz;
+  for (long r = long(blockIdx.x) * blockDim.x + threadIdx.x; r < nr; r += long(gridDim.x) * blockDim.x) {
+    const long base = box_to_grid(r * g.bx, g);
+    int lo = -1, hi = -1;
+    for (int x = 0; x < g.bx; ++x) {
+      bool nz = false;
+      for (int e = 0; e < 9; ++e) {
+        const c128 h = H[e * n3 + base + x];
+        nz = nz || h.re != 0.0 || h.im != 0.0;
+        if (Hmu) {
+          const c128 m = Hmu[e * n3 + base + x];
+          nz = nz || m.re != 0.0 || m.im != 0.0;
+        }
+      }
+      if (nz) {
+        if (lo < 0) lo = x;
+        hi = x;
+      }
+    }
+    xalen[2 * r] = lo < 0 ? 0 : lo;
+    xalen[2 * r + 1] = lo < 0 ? 0 : hi - lo + 1;
+  }
+}
+
+// b = 2 H g on the box; g on the whole grid [rhs][C][n^3], b in box vector layout
 __global__ void __launch_bounds__(kBlock) k_rhs(const c128* __restrict__ H, const c128* __restrict__ Hmu,
                                                 const c128* __restrict__ inc, c128* __restrict__ b, int nrhs,
                                                 int C, Box g) {
@@ -169,19 +204,21 @@ __global__ void __launch_bounds__(kBlock) k_rhs(const c128* __restrict__ H, cons
   const long n3 = long(g.n) * g.n * g.n;
   const long total = long(nrhs) * (C / 3) * vn3;
   for (long t = long(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
-    const long p = t % vn3;
+    const long q = t % vn3;
     const long rh = t / vn3;  // rhs * (C/3) + half
+    const long p = box_to_vec(q, g);
+    if (p < 0) continue;
     const int half = int(rh % (C / 3));
     const c128* Hh = half == 0 ? H : Hmu;
-    const long ph = box_to_grid(p, g);
-    const long vb = rh * 3 * vn3 + p;
+    const long ph = box_to_grid(q, g);
+    const long vb = rh * 3 * g.np + p;
     const long gb = rh * 3 * n3 + ph;
     c128 v[3];
     for (int c = 0; c < 3; ++c) v[c] = inc[gb + c * n3];
     for (int r = 0; r < 3; ++r) {
       c128 acc = {0.0, 0.0};
       for (int c = 0; c < 3; ++c) acc = acc + Hh[(3 * r + c) * n3 + ph] * v[c];
-      b[vb + r * vn3] = 2.0 * acc;
+      b[vb + r * g.np] = 2.0 * acc;
     }
   }
 }
@@ -193,23 +230,25 @@ __global__ void __launch_bounds__(kBlock) k_gather(const c128* __restrict__ full
   const long n3 = long(g.n) * g.n * g.n;
   const long total = nv * vn3;
   for (long t = long(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
-    const long p = t % vn3, c = t / vn3;
-    box[t] = full[c * n3 + box_to_grid(p, g)];
+    const long q = t % vn3, c = t / vn3;
+    const long p = box_to_vec(q, g);
+    if (p >= 0) box[c * g.np + p] = full[c * n3 + box_to_grid(q, g)];
   }
 }
 
 // grid <- box with zeros outside the box (scatter), over the whole grid
 __global__ void __launch_bounds__(kBlock) k_scatter(const c128* __restrict__ box, c128* __restrict__ full, long nv,
                                                     Box g) {
-  const long vn3 = long(g.bx) * g.by * g.bz;
   const long n3 = long(g.n) * g.n * g.n;
   const long total = nv * n3;
   for (long t = long(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
     const long ph = t % n3, c = t / n3;
     const int x = int(ph % g.n) - g.x0, y = int((ph / g.n) % g.n) - g.y0, z = int(ph / (long(g.n) * g.n)) - g.z0;
     c128 v = {0.0, 0.0};
-    if (x >= 0 && x < g.bx && y >= 0 && y < g.by && z >= 0 && z < g.bz)
-      v = box[c * vn3 + (long(z) * g.by + y) * g.bx + x];
+    if (x >= 0 && x < g.bx && y >= 0 && y < g.by && z >= 0 && z < g.bz) {
+      const long p = box_to_vec((long(z) * g.by + y) * g.bx + x, g);
+      if (p >= 0) v = box[c * g.np + p];
+    }
     full[t] = v;
   }
 }
@@ -385,6 +424,11 @@ hipError_t launch_contrast(const c128* coef, c128* H64, c64* H32, int n, double*
 hipError_t launch_rhs(const c128* H, const c128* Hmu, const c128* inc, c128* b, int nrhs, int C, const Box& g,
                       hipStream_t s) {
   k_rhs<<<grid_for(long(nrhs) * (C / 3) * g.bx * g.by * g.bz), kBlock, 0, s>>>(H, Hmu, inc, b, nrhs, C, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_support(const c128* H, const c128* Hmu, const Box& g, int* xalen, hipStream_t s) {
+  k_row_support<<<grid_for(long(g.by) * g.bz), kBlock, 0, s>>>(H, Hmu, g, xalen);
   return hipGetLastError();
 }
 

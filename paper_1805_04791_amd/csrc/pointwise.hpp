@@ -8,12 +8,21 @@
 namespace vie {
 
 // A box of the n^3 grid: extent (bx, by, bz), corner (x0, y0, z0).  Box
-// vectors are laid out [bz][by][bx] per component.
+// vectors are laid out [bz][by][bx] per component, or, when rows is set,
+// hold only the samples [xa, xa + len) of each (z, y) row r = z * by + y,
+// at offset off (rows[3 r .. 3 r + 2] = xa, len, off; np points in all).
 struct Box {
   int n;
   int bx, by, bz;
   int x0, y0, z0;
+  const int* rows;
+  long np;
 };
+
+// Support rows of a box: for each (z, y) row, the first x and the count of
+// samples from the first to the last point where H (or H_mu, if given) has a
+// non-zero entry (0, 0 for a row without such points).  xalen[2 r], xalen[2 r + 1].
+hipError_t launch_row_support(const c128* H, const c128* Hmu, const Box& g, int* xalen, hipStream_t s);
 
 // H = (a + I)^{-1} (a - I) = I - 2 (a + I)^{-1} at every point (eq. rhodef).
 // Writes H in FP64 and FP32, and per block: max ||H||_2 (blk_max), the count
@@ -24,12 +33,13 @@ hipError_t launch_contrast(const c128* coef, c128* H64, c64* H32, int n, double*
                            int* blk_box, int nblocks, hipStream_t s);
 
 // b = 2 H g per 3-component half (H for the first half, Hmu for the second),
-// at the points of box g: inc on the whole grid [nrhs][C][n^3], b in box layout.
+// at the points of box g: inc on the whole grid [nrhs][C][n^3], b in box layout
+// (dense or support rows).
 hipError_t launch_rhs(const c128* H, const c128* Hmu, const c128* inc, c128* b, int nrhs, int C, const Box& g,
                       hipStream_t s);
 // box[v] <- full[v] restricted to the box, v < nv components
 hipError_t launch_gather(const c128* full, c128* box, long nv, const Box& g, hipStream_t s);
-// full[v] <- box[v] inside the box, 0 outside, v < nv components
+// full[v] <- box[v] at the points the box vectors hold, 0 elsewhere, v < nv components
 hipError_t launch_scatter(const c128* box, c128* full, long nv, const Box& g, hipStream_t s);
 
 // Partial sums, per right-hand side r and block: conj(V_i) . w_r for i < nv and

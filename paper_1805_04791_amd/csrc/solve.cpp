@@ -79,7 +79,7 @@ int ensure_krylov(vie_plan* pl, int cap, int m, hipStream_t s) {
   pl->red_host = pl->coef_host = nullptr;
   pl->scale_host = nullptr;
   pl->kr_cap = pl->kr_m = 0;
-  const size_t L = zu(pl->C) * zu(pl->box.vn3());  // vectors live on the support box
+  const size_t L = zu(pl->C) * zu(pl->box.np);  // vectors hold the support rows of the box
   const size_t nblk = zu(krylov_blocks(long(L)));
   const size_t vec = sizeof(c128) * L * zu(cap);
   int rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->V), vec * zu(m + 1));
@@ -480,8 +480,9 @@ int solve_batch(vie_plan* pl, const c128* inc, c128* density, c128* field, int n
   const bool mixed = pl->precision == VIE_PREC_MIXED && !(o.flags & VIE_SOLVE_FP64);
   const int m = o.solver == VIE_SOLVER_BICGSTAB ? 5 : std::max(1, o.restart);
   // Outside supp(H) the equation gives J = 0 exactly, so the unknowns are
-  // the points of the bounding box of supp(H); U is needed only there too.
-  const long L = long(pl->C) * pl->box.vn3();
+  // the points of supp(H): per (z, y) row of its bounding box, the x-interval
+  // from the first to the last support point.  U is needed only there too.
+  const long L = long(pl->C) * pl->box.np;
   const long Lg = long(pl->C) * pl->n3;
   const Box box = box_of(pl->box, pl->n);
   const int cap = std::max(1, std::min(nrhs, pl->max_rhs));

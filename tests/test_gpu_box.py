@@ -1,11 +1,13 @@
-"""Support-box restriction of the solver (GPU, through the C ABI).
+"""Support restriction of the solver (GPU, through the C ABI).
 
-Where H(x) = 0 the integral equation reads J(x) = 0, so the solver keeps its
-unknowns on the bounding box of supp(H) only.  These tests check that the box
-the library finds is exactly the bounding box of the oracle contrast's
-support, that solves on ragged, off-centre boxes agree with the oracle's
-full-grid solution, that the density is exactly zero outside the box, and
-that a box solve agrees with the whole-grid solve.
+Where H(x) = 0 the integral equation reads J(x) = 0, so the solver keeps as
+unknowns only the support rows of H: in each (z, y) row of the bounding box
+of supp(H), the x-interval from the first to the last support point.  These
+tests check that the box and the row intervals the library finds are exactly
+those of the oracle contrast, that solves on ragged, off-centre supports
+agree with the oracle's full-grid solution, that the density is exactly zero
+outside the support rows, and that the restricted solve agrees with the
+whole-grid and dense-box solves.
 """
 
 import math
@@ -51,6 +53,18 @@ def support_box(*Hs):
             int(xs.max() - xs.min() + 1), int(ys.max() - ys.min() + 1), int(zs.max() - zs.min() + 1))
 
 
+def support_rows_mask(*Hs):
+    """Points of the support rows: per (z, y), x from the first to the last support point."""
+    nz = np.zeros(Hs[0].shape[-3:], dtype=bool)
+    for H in Hs:
+        nz |= np.any(H.reshape(9, *H.shape[-3:]) != 0, axis=0)
+    mask = np.zeros_like(nz)
+    for z, y in zip(*np.nonzero(nz.any(axis=2))):
+        xs = np.nonzero(nz[z, y])[0]
+        mask[z, y, xs.min():xs.max() + 1] = True
+    return mask
+
+
 def plane_waves(n, omega, count, item):
     out = []
     for j in range(count):
@@ -82,7 +96,9 @@ def test_box_is_support_bounding_box(vie):
              gen.identity_field(n)]
     for c in cases:
         plan = vie.Plan(op.KIND_HELMHOLTZ, c, omega=omega, precision=vie.PREC_MIXED)
-        assert plan.info()["box"] == support_box(op.contrast(c)), plan.info()["box"]
+        H = op.contrast(c)
+        assert plan.info()["box"] == support_box(H), plan.info()["box"]
+        assert plan.info()["unknown_points"] == int(support_rows_mask(H).sum())
         plan.close()
 
 
@@ -93,7 +109,9 @@ def test_box_union_of_eps_and_mu_supports(vie):
     eps = masked(eps, (Z > 0.0).astype(float))
     mu = masked(mu, (X < -0.2).astype(float))
     plan = vie.Plan(op.KIND_MAXWELL, eps, omega=omega, mu=mu, precision=vie.PREC_MIXED)
-    assert plan.info()["box"] == support_box(op.contrast(eps), op.contrast(mu))
+    He, Hm = op.contrast(eps), op.contrast(mu)
+    assert plan.info()["box"] == support_box(He, Hm)
+    assert plan.info()["unknown_points"] == int(support_rows_mask(He, Hm).sum())
     plan.close()
 
 
@@ -107,8 +125,7 @@ def test_offcentre_box_solve_matches_oracle(vie, n):
     plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2)
     x0, y0, z0, bx, by, bz = plan.info()["box"]
     assert (bx, by, bz) != (n, n, n)
-    inside = np.zeros((n, n, n), dtype=bool)
-    inside[z0:z0 + bz, y0:y0 + by, x0:x0 + bx] = True
+    inside = support_rows_mask(op.contrast(coef))
     for fp64, tol, err in ((True, 1e-12, 1e-10), (False, 1e-9, 1e-8)):
         d, f, st, rc = plan.solve(inc, tol=tol, fp64=fp64)
         assert rc == vie.OK
@@ -139,30 +156,37 @@ def test_offcentre_box_full_maxwell_matches_oracle(vie):
     plan.close()
 
 
-def test_box_solve_equals_whole_grid_solve(vie, monkeypatch):
+def test_restricted_solve_equals_whole_grid_solve(vie, monkeypatch):
     n = 24
     coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 15)
     inc = plane_waves(n, omega, 3, 10)
     monkeypatch.setenv("VIE_BOX", "0")
     whole = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
     monkeypatch.delenv("VIE_BOX")
-    boxed = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
-    assert whole.info()["box"] == (0, 0, 0, n, n, n)
-    assert boxed.info()["box"] != (0, 0, 0, n, n, n)
+    monkeypatch.setenv("VIE_ROWS", "0")
+    dense = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
+    monkeypatch.delenv("VIE_ROWS")
+    rows = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
+    assert whole.info()["box"] == (0, 0, 0, n, n, n) and whole.info()["unknown_points"] == n ** 3
+    box = dense.info()["box"]
+    assert box != (0, 0, 0, n, n, n) and dense.info()["unknown_points"] == box[3] * box[4] * box[5]
+    assert rows.info()["box"] == box and rows.info()["unknown_points"] < 0.7 * box[3] * box[4] * box[5]
     for fp64, tol, err in ((True, 1e-12, 1e-10), (False, 1e-10, 1e-9)):
         dw, _, sw, _ = whole.solve(inc, tol=tol, fp64=fp64, want_field=False)
-        db, _, sb, _ = boxed.solve(inc, tol=tol, fp64=fp64, want_field=False)
-        dw, db = dw.cpu().numpy(), db.cpu().numpy()
-        for r in range(3):
-            assert rel(db[r], dw[r]) < err
-            assert abs(sb[r]["iters"] - sw[r]["iters"]) <= 2
-    whole.close()
-    boxed.close()
+        dw = dw.cpu().numpy()
+        for plan in (dense, rows):
+            d, _, st, _ = plan.solve(inc, tol=tol, fp64=fp64, want_field=False)
+            d = d.cpu().numpy()
+            for r in range(3):
+                assert rel(d[r], dw[r]) < err
+                assert abs(st[r]["iters"] - sw[r]["iters"]) <= 2
+    for plan in (whole, dense, rows):
+        plan.close()
 
 
-def test_x0_outside_box_is_ignored(vie):
-    """A warm start is restricted to the box: values outside it cannot
-    change the solution (the equation fixes J = 0 there)."""
+def test_x0_outside_support_rows_is_ignored(vie):
+    """A warm start is restricted to the support rows: values elsewhere
+    cannot change the solution (the equation fixes J = 0 there)."""
     n = 16
     coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 16)
     coef = masked(coef, offcentre_mask(n))
@@ -170,10 +194,8 @@ def test_x0_outside_box_is_ignored(vie):
     plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_FP64)
     d1, _, _, _ = plan.solve(inc, tol=1e-12, max_iters=4, restart=4, want_field=False)
     d1 = d1.cpu().numpy()
-    x0, y0, z0, bx, by, bz = plan.info()["box"]
     junk = d1.copy()
-    outside = np.ones((n, n, n), dtype=bool)
-    outside[z0:z0 + bz, y0:y0 + by, x0:x0 + bx] = False
+    outside = ~support_rows_mask(op.contrast(coef))
     junk[:, :, outside] = 1e3
     da, _, sa, _ = plan.solve(inc, tol=1e-12, x0=d1, want_field=False)
     db, _, sb, _ = plan.solve(inc, tol=1e-12, x0=junk, want_field=False)
