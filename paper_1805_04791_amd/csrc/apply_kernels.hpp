@@ -31,9 +31,9 @@ enum { MODE_MATVEC = 0, MODE_FIELD = 1, MODE_CONV = 2, MODE_RESIDUAL = 3 };
 struct ZArgs {
   int T;            // kx columns per block
   int ntiles;       // P / T
-  int n;            // grid points per axis (the tables' octant is [0, n])
+  int n;            // grid points per axis (the tables' octant is [0, n]; n = P / 2)
   int P;            // 2n
-  int nxp;          // padded octant row length (>= n + 1)
+  int nxp;          // padded octant row length (n + 1 rounded up to 16)
   int ne;           // table entries (6 or 9)
   long comp_stride; // n * P * P
   long rhs_stride;  // C * n * P * P
@@ -100,27 +100,38 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
   });
 
   if (j < P1 && valid) {
-    const int N = a.n;
+    // table geometry follows from P: octant [0, N]^3, rows of NXP (N + 1
+    // padded to 16) per entry, NE entries per (qz, qy)
+    constexpr int N = P / 2;
+    constexpr int NXP = ((N + 1 + 15) / 16) * 16;
+    constexpr int NE = MUL == MUL_SYM3 ? 6 : 9;
+    constexpr int ROW = NE * NXP;
+    static_assert(P2 % 2 == 0, "the z fold assumes P2 even");
     const int fy = ky <= N ? ky : P - ky;
     const int fx = kx <= N ? kx : P - kx;
     const R sy = ky > N ? R(-1) : R(1);
     const R sx = kx > N ? R(-1) : R(1);
+    const R sxy = sx * sy;
+    const cx<R>* tb = tab + (fy * ROW + fx);  // offsets below 2^31 elements
     static_for<0, P2>([&](auto k2) {
-      const int kz = j + P1 * k2;
-      const int fz = kz <= N ? kz : P - kz;
-      const R sz = kz > N ? R(-1) : R(1);
-      const cx<R>* t = tab + (long(fz * (N + 1) + fy) * a.ne) * a.nxp + fx;
-      const cx<R> kxx = t[0], kyy = t[a.nxp], kzz = t[2 * a.nxp];
-      const cx<R> kxy = (sx * sy) * t[3 * a.nxp];
-      const cx<R> kxz = (sx * sz) * t[4 * a.nxp];
-      const cx<R> kyz = (sy * sz) * t[5 * a.nxp];
+      // kz = j + P1 k2 < N exactly when k2 < P2 / 2.  The entries odd in s_z
+      // vanish on the plane kz = N, so taking the folded side there is exact.
+      constexpr bool upper = 2 * decltype(k2)::value >= P2;
+      constexpr R sz = upper ? R(-1) : R(1);
+      const int kz = j + P1 * decltype(k2)::value;
+      const int fz = upper ? P - kz : kz;
+      const cx<R>* t = tb + fz * ((N + 1) * ROW);
+      const cx<R> kxx = t[0], kyy = t[NXP], kzz = t[2 * NXP];
+      const cx<R> kxy = sxy * t[3 * NXP];
+      const cx<R> kxz = (sx * sz) * t[4 * NXP];
+      const cx<R> kyz = (sy * sz) * t[5 * NXP];
       if constexpr (MUL == MUL_SYM3) {
         const cx<R> x0 = X[0][k2], x1 = X[1][k2], x2 = X[2][k2];
         X[0][k2] = kxx * x0 + kxy * x1 + kxz * x2;
         X[1][k2] = kxy * x0 + kyy * x1 + kyz * x2;
         X[2][k2] = kxz * x0 + kyz * x1 + kzz * x2;
       } else {
-        const cx<R> cxv = sx * t[6 * a.nxp], cyv = sy * t[7 * a.nxp], czv = sz * t[8 * a.nxp];
+        const cx<R> cxv = sx * t[6 * NXP], cyv = sy * t[7 * NXP], czv = sz * t[8 * NXP];
         const cx<R> j0 = X[0][k2], j1 = X[1][k2], j2 = X[2][k2];
         const cx<R> m0 = X[3][k2], m1 = X[4][k2], m2 = X[5][k2];
         // c x m and c x j
@@ -136,9 +147,10 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
     });
   }
 
+  // outputs z < nz <= N: only m2 < P1 / 2 of the last step are ever stored
   static_for<0, C>([&](auto c) {
     cx<R>* dst = base + c * a.comp_stride;
-    fft_inv_CD<R, P1, P2, false>(
+    fft_inv_CD<R, P1, P2, false, P1 / 2>(
         X[c], [&](auto, int z, cx<R> v) { dst[long(z) * PP] = v; }, a.nz, lds, twr, col, j, a.T, valid);
   });
 }
@@ -209,7 +221,7 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
   cx<R> U[C][NV];
   static_for<0, C>([&](auto c) {
     if constexpr (!kUpfront<R>) load_comp(c, X[0]);
-    fft_inv_CD<R, P1, P2, true>(
+    fft_inv_CD<R, P1, P2, true, NV>(
         X[kUpfront<R> ? int(c) : 0],
         [&](auto m2, int, cx<R> v) {
           if constexpr (decltype(m2)::value < NV) U[c][decltype(m2)::value] = v;

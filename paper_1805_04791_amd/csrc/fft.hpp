@@ -224,8 +224,10 @@ __device__ __forceinline__ void fft_fwd_AB(LoadF&& load, int nin, cx<R>* lds, co
 }
 
 // Step C + D.  Threads with j < P1 supply X[j + P1 k2] in X[k2] (destroyed).
-// store(m2, n, v) is called for n = j + P2 m2 < nout only (m2 is a compile-time index).
-template <typename R, int P1, int P2, bool CONTIG, typename StoreF, typename TW>
+// store(m2, n, v) is called for n = j + P2 m2 < nout only (m2 is a compile-time
+// index), and only for m2 < M2MAX: the outputs of the last step beyond it are
+// never formed (M2MAX = P1 / 2 covers nout <= P / 2).
+template <typename R, int P1, int P2, bool CONTIG, int M2MAX = P1, typename StoreF, typename TW>
 __device__ __forceinline__ void fft_inv_CD(cx<R> (&X)[P2], StoreF&& store, int nout, cx<R>* lds, const TW& twr,
                                            int col, int j, int T, bool valid) {
   if (j < P1) {
@@ -238,7 +240,7 @@ __device__ __forceinline__ void fft_inv_CD(cx<R> (&X)[P2], StoreF&& store, int n
     cx<R> u[P1];
     static_for<0, P1>([&](auto k1) { u[k1] = lds[Layout<CONTIG>::idx(col, k1, j, P2, P1, T)]; });
     DFT<P1, true>::run(u);
-    static_for<0, P1>([&](auto m2) {
+    static_for<0, M2MAX>([&](auto m2) {
       const int n = j + P2 * m2;
       if (valid && n < nout) store(m2, n, u[m2]);
     });
@@ -289,7 +291,9 @@ __global__ void __launch_bounds__(kPassMaxThreads) k_pass(Src src, Dst dst, Geo 
         X[k2] = (valid && n < geo.nin) ? col_src.template load<R>(n) : czero<R>();
       });
     }
-    fft_inv_CD<R, P1, P2, CONTIG>(
+    // every inverse pass keeps at most the first half of its outputs (the
+    // launchers check nout <= P / 2)
+    fft_inv_CD<R, P1, P2, CONTIG, P1 / 2>(
         X, [&](auto, int n, cx<R> v) { dst.template store<R>(g, c, n, v); }, geo.nout, lds, twr, col, j, geo.T, valid);
   }
 }

@@ -132,6 +132,7 @@ struct LenImpl {
   static hipError_t strided(bool inv, MemLoad<cx<R>> src, MemStore<cx<R>> dst, Geo geo, long ngroups,
                             const cx<R>* tw, hipStream_t s) {
     const long blocks = long(geo.ntiles) * ngroups;
+    if (inv && 2 * geo.nout > P) return hipErrorInvalidValue;  // inverse passes keep outputs < P / 2
     if (inv)
       k_pass<R, P1, P2, false, true, MemLoad<cx<R>>, MemStore<cx<R>>><<<dim3(unsigned(blocks)), dim3(geo.T * J), pass_lds_bytes<R, P1, P2, false>(geo.T), s>>>(src, dst, geo, tw);
     else
@@ -140,6 +141,9 @@ struct LenImpl {
   }
   static hipError_t zpass(int mul, cx<R>* buf, const cx<R>* tab, ZArgs a, long nblocks, const cx<R>* tw,
                           hipStream_t s) {
+    // the kernel takes the table geometry from P
+    if (2 * a.n != P || a.nxp != ((a.n + 1 + 15) / 16) * 16 || a.ne != (mul == MUL_SYM3 ? 6 : 9) || 2 * a.nz > P)
+      return hipErrorInvalidValue;
     const size_t lds = pass_lds_bytes<R, P1, P2, false>(a.T);
     if (mul == MUL_SYM3)
       k_zpass<R, P1, P2, 3, MUL_SYM3><<<dim3(unsigned(nblocks)), dim3(a.T * J), lds, s>>>(buf, tab, a, tw);
@@ -171,6 +175,7 @@ struct LenImpl {
   static hipError_t symbol_inv(SymbolSrc src, MemStore<c128> dst, Geo geo, long ngroups, const c128* tw,
                                hipStream_t s) {
     const long blocks = long(geo.ntiles) * ngroups;
+    if (2 * geo.nout > P) return hipErrorInvalidValue;
     k_pass<double, P1, P2, true, true, SymbolSrc, MemStore<c128>><<<dim3(unsigned(blocks)), dim3(geo.T * J), pass_lds_bytes<double, P1, P2, true>(geo.T), s>>>(src, dst, geo, tw);
     return hipGetLastError();
   }
