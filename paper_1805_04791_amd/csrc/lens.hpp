@@ -13,12 +13,13 @@ namespace vie {
 
 // Source functor of the first precompute pass: symbol samples on the M^3
 // frequency grid, odd entries zeroed on their Nyquist planes, modulated by
-// (-i)^(ix + iy + iz) so that the inverse transform's first 2n outputs are the
-// displacements -n .. n-1.
+// exp(-i pi (ix + iy + iz) P / M) so that the inverse transform's first P
+// outputs are the displacements -P/2 .. P/2 - 1.
 struct SymbolSrc {
   int M;
   int set;      // SYM_GRAD or SYM_MAXWELL
   int entry0;   // table entry of group 0
+  int shift;    // P / 2
   double h, w, R;
   struct Col {
     const SymbolSrc* s;
@@ -42,11 +43,19 @@ struct SymbolSrc {
     const double sy = ds * double(iy < half ? iy : iy - M);
     const double sz = ds * double(iz < half ? iz : iz - M);
     c128 v = symbol_entry(set, e, sx, sy, sz, w, R);
-    switch ((ix + iy + iz) & 3) {
-      case 1: v = times_mi(v); break;
-      case 2: v = -v; break;
-      case 3: v = times_i(v); break;
-      default: break;
+    // phase -pi k shift / half = -2 pi (k shift mod M) / M, k = ix + iy + iz
+    const long q = (long(ix + iy + iz) * shift) % M;
+    if ((4 * q) % M == 0) {
+      switch (int(4 * q / M)) {
+        case 1: v = times_mi(v); break;
+        case 2: v = -v; break;
+        case 3: v = times_i(v); break;
+        default: break;
+      }
+    } else {
+      double sn, cs;
+      sincospi(-2.0 * double(q) / double(M), &sn, &cs);
+      v = c128{v.re * cs - v.im * sn, v.re * sn + v.im * cs};
     }
     return cvt<Rt>(v);
   }

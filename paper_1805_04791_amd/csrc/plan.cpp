@@ -241,8 +241,9 @@ hipError_t pass_xfwd(const ApplyCall<R>& c, const TV* in, int T, hipStream_t s) 
   const vie_plan* pl = c.pl;
   const long nr = long(c.g.bz) * c.g.by;
   const long rows = long(c.nb) * pl->C * nr;
-  Geo g{T, int((rows + T - 1) / T), rows, c.g.bx, pl->P};
-  MemStore<cx<R>> dst{c.A, 0, pl->P, 1, 1.0, 0};
+  const int P = c.g.sp->P;
+  Geo g{T, int((rows + T - 1) / T), rows, c.g.bx, P};
+  MemStore<cx<R>> dst{c.A, 0, P, 1, 1.0, 0};
   if constexpr (std::is_same<TV, c128>::value) {
     if (c.g.rows) return c.ops->contig_fwd_rows(RowLoad<c128>{in, c.g.rows, nr, c.g.np}, dst, g, 1, c.tw, s);
     return c.ops->contig_fwd(MemLoad<c128>{in, 0, c.g.bx, 1}, dst, g, 1, c.tw, s);
@@ -256,7 +257,7 @@ hipError_t pass_xfwd(const ApplyCall<R>& c, const TV* in, int T, hipStream_t s) 
 template <typename R>
 hipError_t pass_yfwd(const ApplyCall<R>& c, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long P = pl->P, by = c.g.by;
+  const long P = c.g.sp->P, by = c.g.by;
   Geo g{T, int(P / T), P, int(by), int(P)};
   MemLoad<cx<R>> src{c.A, by * P, 1, P};
   MemStore<cx<R>> dst{c.B, P * P, 1, P, 1.0, 0};
@@ -266,8 +267,9 @@ hipError_t pass_yfwd(const ApplyCall<R>& c, int T, hipStream_t s) {
 template <typename R>
 hipError_t pass_z(const ApplyCall<R>& c, const cx<R>* tab, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long N = pl->n, P = pl->P, bz = c.g.bz;
-  ZArgs a{T, int(P / T), int(N), int(P), pl->nxp, pl->ne, bz * P * P, long(pl->C) * bz * P * P, c.nb, int(bz)};
+  const long P = c.g.sp->P, bz = c.g.bz;
+  ZArgs a{T, int(P / T), int(P / 2), int(P), c.g.sp->nxp, pl->ne, bz * P * P, long(pl->C) * bz * P * P, c.nb, int(bz)};
+  if ((P / T) * P % 8 != 0) return hipErrorInvalidValue;  // the XCD block order deals slices in groups of 8
   const long nblocks = long(P / T) * P * c.nb;
   return c.ops->zpass(pl->full ? MUL_MAX6 : MUL_SYM3, c.B, tab, a, nblocks, c.tw, s);
 }
@@ -276,7 +278,7 @@ hipError_t pass_z(const ApplyCall<R>& c, const cx<R>* tab, int T, hipStream_t s)
 template <typename R>
 hipError_t pass_yinv(const ApplyCall<R>& c, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long P = pl->P, by = c.g.by;
+  const long P = c.g.sp->P, by = c.g.by;
   Geo g{T, int(P / T), P, int(P), int(by)};
   MemLoad<cx<R>> src{c.B, P * P, 1, P};
   MemStore<cx<R>> dst{c.A, by * P, 1, P, 1.0, 0};
@@ -370,7 +372,7 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStre
   }
   const int P1 = c.ops->P1, P2 = c.ops->P2;
   Tune d;
-  const int P = P1 * P2;
+  const int P = P1 * P2;  // the geometry's transform length
   d.tx_fwd = default_tile<R>(pl, P1, P2, true, kPassMaxThreads, P);
   const int fmax = pl->C == 6 ? fused_max_threads<R, 6>() : fused_max_threads<R, 3>();
   d.tx_inv = default_tile<R>(pl, P1, P2, true, fmax, P);
@@ -397,9 +399,9 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStre
     // measure only where it pays: large grids, unless switched off
     const cx<R>* tab;
     if constexpr (std::is_same<R, float>::value)
-      tab = pl->tab32;
+      tab = c.g.sp->tab32;
     else
-      tab = pl->tab64;
+      tab = c.g.sp->tab64;
     int rc;
     rc = pick_tile<R>(pl, P1, P2, true, kPassMaxThreads, [&](int T) { return pass_xfwd<R, TV>(c, in, T, s); }, s, &d.tx_fwd);
     if (rc) return rc;
@@ -417,7 +419,7 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStre
   }
   d.tuned = true;
   if (env_flag("VIE_DEBUG", false))
-    std::fprintf(stderr, "[vie] tiles P=%d fp%d nb=%d box %dx%dx%d: xfwd %d yfwd %d z %d yinv %d xinv %d\n", pl->P,
+    std::fprintf(stderr, "[vie] tiles P=%d fp%d nb=%d box %dx%dx%d: xfwd %d yfwd %d z %d yinv %d xinv %d\n", P,
                  int(8 * sizeof(R)), c.nb, c.g.bx, c.g.by, c.g.bz, d.tx_fwd, d.ty_fwd, d.tz, d.ty_inv, d.tx_inv);
   pl->tune[idx][key] = d;
   *t = d;
@@ -427,9 +429,10 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStre
 template <typename R, typename TV>
 int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, const c128* bvec, TV* out,
                 int nrhs, int mode, hipStream_t s) {
-  const LenOps<R>* ops = len_ops<R>(pl->P);
+  const Spec& sp = *geom.sp;
+  const LenOps<R>* ops = len_ops<R>(sp.P);
   if (!ops || !ops->contig_fwd || !ops->zpass || !ops->xinv)
-    return fail(pl, VIE_E_SIZE, "no compiled FFT length " + std::to_string(pl->P));
+    return fail(pl, VIE_E_SIZE, "no compiled FFT length " + std::to_string(sp.P));
   if (!std::is_same<TV, c128>::value && (!ops->contig_fwd_v32 || !ops->xinv_v32))
     return fail(pl, VIE_E_STATE, "complex64 vectors need the FP32 apply");
   const int idx = std::is_same<R, double>::value ? 1 : 0;
@@ -439,11 +442,11 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
   const cx<R>* tw;
   const cx<R>* tab;
   if constexpr (std::is_same<R, float>::value) {
-    tw = pl->tw32;
-    tab = pl->tab32;
+    tw = sp.tw32;
+    tab = sp.tab32;
   } else {
-    tw = pl->tw64;
-    tab = pl->tab64;
+    tw = sp.tw64;
+    tab = sp.tab64;
   }
   const long L = long(pl->C) * geom.np;
   for (int r0 = 0; r0 < nrhs; r0 += chunk) {
@@ -459,14 +462,14 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     // algorithmic bytes: every operand read or written once per launch
     const double cr = double(sizeof(cx<R>)), c16 = double(sizeof(TV));
     const double vN3 = double(nb) * pl->C * double(geom.np);
-    const double vN2P = double(nb) * pl->C * geom.bz * geom.by * pl->P, vNP2 = vN2P / geom.by * pl->P;
+    const double vN2P = double(nb) * pl->C * geom.bz * geom.by * sp.P, vNP2 = vN2P / geom.by * sp.P;
     const double hb = 9.0 * double(geom.np) * cr * (pl->full ? 2 : 1);
     const double xinv_b = vN2P * cr + hb * (mode == MODE_MATVEC || mode == MODE_RESIDUAL) +
                           vN3 * c16 * (1 + (mode != MODE_CONV)) + vN3 * sizeof(c128) * (mode == MODE_RESIDUAL);
     // nominal flops: 5 P log2 P per transformed pencil of length P; 66 per
     // frequency point for the 3x3 multiply (216 for the 6x6 Maxwell block);
     // 72 per point and 3-component half for the combine
-    const double P = pl->P, fft_row = 5.0 * P * std::log2(P);
+    const double P = sp.P, fft_row = 5.0 * P * std::log2(P);
     const double rows_x = vN2P / P, rows_y = vN2P / geom.by, rows_z = vNP2 / geom.bz;
     const double pts = double(nb) * P * P * P;
     const double mul_f = (pl->full ? 216.0 : 66.0) * pts;
@@ -479,7 +482,7 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     prof_end(pl, f0 + 1, tok, s, (vN2P + vNP2) * cr, rows_y * fft_row);
     tok = prof_begin(pl, s);
     HIPCHK(pl, pass_z<R>(c, tab, t.tz, s));
-    prof_end(pl, f0 + 2, tok, s, 2.0 * vNP2 * cr + double(pl->tab_elems) * cr, 2.0 * rows_z * fft_row + mul_f);
+    prof_end(pl, f0 + 2, tok, s, 2.0 * vNP2 * cr + double(sp.tab_elems) * cr, 2.0 * rows_z * fft_row + mul_f);
     tok = prof_begin(pl, s);
     HIPCHK(pl, pass_yinv<R>(c, t.ty_inv, s));
     prof_end(pl, f0 + 3, tok, s, (vN2P + vNP2) * cr, rows_y * fft_row);
@@ -493,8 +496,12 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
 // ---------------------------------------------------------------------------
 // precompute of the kernel-transform tables (FP64)
 // ---------------------------------------------------------------------------
-int build_tables(vie_plan* pl, hipStream_t s) {
-  const int N = pl->n, P = pl->P, M = pl->M, NE = pl->ne;
+// Tables of transform length sp.P (<= 2n): the windowed kernel K_m for
+// |m_a| <= P/2 - 1 (the window of the whole grid when P = 2n), transformed on
+// the P grid.  The box convolution needs offsets |m_a| <= b - 1 < P/2 only,
+// and its wrapped copies lie at |m_a| >= P - (b - 1) > P/2 - 1.
+int build_tables(vie_plan* pl, Spec& sp, hipStream_t s) {
+  const int P = sp.P, N = P / 2, M = pl->M, NE = pl->ne;
   const LenOps<double>* opsM = len_ops<double>(M);
   const LenOps<double>* opsP = len_ops<double>(P);
   if (!opsM || !opsM->symbol_inv || !opsM->strided)
@@ -531,9 +538,9 @@ int build_tables(vie_plan* pl, hipStream_t s) {
   hipError_t e = hipSuccess;
   for (int ent = 0; ent < NE && e == hipSuccess; ++ent) {
     // (a) symbol samples of entry `ent` -> inverse transform along x; keep
-    //     outputs 0..P-1 (displacements -n..n-1), zero displacement -n
+    //     outputs 0..P-1 (displacements -P/2..P/2-1), zero displacement -P/2
     {
-      SymbolSrc src{M, pl->sym_set, ent, pl->h, pl->omega, pl->R};
+      SymbolSrc src{M, pl->sym_set, ent, P / 2, pl->h, pl->omega, pl->R};
       const long rows = MM * MM;
       Geo g{TcM, int((rows + TcM - 1) / TcM), rows, M, P};
       MemStore<c128> dst{buf1, 0, PP, 1, 1.0 / double(M), 1};
@@ -561,23 +568,23 @@ int build_tables(vie_plan* pl, hipStream_t s) {
     Geo g{TcP, int((rows + TcP - 1) / TcP), rows, P, P};
     MemLoad<c128> src{buf3, 0, PP, 1};
     MemStore<c128> dst{buf3, 0, PP, 1, 1.0, 0};
-    e = opsP->contig_fwd(src, dst, g, 1, pl->tw64, s);
+    e = opsP->contig_fwd(src, dst, g, 1, sp.tw64, s);
   }
   if (e == hipSuccess) {
     Geo g{TsP, int(PP / TsP), PP, P, P};
     MemLoad<c128> src{buf3, PP * PP, 1, PP};
     MemStore<c128> dst{buf3, PP * PP, 1, PP, 1.0, 0};
-    e = opsP->strided(false, src, dst, g, long(NE) * PP, pl->tw64, s);
+    e = opsP->strided(false, src, dst, g, long(NE) * PP, sp.tw64, s);
   }
   if (e == hipSuccess) {
     const long cols = PP * PP;
     Geo g{TsP, int(cols / TsP), cols, P, P};
     MemLoad<c128> src{buf3, PP * PP * PP, 1, PP * PP};
     MemStore<c128> dst{buf3, PP * PP * PP, 1, PP * PP, 1.0, 0};
-    e = opsP->strided(false, src, dst, g, NE, pl->tw64, s);
+    e = opsP->strided(false, src, dst, g, NE, sp.tw64, s);
   }
-  // (e) shift by n in every axis ((-1)^q), scale by P^-3, fold to the octant
-  if (e == hipSuccess) e = launch_finalize_tables(buf3, pl->tab64, pl->tab32, N, P, pl->nxp, NE, pl->omega, s);
+  // (e) shift by P/2 in every axis ((-1)^q), scale by P^-3, fold to the octant
+  if (e == hipSuccess) e = launch_finalize_tables(buf3, sp.tab64, sp.tab32, N, P, sp.nxp, NE, pl->omega, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup();
   return e == hipSuccess ? VIE_OK : hip_fail(pl, e, "table precompute");
@@ -691,6 +698,35 @@ void destroy_plan(vie_plan* pl) {
   delete pl;
 }
 
+// twiddles and kernel-transform tables of length P
+int make_spec(vie_plan* pl, int P, Spec& sp, hipStream_t s) {
+  sp.P = P;
+  sp.nxp = ((P / 2 + 1 + 15) / 16) * 16;
+  int rc = upload_twiddles<double>(pl, P, &sp.tw64, s);
+  if (!rc) rc = upload_twiddles<float>(pl, P, &sp.tw32, s);
+  if (rc) return rc;
+  sp.tab_elems = long(P / 2 + 1) * (P / 2 + 1) * pl->ne * sp.nxp;
+  rc = dev_alloc(pl, reinterpret_cast<void**>(&sp.tab64), sizeof(c128) * size_t(sp.tab_elems));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&sp.tab32), sizeof(c64) * size_t(sp.tab_elems));
+  if (rc) return rc;
+  return build_tables(pl, sp, s);
+}
+
+// The shortest compiled transform length L <= 2n with L >= 2 max(bx, by, bz)
+// (so that the cyclic convolution of box data has no wrap-around) whose
+// apply and precompute kernels exist.
+int box_length(const vie_plan* pl) {
+  const int need = 2 * std::max(pl->box.bx, std::max(pl->box.by, pl->box.bz));
+  for (int L = need + (need & 1); L < pl->P; L += 2) {
+    const LenOps<float>* o32 = len_ops<float>(L);
+    const LenOps<double>* o64 = len_ops<double>(L);
+    if (L % 8 == 0 && o32 && o64 && o32->contig_fwd && o32->zpass && o64->contig_fwd && o64->zpass &&
+        o64->strided)
+      return L;
+  }
+  return pl->P;
+}
+
 // Support rows of the box: per (z, y) row the x-interval of the points where
 // H (or H_mu) is non-zero; the solver's vectors hold only these points.
 int build_rows(vie_plan* pl, hipStream_t s) {
@@ -740,7 +776,6 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   pl->R = std::sqrt(3.0) * p->n * p->h;
   pl->sym_set = p->kind == VIE_MAXWELL ? SYM_MAXWELL : SYM_GRAD;
   pl->ne = pl->full ? 9 : 6;
-  pl->nxp = ((p->n + 1 + 15) / 16) * 16;
   pl->precision = p->precision;
   pl->max_rhs = p->max_rhs;
   pl->flags = p->flags;
@@ -807,15 +842,16 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   dev_free(pl, bbad);
   dev_free(pl, bbox);
   // whole grid and the bounding box of supp(H) (a single point if H vanishes)
-  pl->grid = Geom{p->n, p->n, p->n, 0, 0, 0, 0, nullptr, pl->n3};
+  pl->grid = Geom{&pl->sg, p->n, p->n, p->n, 0, 0, 0, 0, nullptr, pl->n3};
   if (hi[0] < 0) {
     for (int a = 0; a < 3; ++a) lo[a] = hi[a] = 0;
   }
-  pl->box = Geom{hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1, lo[0], lo[1], lo[2], 1, nullptr, 0};
+  pl->box = Geom{&pl->sb, hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1, lo[0], lo[1], lo[2], 1, nullptr, 0};
   pl->box.np = long(pl->box.bx) * pl->box.by * pl->box.bz;
   pl->use_box = env_flag("VIE_BOX", true);
   if (!pl->use_box) {
     pl->box = pl->grid;
+    pl->box.sp = &pl->sb;
   } else if (env_flag("VIE_ROWS", true)) {
     rc = build_rows(pl, s);
     if (rc) return rc;
@@ -825,16 +861,16 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
     return fail(pl, VIE_E_MEDIUM, std::to_string(bad) + " grid points where a + I is singular or not finite");
   if ((p->flags & VIE_STRICT_MEDIUM) && !(worst < 1.0))
     return fail(pl, VIE_E_MEDIUM, "max ||H(x)||_2 = " + std::to_string(worst) + " >= 1 (contrast not a contraction)");
-  // twiddles and kernel tables
-  rc = upload_twiddles<double>(pl, pl->P, &pl->tw64, s);
-  if (!rc) rc = upload_twiddles<float>(pl, pl->P, &pl->tw32, s);
+  // twiddles and kernel tables: the whole grid's, and the box's when shorter
+  rc = make_spec(pl, pl->P, pl->sg, s);
   if (rc) return rc;
-  pl->tab_elems = long(pl->n + 1) * (pl->n + 1) * pl->ne * pl->nxp;
-  rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->tab64), sizeof(c128) * size_t(pl->tab_elems));
-  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->tab32), sizeof(c64) * size_t(pl->tab_elems));
-  if (rc) return rc;
-  rc = build_tables(pl, s);
-  if (rc) return rc;
+  const int pb = pl->use_box && env_flag("VIE_PBOX", true) ? box_length(pl) : pl->P;
+  if (pb == pl->P) {
+    pl->sb = pl->sg;
+  } else {
+    rc = make_spec(pl, pb, pl->sb, s);
+    if (rc) return rc;
+  }
   return VIE_OK;
 }
 
@@ -906,23 +942,24 @@ int vie_field(vie_plan* pl, const double* density, const double* inc, double* fi
 
 int vie_plan_info(const vie_plan* pl, double* out, int nout) {
   if (!pl || !out) return VIE_E_ARG;
-  const double v[15] = {double(pl->n),         double(pl->C),      double(pl->P),      double(pl->M),
+  const double v[16] = {double(pl->n),         double(pl->C),      double(pl->P),      double(pl->M),
                         pl->hmax,              double(pl->ne),     double(pl->dev_bytes),
                         double(pl->graph_launches), double(pl->box.x0), double(pl->box.y0), double(pl->box.z0),
-                        double(pl->box.bx),    double(pl->box.by), double(pl->box.bz), double(pl->box.np)};
-  for (int i = 0; i < nout && i < 15; ++i) out[i] = v[i];
+                        double(pl->box.bx),    double(pl->box.by), double(pl->box.bz), double(pl->box.np),
+                        double(pl->sb.P)};
+  for (int i = 0; i < nout && i < 16; ++i) out[i] = v[i];
   return VIE_OK;
 }
 
 int vie_copy_tables(const vie_plan* pl, double* host, long host_bytes, long* needed, int* nxp, int* ne) {
   if (!pl) return VIE_E_ARG;
-  const long bytes = long(sizeof(c128)) * pl->tab_elems;
+  const long bytes = long(sizeof(c128)) * pl->sg.tab_elems;
   if (needed) *needed = bytes;
-  if (nxp) *nxp = pl->nxp;
+  if (nxp) *nxp = pl->sg.nxp;
   if (ne) *ne = pl->ne;
   if (!host) return VIE_OK;
   if (host_bytes < bytes) return VIE_E_ARG;
-  hipError_t e = hipMemcpy(host, pl->tab64, size_t(bytes), hipMemcpyDeviceToHost);
+  hipError_t e = hipMemcpy(host, pl->sg.tab64, size_t(bytes), hipMemcpyDeviceToHost);
   return e == hipSuccess ? VIE_OK : VIE_E_DEVICE;
 }
 
@@ -963,7 +1000,7 @@ long vie_footprint_bytes(int kind, int n, int full, int nrhs_batch, int restart)
   (void)kind;
   double b = 0;
   b += (full ? 2 : 1) * 9 * n3 * (16 + 8);                       // H in FP64 and FP32
-  b += double(n + 1) * (n + 1) * ne * nxp * (16 + 8);            // octant tables
+  b += 2 * double(n + 1) * (n + 1) * ne * nxp * (16 + 8);        // octant tables (grid and box lengths)
   const double precompute = (M * M * P + M * P * P + ne * P * P * P) * 16 + 9 * n3 * 16;
   const double nb = nrhs_batch;
   const double ws = nb * C * (double(n) * n * P + double(n) * P * P);  // apply workspace elements

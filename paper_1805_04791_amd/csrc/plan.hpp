@@ -17,7 +17,19 @@ namespace vie {
 
 // Extent of the data an apply works on: the whole grid, or the bounding box
 // of the support of H (the Krylov vectors vanish outside it exactly).
+// Spectral data of one periodic transform length P: the kernel-transform
+// octant tables (q in [0, P/2]^3, rows of nxp) and the twiddles.
+struct Spec {
+  int P = 0, nxp = 0;
+  long tab_elems = 0;
+  c128* tab64 = nullptr;
+  c64* tab32 = nullptr;
+  c128* tw64 = nullptr;
+  c64* tw32 = nullptr;
+};
+
 struct Geom {
+  const Spec* sp = nullptr;  // transform length and tables used on this geometry
   int bx = 0, by = 0, bz = 0;
   int x0 = 0, y0 = 0, z0 = 0;
   int id = 0;                // 0 whole grid, 1 solver geometry
@@ -40,7 +52,7 @@ struct DeviceArena {
 }  // namespace vie
 
 struct vie_plan {
-  int kind = 0, n = 0, C = 3, P = 0, M = 0, ne = 6, nxp = 0, sym_set = 0, precision = 0, max_rhs = 1;
+  int kind = 0, n = 0, C = 3, P = 0, M = 0, ne = 6, sym_set = 0, precision = 0, max_rhs = 1;
   unsigned flags = 0;
   double h = 0, omega = 0, R = 0, hmax = 0;
   long n3 = 0;
@@ -54,11 +66,8 @@ struct vie_plan {
 
   vie::c128 *H64 = nullptr, *Hmu64 = nullptr;
   vie::c64 *H32 = nullptr, *Hmu32 = nullptr;
-  vie::c128* tab64 = nullptr;
-  vie::c64* tab32 = nullptr;
-  long tab_elems = 0;
-  vie::c128* tw64 = nullptr;
-  vie::c64* tw32 = nullptr;
+  vie::Spec sg;  // P = 2n: the whole grid (vie_apply, vie_field)
+  vie::Spec sb;  // the solver's box: the shortest compiled length >= 2 max(bx, by, bz), <= 2n
 
   // apply workspaces [0] FP32, [1] FP64; capacity in right-hand sides
   void* wsA[2] = {nullptr, nullptr};

@@ -240,13 +240,14 @@ class Plan:
         return dens, fld, [s.as_dict() for s in st], rc
 
     def info(self) -> dict:
-        out = (ctypes.c_double * 15)()
-        self._check(self.lib.vie_plan_info(self._h, out, 15), "vie_plan_info")
+        out = (ctypes.c_double * 16)()
+        self._check(self.lib.vie_plan_info(self._h, out, 16), "vie_plan_info")
         keys = ["n", "ncomp", "P", "M", "max_contrast_norm", "table_entries", "device_bytes", "graph_launches",
-                "box_x0", "box_y0", "box_z0", "box_nx", "box_ny", "box_nz", "unknown_points"]
+                "box_x0", "box_y0", "box_z0", "box_nx", "box_ny", "box_nz", "unknown_points", "box_P"]
         d = dict(zip(keys, list(out)))
         d["box"] = tuple(int(d.pop(k)) for k in keys[8:14])
         d["unknown_points"] = int(d["unknown_points"])
+        d["box_P"] = int(d["box_P"])
         return d
 
     def tables(self) -> np.ndarray:

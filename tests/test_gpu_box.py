@@ -184,6 +184,57 @@ def test_restricted_solve_equals_whole_grid_solve(vie, monkeypatch):
         plan.close()
 
 
+def ball_medium(n, radius, seed_item):
+    """The Helmholtz test medium restricted to a centred ball."""
+    coef, _, omega = medium(op.KIND_HELMHOLTZ, n, seed_item)
+    X, Y, Z = gen.grid_coords(n)
+    return masked(coef, (X * X + Y * Y + Z * Z < radius * radius).astype(float)), omega
+
+
+@pytest.mark.parametrize("n,radius", [(24, 0.45), (32, 0.4)])
+def test_short_box_transform_matches_oracle(vie, n, radius):
+    """A support box of at most n/2 points per axis is convolved on a
+    transform grid shorter than 2n; the solution is the oracle's (whole grid,
+    window of the whole grid) to FP64 and mixed accuracy."""
+    coef, omega = ball_medium(n, radius, 17)
+    inc = plane_waves(n, omega, 2, 30)
+    A = op.Operator(op.KIND_HELMHOLTZ, coef, omega)
+    ref = [sv.gmres(A.apply, A.rhs(inc[r]), tol=1e-13)[0] for r in range(2)]
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2)
+    info = plan.info()
+    assert info["box_P"] < 2 * n and info["box_P"] >= 2 * max(info["box"][3:])
+    for fp64, tol, err in ((True, 1e-12, 1e-10), (False, 1e-9, 1e-8)):
+        d, f, st, rc = plan.solve(inc, tol=tol, fp64=fp64)
+        assert rc == vie.OK
+        d, f = d.cpu().numpy(), f.cpu().numpy()
+        for r in range(2):
+            assert st[r]["rel_residual"] <= tol
+            assert rel(d[r], ref[r]) < err
+            assert rel(f[r], A.field(ref[r], inc[r])) < err
+    plan.close()
+
+
+def test_short_box_transform_equals_full_length(vie, monkeypatch):
+    """n = 64, bump of radius 0.8: the solver's transform length is 120 (not
+    128); FP64 solves agree with those on the 2n grid."""
+    n = 64
+    coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 18)
+    inc = plane_waves(n, omega, 2, 40)
+    short = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2)
+    monkeypatch.setenv("VIE_PBOX", "0")
+    full = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2)
+    assert short.info()["box_P"] < 2 * n and full.info()["box_P"] == 2 * n
+    for fp64, tol, err in ((True, 1e-12, 1e-10), (False, 1e-10, 1e-9)):
+        ds, _, ss, _ = short.solve(inc, tol=tol, fp64=fp64, want_field=False)
+        df, _, sf, _ = full.solve(inc, tol=tol, fp64=fp64, want_field=False)
+        ds, df = ds.cpu().numpy(), df.cpu().numpy()
+        for r in range(2):
+            assert rel(ds[r], df[r]) < err
+            assert abs(ss[r]["iters"] - sf[r]["iters"]) <= 2
+    short.close()
+    full.close()
+
+
 def test_x0_outside_support_rows_is_ignored(vie):
     """A warm start is restricted to the support rows: values elsewhere
     cannot change the solution (the equation fixes J = 0 there)."""
