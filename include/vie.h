@@ -196,9 +196,10 @@ int vie_destroy(vie_plan *pl);
  * component: in each (z, y) row of the box, the x-interval from the first to
  * the last point where H (or H_mu) is non-zero (the whole box with
  * VIE_ROWS=0, the whole grid with VIE_BOX=0), out[15] = the periodic
- * transform length of the solver's applies: the shortest compiled length
- * >= 2 max(bx, by, bz) and <= 2n (2n with VIE_PBOX=0); its kernel tables are
- * the transform of the kernel windowed to |m_a| <= length/2 - 1. */
+ * transform length along x and y of the solver's applies: the shortest
+ * compiled length >= 2 max(bx, by) and <= 2n (2n with VIE_PBOX=0; along z
+ * always 2n); its kernel tables are the transform of the kernel windowed to
+ * |m_a| <= length_a/2 - 1. */
 int vie_plan_info(const vie_plan *pl, double *out, int nout);
 
 /* Copies the FP64 kernel-transform tables into host memory:

@@ -30,21 +30,22 @@ enum { MODE_MATVEC = 0, MODE_FIELD = 1, MODE_CONV = 2, MODE_RESIDUAL = 3 };
 
 struct ZArgs {
   int T;            // kx columns per block
-  int ntiles;       // P / T
-  int n;            // grid points per axis (the tables' octant is [0, n]; n = P / 2)
-  int P;            // 2n
+  int ntiles;       // pxy / T
+  int n;            // P / 2: the tables' octant is qz in [0, n], qy, qx in [0, n] (only <= pxy / 2 used)
+  int P;            // z transform length
   int nxp;          // padded octant row length (n + 1 rounded up to 16)
   int ne;           // table entries (6 or 9)
-  long comp_stride; // n * P * P
-  long rhs_stride;  // C * n * P * P
+  long comp_stride; // nz * pxy * pxy
+  long rhs_stride;  // C * comp_stride
   int nb;           // right-hand sides in the launch
   int nz;           // z extent of the data (n, or the support box): inputs z < nz, outputs z < nz
+  int pxy;          // x and y transform length (<= P): columns (ky, kx) in [0, pxy)^2
 };
 
 // Block order: blocks are dealt round-robin to the 8 XCDs (block b runs on
 // XCD b % 8).  The nb right-hand sides of one (ky, kx-tile) slice read the
 // same table slice, so they are given consecutive launch slots on one XCD and
-// the slice is re-read from that XCD's L2.  Requires (P / T) * P % 8 == 0.
+// the slice is re-read from that XCD's L2.  Requires (pxy / T) * pxy % 8 == 0.
 template <typename R, int P1, int P2, int C, int MUL>
 __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* buf, const cx<R>* __restrict__ tab, ZArgs a,
                                                             const cx<R>* __restrict__ twg) {
@@ -67,9 +68,9 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
   const int tile = int(slice % a.ntiles);
   const int ky = int(slice / a.ntiles);
   const int kx = tile * a.T + col;
-  const bool valid = kx < P;
-  const long PP = long(P) * P;
-  cx<R>* base = buf + rhs * a.rhs_stride + long(ky) * P + kx;
+  const bool valid = kx < a.pxy;
+  const long PP = long(a.pxy) * a.pxy;
+  cx<R>* base = buf + rhs * a.rhs_stride + long(ky) * a.pxy + kx;
 
   // kUpfront: all inputs of the block in flight at once
   constexpr int CU = kUpfront<R> ? C : 1;
@@ -107,10 +108,11 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
     constexpr int NE = MUL == MUL_SYM3 ? 6 : 9;
     constexpr int ROW = NE * NXP;
     static_assert(P2 % 2 == 0, "the z fold assumes P2 even");
-    const int fy = ky <= N ? ky : P - ky;
-    const int fx = kx <= N ? kx : P - kx;
-    const R sy = ky > N ? R(-1) : R(1);
-    const R sx = kx > N ? R(-1) : R(1);
+    const int Nxy = a.pxy / 2;
+    const int fy = ky <= Nxy ? ky : a.pxy - ky;
+    const int fx = kx <= Nxy ? kx : a.pxy - kx;
+    const R sy = ky > Nxy ? R(-1) : R(1);
+    const R sx = kx > Nxy ? R(-1) : R(1);
     const R sxy = sx * sy;
     const cx<R>* tb = tab + (fy * ROW + fx);  // offsets below 2^31 elements
     static_for<0, P2>([&](auto k2) {

@@ -13,13 +13,14 @@ namespace vie {
 
 // Source functor of the first precompute pass: symbol samples on the M^3
 // frequency grid, odd entries zeroed on their Nyquist planes, modulated by
-// exp(-i pi (ix + iy + iz) P / M) so that the inverse transform's first P
-// outputs are the displacements -P/2 .. P/2 - 1.
+// exp(-2 pi i (ix shx + iy shy + iz shz) / M) so that the inverse
+// transform's first P_a outputs along axis a are the displacements
+// -P_a / 2 .. P_a / 2 - 1 (sh_a = P_a / 2).
 struct SymbolSrc {
   int M;
   int set;      // SYM_GRAD or SYM_MAXWELL
   int entry0;   // table entry of group 0
-  int shift;    // P / 2
+  int shx, shy, shz;  // P_x / 2, P_y / 2, P_z / 2
   double h, w, R;
   struct Col {
     const SymbolSrc* s;
@@ -43,8 +44,8 @@ struct SymbolSrc {
     const double sy = ds * double(iy < half ? iy : iy - M);
     const double sz = ds * double(iz < half ? iz : iz - M);
     c128 v = symbol_entry(set, e, sx, sy, sz, w, R);
-    // phase -pi k shift / half = -2 pi (k shift mod M) / M, k = ix + iy + iz
-    const long q = (long(ix + iy + iz) * shift) % M;
+    // phase -2 pi q / M
+    const long q = (long(ix) * shx + long(iy) * shy + long(iz) * shz) % M;
     if ((4 * q) % M == 0) {
       switch (int(4 * q / M)) {
         case 1: v = times_mi(v); break;
@@ -151,7 +152,9 @@ struct LenImpl {
   static hipError_t zpass(int mul, cx<R>* buf, const cx<R>* tab, ZArgs a, long nblocks, const cx<R>* tw,
                           hipStream_t s) {
     // the kernel takes the table geometry from P
-    if (2 * a.n != P || a.nxp != ((a.n + 1 + 15) / 16) * 16 || a.ne != (mul == MUL_SYM3 ? 6 : 9) || 2 * a.nz > P)
+    if (2 * a.n != P || a.nxp != ((a.n + 1 + 15) / 16) * 16 || a.ne != (mul == MUL_SYM3 ? 6 : 9) || 2 * a.nz > P ||
+        a.pxy > P || a.ntiles != (a.pxy + a.T - 1) / a.T || nblocks != long(a.ntiles) * a.pxy * a.nb ||
+        (long(a.ntiles) * a.pxy) % 8 != 0)
       return hipErrorInvalidValue;
     const size_t lds = pass_lds_bytes<R, P1, P2, false>(a.T);
     if (mul == MUL_SYM3)

@@ -181,12 +181,14 @@ size_t lds_need(int P1, int P2, int T) {
 // a run shorter than a 128-byte cache line makes neighbouring tiles, which
 // run on different XCDs, fetch the same line twice, so T * sizeof >= 128 B
 // whenever the column count allows it.
+// ragged: the last tile of columns may be partial (the fused z pass masks
+// columns beyond cols)
 template <typename R>
 bool tile_ok(const vie_plan* pl, int P1, int P2, int T, bool contig, long cols, int maxthreads,
-             bool full_lines = true) {
+             bool full_lines = true, bool ragged = false) {
   const int J = std::max(P1, P2);
   if (T * J > maxthreads || T * J < 16) return false;
-  if (cols > 0 && cols % T != 0) return false;
+  if (cols > 0 && !ragged && cols % T != 0) return false;
   const int full = int(128 / sizeof(cx<R>));
   if (full_lines && !contig && T < full && (cols <= 0 || cols >= full)) return false;
   const size_t need = contig ? lds_need<R, true>(P1, P2, T) : lds_need<R, false>(P1, P2, T);
@@ -194,12 +196,12 @@ bool tile_ok(const vie_plan* pl, int P1, int P2, int T, bool contig, long cols, 
 }
 
 template <typename R>
-int default_tile(const vie_plan* pl, int P1, int P2, bool contig, int maxthreads, long cols) {
+int default_tile(const vie_plan* pl, int P1, int P2, bool contig, int maxthreads, long cols, bool ragged = false) {
   const int J = std::max(P1, P2);
   for (int strict = 1; strict >= 0; --strict) {
     int best = 0;
     for (int T : kTileChoices) {
-      if (!tile_ok<R>(pl, P1, P2, T, contig, cols, maxthreads, strict != 0)) continue;
+      if (!tile_ok<R>(pl, P1, P2, T, contig, cols, maxthreads, strict != 0, ragged)) continue;
       // prefer ~256 threads per block
       if (best == 0 || std::abs(T * J - 256) < std::abs(best * J - 256)) best = T;
     }
@@ -226,8 +228,10 @@ bool env_flag(const char* name, bool dflt) {
 template <typename R>
 struct ApplyCall {
   vie_plan* pl;
-  const LenOps<R>* ops;
+  const LenOps<R>* ops;   // length Pxy: x and y passes
   const cx<R>* tw;
+  const LenOps<R>* opsz;  // length Pz: the fused z pass
+  const cx<R>* twz;
   cx<R>* A;
   cx<R>* B;
   int nb;
@@ -241,7 +245,7 @@ hipError_t pass_xfwd(const ApplyCall<R>& c, const TV* in, int T, hipStream_t s) 
   const vie_plan* pl = c.pl;
   const long nr = long(c.g.bz) * c.g.by;
   const long rows = long(c.nb) * pl->C * nr;
-  const int P = c.g.sp->P;
+  const int P = c.g.sp->Pxy;
   Geo g{T, int((rows + T - 1) / T), rows, c.g.bx, P};
   MemStore<cx<R>> dst{c.A, 0, P, 1, 1.0, 0};
   if constexpr (std::is_same<TV, c128>::value) {
@@ -257,7 +261,7 @@ hipError_t pass_xfwd(const ApplyCall<R>& c, const TV* in, int T, hipStream_t s) 
 template <typename R>
 hipError_t pass_yfwd(const ApplyCall<R>& c, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long P = c.g.sp->P, by = c.g.by;
+  const long P = c.g.sp->Pxy, by = c.g.by;
   Geo g{T, int(P / T), P, int(by), int(P)};
   MemLoad<cx<R>> src{c.A, by * P, 1, P};
   MemStore<cx<R>> dst{c.B, P * P, 1, P, 1.0, 0};
@@ -267,18 +271,20 @@ hipError_t pass_yfwd(const ApplyCall<R>& c, int T, hipStream_t s) {
 template <typename R>
 hipError_t pass_z(const ApplyCall<R>& c, const cx<R>* tab, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long P = c.g.sp->P, bz = c.g.bz;
-  ZArgs a{T, int(P / T), int(P / 2), int(P), c.g.sp->nxp, pl->ne, bz * P * P, long(pl->C) * bz * P * P, c.nb, int(bz)};
-  if ((P / T) * P % 8 != 0) return hipErrorInvalidValue;  // the XCD block order deals slices in groups of 8
-  const long nblocks = long(P / T) * P * c.nb;
-  return c.ops->zpass(pl->full ? MUL_MAX6 : MUL_SYM3, c.B, tab, a, nblocks, c.tw, s);
+  const long Pz = c.g.sp->Pz, Q = c.g.sp->Pxy, bz = c.g.bz;
+  const long ntiles = (Q + T - 1) / T;  // the last tile may be partial
+  ZArgs a{T,      int(ntiles), int(Pz / 2),           int(Pz), c.g.sp->nxp, pl->ne, bz * Q * Q,
+          long(pl->C) * bz * Q * Q, c.nb, int(bz), int(Q)};
+  if (ntiles * Q % 8 != 0) return hipErrorInvalidValue;  // XCD block order: slices in groups of 8
+  const long nblocks = ntiles * Q * c.nb;
+  return c.opsz->zpass(pl->full ? MUL_MAX6 : MUL_SYM3, c.B, tab, a, nblocks, c.twz, s);
 }
 
 // y inverse: B -> A, outputs y < by
 template <typename R>
 hipError_t pass_yinv(const ApplyCall<R>& c, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long P = c.g.sp->P, by = c.g.by;
+  const long P = c.g.sp->Pxy, by = c.g.by;
   Geo g{T, int(P / T), P, int(P), int(by)};
   MemLoad<cx<R>> src{c.B, P * P, 1, P};
   MemStore<cx<R>> dst{c.A, by * P, 1, P, 1.0, 0};
@@ -330,16 +336,18 @@ int ensure_workspace(vie_plan* pl, int nb) {
 
 // time one pass for each tile candidate and keep the fastest
 template <typename R, typename F>
-int pick_tile(vie_plan* pl, int P1, int P2, bool contig, int maxthreads, F&& run, hipStream_t s, int* out) {
+int pick_tile(vie_plan* pl, int P1, int P2, bool contig, int maxthreads, int cols, F&& run, hipStream_t s, int* out,
+              bool ragged = false) {
   hipEvent_t e0, e1;
   HIPCHK(pl, hipEventCreate(&e0));
   HIPCHK(pl, hipEventCreate(&e1));
   float best_ms = 1e30f;
   int best = 0;
   bool any_full = false;
-  for (int T : kTileChoices) any_full = any_full || tile_ok<R>(pl, P1, P2, T, contig, P1 * P2, maxthreads, true);
+  for (int T : kTileChoices)
+    any_full = any_full || tile_ok<R>(pl, P1, P2, T, contig, cols, maxthreads, true, ragged);
   for (int T : kTileChoices) {
-    if (!tile_ok<R>(pl, P1, P2, T, contig, P1 * P2, maxthreads, any_full)) continue;
+    if (!tile_ok<R>(pl, P1, P2, T, contig, cols, maxthreads, any_full, ragged)) continue;
     HIPCHK(pl, run(T));  // warm-up
     HIPCHK(pl, hipEventRecord(e0, s));
     for (int r = 0; r < 3; ++r) HIPCHK(pl, run(T));
@@ -370,14 +378,14 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStre
     *t = it->second;
     return VIE_OK;
   }
-  const int P1 = c.ops->P1, P2 = c.ops->P2;
+  const int P1 = c.ops->P1, P2 = c.ops->P2, Z1 = c.opsz->P1, Z2 = c.opsz->P2;
   Tune d;
-  const int P = P1 * P2;  // the geometry's transform length
+  const int P = P1 * P2;  // the x and y transform length; the z pass runs over P x P columns
   d.tx_fwd = default_tile<R>(pl, P1, P2, true, kPassMaxThreads, P);
   const int fmax = pl->C == 6 ? fused_max_threads<R, 6>() : fused_max_threads<R, 3>();
   d.tx_inv = default_tile<R>(pl, P1, P2, true, fmax, P);
   d.ty_fwd = d.ty_inv = default_tile<R>(pl, P1, P2, false, kPassMaxThreads, P);
-  d.tz = default_tile<R>(pl, P1, P2, false, fmax, P);
+  d.tz = default_tile<R>(pl, Z1, Z2, false, fmax, P, true);
   if (d.tx_fwd == 0 || d.tz == 0 || d.tx_inv == 0 || d.ty_fwd == 0) return fail(pl, VIE_E_SIZE, "no tile shape fits the LDS limit");
   // VIE_TILES="xfwd,yfwd,z,yinv,xinv" pins the tiles of this FFT length and
   // precision (profiling runs that must repeat a measured launch shape)
@@ -386,7 +394,7 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStre
   if (pin && std::sscanf(pin, "%d,%d,%d,%d,%d", &pt[0], &pt[1], &pt[2], &pt[3], &pt[4]) == 5) {
     const bool ok = tile_ok<R>(pl, P1, P2, pt[0], true, P, kPassMaxThreads, false) &&
                     tile_ok<R>(pl, P1, P2, pt[1], false, P, kPassMaxThreads, false) &&
-                    tile_ok<R>(pl, P1, P2, pt[2], false, P, fmax, false) &&
+                    tile_ok<R>(pl, Z1, Z2, pt[2], false, P, fmax, false, true) &&
                     tile_ok<R>(pl, P1, P2, pt[3], false, P, kPassMaxThreads, false) &&
                     tile_ok<R>(pl, P1, P2, pt[4], true, P, fmax, false);
     if (!ok) return fail(pl, VIE_E_ARG, std::string("tiles pinned by the environment do not fit: ") + pin);
@@ -403,17 +411,17 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStre
     else
       tab = c.g.sp->tab64;
     int rc;
-    rc = pick_tile<R>(pl, P1, P2, true, kPassMaxThreads, [&](int T) { return pass_xfwd<R, TV>(c, in, T, s); }, s, &d.tx_fwd);
+    rc = pick_tile<R>(pl, P1, P2, true, kPassMaxThreads, P, [&](int T) { return pass_xfwd<R, TV>(c, in, T, s); }, s, &d.tx_fwd);
     if (rc) return rc;
-    rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, [&](int T) { return pass_yfwd<R>(c, T, s); }, s, &d.ty_fwd);
+    rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, P, [&](int T) { return pass_yfwd<R>(c, T, s); }, s, &d.ty_fwd);
     if (rc) return rc;
-    rc = pick_tile<R>(pl, P1, P2, false, fmax, [&](int T) { return pass_z<R>(c, tab, T, s); }, s, &d.tz);
+    rc = pick_tile<R>(pl, Z1, Z2, false, fmax, P, [&](int T) { return pass_z<R>(c, tab, T, s); }, s, &d.tz, true);
     if (rc) return rc;
-    rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, [&](int T) { return pass_yinv<R>(c, T, s); }, s, &d.ty_inv);
+    rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, P, [&](int T) { return pass_yinv<R>(c, T, s); }, s, &d.ty_inv);
     if (rc) return rc;
     // the raw convolution for complex128 vectors (any J), the matvec for complex64
     const int xmode = std::is_same<TV, c128>::value ? MODE_CONV : MODE_MATVEC;
-    rc = pick_tile<R>(pl, P1, P2, true, fmax,
+    rc = pick_tile<R>(pl, P1, P2, true, fmax, P,
                       [&](int T) { return pass_xinv<R, TV>(c, in, nullptr, out, xmode, T, s); }, s, &d.tx_inv);
     if (rc) return rc;
   }
@@ -430,9 +438,10 @@ template <typename R, typename TV>
 int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, const c128* bvec, TV* out,
                 int nrhs, int mode, hipStream_t s) {
   const Spec& sp = *geom.sp;
-  const LenOps<R>* ops = len_ops<R>(sp.P);
-  if (!ops || !ops->contig_fwd || !ops->zpass || !ops->xinv)
-    return fail(pl, VIE_E_SIZE, "no compiled FFT length " + std::to_string(sp.P));
+  const LenOps<R>* ops = len_ops<R>(sp.Pxy);
+  const LenOps<R>* opsz = len_ops<R>(sp.Pz);
+  if (!ops || !ops->contig_fwd || !ops->xinv || !opsz || !opsz->zpass)
+    return fail(pl, VIE_E_SIZE, "no compiled FFT lengths " + std::to_string(sp.Pxy) + ", " + std::to_string(sp.Pz));
   if (!std::is_same<TV, c128>::value && (!ops->contig_fwd_v32 || !ops->xinv_v32))
     return fail(pl, VIE_E_STATE, "complex64 vectors need the FP32 apply");
   const int idx = std::is_same<R, double>::value ? 1 : 0;
@@ -440,18 +449,22 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
   int rc = ensure_workspace<R>(pl, chunk);
   if (rc) return rc;
   const cx<R>* tw;
+  const cx<R>* twz;
   const cx<R>* tab;
   if constexpr (std::is_same<R, float>::value) {
     tw = sp.tw32;
+    twz = sp.twz32;
     tab = sp.tab32;
   } else {
     tw = sp.tw64;
+    twz = sp.twz64;
     tab = sp.tab64;
   }
   const long L = long(pl->C) * geom.np;
   for (int r0 = 0; r0 < nrhs; r0 += chunk) {
     const int nb = std::min(chunk, nrhs - r0);
-    ApplyCall<R> c{pl, ops, tw, static_cast<cx<R>*>(pl->wsA[idx]), static_cast<cx<R>*>(pl->wsB[idx]), nb, geom};
+    ApplyCall<R> c{pl,  ops, tw, opsz, twz, static_cast<cx<R>*>(pl->wsA[idx]), static_cast<cx<R>*>(pl->wsB[idx]),
+                   nb,  geom};
     const long off = long(r0) * L;
     const TV* inr = in + off;
     TV* outr = out + off;
@@ -462,16 +475,17 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     // algorithmic bytes: every operand read or written once per launch
     const double cr = double(sizeof(cx<R>)), c16 = double(sizeof(TV));
     const double vN3 = double(nb) * pl->C * double(geom.np);
-    const double vN2P = double(nb) * pl->C * geom.bz * geom.by * sp.P, vNP2 = vN2P / geom.by * sp.P;
+    const double vN2P = double(nb) * pl->C * geom.bz * geom.by * sp.Pxy, vNP2 = vN2P / geom.by * sp.Pxy;
     const double hb = 9.0 * double(geom.np) * cr * (pl->full ? 2 : 1);
     const double xinv_b = vN2P * cr + hb * (mode == MODE_MATVEC || mode == MODE_RESIDUAL) +
                           vN3 * c16 * (1 + (mode != MODE_CONV)) + vN3 * sizeof(c128) * (mode == MODE_RESIDUAL);
     // nominal flops: 5 P log2 P per transformed pencil of length P; 66 per
     // frequency point for the 3x3 multiply (216 for the 6x6 Maxwell block);
     // 72 per point and 3-component half for the combine
-    const double P = sp.P, fft_row = 5.0 * P * std::log2(P);
+    const double P = sp.Pxy, fft_row = 5.0 * P * std::log2(P);
+    const double Pz = sp.Pz, fft_row_z = 5.0 * Pz * std::log2(Pz);
     const double rows_x = vN2P / P, rows_y = vN2P / geom.by, rows_z = vNP2 / geom.bz;
-    const double pts = double(nb) * P * P * P;
+    const double pts = double(nb) * P * P * Pz;
     const double mul_f = (pl->full ? 216.0 : 66.0) * pts;
     const double comb_f = (mode == MODE_CONV) ? 0.0 : 72.0 * vN3 / 3.0;
     int tok = prof_begin(pl, s);
@@ -482,7 +496,7 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     prof_end(pl, f0 + 1, tok, s, (vN2P + vNP2) * cr, rows_y * fft_row);
     tok = prof_begin(pl, s);
     HIPCHK(pl, pass_z<R>(c, tab, t.tz, s));
-    prof_end(pl, f0 + 2, tok, s, 2.0 * vNP2 * cr + double(sp.tab_elems) * cr, 2.0 * rows_z * fft_row + mul_f);
+    prof_end(pl, f0 + 2, tok, s, 2.0 * vNP2 * cr + double(sp.tab_elems) * cr, 2.0 * rows_z * fft_row_z + mul_f);
     tok = prof_begin(pl, s);
     HIPCHK(pl, pass_yinv<R>(c, t.ty_inv, s));
     prof_end(pl, f0 + 3, tok, s, (vN2P + vNP2) * cr, rows_y * fft_row);
@@ -496,26 +510,28 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
 // ---------------------------------------------------------------------------
 // precompute of the kernel-transform tables (FP64)
 // ---------------------------------------------------------------------------
-// Tables of transform length sp.P (<= 2n): the windowed kernel K_m for
-// |m_a| <= P/2 - 1 (the window of the whole grid when P = 2n), transformed on
-// the P grid.  The box convolution needs offsets |m_a| <= b - 1 < P/2 only,
-// and its wrapped copies lie at |m_a| >= P - (b - 1) > P/2 - 1.
+// Tables of the periodic grid (Pz, Pxy, Pxy) <= 2n: the kernel windowed to
+// |m_z| <= Pz/2 - 1, |m_x|, |m_y| <= Pxy/2 - 1 (the window of the whole grid
+// when both are 2n), transformed on that grid.  The box convolution needs
+// offsets |m_a| <= b_a - 1 < P_a/2 only, and its wrapped copies lie at
+// |m_a| >= P_a - (b_a - 1) > P_a/2 - 1.
 int build_tables(vie_plan* pl, Spec& sp, hipStream_t s) {
-  const int P = sp.P, N = P / 2, M = pl->M, NE = pl->ne;
+  const int Z = sp.Pz, Q = sp.Pxy, M = pl->M, NE = pl->ne;
   const LenOps<double>* opsM = len_ops<double>(M);
-  const LenOps<double>* opsP = len_ops<double>(P);
+  const LenOps<double>* opsQ = len_ops<double>(Q);
+  const LenOps<double>* opsZ = len_ops<double>(Z);
   if (!opsM || !opsM->symbol_inv || !opsM->strided)
     return fail(pl, VIE_E_SIZE, "no compiled oversampled FFT length " + std::to_string(M));
-  if (!opsP || !opsP->contig_fwd || !opsP->strided)
-    return fail(pl, VIE_E_SIZE, "no compiled FFT length " + std::to_string(P));
+  if (!opsQ || !opsQ->contig_fwd || !opsQ->strided || !opsZ || !opsZ->strided)
+    return fail(pl, VIE_E_SIZE, "no compiled FFT lengths " + std::to_string(Q) + ", " + std::to_string(Z));
   c128* twM = nullptr;
   int rc = upload_twiddles<double>(pl, M, &twM, s);
   if (rc) return rc;
-  const long MM = long(M), PP = long(P);
+  const long MM = long(M), QQ = long(Q), ZZ = long(Z);
   c128 *buf1 = nullptr, *buf2 = nullptr, *buf3 = nullptr;
-  rc = dev_alloc(pl, reinterpret_cast<void**>(&buf1), sizeof(c128) * size_t(MM * MM * PP));
-  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&buf2), sizeof(c128) * size_t(MM * PP * PP));
-  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&buf3), sizeof(c128) * size_t(NE) * size_t(PP * PP * PP));
+  rc = dev_alloc(pl, reinterpret_cast<void**>(&buf1), sizeof(c128) * size_t(MM * MM * QQ));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&buf2), sizeof(c128) * size_t(MM * QQ * QQ));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&buf3), sizeof(c128) * size_t(NE) * size_t(ZZ * QQ * QQ));
   auto cleanup = [&]() {
     dev_free(pl, buf1);
     dev_free(pl, buf2);
@@ -526,65 +542,66 @@ int build_tables(vie_plan* pl, Spec& sp, hipStream_t s) {
     cleanup();
     return rc;
   }
-  // strided passes of length M run over P (y) or P^2 (z) columns
+  // strided passes run over Q (y) or Q^2 (z) columns
   const int TcM = default_tile<double>(pl, opsM->P1, opsM->P2, true, kPassMaxThreads, 0);
-  const int TsM = default_tile<double>(pl, opsM->P1, opsM->P2, false, kPassMaxThreads, P);
-  const int TcP = default_tile<double>(pl, opsP->P1, opsP->P2, true, kPassMaxThreads, 0);
-  const int TsP = default_tile<double>(pl, opsP->P1, opsP->P2, false, kPassMaxThreads, P);
-  if (!TcM || !TsM || !TcP || !TsP) {
+  const int TsM = default_tile<double>(pl, opsM->P1, opsM->P2, false, kPassMaxThreads, Q);
+  const int TcQ = default_tile<double>(pl, opsQ->P1, opsQ->P2, true, kPassMaxThreads, 0);
+  const int TsQ = default_tile<double>(pl, opsQ->P1, opsQ->P2, false, kPassMaxThreads, Q);
+  const int TsZ = default_tile<double>(pl, opsZ->P1, opsZ->P2, false, kPassMaxThreads, Q);
+  if (!TcM || !TsM || !TcQ || !TsQ || !TsZ) {
     cleanup();
     return fail(pl, VIE_E_SIZE, "no tile shape fits the LDS limit for the precompute");
   }
   hipError_t e = hipSuccess;
   for (int ent = 0; ent < NE && e == hipSuccess; ++ent) {
     // (a) symbol samples of entry `ent` -> inverse transform along x; keep
-    //     outputs 0..P-1 (displacements -P/2..P/2-1), zero displacement -P/2
+    //     outputs 0..Q-1 (displacements -Q/2..Q/2-1), zero displacement -Q/2
     {
-      SymbolSrc src{M, pl->sym_set, ent, P / 2, pl->h, pl->omega, pl->R};
+      SymbolSrc src{M, pl->sym_set, ent, Q / 2, Q / 2, Z / 2, pl->h, pl->omega, pl->R};
       const long rows = MM * MM;
-      Geo g{TcM, int((rows + TcM - 1) / TcM), rows, M, P};
-      MemStore<c128> dst{buf1, 0, PP, 1, 1.0 / double(M), 1};
+      Geo g{TcM, int((rows + TcM - 1) / TcM), rows, M, Q};
+      MemStore<c128> dst{buf1, 0, QQ, 1, 1.0 / double(M), 1};
       e = opsM->symbol_inv(src, dst, g, 1, twM, s);
     }
-    // (b) inverse along y: buf1[kz][ky][nx] -> buf2[kz][ny][nx]
+    // (b) inverse along y: buf1[kz][ky][nx] -> buf2[kz][ny][nx], ny < Q
     if (e == hipSuccess) {
-      Geo g{TsM, int(PP / TsM), PP, M, P};
-      MemLoad<c128> src{buf1, MM * PP, 1, PP};
-      MemStore<c128> dst{buf2, PP * PP, 1, PP, 1.0 / double(M), 1};
+      Geo g{TsM, int(QQ / TsM), QQ, M, Q};
+      MemLoad<c128> src{buf1, MM * QQ, 1, QQ};
+      MemStore<c128> dst{buf2, QQ * QQ, 1, QQ, 1.0 / double(M), 1};
       e = opsM->strided(true, src, dst, g, MM, twM, s);
     }
-    // (c) inverse along z: buf2[kz][ny][nx] -> buf3[ent][nz][ny][nx]
+    // (c) inverse along z: buf2[kz][ny][nx] -> buf3[ent][nz][ny][nx], nz < Z
     if (e == hipSuccess) {
-      const long cols = PP * PP;
-      Geo g{TsM, int(cols / TsM), cols, M, P};
-      MemLoad<c128> src{buf2, 0, 1, PP * PP};
-      MemStore<c128> dst{buf3 + long(ent) * PP * PP * PP, 0, 1, PP * PP, 1.0 / double(M), 1};
+      const long cols = QQ * QQ;
+      Geo g{TsM, int(cols / TsM), cols, M, Z};
+      MemLoad<c128> src{buf2, 0, 1, QQ * QQ};
+      MemStore<c128> dst{buf3 + long(ent) * ZZ * QQ * QQ, 0, 1, QQ * QQ, 1.0 / double(M), 1};
       e = opsM->strided(true, src, dst, g, 1, twM, s);
     }
   }
-  // (d) forward transforms of length P along x, y, z (in place, all entries)
+  // (d) forward transforms along x (Q), y (Q), z (Z) (in place, all entries)
   if (e == hipSuccess) {
-    const long rows = long(NE) * PP * PP;
-    Geo g{TcP, int((rows + TcP - 1) / TcP), rows, P, P};
-    MemLoad<c128> src{buf3, 0, PP, 1};
-    MemStore<c128> dst{buf3, 0, PP, 1, 1.0, 0};
-    e = opsP->contig_fwd(src, dst, g, 1, sp.tw64, s);
+    const long rows = long(NE) * ZZ * QQ;
+    Geo g{TcQ, int((rows + TcQ - 1) / TcQ), rows, Q, Q};
+    MemLoad<c128> src{buf3, 0, QQ, 1};
+    MemStore<c128> dst{buf3, 0, QQ, 1, 1.0, 0};
+    e = opsQ->contig_fwd(src, dst, g, 1, sp.tw64, s);
   }
   if (e == hipSuccess) {
-    Geo g{TsP, int(PP / TsP), PP, P, P};
-    MemLoad<c128> src{buf3, PP * PP, 1, PP};
-    MemStore<c128> dst{buf3, PP * PP, 1, PP, 1.0, 0};
-    e = opsP->strided(false, src, dst, g, long(NE) * PP, sp.tw64, s);
+    Geo g{TsQ, int(QQ / TsQ), QQ, Q, Q};
+    MemLoad<c128> src{buf3, QQ * QQ, 1, QQ};
+    MemStore<c128> dst{buf3, QQ * QQ, 1, QQ, 1.0, 0};
+    e = opsQ->strided(false, src, dst, g, long(NE) * ZZ, sp.tw64, s);
   }
   if (e == hipSuccess) {
-    const long cols = PP * PP;
-    Geo g{TsP, int(cols / TsP), cols, P, P};
-    MemLoad<c128> src{buf3, PP * PP * PP, 1, PP * PP};
-    MemStore<c128> dst{buf3, PP * PP * PP, 1, PP * PP, 1.0, 0};
-    e = opsP->strided(false, src, dst, g, NE, sp.tw64, s);
+    const long cols = QQ * QQ;
+    Geo g{TsZ, int(cols / TsZ), cols, Z, Z};
+    MemLoad<c128> src{buf3, ZZ * QQ * QQ, 1, QQ * QQ};
+    MemStore<c128> dst{buf3, ZZ * QQ * QQ, 1, QQ * QQ, 1.0, 0};
+    e = opsZ->strided(false, src, dst, g, NE, sp.twz64, s);
   }
-  // (e) shift by P/2 in every axis ((-1)^q), scale by P^-3, fold to the octant
-  if (e == hipSuccess) e = launch_finalize_tables(buf3, sp.tab64, sp.tab32, N, P, sp.nxp, NE, pl->omega, s);
+  // (e) shift by P_a/2 in every axis ((-1)^q), scale by 1/(Z Q^2), fold to the octant
+  if (e == hipSuccess) e = launch_finalize_tables(buf3, sp.tab64, sp.tab32, Q, Z, sp.nxp, NE, pl->omega, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup();
   return e == hipSuccess ? VIE_OK : hip_fail(pl, e, "table precompute");
@@ -698,30 +715,39 @@ void destroy_plan(vie_plan* pl) {
   delete pl;
 }
 
-// twiddles and kernel-transform tables of length P
-int make_spec(vie_plan* pl, int P, Spec& sp, hipStream_t s) {
-  sp.P = P;
-  sp.nxp = ((P / 2 + 1 + 15) / 16) * 16;
-  int rc = upload_twiddles<double>(pl, P, &sp.tw64, s);
-  if (!rc) rc = upload_twiddles<float>(pl, P, &sp.tw32, s);
+// twiddles and kernel-transform tables of the grid (Pz, Pxy, Pxy)
+int make_spec(vie_plan* pl, int Pz, int Pxy, Spec& sp, hipStream_t s) {
+  sp.Pz = Pz;
+  sp.Pxy = Pxy;
+  sp.nxp = ((Pz / 2 + 1 + 15) / 16) * 16;
+  int rc = upload_twiddles<double>(pl, Pxy, &sp.tw64, s);
+  if (!rc) rc = upload_twiddles<float>(pl, Pxy, &sp.tw32, s);
+  if (!rc && Pz == Pxy) {
+    sp.twz64 = sp.tw64;
+    sp.twz32 = sp.tw32;
+  } else {
+    if (!rc) rc = upload_twiddles<double>(pl, Pz, &sp.twz64, s);
+    if (!rc) rc = upload_twiddles<float>(pl, Pz, &sp.twz32, s);
+  }
   if (rc) return rc;
-  sp.tab_elems = long(P / 2 + 1) * (P / 2 + 1) * pl->ne * sp.nxp;
+  sp.tab_elems = long(Pz / 2 + 1) * (Pz / 2 + 1) * pl->ne * sp.nxp;
   rc = dev_alloc(pl, reinterpret_cast<void**>(&sp.tab64), sizeof(c128) * size_t(sp.tab_elems));
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&sp.tab32), sizeof(c64) * size_t(sp.tab_elems));
   if (rc) return rc;
   return build_tables(pl, sp, s);
 }
 
-// The shortest compiled transform length L <= 2n with L >= 2 max(bx, by, bz)
-// (so that the cyclic convolution of box data has no wrap-around) whose
-// apply and precompute kernels exist.
+// The shortest compiled transform length L <= 2n with L >= 2 max(bx, by)
+// (so that the cyclic convolution of box data has no wrap-around along x and
+// y) whose apply and precompute kernels exist.  Along z the fused pass keeps
+// 2n, whose balanced split suits it best.
 int box_length(const vie_plan* pl) {
-  const int need = 2 * std::max(pl->box.bx, std::max(pl->box.by, pl->box.bz));
+  const int need = 2 * std::max(pl->box.bx, pl->box.by);
   for (int L = need + (need & 1); L < pl->P; L += 2) {
     const LenOps<float>* o32 = len_ops<float>(L);
     const LenOps<double>* o64 = len_ops<double>(L);
-    if (L % 8 == 0 && o32 && o64 && o32->contig_fwd && o32->zpass && o64->contig_fwd && o64->zpass &&
-        o64->strided)
+    if (L % 8 == 0 && o32 && o64 && o32->contig_fwd && o32->strided && o32->xinv && o64->contig_fwd &&
+        o64->strided && o64->xinv)
       return L;
   }
   return pl->P;
@@ -862,13 +888,13 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   if ((p->flags & VIE_STRICT_MEDIUM) && !(worst < 1.0))
     return fail(pl, VIE_E_MEDIUM, "max ||H(x)||_2 = " + std::to_string(worst) + " >= 1 (contrast not a contraction)");
   // twiddles and kernel tables: the whole grid's, and the box's when shorter
-  rc = make_spec(pl, pl->P, pl->sg, s);
+  rc = make_spec(pl, pl->P, pl->P, pl->sg, s);
   if (rc) return rc;
   const int pb = pl->use_box && env_flag("VIE_PBOX", true) ? box_length(pl) : pl->P;
   if (pb == pl->P) {
     pl->sb = pl->sg;
   } else {
-    rc = make_spec(pl, pb, pl->sb, s);
+    rc = make_spec(pl, pl->P, pb, pl->sb, s);
     if (rc) return rc;
   }
   return VIE_OK;
@@ -946,7 +972,7 @@ int vie_plan_info(const vie_plan* pl, double* out, int nout) {
                         pl->hmax,              double(pl->ne),     double(pl->dev_bytes),
                         double(pl->graph_launches), double(pl->box.x0), double(pl->box.y0), double(pl->box.z0),
                         double(pl->box.bx),    double(pl->box.by), double(pl->box.bz), double(pl->box.np),
-                        double(pl->sb.P)};
+                        double(pl->sb.Pxy)};
   for (int i = 0; i < nout && i < 16; ++i) out[i] = v[i];
   return VIE_OK;
 }

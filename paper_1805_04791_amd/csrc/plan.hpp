@@ -17,15 +17,19 @@ namespace vie {
 
 // Extent of the data an apply works on: the whole grid, or the bounding box
 // of the support of H (the Krylov vectors vanish outside it exactly).
-// Spectral data of one periodic transform length P: the kernel-transform
-// octant tables (q in [0, P/2]^3, rows of nxp) and the twiddles.
+// Spectral data of one periodic grid: transform length Pz along z and Pxy
+// along x and y (Pxy <= Pz); the kernel-transform octant tables
+// [qz][qy][entry][qx], qz, qy in [0, Pz/2], qx < nxp = (Pz/2 + 1) rounded up to
+// 16 (entries with qy or qx > Pxy/2 are zero); twiddles of both lengths.
 struct Spec {
-  int P = 0, nxp = 0;
+  int Pz = 0, Pxy = 0, nxp = 0;
   long tab_elems = 0;
   c128* tab64 = nullptr;
   c64* tab32 = nullptr;
-  c128* tw64 = nullptr;
+  c128* tw64 = nullptr;   // length Pxy
   c64* tw32 = nullptr;
+  c128* twz64 = nullptr;  // length Pz
+  c64* twz32 = nullptr;
 };
 
 struct Geom {
@@ -67,7 +71,7 @@ struct vie_plan {
   vie::c128 *H64 = nullptr, *Hmu64 = nullptr;
   vie::c64 *H32 = nullptr, *Hmu32 = nullptr;
   vie::Spec sg;  // P = 2n: the whole grid (vie_apply, vie_field)
-  vie::Spec sb;  // the solver's box: the shortest compiled length >= 2 max(bx, by, bz), <= 2n
+  vie::Spec sb;  // the solver's box: Pz = 2n, Pxy the shortest compiled length >= 2 max(bx, by), <= 2n
 
   // apply workspaces [0] FP32, [1] FP64; capacity in right-hand sides
   void* wsA[2] = {nullptr, nullptr};

@@ -374,12 +374,12 @@ __global__ void __launch_bounds__(kBlock) k_demote(const c128* __restrict__ s, c
 }
 
 __global__ void __launch_bounds__(kBlock) k_finalize(const c128* __restrict__ buf, c128* __restrict__ tab64,
-                                                     c64* __restrict__ tab32, int n, int P, int nxp, int ne,
+                                                     c64* __restrict__ tab32, int Q, int Z, int nxp, int ne,
                                                      double omega) {
-  const long n1 = n + 1;
+  const long n1 = Z / 2 + 1;
   const long total = n1 * n1 * ne * nxp;
-  const double sc = 1.0 / (double(P) * double(P) * double(P));
-  const long P3 = long(P) * P * P;
+  const double sc = 1.0 / (double(Q) * double(Q) * double(Z));
+  const long V = long(Z) * Q * Q;
   for (long t = long(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
     const int qx = int(t % nxp);
     long r = t / nxp;
@@ -388,8 +388,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const c128* __restrict__ bu
     const int qy = int(r % n1);
     const int qz = int(r / n1);
     c128 v = {0.0, 0.0};
-    if (qx <= n) {
-      v = buf[e * P3 + (long(qz) * P + qy) * P + qx];
+    if (qx <= Q / 2 && qy <= Q / 2) {
+      v = buf[e * V + (long(qz) * Q + qy) * Q + qx];
       double f = ((qx + qy + qz) & 1) ? -sc : sc;
       v = f * v;
       if (e >= 6) v = omega * times_i(v);
@@ -487,10 +487,10 @@ hipError_t launch_demote(const c128* src, c64* dst, long n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_finalize_tables(const c128* buf, c128* tab64, c64* tab32, int n, int P, int nxp, int ne,
+hipError_t launch_finalize_tables(const c128* buf, c128* tab64, c64* tab32, int Q, int Z, int nxp, int ne,
                                   double omega, hipStream_t s) {
-  const long total = long(n + 1) * (n + 1) * ne * nxp;
-  k_finalize<<<grid_for(total), kBlock, 0, s>>>(buf, tab64, tab32, n, P, nxp, ne, omega);
+  const long total = long(Z / 2 + 1) * (Z / 2 + 1) * ne * nxp;
+  k_finalize<<<grid_for(total), kBlock, 0, s>>>(buf, tab64, tab32, Q, Z, nxp, ne, omega);
   return hipGetLastError();
 }
 

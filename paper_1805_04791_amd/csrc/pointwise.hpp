@@ -61,10 +61,12 @@ hipError_t launch_copy(const c128* src, c128* dst, long n, hipStream_t s);
 // FP32 tables from FP64
 hipError_t launch_demote(const c128* src, c64* dst, long n, hipStream_t s);
 
-// Octant tables from the P^3 transforms of the windowed kernel:
-// tab[((qz (n+1) + qy) ne + e) nxp + qx] = (-1)^(qx+qy+qz) * scale_e * buf[e][qz][qy][qx]
-// for q in [0, n]^3; scale_e = 1/P^3, times i*omega for the curl entries e >= 6.
-hipError_t launch_finalize_tables(const c128* buf, c128* tab64, c64* tab32, int n, int P, int nxp, int ne,
+// Octant tables from the (Z, Q, Q) transforms of the windowed kernel
+// buf[e][qz][qy][qx]: tab[((qz (Z/2+1) + qy) ne + e) nxp + qx] =
+// (-1)^(qx+qy+qz) * scale_e * buf[e][qz][qy][qx] for qz, qy in [0, Z/2], qx < nxp,
+// zero where qx or qy > Q/2; scale_e = 1/(Z Q^2), times i*omega for the curl
+// entries e >= 6.
+hipError_t launch_finalize_tables(const c128* buf, c128* tab64, c64* tab32, int Q, int Z, int nxp, int ne,
                                   double omega, hipStream_t s);
 
 int krylov_blocks(long L);

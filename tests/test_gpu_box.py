@@ -193,16 +193,17 @@ def ball_medium(n, radius, seed_item):
 
 @pytest.mark.parametrize("n,radius", [(24, 0.45), (32, 0.4)])
 def test_short_box_transform_matches_oracle(vie, n, radius):
-    """A support box of at most n/2 points per axis is convolved on a
-    transform grid shorter than 2n; the solution is the oracle's (whole grid,
-    window of the whole grid) to FP64 and mixed accuracy."""
+    """A support box of at most n/2 points along x and y is convolved on a
+    transform grid shorter than 2n along x and y; the solution is the
+    oracle's (whole grid, window of the whole grid) to FP64 and mixed
+    accuracy."""
     coef, omega = ball_medium(n, radius, 17)
     inc = plane_waves(n, omega, 2, 30)
     A = op.Operator(op.KIND_HELMHOLTZ, coef, omega)
     ref = [sv.gmres(A.apply, A.rhs(inc[r]), tol=1e-13)[0] for r in range(2)]
     plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2)
     info = plan.info()
-    assert info["box_P"] < 2 * n and info["box_P"] >= 2 * max(info["box"][3:])
+    assert info["box_P"] < 2 * n and info["box_P"] >= 2 * max(info["box"][3:5])
     for fp64, tol, err in ((True, 1e-12, 1e-10), (False, 1e-9, 1e-8)):
         d, f, st, rc = plan.solve(inc, tol=tol, fp64=fp64)
         assert rc == vie.OK
@@ -215,8 +216,8 @@ def test_short_box_transform_matches_oracle(vie, n, radius):
 
 
 def test_short_box_transform_equals_full_length(vie, monkeypatch):
-    """n = 64, bump of radius 0.8: the solver's transform length is 120 (not
-    128); FP64 solves agree with those on the 2n grid."""
+    """n = 64, bump of radius 0.8: the solver's transform length along x and y
+    is 120 (not 128); solves agree with those on the 2n grid."""
     n = 64
     coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 18)
     inc = plane_waves(n, omega, 2, 40)
