@@ -193,6 +193,21 @@ def main(argv=None):
                      "TFLOP/s": v[3] / (v[0] * 1e-3) / 1e12 if v[0] > 0 else None}
                  for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
 
+    # achievable HBM bandwidth on this device: a plain 2 GiB device-to-device copy
+    src = torch.empty(2 ** 29, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    roof["copy_GBs"] = copy_gbs
+    roof["hbm_frac_of_copy"] = roof["hbm_GBs"] / copy_gbs
+
     cpu = None
     if not args.no_cpu_baseline:
         mv = fp64.get("fp64_matvecs_per_solve") or float(np.mean([s["matvecs_fp32"] + s["matvecs_fp64"]
