@@ -613,11 +613,19 @@ namespace vie {
 
 int apply_any(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
               c128* out, int nrhs, int mode, hipStream_t s) {
+  if (g.sp == &pl->sg) {
+    const int rc = ensure_grid_spec(pl, s);
+    if (rc) return rc;
+  }
   return fp64 ? apply_typed<double, c128>(pl, g, in, addv, bvec, out, nrhs, mode, s)
               : apply_typed<float, c128>(pl, g, in, addv, bvec, out, nrhs, mode, s);
 }
 
 int apply_any(vie_plan* pl, const Geom& g, const c64* in, c64* out, int nrhs, hipStream_t s) {
+  if (g.sp == &pl->sg) {
+    const int rc = ensure_grid_spec(pl, s);
+    if (rc) return rc;
+  }
   return apply_typed<float, c64>(pl, g, in, in, nullptr, out, nrhs, MODE_MATVEC, s);
 }
 
@@ -736,6 +744,15 @@ int make_spec(vie_plan* pl, int Pz, int Pxy, Spec& sp, hipStream_t s) {
   if (rc) return rc;
   return build_tables(pl, sp, s);
 }
+
+}  // namespace
+
+int vie::ensure_grid_spec(vie_plan* pl, hipStream_t s) {
+  if (pl->sg.tab64) return VIE_OK;
+  return make_spec(pl, pl->P, pl->P, pl->sg, s);
+}
+
+namespace {
 
 // The shortest compiled transform length L <= 2n with L >= 2 max(bx, by)
 // (so that the cyclic convolution of box data has no wrap-around along x and
@@ -888,15 +905,12 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   if ((p->flags & VIE_STRICT_MEDIUM) && !(worst < 1.0))
     return fail(pl, VIE_E_MEDIUM, "max ||H(x)||_2 = " + std::to_string(worst) + " >= 1 (contrast not a contraction)");
   // twiddles and kernel tables: the whole grid's, and the box's when shorter
-  rc = make_spec(pl, pl->P, pl->P, pl->sg, s);
-  if (rc) return rc;
+  // (the whole grid's are built at its first use when they differ: a solve
+  // without field output never needs them)
   const int pb = pl->use_box && env_flag("VIE_PBOX", true) ? box_length(pl) : pl->P;
-  if (pb == pl->P) {
-    pl->sb = pl->sg;
-  } else {
-    rc = make_spec(pl, pl->P, pb, pl->sb, s);
-    if (rc) return rc;
-  }
+  rc = make_spec(pl, pl->P, pb, pl->sb, s);
+  if (rc) return rc;
+  if (pb == pl->P) pl->sg = pl->sb;
   return VIE_OK;
 }
 
@@ -977,8 +991,12 @@ int vie_plan_info(const vie_plan* pl, double* out, int nout) {
   return VIE_OK;
 }
 
-int vie_copy_tables(const vie_plan* pl, double* host, long host_bytes, long* needed, int* nxp, int* ne) {
-  if (!pl) return VIE_E_ARG;
+int vie_copy_tables(const vie_plan* cpl, double* host, long host_bytes, long* needed, int* nxp, int* ne) {
+  if (!cpl) return VIE_E_ARG;
+  // the tables of the whole grid are built at their first use
+  vie_plan* pl = const_cast<vie_plan*>(cpl);
+  const int rc = ensure_grid_spec(pl, pl->last_stream);
+  if (rc) return rc;
   const long bytes = long(sizeof(c128)) * pl->sg.tab_elems;
   if (needed) *needed = bytes;
   if (nxp) *nxp = pl->sg.nxp;

@@ -161,6 +161,8 @@ int apply_any(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128
 // calls with stable pointers); falls back to apply_any when capture is off
 int apply_graph(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
                 c128* out, int nrhs, int mode, hipStream_t s);
+// builds the whole grid's tables at their first use
+int ensure_grid_spec(vie_plan* pl, hipStream_t s);
 // FP32 matvec y = A x with x, y stored as complex64
 int apply_any(vie_plan* pl, const Geom& g, const c64* in, c64* out, int nrhs, hipStream_t s);
 void clear_graphs(vie_plan* pl);
