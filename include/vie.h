@@ -221,6 +221,45 @@ const char *vie_last_error(const vie_plan *pl);
 /* Whether n is a supported grid size (1/0). */
 int vie_supported_n(int n);
 
+/* Scattered potential phi_scat = div V_omega J on the grid (Laplace and
+ * Helmholtz; the summary of Section 3: F = V_omega J solves the vector
+ * problem and div F the anisotropic scalar one).  density: complex128
+ * [nrhs][3][n^3], phi: complex128 [nrhs][n^3], device pointers.  The symbol
+ * i s G^ is windowed and transformed like the operator's (built at the first
+ * call); FP64.  VIE_E_STATE for Maxwell plans. */
+int vie_potential(vie_plan *pl, const double *density, double *phi, int nrhs, void *hip_stream);
+
+/* Maxwell with mu = I: H_tot = H_inc - i omega curl V_omega J on the grid
+ * (eq. represent_Maxwell_reduced; vie_field gives E).  h_inc may be NULL
+ * (then the scattered field).  Device pointers, complex128 [nrhs][3][n^3];
+ * FP64.  VIE_E_STATE for other plans (full Maxwell: vie_field gives E and H). */
+int vie_field_h(vie_plan *pl, const double *density, const double *h_inc, double *h, int nrhs, void *hip_stream);
+
+/* Scattered fields at user points away from the density, by direct sums over
+ * the grid points y of the free-space kernel G = e^{i omega r}/(4 pi r) with
+ * weights h^3 (the representations of Sections 3 and 4, eqs. Vw,
+ * represent_Maxwell):
+ *   Laplace, Helmholtz: (phi, d_x phi, d_y phi, d_z phi), phi = div V J;
+ *   Maxwell: (E_x, E_y, E_z, H_x, H_y, H_z) of eq. represent_Maxwell (M = 0
+ *   for mu = I).
+ * density: device complex128 [nrhs][c][n^3]; points: HOST double [npts][3]
+ * (grid coordinates, origin as in vie_problem); out: device complex128
+ * [nrhs][npts][4 or 6].  Every point must lie outside the support box grown
+ * by 2h (VIE_E_ARG otherwise), where the sums are spectrally accurate for
+ * smooth densities.  FP64. */
+int vie_fields_at(vie_plan *pl, const double *density, int nrhs, const double *points, int npts, double *out,
+                  void *hip_stream);
+
+/* Far-field patterns f(r d) = e^{i omega r}/r f_inf(d) + O(1/r^2) in unit
+ * directions d (HOST double [ndirs][3]), from J^(d) = sum h^3 e^{-i omega d.y} J(y):
+ *   Helmholtz: phi_inf = (i omega / 4 pi) d . J^  (1 value);
+ *   Maxwell: E_inf = (omega^2 / 4 pi)[(I - d d^T) J^ - d x M^],
+ *            H_inf = (omega^2 / 4 pi)[(I - d d^T) M^ + d x J^]  (6 values).
+ * out: device complex128 [nrhs][ndirs][1 or 6].  VIE_E_STATE for Laplace;
+ * VIE_E_ARG for a direction that is not a unit vector.  FP64. */
+int vie_far_field(vie_plan *pl, const double *density, int nrhs, const double *dirs, int ndirs, double *out,
+                  void *hip_stream);
+
 /* Upper estimate of the device bytes a plan of this size holds at its peak
  * (the larger of: the kernel-table precompute, or the plan plus apply
  * workspaces and a Krylov basis of `restart` vectors for batches of

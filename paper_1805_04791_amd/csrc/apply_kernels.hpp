@@ -9,6 +9,10 @@
 //             (grad div + omega^2) V symbol and c = i omega (i s G^) the curl
 //             symbol scaled by i omega, 9 tables; so that Z_J = U_J + i omega W_M and
 //             Z_M = U_M - i omega W_J (eqs. intM and represent_Maxwell).
+//   MUL_DIV:  phi^ = d . J^ into component 0 (components 1, 2 zero), d = i s G^,
+//             3 tables: the potential div V J (Section 3's summary).
+//   MUL_CURLH: H^ = -i omega d x J^, 3 tables: the H field of Maxwell with mu = I
+//             (eq. represent_Maxwell_reduced).
 // The tables hold one octant q in [0, n]^3 of the 2n-periodic transform; the
 // other octants follow from the parity of each entry (odd in s_a for the
 // off-diagonal entries ab and for curl component a).
@@ -25,7 +29,9 @@
 
 namespace vie {
 
-enum { MUL_SYM3 = 0, MUL_MAX6 = 1 };
+enum { MUL_SYM3 = 0, MUL_MAX6 = 1, MUL_DIV = 2, MUL_CURLH = 3 };
+// table entries each multiply reads
+__host__ __device__ constexpr int mul_entries(int mul) { return mul == MUL_SYM3 ? 6 : (mul == MUL_MAX6 ? 9 : 3); }
 enum { MODE_MATVEC = 0, MODE_FIELD = 1, MODE_CONV = 2, MODE_RESIDUAL = 3 };
 
 struct ZArgs {
@@ -40,6 +46,7 @@ struct ZArgs {
   int nb;           // right-hand sides in the launch
   int nz;           // z extent of the data (n, or the support box): inputs z < nz, outputs z < nz
   int pxy;          // x and y transform length (<= P): columns (ky, kx) in [0, pxy)^2
+  double omega;     // MUL_CURLH: the factor -i omega
 };
 
 // Block order: blocks are dealt round-robin to the 8 XCDs (block b runs on
@@ -55,6 +62,7 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
   static_assert(P1 % 2 == 0, "pruned z input assumes P1 even");
   static_assert(MUL != MUL_SYM3 || C == 3, "SYM3 multiply acts on 3 components");
   static_assert(MUL != MUL_MAX6 || C == 6, "MAX6 multiply acts on 6 components");
+  static_assert((MUL != MUL_DIV && MUL != MUL_CURLH) || C == 3, "DIV and CURLH act on 3 components");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<R>* tw = reinterpret_cast<cx<R>*>(smem_raw);
   cx<R>* lds = tw + P;
@@ -105,7 +113,7 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
     // padded to 16) per entry, NE entries per (qz, qy)
     constexpr int N = P / 2;
     constexpr int NXP = ((N + 1 + 15) / 16) * 16;
-    constexpr int NE = MUL == MUL_SYM3 ? 6 : 9;
+    constexpr int NE = mul_entries(MUL);
     constexpr int ROW = NE * NXP;
     static_assert(P2 % 2 == 0, "the z fold assumes P2 even");
     const int Nxy = a.pxy / 2;
@@ -123,28 +131,44 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
       const int kz = j + P1 * decltype(k2)::value;
       const int fz = upper ? P - kz : kz;
       const cx<R>* t = tb + fz * ((N + 1) * ROW);
-      const cx<R> kxx = t[0], kyy = t[NXP], kzz = t[2 * NXP];
-      const cx<R> kxy = sxy * t[3 * NXP];
-      const cx<R> kxz = (sx * sz) * t[4 * NXP];
-      const cx<R> kyz = (sy * sz) * t[5 * NXP];
-      if constexpr (MUL == MUL_SYM3) {
+      if constexpr (MUL == MUL_DIV || MUL == MUL_CURLH) {
+        const cx<R> dx = sx * t[0], dy = sy * t[NXP], dz = sz * t[2 * NXP];
         const cx<R> x0 = X[0][k2], x1 = X[1][k2], x2 = X[2][k2];
-        X[0][k2] = kxx * x0 + kxy * x1 + kxz * x2;
-        X[1][k2] = kxy * x0 + kyy * x1 + kyz * x2;
-        X[2][k2] = kxz * x0 + kyz * x1 + kzz * x2;
+        if constexpr (MUL == MUL_DIV) {
+          X[0][k2] = dx * x0 + dy * x1 + dz * x2;
+          X[1][k2] = czero<R>();
+          X[2][k2] = czero<R>();
+        } else {
+          const R w = R(a.omega);
+          const cx<R> w0 = dy * x2 - dz * x1, w1 = dz * x0 - dx * x2, w2 = dx * x1 - dy * x0;
+          X[0][k2] = {w * w0.im, -w * w0.re};  // -i omega w
+          X[1][k2] = {w * w1.im, -w * w1.re};
+          X[2][k2] = {w * w2.im, -w * w2.re};
+        }
       } else {
-        const cx<R> cxv = sx * t[6 * NXP], cyv = sy * t[7 * NXP], czv = sz * t[8 * NXP];
-        const cx<R> j0 = X[0][k2], j1 = X[1][k2], j2 = X[2][k2];
-        const cx<R> m0 = X[3][k2], m1 = X[4][k2], m2 = X[5][k2];
-        // c x m and c x j
-        const cx<R> cm0 = cyv * m2 - czv * m1, cm1 = czv * m0 - cxv * m2, cm2 = cxv * m1 - cyv * m0;
-        const cx<R> cj0 = cyv * j2 - czv * j1, cj1 = czv * j0 - cxv * j2, cj2 = cxv * j1 - cyv * j0;
-        X[0][k2] = kxx * j0 + kxy * j1 + kxz * j2 + cm0;
-        X[1][k2] = kxy * j0 + kyy * j1 + kyz * j2 + cm1;
-        X[2][k2] = kxz * j0 + kyz * j1 + kzz * j2 + cm2;
-        X[3][k2] = kxx * m0 + kxy * m1 + kxz * m2 - cj0;
-        X[4][k2] = kxy * m0 + kyy * m1 + kyz * m2 - cj1;
-        X[5][k2] = kxz * m0 + kyz * m1 + kzz * m2 - cj2;
+        const cx<R> kxx = t[0], kyy = t[NXP], kzz = t[2 * NXP];
+        const cx<R> kxy = sxy * t[3 * NXP];
+        const cx<R> kxz = (sx * sz) * t[4 * NXP];
+        const cx<R> kyz = (sy * sz) * t[5 * NXP];
+        if constexpr (MUL == MUL_SYM3) {
+          const cx<R> x0 = X[0][k2], x1 = X[1][k2], x2 = X[2][k2];
+          X[0][k2] = kxx * x0 + kxy * x1 + kxz * x2;
+          X[1][k2] = kxy * x0 + kyy * x1 + kyz * x2;
+          X[2][k2] = kxz * x0 + kyz * x1 + kzz * x2;
+        } else {
+          const cx<R> cxv = sx * t[6 * NXP], cyv = sy * t[7 * NXP], czv = sz * t[8 * NXP];
+          const cx<R> j0 = X[0][k2], j1 = X[1][k2], j2 = X[2][k2];
+          const cx<R> m0 = X[3][k2], m1 = X[4][k2], m2 = X[5][k2];
+          // c x m and c x j
+          const cx<R> cm0 = cyv * m2 - czv * m1, cm1 = czv * m0 - cxv * m2, cm2 = cxv * m1 - cyv * m0;
+          const cx<R> cj0 = cyv * j2 - czv * j1, cj1 = czv * j0 - cxv * j2, cj2 = cxv * j1 - cyv * j0;
+          X[0][k2] = kxx * j0 + kxy * j1 + kxz * j2 + cm0;
+          X[1][k2] = kxy * j0 + kyy * j1 + kyz * j2 + cm1;
+          X[2][k2] = kxz * j0 + kyz * j1 + kzz * j2 + cm2;
+          X[3][k2] = kxx * m0 + kxy * m1 + kxz * m2 - cj0;
+          X[4][k2] = kxy * m0 + kyy * m1 + kyz * m2 - cj1;
+          X[5][k2] = kxz * m0 + kyz * m1 + kzz * m2 - cj2;
+        }
       }
     });
   }

@@ -37,7 +37,8 @@ struct SymbolSrc {
     const int e = entry0 + int(g);
     const int ix = n, iy = int(c % M), iz = int(c / M);
     const int half = M / 2;
-    if ((ix == half && symbol_odd(e, 0)) || (iy == half && symbol_odd(e, 1)) || (iz == half && symbol_odd(e, 2)))
+    if ((ix == half && symbol_odd_in_set(set, e, 0)) || (iy == half && symbol_odd_in_set(set, e, 1)) ||
+        (iz == half && symbol_odd_in_set(set, e, 2)))
       return czero<Rt>();
     const double ds = 2.0 * kPi / (double(M) * h);
     const double sx = ds * double(ix < half ? ix : ix - M);
@@ -152,15 +153,28 @@ struct LenImpl {
   static hipError_t zpass(int mul, cx<R>* buf, const cx<R>* tab, ZArgs a, long nblocks, const cx<R>* tw,
                           hipStream_t s) {
     // the kernel takes the table geometry from P
-    if (2 * a.n != P || a.nxp != ((a.n + 1 + 15) / 16) * 16 || a.ne != (mul == MUL_SYM3 ? 6 : 9) || 2 * a.nz > P ||
+    if (2 * a.n != P || a.nxp != ((a.n + 1 + 15) / 16) * 16 || a.ne != mul_entries(mul) || 2 * a.nz > P ||
         a.pxy > P || a.ntiles != (a.pxy + a.T - 1) / a.T || nblocks != long(a.ntiles) * a.pxy * a.nb ||
         (long(a.ntiles) * a.pxy) % 8 != 0)
       return hipErrorInvalidValue;
     const size_t lds = pass_lds_bytes<R, P1, P2, false>(a.T);
-    if (mul == MUL_SYM3)
+    if (mul == MUL_SYM3) {
       k_zpass<R, P1, P2, 3, MUL_SYM3><<<dim3(unsigned(nblocks)), dim3(a.T * J), lds, s>>>(buf, tab, a, tw);
-    else
+    } else if (mul == MUL_MAX6) {
       k_zpass<R, P1, P2, 6, MUL_MAX6><<<dim3(unsigned(nblocks)), dim3(a.T * J), lds, s>>>(buf, tab, a, tw);
+    } else {
+      // potentials and the reduced Maxwell H field: FP64 only
+      if constexpr (std::is_same<R, double>::value) {
+        if (mul == MUL_DIV)
+          k_zpass<R, P1, P2, 3, MUL_DIV><<<dim3(unsigned(nblocks)), dim3(a.T * J), lds, s>>>(buf, tab, a, tw);
+        else if (mul == MUL_CURLH)
+          k_zpass<R, P1, P2, 3, MUL_CURLH><<<dim3(unsigned(nblocks)), dim3(a.T * J), lds, s>>>(buf, tab, a, tw);
+        else
+          return hipErrorInvalidValue;
+      } else {
+        return hipErrorInvalidValue;
+      }
+    }
     return hipGetLastError();
   }
   template <int C, int MODE>

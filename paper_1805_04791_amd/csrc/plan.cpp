@@ -12,6 +12,7 @@
 
 #include "lens.hpp"
 #include "pointwise.hpp"
+#include "postprocess.hpp"
 
 using namespace vie;
 
@@ -225,6 +226,12 @@ bool env_flag(const char* name, bool dflt) {
 // ---------------------------------------------------------------------------
 // the five passes of one batched apply
 // ---------------------------------------------------------------------------
+// the spectral multiply applied on a geometry
+int geom_mul(const vie_plan* pl, const Geom& g) {
+  if (g.mul >= 0) return g.mul;
+  return pl->full ? MUL_MAX6 : MUL_SYM3;
+}
+
 template <typename R>
 struct ApplyCall {
   vie_plan* pl;
@@ -273,11 +280,11 @@ hipError_t pass_z(const ApplyCall<R>& c, const cx<R>* tab, int T, hipStream_t s)
   const vie_plan* pl = c.pl;
   const long Pz = c.g.sp->Pz, Q = c.g.sp->Pxy, bz = c.g.bz;
   const long ntiles = (Q + T - 1) / T;  // the last tile may be partial
-  ZArgs a{T,      int(ntiles), int(Pz / 2),           int(Pz), c.g.sp->nxp, pl->ne, bz * Q * Q,
-          long(pl->C) * bz * Q * Q, c.nb, int(bz), int(Q)};
+  ZArgs a{T,      int(ntiles), int(Pz / 2),           int(Pz), c.g.sp->nxp, c.g.sp->ne, bz * Q * Q,
+          long(pl->C) * bz * Q * Q, c.nb, int(bz), int(Q), pl->omega};
   if (ntiles * Q % 8 != 0) return hipErrorInvalidValue;  // XCD block order: slices in groups of 8
   const long nblocks = ntiles * Q * c.nb;
-  return c.opsz->zpass(pl->full ? MUL_MAX6 : MUL_SYM3, c.B, tab, a, nblocks, c.twz, s);
+  return c.opsz->zpass(geom_mul(pl, c.g), c.B, tab, a, nblocks, c.twz, s);
 }
 
 // y inverse: B -> A, outputs y < by
@@ -367,7 +374,7 @@ int pick_tile(vie_plan* pl, int P1, int P2, bool contig, int maxthreads, int col
   return VIE_OK;
 }
 
-int tune_key(int nb, const Geom& g) { return bucket_of(nb) + (g.id << 20); }
+int tune_key(int nb, const Geom& g) { return bucket_of(nb) + (g.id << 20) + ((g.mul + 1) << 24); }
 
 template <typename R, typename TV>
 int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStream_t s, Tune* t) {
@@ -486,7 +493,8 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     const double Pz = sp.Pz, fft_row_z = 5.0 * Pz * std::log2(Pz);
     const double rows_x = vN2P / P, rows_y = vN2P / geom.by, rows_z = vNP2 / geom.bz;
     const double pts = double(nb) * P * P * Pz;
-    const double mul_f = (pl->full ? 216.0 : 66.0) * pts;
+    const int mul = geom_mul(pl, geom);
+    const double mul_f = (mul == MUL_MAX6 ? 216.0 : (mul == MUL_SYM3 ? 66.0 : 24.0)) * pts;
     const double comb_f = (mode == MODE_CONV) ? 0.0 : 72.0 * vN3 / 3.0;
     int tok = prof_begin(pl, s);
     HIPCHK(pl, (pass_xfwd<R, TV>(c, inr, t.tx_fwd, s)));
@@ -516,7 +524,7 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
 // offsets |m_a| <= b_a - 1 < P_a/2 only, and its wrapped copies lie at
 // |m_a| >= P_a - (b_a - 1) > P_a/2 - 1.
 int build_tables(vie_plan* pl, Spec& sp, hipStream_t s) {
-  const int Z = sp.Pz, Q = sp.Pxy, M = pl->M, NE = pl->ne;
+  const int Z = sp.Pz, Q = sp.Pxy, M = pl->M, NE = sp.ne;
   const LenOps<double>* opsM = len_ops<double>(M);
   const LenOps<double>* opsQ = len_ops<double>(Q);
   const LenOps<double>* opsZ = len_ops<double>(Z);
@@ -557,7 +565,7 @@ int build_tables(vie_plan* pl, Spec& sp, hipStream_t s) {
     // (a) symbol samples of entry `ent` -> inverse transform along x; keep
     //     outputs 0..Q-1 (displacements -Q/2..Q/2-1), zero displacement -Q/2
     {
-      SymbolSrc src{M, pl->sym_set, ent, Q / 2, Q / 2, Z / 2, pl->h, pl->omega, pl->R};
+      SymbolSrc src{M, sp.set, ent, Q / 2, Q / 2, Z / 2, pl->h, pl->omega, pl->R};
       const long rows = MM * MM;
       Geo g{TcM, int((rows + TcM - 1) / TcM), rows, M, Q};
       MemStore<c128> dst{buf1, 0, QQ, 1, 1.0 / double(M), 1};
@@ -723,8 +731,11 @@ void destroy_plan(vie_plan* pl) {
   delete pl;
 }
 
-// twiddles and kernel-transform tables of the grid (Pz, Pxy, Pxy)
-int make_spec(vie_plan* pl, int Pz, int Pxy, Spec& sp, hipStream_t s) {
+// twiddles and kernel-transform tables of the grid (Pz, Pxy, Pxy) for the
+// symbol set `set` (ne entries)
+int make_spec(vie_plan* pl, int Pz, int Pxy, int set, int ne, Spec& sp, hipStream_t s) {
+  sp.set = set;
+  sp.ne = ne;
   sp.Pz = Pz;
   sp.Pxy = Pxy;
   sp.nxp = ((Pz / 2 + 1 + 15) / 16) * 16;
@@ -738,7 +749,7 @@ int make_spec(vie_plan* pl, int Pz, int Pxy, Spec& sp, hipStream_t s) {
     if (!rc) rc = upload_twiddles<float>(pl, Pz, &sp.twz32, s);
   }
   if (rc) return rc;
-  sp.tab_elems = long(Pz / 2 + 1) * (Pz / 2 + 1) * pl->ne * sp.nxp;
+  sp.tab_elems = long(Pz / 2 + 1) * (Pz / 2 + 1) * ne * sp.nxp;
   rc = dev_alloc(pl, reinterpret_cast<void**>(&sp.tab64), sizeof(c128) * size_t(sp.tab_elems));
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&sp.tab32), sizeof(c64) * size_t(sp.tab_elems));
   if (rc) return rc;
@@ -749,7 +760,12 @@ int make_spec(vie_plan* pl, int Pz, int Pxy, Spec& sp, hipStream_t s) {
 
 int vie::ensure_grid_spec(vie_plan* pl, hipStream_t s) {
   if (pl->sg.tab64) return VIE_OK;
-  return make_spec(pl, pl->P, pl->P, pl->sg, s);
+  return make_spec(pl, pl->P, pl->P, pl->sym_set, pl->ne, pl->sg, s);
+}
+
+int vie::ensure_div_spec(vie_plan* pl, hipStream_t s) {
+  if (pl->sdiv.tab64) return VIE_OK;
+  return make_spec(pl, pl->P, pl->P, SYM_DIV, 3, pl->sdiv, s);
 }
 
 namespace {
@@ -811,6 +827,7 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   pl->kind = p->kind;
   pl->n = p->n;
   pl->h = p->h;
+  for (int a = 0; a < 3; ++a) pl->origin[a] = p->origin[a];
   pl->omega = p->kind == VIE_LAPLACE ? 0.0 : p->omega;
   pl->full = p->mu != nullptr;
   pl->C = pl->full ? 6 : 3;
@@ -908,10 +925,40 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   // (the whole grid's are built at its first use when they differ: a solve
   // without field output never needs them)
   const int pb = pl->use_box && env_flag("VIE_PBOX", true) ? box_length(pl) : pl->P;
-  rc = make_spec(pl, pl->P, pb, pl->sb, s);
+  rc = make_spec(pl, pl->P, pb, pl->sym_set, pl->ne, pl->sb, s);
   if (rc) return rc;
   if (pb == pl->P) pl->sg = pl->sb;
   return VIE_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// the whole grid with the divergence tables and a multiply mode
+vie::Geom div_geom(vie_plan* pl, int mul) {
+  vie::Geom g = pl->grid;
+  g.sp = &pl->sdiv;
+  g.mul = mul;
+  g.id = mul == vie::MUL_DIV ? 2 : 3;
+  return g;
+}
+
+// grow-only device scratch of the post-processing calls
+int ensure_post(vie_plan* pl, size_t bytes, hipStream_t s) {
+  if (pl->post_bytes >= bytes) return VIE_OK;
+  HIPCHK(pl, hipStreamSynchronize(s));  // earlier calls may still read it
+  vie::dev_free(pl, pl->post_buf);
+  pl->post_buf = nullptr;
+  pl->post_bytes = 0;
+  const int rc = vie::dev_alloc(pl, &pl->post_buf, bytes);
+  if (rc) return rc;
+  pl->post_bytes = bytes;
+  return VIE_OK;
+}
+
+vie::PostGrid post_grid(const vie_plan* pl) {
+  return vie::PostGrid{pl->n, pl->h, pl->origin[0], pl->origin[1], pl->origin[2]};
 }
 
 }  // namespace
@@ -978,6 +1025,105 @@ int vie_field(vie_plan* pl, const double* density, const double* inc, double* fi
   return apply_any(pl, pl->grid, true, reinterpret_cast<const c128*>(density),
                    reinterpret_cast<const c128*>(inc), nullptr, reinterpret_cast<c128*>(field), nrhs, MODE_FIELD,
                    static_cast<hipStream_t>(hip_stream));
+}
+
+int vie_potential(vie_plan* pl, const double* density, double* phi, int nrhs, void* hip_stream) {
+  if (!pl) return VIE_E_ARG;
+  if (!density || !phi || nrhs < 1) return fail(pl, VIE_E_ARG, "vie_potential: null pointer or nrhs < 1");
+  if (pl->kind == VIE_MAXWELL) return fail(pl, VIE_E_STATE, "vie_potential: Laplace and Helmholtz plans only");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  pl->last_stream = s;
+  int rc = ensure_div_spec(pl, s);
+  if (rc) return rc;
+  // (div V J, 0, 0) per right-hand side into the scratch, then its first component
+  const int chunk = std::max(1, std::min(nrhs, pl->max_rhs));
+  const long vec = 3 * pl->n3;
+  rc = ensure_post(pl, sizeof(c128) * size_t(vec) * size_t(chunk), s);
+  if (rc) return rc;
+  c128* tmp = static_cast<c128*>(pl->post_buf);
+  const c128* d = reinterpret_cast<const c128*>(density);
+  c128* out = reinterpret_cast<c128*>(phi);
+  const Geom g = div_geom(pl, MUL_DIV);
+  for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+    const int nb = std::min(chunk, nrhs - r0);
+    rc = apply_any(pl, g, true, d + long(r0) * vec, d + long(r0) * vec, nullptr, tmp, nb, MODE_CONV, s);
+    if (rc) return rc;
+    for (int r = 0; r < nb; ++r) HIPCHK(pl, launch_copy(tmp + long(r) * vec, out + long(r0 + r) * pl->n3, pl->n3, s));
+  }
+  return VIE_OK;
+}
+
+int vie_field_h(vie_plan* pl, const double* density, const double* h_inc, double* h, int nrhs, void* hip_stream) {
+  if (!pl) return VIE_E_ARG;
+  if (!density || !h || nrhs < 1) return fail(pl, VIE_E_ARG, "vie_field_h: null pointer or nrhs < 1");
+  if (pl->kind != VIE_MAXWELL || pl->full)
+    return fail(pl, VIE_E_STATE, "vie_field_h: Maxwell plans with mu = I only (vie_field returns E and H otherwise)");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  pl->last_stream = s;
+  const int rc = ensure_div_spec(pl, s);
+  if (rc) return rc;
+  const c128* d = reinterpret_cast<const c128*>(density);
+  const c128* add = h_inc ? reinterpret_cast<const c128*>(h_inc) : d;
+  return apply_any(pl, div_geom(pl, MUL_CURLH), true, d, add, nullptr, reinterpret_cast<c128*>(h), nrhs,
+                   h_inc ? MODE_FIELD : MODE_CONV, s);
+}
+
+int vie_fields_at(vie_plan* pl, const double* density, int nrhs, const double* points, int npts, double* out,
+                  void* hip_stream) {
+  if (!pl) return VIE_E_ARG;
+  if (!density || !points || !out || nrhs < 1 || npts < 1)
+    return fail(pl, VIE_E_ARG, "vie_fields_at: null pointer, nrhs < 1 or npts < 1");
+  if (npts > 65535 || nrhs > 65535) return fail(pl, VIE_E_ARG, "vie_fields_at: at most 65535 points and rhs");
+  // the sums are accurate away from the density: outside the support box grown by 2h
+  const Geom& b = pl->box;
+  const double lo[3] = {pl->origin[0] + (b.x0 - 1.5) * pl->h, pl->origin[1] + (b.y0 - 1.5) * pl->h,
+                        pl->origin[2] + (b.z0 - 1.5) * pl->h};
+  const double hi[3] = {pl->origin[0] + (b.x0 + b.bx + 1.5) * pl->h, pl->origin[1] + (b.y0 + b.by + 1.5) * pl->h,
+                        pl->origin[2] + (b.z0 + b.bz + 1.5) * pl->h};
+  for (int p = 0; p < npts; ++p) {
+    bool inside = true;
+    for (int a = 0; a < 3; ++a) inside = inside && points[3 * p + a] > lo[a] && points[3 * p + a] < hi[a];
+    if (inside || !std::isfinite(points[3 * p]) || !std::isfinite(points[3 * p + 1]) ||
+        !std::isfinite(points[3 * p + 2]))
+      return fail(pl, VIE_E_ARG, "vie_fields_at: point " + std::to_string(p) + " is within 2h of the support box");
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  pl->last_stream = s;
+  const bool mx = pl->kind == VIE_MAXWELL;
+  const long part = post_partial_doubles(pl->n3, npts, nrhs, mx ? 6 : 4);
+  int rc = ensure_post(pl, sizeof(double) * (size_t(3 * npts) + size_t(part)), s);
+  if (rc) return rc;
+  double* dpts = static_cast<double*>(pl->post_buf);
+  HIPCHK(pl, hipMemcpyAsync(dpts, points, sizeof(double) * 3 * size_t(npts), hipMemcpyHostToDevice, s));
+  HIPCHK(pl, launch_fields_at(reinterpret_cast<const c128*>(density), pl->C, mx, post_grid(pl), dpts, npts, nrhs,
+                              pl->omega, dpts + 3 * npts, reinterpret_cast<c128*>(out), s));
+  return VIE_OK;
+}
+
+int vie_far_field(vie_plan* pl, const double* density, int nrhs, const double* dirs, int ndirs, double* out,
+                  void* hip_stream) {
+  if (!pl) return VIE_E_ARG;
+  if (!density || !dirs || !out || nrhs < 1 || ndirs < 1)
+    return fail(pl, VIE_E_ARG, "vie_far_field: null pointer, nrhs < 1 or ndirs < 1");
+  if (ndirs > 65535 || nrhs > 65535) return fail(pl, VIE_E_ARG, "vie_far_field: at most 65535 directions and rhs");
+  if (!(pl->omega > 0.0)) return fail(pl, VIE_E_STATE, "vie_far_field: needs omega > 0 (Helmholtz, Maxwell)");
+  for (int d = 0; d < ndirs; ++d) {
+    const double nrm = std::sqrt(dirs[3 * d] * dirs[3 * d] + dirs[3 * d + 1] * dirs[3 * d + 1] +
+                                 dirs[3 * d + 2] * dirs[3 * d + 2]);
+    if (!(std::fabs(nrm - 1.0) < 1e-9))
+      return fail(pl, VIE_E_ARG, "vie_far_field: direction " + std::to_string(d) + " is not a unit vector");
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  pl->last_stream = s;
+  const bool mx = pl->kind == VIE_MAXWELL;
+  const long part = post_partial_doubles(pl->n3, ndirs, nrhs, pl->C);
+  int rc = ensure_post(pl, sizeof(double) * (size_t(3 * ndirs) + size_t(part)), s);
+  if (rc) return rc;
+  double* ddirs = static_cast<double*>(pl->post_buf);
+  HIPCHK(pl, hipMemcpyAsync(ddirs, dirs, sizeof(double) * 3 * size_t(ndirs), hipMemcpyHostToDevice, s));
+  HIPCHK(pl, launch_far_field(reinterpret_cast<const c128*>(density), pl->C, mx, post_grid(pl), ddirs, ndirs, nrhs,
+                              pl->omega, ddirs + 3 * ndirs, reinterpret_cast<c128*>(out), s));
+  return VIE_OK;
 }
 
 int vie_plan_info(const vie_plan* pl, double* out, int nout) {

@@ -22,6 +22,7 @@ namespace vie {
 // [qz][qy][entry][qx], qz, qy in [0, Pz/2], qx < nxp = (Pz/2 + 1) rounded up to
 // 16 (entries with qy or qx > Pxy/2 are zero); twiddles of both lengths.
 struct Spec {
+  int set = 0, ne = 0;  // symbol set (SYM_*) and its table entries
   int Pz = 0, Pxy = 0, nxp = 0;
   long tab_elems = 0;
   c128* tab64 = nullptr;
@@ -39,6 +40,7 @@ struct Geom {
   int id = 0;                // 0 whole grid, 1 solver geometry
   const int* rows = nullptr; // support rows (xa, len, off) per (z, y) row; null: dense box
   long np = 0;               // points per component of the vectors
+  int mul = -1;              // spectral multiply (MUL_*); -1: the plan's operator
 };
 inline Box box_of(const Geom& g, int n) { return Box{n, g.bx, g.by, g.bz, g.x0, g.y0, g.z0, g.rows, g.np}; }
 
@@ -72,6 +74,10 @@ struct vie_plan {
   vie::c64 *H32 = nullptr, *Hmu32 = nullptr;
   vie::Spec sg;  // P = 2n: the whole grid (vie_apply, vie_field)
   vie::Spec sb;  // the solver's box: Pz = 2n, Pxy the shortest compiled length >= 2 max(bx, by), <= 2n
+  vie::Spec sdiv;  // the divergence / curl symbol i s G^ on the 2n grid (built at first use)
+  double origin[3] = {0, 0, 0};
+  void* post_buf = nullptr;  // device scratch of the point and far-field sums
+  size_t post_bytes = 0;
 
   // apply workspaces [0] FP32, [1] FP64; capacity in right-hand sides
   void* wsA[2] = {nullptr, nullptr};
@@ -161,8 +167,9 @@ int apply_any(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128
 // calls with stable pointers); falls back to apply_any when capture is off
 int apply_graph(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
                 c128* out, int nrhs, int mode, hipStream_t s);
-// builds the whole grid's tables at their first use
+// builds the whole grid's tables, or the divergence tables, at their first use
 int ensure_grid_spec(vie_plan* pl, hipStream_t s);
+int ensure_div_spec(vie_plan* pl, hipStream_t s);
 // FP32 matvec y = A x with x, y stored as complex64
 int apply_any(vie_plan* pl, const Geom& g, const c64* in, c64* out, int nrhs, hipStream_t s);
 void clear_graphs(vie_plan* pl);

@@ -19,7 +19,9 @@
 
 namespace vie {
 
-enum { SYM_GRAD = 0, SYM_MAXWELL = 1 };  // MAXWELL: 6 D entries then 3 curl entries
+// MAXWELL: 6 D entries then 3 curl entries; DIV: the 3 entries i s_b G^ (the
+// symbol of div V, and of curl V as (i s G^) x)
+enum { SYM_GRAD = 0, SYM_MAXWELL = 1, SYM_DIV = 2 };
 
 __device__ __forceinline__ double sinc_dev(double a) { return a == 0.0 ? 1.0 : sin(a) / a; }
 __device__ __forceinline__ double vers_dev(double a) {
@@ -63,7 +65,9 @@ __device__ inline c128 ghat_dev(double s, double w, double R) {
 // entry e of the symbol set at frequency (sx, sy, sz)
 // SYM_GRAD:    e = 0..5 -> xx, yy, zz, xy, xz, yz of -s s^T G^
 // SYM_MAXWELL: e = 0..5 -> (w^2 I - s s^T) G^,  e = 6..8 -> i s_b G^
+// SYM_DIV:     e = 0..2 -> i s_b G^
 __device__ inline c128 symbol_entry(int set, int e, double sx, double sy, double sz, double w, double R) {
+  if (set == SYM_DIV) e += 6;
   const double s = sqrt(sx * sx + sy * sy + sz * sz);
   const c128 g = ghat_dev(s, w, R);
   const double sv[3] = {sx, sy, sz};
@@ -78,7 +82,12 @@ __device__ inline c128 symbol_entry(int set, int e, double sx, double sy, double
   return {-sb * g.im, sb * g.re};  // i s_b G^
 }
 
-// is entry e odd in s_axis?
+// is entry e of the set odd in s_axis?
+__host__ __device__ inline bool symbol_odd(int e, int axis);
+__host__ __device__ inline bool symbol_odd_in_set(int set, int e, int axis) {
+  return symbol_odd(set == SYM_DIV ? e + 6 : e, axis);
+}
+
 __host__ __device__ inline bool symbol_odd(int e, int axis) {
   if (e < 3) return false;
   if (e < 6) {

@@ -57,7 +57,7 @@ class SolveStats(ctypes.Structure):
 EXPORTS = ["vie_plan_create", "vie_apply", "vie_rhs", "vie_field", "vie_solve", "vie_destroy",
            "vie_plan_info", "vie_copy_tables", "vie_copy_contrast", "vie_status_string",
            "vie_last_error", "vie_supported_n", "vie_profile", "vie_profile_read", "vie_profile_family",
-           "vie_footprint_bytes"]
+           "vie_footprint_bytes", "vie_potential", "vie_field_h", "vie_fields_at", "vie_far_field"]
 
 _lib = None
 
@@ -91,11 +91,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                    ctypes.POINTER(cd), ctypes.POINTER(cd), ci]
     L.vie_profile_family.argtypes = [ci]
     L.vie_profile_family.restype = ctypes.c_char_p
+    L.vie_potential.argtypes = [vp, vp, vp, ci, vp]
+    L.vie_field_h.argtypes = [vp, vp, vp, vp, ci, vp]
+    L.vie_fields_at.argtypes = [vp, vp, ci, vp, ci, vp, vp]
+    L.vie_far_field.argtypes = [vp, vp, ci, vp, ci, vp, vp]
     L.vie_footprint_bytes.argtypes = [ci, ci, ci, ci, ci]
     L.vie_footprint_bytes.restype = ctypes.c_long
     for name in ("vie_plan_create", "vie_apply", "vie_rhs", "vie_field", "vie_solve", "vie_destroy",
                  "vie_plan_info", "vie_copy_tables", "vie_copy_contrast", "vie_supported_n",
-                 "vie_profile", "vie_profile_read"):
+                 "vie_profile", "vie_profile_read", "vie_potential", "vie_field_h", "vie_fields_at",
+                 "vie_far_field"):
         getattr(L, name).restype = ci
     _lib = L
     return L
@@ -217,6 +222,47 @@ class Plan:
         self._check(self.lib.vie_field(self._h, d.data_ptr(), inc.data_ptr(), f.data_ptr(), d.shape[0],
                                        _stream_ptr(stream)), "vie_field")
         return f
+
+    def potential(self, density, stream=None):
+        """phi_scat = div V J on the grid (Laplace, Helmholtz): complex128 [nrhs][n][n][n]."""
+        torch = _torch()
+        d = self._vec(density, "density")
+        phi = torch.empty((d.shape[0], self.n, self.n, self.n), dtype=torch.complex128, device=self.device)
+        self._check(self.lib.vie_potential(self._h, d.data_ptr(), phi.data_ptr(), d.shape[0], _stream_ptr(stream)),
+                    "vie_potential")
+        return phi
+
+    def field_h(self, density, h_inc=None, stream=None):
+        """Maxwell with mu = I: H_inc - i omega curl V J on the grid (H_scat if h_inc is None)."""
+        torch = _torch()
+        d = self._vec(density, "density")
+        hi = self._vec(h_inc, "h_inc") if h_inc is not None else None
+        out = torch.empty_like(d)
+        self._check(self.lib.vie_field_h(self._h, d.data_ptr(), hi.data_ptr() if hi is not None else None,
+                                         out.data_ptr(), d.shape[0], _stream_ptr(stream)), "vie_field_h")
+        return out
+
+    def fields_at(self, density, points, stream=None):
+        """Scattered fields at points away from the support: [nrhs][npts][4] (phi, grad phi) or [nrhs][npts][6] (E, H)."""
+        torch = _torch()
+        d = self._vec(density, "density")
+        pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 3))
+        k = 6 if self.kind == MAXWELL else 4
+        out = torch.empty((d.shape[0], pts.shape[0], k), dtype=torch.complex128, device=self.device)
+        self._check(self.lib.vie_fields_at(self._h, d.data_ptr(), d.shape[0], pts.ctypes.data, pts.shape[0],
+                                           out.data_ptr(), _stream_ptr(stream)), "vie_fields_at")
+        return out
+
+    def far_field(self, density, dirs, stream=None):
+        """Far-field patterns in unit directions: [nrhs][ndirs][1] (Helmholtz) or [nrhs][ndirs][6] (Maxwell)."""
+        torch = _torch()
+        d = self._vec(density, "density")
+        dd = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+        k = 6 if self.kind == MAXWELL else 1
+        out = torch.empty((d.shape[0], dd.shape[0], k), dtype=torch.complex128, device=self.device)
+        self._check(self.lib.vie_far_field(self._h, d.data_ptr(), d.shape[0], dd.ctypes.data, dd.shape[0],
+                                           out.data_ptr(), _stream_ptr(stream)), "vie_far_field")
+        return out
 
     def solve(self, inc, tol: float = 1e-10, max_iters: int = 2000, restart: int = 40,
               inner_tol: float = 0.0, solver: int = SOLVER_GMRES, fp64: bool = False, x0=None,
