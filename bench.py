@@ -77,6 +77,7 @@ def main(argv=None):
     ap.add_argument("--latency-solves", type=int, default=8, help="single-RHS mixed solves for p50/p99")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-post", action="store_true", help="skip timing the post-processing calls")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain fp32 copy kernel (x * 1.0) over this many MiB, three times, "
                          "as the reference for hardware byte counters")
@@ -193,6 +194,25 @@ def main(argv=None):
                      "TFLOP/s": v[3] / (v[0] * 1e-3) / 1e12 if v[0] > 0 else None}
                  for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
 
+    # post-processing of the batch's densities: potential on the grid, fields at
+    # 64 points outside the support, far-field patterns in 256 directions
+    post = {}
+    if not args.no_post:
+        rng = np.random.default_rng(7)
+        pts = rng.standard_normal((64, 3))
+        pts = 2.5 * pts / np.linalg.norm(pts, axis=1, keepdims=True)
+        dirs = rng.standard_normal((256, 3))
+        dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+        for name, fn in (("potential", lambda: plan.potential(d_mixed)),
+                         ("fields_at_64_points", lambda: plan.fields_at(d_mixed, pts)),
+                         ("far_field_256_dirs", lambda: plan.far_field(d_mixed, dirs))):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            post[name] = 1e3 * (time.perf_counter() - t0)
+
     # achievable HBM bandwidth on this device: a plain 2 GiB device-to-device copy
     src = torch.empty(2 ** 29, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
@@ -233,6 +253,7 @@ def main(argv=None):
         "max_rel_residual": float(max(s["rel_residual"] for s in stats_all)),
         **fp64,
         "roofline": roof,
+        "postprocess_ms_per_batch": post,
         "kernels": breakdown,
         "cpu_baseline": cpu,
     }

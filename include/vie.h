@@ -246,7 +246,8 @@ int vie_field_h(vie_plan *pl, const double *density, const double *h_inc, double
  * (grid coordinates, origin as in vie_problem); out: device complex128
  * [nrhs][npts][4 or 6].  Every point must lie outside the support box grown
  * by 2h (VIE_E_ARG otherwise), where the sums are spectrally accurate for
- * smooth densities.  FP64. */
+ * smooth densities.  Only the density inside the support box is read (a
+ * solution of vie_solve is zero outside it).  FP64. */
 int vie_fields_at(vie_plan *pl, const double *density, int nrhs, const double *points, int npts, double *out,
                   void *hip_stream);
 
@@ -256,7 +257,8 @@ int vie_fields_at(vie_plan *pl, const double *density, int nrhs, const double *p
  *   Maxwell: E_inf = (omega^2 / 4 pi)[(I - d d^T) J^ - d x M^],
  *            H_inf = (omega^2 / 4 pi)[(I - d d^T) M^ + d x J^]  (6 values).
  * out: device complex128 [nrhs][ndirs][1 or 6].  VIE_E_STATE for Laplace;
- * VIE_E_ARG for a direction that is not a unit vector.  FP64. */
+ * VIE_E_ARG for a direction that is not a unit vector.  Only the density
+ * inside the support box is read.  FP64. */
 int vie_far_field(vie_plan *pl, const double *density, int nrhs, const double *dirs, int ndirs, double *out,
                   void *hip_stream);
 

@@ -958,7 +958,8 @@ int ensure_post(vie_plan* pl, size_t bytes, hipStream_t s) {
 }
 
 vie::PostGrid post_grid(const vie_plan* pl) {
-  return vie::PostGrid{pl->n, pl->h, pl->origin[0], pl->origin[1], pl->origin[2]};
+  const vie::Geom& b = pl->box;
+  return vie::PostGrid{pl->n, pl->h, pl->origin[0], pl->origin[1], pl->origin[2], b.x0, b.y0, b.z0, b.bx, b.by, b.bz};
 }
 
 }  // namespace
@@ -1090,7 +1091,7 @@ int vie_fields_at(vie_plan* pl, const double* density, int nrhs, const double* p
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   pl->last_stream = s;
   const bool mx = pl->kind == VIE_MAXWELL;
-  const long part = post_partial_doubles(pl->n3, npts, nrhs, mx ? 6 : 4);
+  const long part = points_partial_doubles(post_grid(pl), mx, npts, nrhs);
   int rc = ensure_post(pl, sizeof(double) * (size_t(3 * npts) + size_t(part)), s);
   if (rc) return rc;
   double* dpts = static_cast<double*>(pl->post_buf);
@@ -1116,7 +1117,7 @@ int vie_far_field(vie_plan* pl, const double* density, int nrhs, const double* d
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   pl->last_stream = s;
   const bool mx = pl->kind == VIE_MAXWELL;
-  const long part = post_partial_doubles(pl->n3, ndirs, nrhs, pl->C);
+  const long part = far_partial_doubles(post_grid(pl), pl->C, ndirs, nrhs);
   int rc = ensure_post(pl, sizeof(double) * (size_t(3 * ndirs) + size_t(part)), s);
   if (rc) return rc;
   double* ddirs = static_cast<double*>(pl->post_buf);

@@ -118,3 +118,44 @@ def test_postprocess_argument_errors(vie):
         plan.potential(x)                             # Maxwell
     assert e.value.code == vie.E_STATE
     plan.close()
+
+
+def offcentre(coef, n):
+    """The medium restricted to an off-centre box (x > 0.1, y < 0.3)."""
+    X, Y, Z = gen.grid_coords(n)
+    mask = ((X > 0.1) & (Y < 0.3)).astype(np.float64)
+    eye = np.eye(3, dtype=np.complex128).reshape(9, 1, 1, 1)
+    return eye + mask[None] * (coef - eye)
+
+
+@pytest.mark.parametrize("kind,full,n", [(op.KIND_LAPLACE, False, 24), (op.KIND_HELMHOLTZ, False, 48),
+                                         (op.KIND_MAXWELL, False, 32), (op.KIND_MAXWELL, True, 24)])
+def test_batched_sums_over_an_off_centre_support_box(vie, kind, full, n):
+    """Five right-hand sides (not a multiple of the kernels' groups of
+    right-hand sides or directions), densities that vanish outside the
+    plan's support box, 37 points and 21 directions, against the oracle's sums."""
+    coef, mu, omega = medium(kind, n, 36, full)
+    coef = offcentre(coef, n)
+    if mu is not None:
+        mu = offcentre(mu, n)
+    plan = vie.Plan(kind, coef, omega=omega, mu=mu, precision=vie.PREC_MIXED, max_rhs=5)
+    x0, y0, z0, bx, by, bz = plan.info()["box"]
+    assert (bx, by) != (n, n)
+    C = 6 if full else 3
+    x = density(n, C, 40 + n)
+    x = np.concatenate([x, density(n, C, 41 + n), density(n, C, 42 + n)[:1]])
+    inside = np.zeros((n, n, n))
+    inside[z0:z0 + bz, y0:y0 + by, x0:x0 + bx] = 1.0
+    x = x * inside
+    rng = gen.rng_for(gen.CONFIG_IDS["test"], 1500 + n)
+    pts = rng.standard_normal((37, 3))
+    pts = 2.6 * pts / np.linalg.norm(pts, axis=1, keepdims=True)
+    dirs = rng.standard_normal((21, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    got = plan.fields_at(x, pts).cpu().numpy()
+    far = plan.far_field(x, dirs).cpu().numpy() if kind != op.KIND_LAPLACE else None
+    for r in range(5):
+        assert rel(got[r], pp.fields_at(kind, x[r], omega, pts)) < 1e-12, r
+        if far is not None:
+            assert rel(far[r], pp.far_field(kind, x[r], omega, dirs)) < 1e-12, r
+    plan.close()

@@ -222,16 +222,18 @@ def constant_field(n: int, E0) -> np.ndarray:
     return out
 
 
-def plane_wave_gradient(n: int, omega: float, d: np.ndarray) -> np.ndarray:
+def plane_wave_gradient(n: int, omega: float, d: np.ndarray, origin: float = -1.0,
+                        h: Optional[float] = None) -> np.ndarray:
     """grad of phi_inc = exp(i omega d.x): i omega d exp(i omega d.x), as [3][n][n][n]."""
-    X, Y, Z = grid_coords(n)
+    X, Y, Z = grid_coords(n, origin, h)
     ph = np.exp(1j * omega * (d[0] * X + d[1] * Y + d[2] * Z))
     return np.ascontiguousarray(np.stack([1j * omega * d[a] * ph for a in range(3)]))
 
 
-def plane_wave_em(n: int, omega: float, d: np.ndarray, p: np.ndarray) -> np.ndarray:
+def plane_wave_em(n: int, omega: float, d: np.ndarray, p: np.ndarray, origin: float = -1.0,
+                  h: Optional[float] = None) -> np.ndarray:
     """[E_inc; H_inc] = [p; d x p] exp(i omega d.x) as [6][n][n][n] (free-space, eps = mu = 1)."""
-    X, Y, Z = grid_coords(n)
+    X, Y, Z = grid_coords(n, origin, h)
     ph = np.exp(1j * omega * (d[0] * X + d[1] * Y + d[2] * Z))
     q = np.cross(d, p)
     return np.ascontiguousarray(np.stack([p[a] * ph for a in range(3)] + [q[a] * ph for a in range(3)]))
