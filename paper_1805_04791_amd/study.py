@@ -119,13 +119,13 @@ def run_case(equation: str, medium: str, n: int, size: float, solver: str = "bic
     kind, coef, omega, h, inc = problem(equation, medium, n, size)
     pts = check_points() if points is None else points
     t0 = time.perf_counter()
-    fp64 = solver != "gmres-mixed"
+    fp64 = not solver.endswith("-mixed")
     plan = vie.Plan(kind, coef, omega=omega, h=h, precision=vie.PREC_FP64 if fp64 else vie.PREC_MIXED,
                     max_rhs=1, graphs=True)
     try:
         torch.cuda.synchronize()
         t_plan = time.perf_counter() - t0
-        code = vie.SOLVER_BICGSTAB if solver == "bicgstab" else vie.SOLVER_GMRES
+        code = vie.SOLVER_BICGSTAB if solver.startswith("bicgstab") else vie.SOLVER_GMRES
         inc_d = torch.from_numpy(inc).to("cuda")
         dens, _, st, rc = plan.solve(inc_d, tol=tol, max_iters=max_iters, restart=restart, solver=code,
                                      fp64=fp64, want_field=False)
@@ -135,7 +135,8 @@ def run_case(equation: str, medium: str, n: int, size: float, solver: str = "bic
         plan.close()
     s = st[0]
     return {"equation": equation, "medium": medium, "n": n, "size": size, "omega": omega, "solver": solver,
-            "tol": tol, "converged": s["status"] == 0, "iters": s["iters"],
+            "restart": restart if solver.startswith("gmres") else None, "tol": tol,
+            "converged": s["status"] == 0, "iters": s["iters"],
             "matvecs": s["matvecs_fp64"] + s["matvecs_fp32"], "matvecs_fp64": s["matvecs_fp64"],
             "matvecs_fp32": s["matvecs_fp32"], "rel_residual": s["rel_residual"], "solve_s": s["seconds"],
             "plan_s": t_plan, "unknowns": 3 * n ** 3, "support_unknowns": 3 * info["unknown_points"],
@@ -179,7 +180,8 @@ def markdown(rows: Iterable[Dict]) -> str:
         k = (r["equation"], r["medium"], r["solver"])
         if k != key:
             key = k
-            out.append(f"\n**{r['equation']}, {r['medium']}, {r['solver']}, tol {r['tol']:g}**\n")
+            rs = f" ({r['restart']})" if r.get("restart") else ""
+            out.append(f"\n**{r['equation']}, {r['medium']}, {r['solver']}{rs}, tol {r['tol']:g}**\n")
             out.append("| size | n | N_tot | unknowns on the support | E2 | Einf | N_matvec | iters | solve (s) | plan (s) |")
             out.append("|---|---|---|---|---|---|---|---|---|---|")
         out.append(f"| {r['size']:g} | {r['n']} | {r['unknowns']:.3g} | {r['support_unknowns']:.3g} | "
@@ -196,7 +198,9 @@ def main(argv=None):
     ap.add_argument("--grids", nargs="+", type=int, default=[64, 96, 128])
     ap.add_argument("--sizes", nargs="+", type=float, default=None,
                     help="omega / 2 pi values (default: the paper's for each medium)")
-    ap.add_argument("--solver", choices=("bicgstab", "gmres", "gmres-mixed"), default="bicgstab")
+    ap.add_argument("--solver", choices=("bicgstab", "bicgstab-mixed", "gmres", "gmres-mixed"), default="bicgstab",
+                    help="Krylov method; -mixed: FP32 applies inside, FP64 residual refinement")
+    ap.add_argument("--restart", type=int, default=40, help="GMRES restart length")
     ap.add_argument("--tol", type=float, default=1e-14)
     ap.add_argument("--max-iters", type=int, default=20000)
     ap.add_argument("--json", default=None, help="write the rows (without the point fields) here")
@@ -206,7 +210,8 @@ def main(argv=None):
     for medium in args.media:
         for size in (args.sizes if args.sizes else sizes_for(medium)):
             for n in args.grids:
-                r = run_case(args.equation, medium, n, size, args.solver, args.tol, args.max_iters)
+                r = run_case(args.equation, medium, n, size, args.solver, args.tol, args.max_iters,
+                             restart=args.restart)
                 rows.append(r)
                 print(f"{args.equation} {medium} size {size:g} n {n}: matvecs {r['matvecs']} "
                       f"res {r['rel_residual']:.2e} {r['solve_s']:.2f} s", flush=True)
