@@ -47,6 +47,7 @@ struct ZArgs {
   int nz;           // z extent of the data (n, or the support box): inputs z < nz, outputs z < nz
   int pxy;          // x and y transform length (<= P): columns (ky, kx) in [0, pxy)^2
   double omega;     // MUL_CURLH: the factor -i omega
+  const int* act = nullptr;  // optional: right-hand side r is skipped when act[r] == 0
 };
 
 // Block order: blocks are dealt round-robin to the 8 XCDs (block b runs on
@@ -64,13 +65,14 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
   static_assert(MUL != MUL_MAX6 || C == 6, "MAX6 multiply acts on 6 components");
   static_assert((MUL != MUL_DIV && MUL != MUL_CURLH) || C == 3, "DIV and CURLH act on 3 components");
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const unsigned xcd = blockIdx.x % 8u;
+  const unsigned k = blockIdx.x / 8u;
+  if (a.act && !a.act[k % unsigned(a.nb)]) return;  // an inactive right-hand side: the whole block
   cx<R>* tw = reinterpret_cast<cx<R>*>(smem_raw);
   cx<R>* lds = tw + P;
   load_twiddles<R, P>(tw, twg);
   int col, j;
   Layout<false>::lane(threadIdx.x, a.T, J, col, j);
-  const unsigned xcd = blockIdx.x % 8u;
-  const unsigned k = blockIdx.x / 8u;
   const long slice = long(k / unsigned(a.nb)) * 8 + xcd;
   const long rhs = long(k % unsigned(a.nb));
   const int tile = int(slice % a.ntiles);
@@ -192,6 +194,7 @@ struct XArgs {
   int x0, y0, z0;   // its corner in the grid
   long np;          // points per component of the vectors
   const int* rows;  // support rows (xa, len, off) per (z, y) row, or null: dense box
+  const int* act = nullptr;  // optional: rows of right-hand side r are skipped when act[r] == 0
 };
 
 // Rows (rhs, z, y) of the data box: inverse x transform of every component,
@@ -210,11 +213,6 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
   static_assert(P1 % 2 == 0, "the cropped inverse assumes bx <= P/2 with P1 even");
   constexpr int NV = P1 / 2;  // outputs per thread per component: x = j + P2 m2 < bx <= P/2
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<R>* tw = reinterpret_cast<cx<R>*>(smem_raw);
-  cx<R>* lds = tw + P;
-  load_twiddles<R, P>(tw, twg);
-  int col, j;
-  Layout<true>::lane(threadIdx.x, a.T, J, col, j);
   const int N = a.n;
   const long NN = long(a.bz) * a.by;  // rows per right-hand side
   // xcd_order: block b runs on XCD b % 8; the nb right-hand sides of one
@@ -226,8 +224,19 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
     const long r = long(k % unsigned(a.nb));
     tile_id = r * (NN / a.T) + slice;
   }
+  if (a.act) {
+    // the whole block belongs to one inactive right-hand side
+    const long first = tile_id * a.T;
+    const long last = (first + a.T < a.nrows ? first + a.T : a.nrows) - 1;
+    if (first / NN == last / NN && !a.act[first / NN]) return;
+  }
+  cx<R>* tw = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* lds = tw + P;
+  load_twiddles<R, P>(tw, twg);
+  int col, j;
+  Layout<true>::lane(threadIdx.x, a.T, J, col, j);
   const long row = tile_id * a.T + col;
-  const bool valid = row < a.nrows;
+  const bool valid = row < a.nrows && (!a.act || a.act[row / NN]);
   const long rhs = valid ? row / NN : 0;
   const long zy = valid ? row % NN : 0;
   const long hrow = (long(a.z0) + zy / a.by) * N + (a.y0 + zy % a.by);  // (z, y) in the grid

@@ -62,6 +62,10 @@ struct Geo {
   long ncols;     // columns per group
   int nin;        // valid inputs along the transform axis
   int nout;       // outputs written along the transform axis
+  // optional: pencil (g, c) belongs to right-hand side (g * ncols + c) /
+  // per_rhs, and is skipped (nothing loaded or stored) when act[rhs] == 0
+  const int* act = nullptr;
+  long per_rhs = 1;
 };
 
 // Sources of a pass: column(g, c) binds pencil (g, c) once per thread; the
@@ -260,15 +264,21 @@ __global__ void __launch_bounds__(kPassMaxThreads) k_pass(Src src, Dst dst, Geo 
   constexpr int P = P1 * P2;
   constexpr int J = P1 > P2 ? P1 : P2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const long tile = long(blockIdx.x) % geo.ntiles;
+  const long g = long(blockIdx.x) / geo.ntiles;
+  if (geo.act) {
+    // the whole block belongs to one inactive right-hand side
+    const long first = g * geo.ncols + tile * geo.T;
+    const long last = g * geo.ncols + (tile * geo.T + geo.T < geo.ncols ? tile * geo.T + geo.T : geo.ncols) - 1;
+    if (first / geo.per_rhs == last / geo.per_rhs && !geo.act[first / geo.per_rhs]) return;
+  }
   cx<R>* tw = reinterpret_cast<cx<R>*>(smem_raw);
   cx<R>* lds = tw + P;
   load_twiddles<R, P>(tw, twg);
   int col, j;
   Layout<CONTIG>::lane(threadIdx.x, geo.T, J, col, j);
-  const long tile = long(blockIdx.x) % geo.ntiles;
-  const long g = long(blockIdx.x) / geo.ntiles;
   const long c = tile * geo.T + col;
-  const bool valid = c < geo.ncols;
+  const bool valid = c < geo.ncols && (!geo.act || geo.act[(g * geo.ncols + c) / geo.per_rhs]);
   cx<R> u[P1];
   const auto col_src = src.column(g, valid ? c : 0);
   if constexpr (!INV) fft_load<R, P1, P2>([&](int n) { return col_src.template load<R>(n); }, geo.nin, j, valid, u);

@@ -243,6 +243,7 @@ struct ApplyCall {
   cx<R>* B;
   int nb;
   Geom g;
+  const int* act = nullptr;  // optional device flags per right-hand side: 0 = skip it
 };
 
 // x forward: rows (rhs, c, z, y) of the box, bx samples -> P; TV is the
@@ -253,7 +254,7 @@ hipError_t pass_xfwd(const ApplyCall<R>& c, const TV* in, int T, hipStream_t s) 
   const long nr = long(c.g.bz) * c.g.by;
   const long rows = long(c.nb) * pl->C * nr;
   const int P = c.g.sp->Pxy;
-  Geo g{T, int((rows + T - 1) / T), rows, c.g.bx, P};
+  Geo g{T, int((rows + T - 1) / T), rows, c.g.bx, P, c.act, long(pl->C) * nr};
   MemStore<cx<R>> dst{c.A, 0, P, 1, 1.0, 0};
   if constexpr (std::is_same<TV, c128>::value) {
     if (c.g.rows) return c.ops->contig_fwd_rows(RowLoad<c128>{in, c.g.rows, nr, c.g.np}, dst, g, 1, c.tw, s);
@@ -269,7 +270,7 @@ template <typename R>
 hipError_t pass_yfwd(const ApplyCall<R>& c, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
   const long P = c.g.sp->Pxy, by = c.g.by;
-  Geo g{T, int(P / T), P, int(by), int(P)};
+  Geo g{T, int(P / T), P, int(by), int(P), c.act, long(pl->C) * c.g.bz * P};
   MemLoad<cx<R>> src{c.A, by * P, 1, P};
   MemStore<cx<R>> dst{c.B, P * P, 1, P, 1.0, 0};
   return c.ops->strided(false, src, dst, g, long(c.nb) * pl->C * c.g.bz, c.tw, s);
@@ -281,7 +282,7 @@ hipError_t pass_z(const ApplyCall<R>& c, const cx<R>* tab, int T, hipStream_t s)
   const long Pz = c.g.sp->Pz, Q = c.g.sp->Pxy, bz = c.g.bz;
   const long ntiles = (Q + T - 1) / T;  // the last tile may be partial
   ZArgs a{T,      int(ntiles), int(Pz / 2),           int(Pz), c.g.sp->nxp, c.g.sp->ne, bz * Q * Q,
-          long(pl->C) * bz * Q * Q, c.nb, int(bz), int(Q), pl->omega};
+          long(pl->C) * bz * Q * Q, c.nb, int(bz), int(Q), pl->omega, c.act};
   if (ntiles * Q % 8 != 0) return hipErrorInvalidValue;  // XCD block order: slices in groups of 8
   const long nblocks = ntiles * Q * c.nb;
   return c.opsz->zpass(geom_mul(pl, c.g), c.B, tab, a, nblocks, c.twz, s);
@@ -292,7 +293,7 @@ template <typename R>
 hipError_t pass_yinv(const ApplyCall<R>& c, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
   const long P = c.g.sp->Pxy, by = c.g.by;
-  Geo g{T, int(P / T), P, int(P), int(by)};
+  Geo g{T, int(P / T), P, int(P), int(by), c.act, long(pl->C) * c.g.bz * P};
   MemLoad<cx<R>> src{c.B, P * P, 1, P};
   MemStore<cx<R>> dst{c.A, by * P, 1, P, 1.0, 0};
   return c.ops->strided(true, src, dst, g, long(c.nb) * pl->C * c.g.bz, c.tw, s);
@@ -305,7 +306,7 @@ hipError_t pass_xinv(const ApplyCall<R>& c, const TV* addv, const c128* bvec, TV
   const long NN = long(c.g.bz) * c.g.by;
   const int xcd = (NN % T == 0) && ((NN / T) % 8 == 0) ? 1 : 0;
   XArgs a{T,      long(c.nb) * NN, pl->n,  pl->n3, c.nb,   xcd,  c.g.bx,
-          c.g.by, c.g.bz,          c.g.x0, c.g.y0, c.g.z0, c.g.np, c.g.rows};
+          c.g.by, c.g.bz,          c.g.x0, c.g.y0, c.g.z0, c.g.np, c.g.rows, c.act};
   const cx<R>* H;
   const cx<R>* Hmu;
   if constexpr (std::is_same<R, float>::value) {
@@ -441,9 +442,11 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStre
   return VIE_OK;
 }
 
+// act (device, optional): per right-hand side, 0 = skip it (its output is
+// left as it was); nact = the number of non-zero flags, for the byte counts
 template <typename R, typename TV>
 int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, const c128* bvec, TV* out,
-                int nrhs, int mode, hipStream_t s) {
+                int nrhs, int mode, hipStream_t s, const int* act = nullptr, int nact = -1) {
   const Spec& sp = *geom.sp;
   const LenOps<R>* ops = len_ops<R>(sp.Pxy);
   const LenOps<R>* opsz = len_ops<R>(sp.Pz);
@@ -478,11 +481,13 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     Tune t;
     rc = get_tune<R, TV>(pl, c, inr, outr, s, &t);
     if (rc) return rc;
+    c.act = act ? act + r0 : nullptr;
+    const int nrun = (act && nact >= 0 && nrhs <= chunk) ? nact : nb;  // right-hand sides computed
     const int f0 = std::is_same<R, double>::value ? FAM_XFWD64 : FAM_XFWD32;
     // algorithmic bytes: every operand read or written once per launch
     const double cr = double(sizeof(cx<R>)), c16 = double(sizeof(TV));
-    const double vN3 = double(nb) * pl->C * double(geom.np);
-    const double vN2P = double(nb) * pl->C * geom.bz * geom.by * sp.Pxy, vNP2 = vN2P / geom.by * sp.Pxy;
+    const double vN3 = double(nrun) * pl->C * double(geom.np);
+    const double vN2P = double(nrun) * pl->C * geom.bz * geom.by * sp.Pxy, vNP2 = vN2P / geom.by * sp.Pxy;
     const double hb = 9.0 * double(geom.np) * cr * (pl->full ? 2 : 1);
     const double xinv_b = vN2P * cr + hb * (mode == MODE_MATVEC || mode == MODE_RESIDUAL) +
                           vN3 * c16 * (1 + (mode != MODE_CONV)) + vN3 * sizeof(c128) * (mode == MODE_RESIDUAL);
@@ -492,7 +497,7 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     const double P = sp.Pxy, fft_row = 5.0 * P * std::log2(P);
     const double Pz = sp.Pz, fft_row_z = 5.0 * Pz * std::log2(Pz);
     const double rows_x = vN2P / P, rows_y = vN2P / geom.by, rows_z = vNP2 / geom.bz;
-    const double pts = double(nb) * P * P * Pz;
+    const double pts = double(nrun) * P * P * Pz;
     const int mul = geom_mul(pl, geom);
     const double mul_f = (mul == MUL_MAX6 ? 216.0 : (mul == MUL_SYM3 ? 66.0 : 24.0)) * pts;
     const double comb_f = (mode == MODE_CONV) ? 0.0 : 72.0 * vN3 / 3.0;
@@ -620,13 +625,13 @@ int build_tables(vie_plan* pl, Spec& sp, hipStream_t s) {
 namespace vie {
 
 int apply_any(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
-              c128* out, int nrhs, int mode, hipStream_t s) {
+              c128* out, int nrhs, int mode, hipStream_t s, const int* act, int nact) {
   if (g.sp == &pl->sg) {
     const int rc = ensure_grid_spec(pl, s);
     if (rc) return rc;
   }
-  return fp64 ? apply_typed<double, c128>(pl, g, in, addv, bvec, out, nrhs, mode, s)
-              : apply_typed<float, c128>(pl, g, in, addv, bvec, out, nrhs, mode, s);
+  return fp64 ? apply_typed<double, c128>(pl, g, in, addv, bvec, out, nrhs, mode, s, act, nact)
+              : apply_typed<float, c128>(pl, g, in, addv, bvec, out, nrhs, mode, s, act, nact);
 }
 
 int apply_any(vie_plan* pl, const Geom& g, const c64* in, c64* out, int nrhs, hipStream_t s) {
@@ -691,10 +696,10 @@ int graph_or_eager(vie_plan* pl, const Geom& g, bool fp64, int nrhs, const vie_p
 }  // namespace
 
 int apply_graph(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
-                c128* out, int nrhs, int mode, hipStream_t s) {
-  const vie_plan::GraphKey key{fp64 ? 1 : 0, mode, nrhs, g.id, in, addv, bvec, out};
+                c128* out, int nrhs, int mode, hipStream_t s, const int* act, int nact) {
+  const vie_plan::GraphKey key{fp64 ? 1 : 0, mode, nrhs, g.id, in, addv, bvec, out, act};
   return graph_or_eager(pl, g, fp64, nrhs, key, s, [&](hipStream_t st) {
-    return apply_any(pl, g, fp64, in, addv, bvec, out, nrhs, mode, st);
+    return apply_any(pl, g, fp64, in, addv, bvec, out, nrhs, mode, st, act, nact);
   });
 }
 
@@ -728,6 +733,7 @@ void destroy_plan(vie_plan* pl) {
   if (pl->red_host) (void)hipHostFree(pl->red_host);
   if (pl->coef_host) (void)hipHostFree(pl->coef_host);
   if (pl->scale_host) (void)hipHostFree(pl->scale_host);
+  if (pl->count_host) (void)hipHostFree(pl->count_host);
   delete pl;
 }
 

@@ -96,6 +96,10 @@ struct vie_plan {
   vie::c128* red_host = nullptr;  // pinned
   vie::c128* coef_host = nullptr; // pinned
   double* scale_host = nullptr;   // pinned
+  int* count_host = nullptr;      // pinned: coefficients used per right-hand side, 2 slots of [cap]
+  int* countd = nullptr;          // [2][cap]
+  int* actd = nullptr;            // [cap] flags of the right-hand sides still iterating (0 = skip)
+  std::vector<int> act_last;      // the flags last written to actd
 
   size_t dev_bytes = 0;
   std::vector<std::pair<void*, size_t>> allocs;
@@ -104,10 +108,10 @@ struct vie_plan {
   // captured applies: key (fp64, mode, nb, in, addv, bvec, out) -> graph
   struct GraphKey {
     int fp64, mode, nb, geom;
-    const void *in, *addv, *bvec, *out;
+    const void *in, *addv, *bvec, *out, *act;
     bool operator<(const GraphKey& o) const {
-      return std::tie(fp64, mode, nb, geom, in, addv, bvec, out) <
-             std::tie(o.fp64, o.mode, o.nb, o.geom, o.in, o.addv, o.bvec, o.out);
+      return std::tie(fp64, mode, nb, geom, in, addv, bvec, out, act) <
+             std::tie(o.fp64, o.mode, o.nb, o.geom, o.in, o.addv, o.bvec, o.out, o.act);
     }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -160,13 +164,15 @@ int hip_fail(vie_plan* pl, hipError_t e, const char* what);
 // being captured.
 std::recursive_mutex& hip_mutex();
 
-// Vectors are laid out on geometry g ([rhs][C][bz][by][bx]).
+// Vectors are laid out on geometry g ([rhs][C][bz][by][bx]).  act (device,
+// optional): a flag per right-hand side of the call, 0 = skip it (nothing of
+// it is read or written); nact = the count of non-zero flags (byte counts).
 int apply_any(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
-              c128* out, int nrhs, int mode, hipStream_t s);
+              c128* out, int nrhs, int mode, hipStream_t s, const int* act = nullptr, int nact = -1);
 // the same through a captured hipGraph replayed on the plan's stream (solver
 // calls with stable pointers); falls back to apply_any when capture is off
 int apply_graph(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
-                c128* out, int nrhs, int mode, hipStream_t s);
+                c128* out, int nrhs, int mode, hipStream_t s, const int* act = nullptr, int nact = -1);
 // builds the whole grid's tables, or the divergence tables, at their first use
 int ensure_grid_spec(vie_plan* pl, hipStream_t s);
 int ensure_div_spec(vie_plan* pl, hipStream_t s);

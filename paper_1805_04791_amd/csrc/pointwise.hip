@@ -260,9 +260,10 @@ constexpr int kGroup = 8;  // basis vectors per accumulation sweep
 template <typename TV, typename TW>
 __global__ void __launch_bounds__(kBlock) k_dots(const TV* __restrict__ V, long vstride, long rstride,
                                                  const TW* __restrict__ w, long L, int nv, long chunk,
-                                                 c128* __restrict__ partials) {
+                                                 c128* __restrict__ partials, const int* __restrict__ act) {
   __shared__ double red[kBlock / 64][2 * kGroup];
   const int rhs = blockIdx.y;
+  if (act && !act[rhs]) return;
   const int blk = blockIdx.x;
   const int nblk = gridDim.x;
   const long lo = long(blk) * chunk;
@@ -313,9 +314,10 @@ __global__ void __launch_bounds__(kBlock) k_dots(const TV* __restrict__ V, long 
 }
 
 __global__ void __launch_bounds__(kBlock) k_reduce(const c128* __restrict__ partials, int nblk, int nv1,
-                                                   c128* __restrict__ out) {
+                                                   c128* __restrict__ out, const int* __restrict__ act) {
   __shared__ double red[kBlock / 64][2];
   const int rhs = blockIdx.x;
+  if (act && !act[rhs]) return;
   for (int i = 0; i < nv1; ++i) {
     double sr = 0.0, si = 0.0;
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
@@ -343,11 +345,16 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const c128* __restrict__ part
 }
 
 // TV, TW, TO: storage of the basis, of w and of out; arithmetic in FP64.
+// count (optional): right-hand side r uses its first count[r] <= nv
+// coefficients, and is skipped (out left as it was) when count[r] < 0.
 template <typename TV, typename TW, typename TO>
 __global__ void __launch_bounds__(kBlock) k_combine(const TV* __restrict__ V, long vstride, long rstride,
                                                     const TW* w, TO* out, long L, int nv,
-                                                    const c128* __restrict__ coef, const double* __restrict__ scale) {
+                                                    const c128* __restrict__ coef, const double* __restrict__ scale,
+                                                    const int* __restrict__ count) {
   const int rhs = blockIdx.y;
+  const int nvr = count ? (count[rhs] < nv ? count[rhs] : nv) : nv;
+  if (nvr < 0) return;
   const TW* wr = w + rhs * rstride;
   TO* outr = out + rhs * rstride;
   const TV* Vr = V + rhs * rstride;
@@ -355,9 +362,17 @@ __global__ void __launch_bounds__(kBlock) k_combine(const TV* __restrict__ V, lo
   const double sc = scale[rhs];
   for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < L; e += long(gridDim.x) * blockDim.x) {
     c128 acc = cvt<double>(wr[e]);
-    for (int i = 0; i < nv; ++i) acc = acc - cvt<double>(Vr[long(i) * vstride + e]) * cr[i];
+    for (int i = 0; i < nvr; ++i) acc = acc - cvt<double>(Vr[long(i) * vstride + e]) * cr[i];
     outr[e] = cvt<decltype(TO::re)>(sc * acc);
   }
+}
+
+struct FlagWords {
+  unsigned long long w[4];
+};
+
+__global__ void __launch_bounds__(kBlock) k_set_flags(FlagWords f, int nb, int* out) {
+  for (int r = threadIdx.x; r < nb; r += blockDim.x) out[r] = int((f.w[r >> 6] >> (r & 63)) & 1ull);
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill(c128* p, long n, c128 v) {
@@ -444,33 +459,42 @@ hipError_t launch_scatter(const c128* box, c128* full, long nv, const Box& g, hi
 
 template <typename TV, typename TW>
 hipError_t launch_dots(const TV* V, long vstride, long rstride, const TW* w, long L, int nv, int nrhs, int nblk,
-                       c128* partials, hipStream_t s) {
+                       c128* partials, hipStream_t s, const int* act) {
   const long chunk = (L + nblk - 1) / nblk;
-  k_dots<TV, TW><<<dim3(nblk, nrhs), kBlock, 0, s>>>(V, vstride, rstride, w, L, nv, chunk, partials);
+  k_dots<TV, TW><<<dim3(nblk, nrhs), kBlock, 0, s>>>(V, vstride, rstride, w, L, nv, chunk, partials, act);
   return hipGetLastError();
 }
 template hipError_t launch_dots<c128, c128>(const c128*, long, long, const c128*, long, int, int, int, c128*,
-                                            hipStream_t);
+                                            hipStream_t, const int*);
 
 
-hipError_t launch_reduce(const c128* partials, int nrhs, int nblk, int nv1, c128* out, hipStream_t s) {
-  k_reduce<<<nrhs, kBlock, 0, s>>>(partials, nblk, nv1, out);
+hipError_t launch_reduce(const c128* partials, int nrhs, int nblk, int nv1, c128* out, hipStream_t s,
+                         const int* act) {
+  k_reduce<<<nrhs, kBlock, 0, s>>>(partials, nblk, nv1, out, act);
   return hipGetLastError();
 }
 
 template <typename TV, typename TW, typename TO>
 hipError_t launch_combine(const TV* V, long vstride, long rstride, const TW* w, TO* out, long L, int nv,
-                          const c128* coef, const double* scale, int nrhs, hipStream_t s) {
+                          const c128* coef, const double* scale, int nrhs, hipStream_t s, const int* count) {
   long bx = (L + kBlock - 1) / kBlock;
   if (bx > 2048) bx = 2048;
-  k_combine<TV, TW, TO><<<dim3(unsigned(bx), nrhs), kBlock, 0, s>>>(V, vstride, rstride, w, out, L, nv, coef, scale);
+  k_combine<TV, TW, TO>
+      <<<dim3(unsigned(bx), nrhs), kBlock, 0, s>>>(V, vstride, rstride, w, out, L, nv, coef, scale, count);
   return hipGetLastError();
 }
 #define VIE_COMBINE_INST(TV, TW, TO)                                                                        \
   template hipError_t launch_combine<TV, TW, TO>(const TV*, long, long, const TW*, TO*, long, int, const c128*, \
-                                                 const double*, int, hipStream_t);
+                                                 const double*, int, hipStream_t, const int*);
 VIE_COMBINE_INST(c128, c128, c128)
 #undef VIE_COMBINE_INST
+
+hipError_t launch_set_flags(const unsigned long long (&words)[4], int nb, int* out, hipStream_t s) {
+  if (nb < 1 || nb > kMaxFlagged) return hipErrorInvalidValue;
+  FlagWords f{{words[0], words[1], words[2], words[3]}};
+  k_set_flags<<<1, kBlock, 0, s>>>(f, nb, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill(c128* p, long n, c128 v, hipStream_t s) {
   k_fill<<<grid_for(n), kBlock, 0, s>>>(p, n, v);

@@ -45,17 +45,24 @@ hipError_t launch_scatter(const c128* box, c128* full, long nv, const Box& g, hi
 // Partial sums, per right-hand side r and block: conj(V_i) . w_r for i < nv and
 // ||w_r||^2 (slot nv).  V_i of rhs r at V + i * vstride + r * rstride.
 // Products and sums in FP64 (vectors complex128; the kernel also reads other
-// storage types, instantiated where used).
+// storage types, instantiated where used).  act (optional): right-hand sides
+// with act[r] == 0 are skipped (their partial sums are not written).
 template <typename TV, typename TW>
 hipError_t launch_dots(const TV* V, long vstride, long rstride, const TW* w, long L, int nv, int nrhs, int nblk,
-                       c128* partials, hipStream_t s);
+                       c128* partials, hipStream_t s, const int* act = nullptr);
 // out[r][i] = sum over blocks of partials[r][blk][i], fixed order.
-hipError_t launch_reduce(const c128* partials, int nrhs, int nblk, int nv1, c128* out, hipStream_t s);
-// out_r = (w_r - sum_i V_i c[r][i]) * s[r]   (out may alias w), in FP64,
-// rounded to the storage of out (instantiated for complex128).
+hipError_t launch_reduce(const c128* partials, int nrhs, int nblk, int nv1, c128* out, hipStream_t s,
+                         const int* act = nullptr);
+// out_r = (w_r - sum_{i < count_r} V_i c[r][i]) * s[r]   (out may alias w), in
+// FP64, rounded to the storage of out (instantiated for complex128); count_r =
+// count[r] (capped at nv), or nv without count; out_r untouched when count[r] < 0.
 template <typename TV, typename TW, typename TO>
 hipError_t launch_combine(const TV* V, long vstride, long rstride, const TW* w, TO* out, long L, int nv,
-                          const c128* coef, const double* scale, int nrhs, hipStream_t s);
+                          const c128* coef, const double* scale, int nrhs, hipStream_t s,
+                          const int* count = nullptr);
+// out[r] = bit r of words[0..3] (r < nb <= kMaxFlagged), as 0 / 1
+constexpr int kMaxFlagged = 256;
+hipError_t launch_set_flags(const unsigned long long (&words)[4], int nb, int* out, hipStream_t s);
 hipError_t launch_fill(c128* p, long n, c128 v, hipStream_t s);
 hipError_t launch_copy(const c128* src, c128* dst, long n, hipStream_t s);
 // FP32 tables from FP64

@@ -71,13 +71,19 @@ int ensure_krylov(vie_plan* pl, int cap, int m, hipStream_t s) {
   dev_free(pl, pl->red);
   dev_free(pl, pl->coefd);
   dev_free(pl, pl->scaled);
+  dev_free(pl, pl->countd);
+  dev_free(pl, pl->actd);
   pl->V = pl->xw = pl->bw = pl->rw = pl->ww = pl->partials = pl->red = pl->coefd = nullptr;
   pl->scaled = nullptr;
+  pl->countd = pl->actd = nullptr;
+  pl->act_last.clear();
   if (pl->red_host) (void)hipHostFree(pl->red_host);
   if (pl->coef_host) (void)hipHostFree(pl->coef_host);
   if (pl->scale_host) (void)hipHostFree(pl->scale_host);
+  if (pl->count_host) (void)hipHostFree(pl->count_host);
   pl->red_host = pl->coef_host = nullptr;
   pl->scale_host = nullptr;
+  pl->count_host = nullptr;
   pl->kr_cap = pl->kr_m = 0;
   const size_t L = zu(pl->C) * zu(pl->box.np);  // vectors hold the support rows of the box
   const size_t nblk = zu(krylov_blocks(long(L)));
@@ -91,10 +97,13 @@ int ensure_krylov(vie_plan* pl, int cap, int m, hipStream_t s) {
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->red), sizeof(c128) * zu(cap) * zu(m + 2));
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->coefd), 2 * sizeof(c128) * zu(cap) * zu(m + 2));
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->scaled), 2 * sizeof(double) * zu(cap));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->countd), 2 * sizeof(int) * zu(cap));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->actd), sizeof(int) * zu(cap));
   if (rc) return rc;
   HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->red_host), sizeof(c128) * zu(cap) * zu(m + 2)));
   HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->coef_host), 2 * sizeof(c128) * zu(cap) * zu(m + 2)));
   HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->scale_host), 2 * sizeof(double) * zu(cap)));
+  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->count_host), 2 * sizeof(int) * zu(cap)));
   pl->stage_epoch[0] = pl->stage_epoch[1] = -1;
   pl->kr_cap = cap;
   pl->kr_m = m;
@@ -112,15 +121,46 @@ struct Batch {
 };
 
 // red[r][0..nv] <- (conj(V_i) . w_r, ||w_r||^2), copied to the host
-template <typename TV, typename TW>
-int dots_host(const Batch& b, const TV* V, const TW* w, int nv) {
+// Device flags of the right-hand sides that take part in the next launches
+// (kernels skip the others entirely), or null when all do or the batch is
+// too large to flag; *nact = how many take part.
+const int* set_active(const Batch& b, const std::vector<bool>& active, int* nact, int* rc) {
   vie_plan* pl = b.pl;
+  *rc = VIE_OK;
+  int n = 0;
+  for (int r = 0; r < b.nb; ++r) n += active[zu(r)] ? 1 : 0;
+  *nact = n;
+  if (n == b.nb || b.nb > kMaxFlagged) {
+    *nact = b.nb;
+    return nullptr;
+  }
+  std::vector<int> want(static_cast<size_t>(b.nb));
+  unsigned long long words[4] = {0, 0, 0, 0};
+  for (int r = 0; r < b.nb; ++r) {
+    want[zu(r)] = active[zu(r)] ? 1 : 0;
+    if (active[zu(r)]) words[r >> 6] |= 1ull << (r & 63);
+  }
+  if (want != pl->act_last) {
+    const hipError_t e = launch_set_flags(words, b.nb, pl->actd, b.s);
+    if (e != hipSuccess) {
+      *rc = hip_fail(pl, e, "launch_set_flags");
+      return nullptr;
+    }
+    pl->act_last = want;
+  }
+  return pl->actd;
+}
+
+template <typename TV, typename TW>
+int dots_host(const Batch& b, const TV* V, const TW* w, int nv, const int* act = nullptr, int nact = -1) {
+  vie_plan* pl = b.pl;
+  const double nrun = act && nact >= 0 ? nact : b.nb;
   int tok = prof_begin(pl, b.s);
-  HIPCHK(pl, launch_dots(V, b.vs, b.L, w, b.L, nv, b.nb, b.nblk, pl->partials, b.s));
-  prof_end(pl, FAM_DOTS, tok, b.s, (double(nv) * sizeof(TV) + sizeof(TW)) * b.nb * double(b.L),
-           (8.0 * nv + 4.0) * b.nb * double(b.L));
+  HIPCHK(pl, launch_dots(V, b.vs, b.L, w, b.L, nv, b.nb, b.nblk, pl->partials, b.s, act));
+  prof_end(pl, FAM_DOTS, tok, b.s, (double(nv) * sizeof(TV) + sizeof(TW)) * nrun * double(b.L),
+           (8.0 * nv + 4.0) * nrun * double(b.L));
   tok = prof_begin(pl, b.s);
-  HIPCHK(pl, launch_reduce(pl->partials, b.nb, b.nblk, nv + 1, pl->red, b.s));
+  HIPCHK(pl, launch_reduce(pl->partials, b.nb, b.nblk, nv + 1, pl->red, b.s, act));
   prof_end(pl, FAM_REDUCE, tok, b.s, double(b.nb) * (b.nblk + 1) * (nv + 1) * sizeof(c128));
   HIPCHK(pl, hipMemcpyAsync(pl->red_host, pl->red, sizeof(c128) * zu(b.nb) * zu(nv + 1),
                             hipMemcpyDeviceToHost, b.s));
@@ -135,9 +175,11 @@ cd red_at(const Batch& b, int r, int i, int nv1) {
 }
 
 // out_r = (w_r - sum_{i<nv} V_i c[r][i]) * scale[r], coefficients from host arrays
+// counts (optional): right-hand side r uses its first counts[r] coefficients
+// and is skipped (out left as it was) when counts[r] < 0
 template <typename TV, typename TW, typename TO>
 int combine_host(const Batch& b, const TV* V, const TW* w, TO* out, int nv, const std::vector<cd>& coef,
-                 const std::vector<double>& scale) {
+                 const std::vector<double>& scale, const std::vector<int>* counts = nullptr) {
   vie_plan* pl = b.pl;
   const int stride = std::max(nv, 1);
   // two staging slots used alternately; a slot is rewritten only after the
@@ -154,6 +196,8 @@ int combine_host(const Batch& b, const TV* V, const TW* w, TO* out, int nv, cons
   double* sh = pl->scale_host + zu(slot) * zu(pl->kr_cap);
   c128* cdv = pl->coefd + zu(slot) * half_c;
   double* sdv = pl->scaled + zu(slot) * zu(pl->kr_cap);
+  int* nh = pl->count_host + zu(slot) * zu(pl->kr_cap);
+  int* ndv = pl->countd + zu(slot) * zu(pl->kr_cap);
   for (int r = 0; r < b.nb; ++r) {
     for (int i = 0; i < stride; ++i) {
       const cd c = i < nv ? coef[zu(r) * zu(nv) + zu(i)] : cd(0.0, 0.0);
@@ -161,18 +205,37 @@ int combine_host(const Batch& b, const TV* V, const TW* w, TO* out, int nv, cons
     }
     sh[r] = scale[zu(r)];
   }
+  // vectors read per right-hand side (for the byte counts)
+  double nvec = 0.0, nrun = 0.0;
+  for (int r = 0; r < b.nb; ++r) {
+    const int k = counts ? std::min((*counts)[zu(r)], nv) : nv;
+    if (counts) nh[r] = k;
+    if (k >= 0) {
+      nvec += k;
+      nrun += 1.0;
+    }
+  }
   HIPCHK(pl, hipMemcpyAsync(cdv, ch, sizeof(c128) * zu(b.nb) * zu(stride), hipMemcpyHostToDevice, b.s));
   HIPCHK(pl, hipMemcpyAsync(sdv, sh, sizeof(double) * zu(b.nb), hipMemcpyHostToDevice, b.s));
+  if (counts) HIPCHK(pl, hipMemcpyAsync(ndv, nh, sizeof(int) * zu(b.nb), hipMemcpyHostToDevice, b.s));
   const int tok = prof_begin(pl, b.s);
-  HIPCHK(pl, launch_combine(V, b.vs, b.L, w, out, b.L, nv, cdv, sdv, b.nb, b.s));
-  prof_end(pl, FAM_COMBINE, tok, b.s, (double(nv) * sizeof(TV) + sizeof(TW) + sizeof(TO)) * b.nb * double(b.L),
-           (8.0 * nv + 2.0) * b.nb * double(b.L));
+  HIPCHK(pl, launch_combine(V, b.vs, b.L, w, out, b.L, nv, cdv, sdv, b.nb, b.s, counts ? ndv : nullptr));
+  prof_end(pl, FAM_COMBINE, tok, b.s, (nvec * sizeof(TV) + nrun * (sizeof(TW) + sizeof(TO))) * double(b.L),
+           (8.0 * nvec + 2.0 * nrun) * double(b.L));
   return VIE_OK;
 }
 
-// ||v_r|| for every slot
-int norms(const Batch& b, const c128* v, std::vector<double>& out) {
-  int rc = dots_host(b, static_cast<const c128*>(nullptr), v, 0);
+// counts of combine_host: nv for the flagged right-hand sides, -1 (skip) for the others
+std::vector<int> counts_of(const std::vector<bool>& active, int nv) {
+  std::vector<int> c(active.size());
+  for (size_t r = 0; r < active.size(); ++r) c[r] = active[r] ? nv : -1;
+  return c;
+}
+
+// ||v_r|| for every slot (for the flagged ones only when act is given; the
+// others' entries are then meaningless)
+int norms(const Batch& b, const c128* v, std::vector<double>& out, const int* act = nullptr, int nact = -1) {
+  int rc = dots_host(b, static_cast<const c128*>(nullptr), v, 0, act, nact);
   if (rc) return rc;
   out.resize(zu(b.nb));
   for (int r = 0; r < b.nb; ++r) out[zu(r)] = std::sqrt(std::max(0.0, red_at(b, r, 0, 1).real()));
@@ -200,7 +263,11 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
   for (int r = 0; r < nb; ++r) scale[zu(r)] = (active[zu(r)] && rnorm[zu(r)] > 0) ? 1.0 / rnorm[zu(r)] : 0.0;
   for (int r = 0; r < nb; ++r)
     if (!(rnorm[zu(r)] > 0)) active[zu(r)] = false;
-  int rc = combine_host(b, static_cast<const c128*>(nullptr), pl->rw, basis, 0, none, scale);
+  // Slots that are not active are skipped by every launch below (applies,
+  // dots, combines): their basis vectors keep whatever they held, and the
+  // final update reads only the vectors each slot wrote in this cycle.
+  std::vector<int> cnt = counts_of(active, 0);
+  int rc = combine_host(b, static_cast<const c128*>(nullptr), pl->rw, basis, 0, none, scale, &cnt);
   if (rc) return rc;
   // Hessenberg (column-major, (m+1) x m), rotations, rhs g
   std::vector<std::vector<cd>> Hs(static_cast<size_t>(nb), std::vector<cd>(zu((m + 1) * m)));
@@ -220,11 +287,15 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
     if (!any) break;
     const c128* Vj = basis + long(j) * b.vs;
     c128* Vn = basis + long(j + 1) * b.vs;
-    rc = apply_graph(pl, pl->box, fp64, Vj, Vj, nullptr, wv, nb, MODE_MATVEC, b.s);
+    int nact = 0;
+    const int* act = set_active(b, active, &nact, &rc);
+    if (rc) return rc;
+    rc = apply_graph(pl, pl->box, fp64, Vj, Vj, nullptr, wv, nb, MODE_MATVEC, b.s, act, nact);
     if (rc) return rc;
     const int nv = j + 1;
-    rc = dots_host(b, basis, wv, nv);
+    rc = dots_host(b, basis, wv, nv, act, nact);
     if (rc) return rc;
+    cnt = counts_of(active, nv);
     bool any_reorth = false;
     for (int r = 0; r < nb; ++r) {
       double p = 0;
@@ -245,9 +316,9 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
       for (int i = 0; i < nv; ++i) hcol[zu(r) * zu(nv + 1) + zu(i)] = h1[zu(r) * zu(nv) + zu(i)];
     if (any_reorth) {
       std::vector<double> one(static_cast<size_t>(nb), 1.0);
-      rc = combine_host(b, basis, wv, wv, nv, h1, one);  // w <- w - V h1
+      rc = combine_host(b, basis, wv, wv, nv, h1, one, &cnt);  // w <- w - V h1
       if (rc) return rc;
-      rc = dots_host(b, basis, wv, nv);
+      rc = dots_host(b, basis, wv, nv, act, nact);
       if (rc) return rc;
       for (int r = 0; r < nb; ++r) {
         double beta2;
@@ -267,7 +338,7 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
         hcol[zu(r) * zu(nv + 1) + zu(nv)] = beta;
         scale[zu(r)] = (active[zu(r)] && beta > 1e-300) ? 1.0 / beta : 0.0;
       }
-      rc = combine_host(b, basis, wv, Vn, nv, coef2, scale);
+      rc = combine_host(b, basis, wv, Vn, nv, coef2, scale, &cnt);
       if (rc) return rc;
     } else {
       for (int r = 0; r < nb; ++r) {
@@ -275,7 +346,7 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
         hcol[zu(r) * zu(nv + 1) + zu(nv)] = beta;
         scale[zu(r)] = (active[zu(r)] && beta > 1e-300) ? 1.0 / beta : 0.0;
       }
-      rc = combine_host(b, basis, wv, Vn, nv, h1, scale);
+      rc = combine_host(b, basis, wv, Vn, nv, h1, scale, &cnt);
       if (rc) return rc;
     }
     // Givens update per active slot
@@ -344,7 +415,8 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
     for (int i = 0; i < k; ++i) coef[zu(r) * zu(nvmax) + zu(i)] = -y[zu(i)];
   }
   std::vector<double> one(static_cast<size_t>(nb), 1.0);
-  return combine_host(b, static_cast<const c128*>(basis), pl->xw, pl->xw, nvmax, coef, one);
+  for (int r = 0; r < nb; ++r) cnt[zu(r)] = jend[zu(r)] > 0 ? jend[zu(r)] : -1;
+  return combine_host(b, static_cast<const c128*>(basis), pl->xw, pl->xw, nvmax, coef, one, &cnt);
 }
 
 // Bi-CGStab on A d = r (r in rw, d accumulated into xw).  Work vectors in the
@@ -544,10 +616,15 @@ int solve_batch(vie_plan* pl, const c128* inc, c128* density, c128* field, int n
       else
         rc = gmres_cycle(b, !mixed, m, rnorm, target, st, active, budget);
       if (rc) return rc;
-      // true residual with the FP64 operator
-      rc = apply_graph(pl, pl->box, true, pl->xw, pl->xw, pl->bw, pl->rw, nb, MODE_RESIDUAL, s);
+      // true residual with the FP64 operator, for the slots still iterating
+      std::vector<bool> live(static_cast<size_t>(nb));
+      for (int r = 0; r < nb; ++r) live[zu(r)] = !st[zu(r)].done;
+      int nlive = 0;
+      const int* act = set_active(b, live, &nlive, &rc);
       if (rc) return rc;
-      rc = norms(b, pl->rw, rnorm);
+      rc = apply_graph(pl, pl->box, true, pl->xw, pl->xw, pl->bw, pl->rw, nb, MODE_RESIDUAL, s, act, nlive);
+      if (rc) return rc;
+      rc = norms(b, pl->rw, rnorm, act, nlive);
       if (rc) return rc;
       bool progressed = false;
       for (int r = 0; r < nb; ++r) {

@@ -117,6 +117,34 @@ def test_batch_result_equals_single(vie):
     plan.close()
 
 
+@pytest.mark.parametrize("fp64,solver", [(False, "gmres"), (True, "gmres"), (False, "bicgstab")])
+def test_batch_with_slots_finishing_at_different_iterations(vie, fp64, solver):
+    """A batch whose slots stop at different iterations: a zero right-hand
+    side (never active), a plane wave, a scaled copy of it and a localised
+    one.  Launches skip the slots that have stopped, and every slot's result
+    and counts are bitwise those of its solve alone; the zero slot gives 0."""
+    n = 16
+    coef, mu, omega = medium(op.KIND_HELMHOLTZ, n, 7)
+    waves = incident(op.KIND_HELMHOLTZ, n, omega, 2, False, item=40)
+    X, Y, Z = gen.grid_coords(n)
+    local = waves[1] * np.exp(-((X - 0.3) ** 2 + Y ** 2 + (Z + 0.2) ** 2) / 0.05)[None]
+    inc = np.stack([waves[0], np.zeros_like(waves[0]), 1e-3 * waves[0], local, waves[1]])
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=5)
+    code = vie.SOLVER_BICGSTAB if solver == "bicgstab" else vie.SOLVER_GMRES
+    db, _, stb, rc = plan.solve(inc, tol=1e-10, fp64=fp64, solver=code, want_field=False)
+    assert rc == vie.OK
+    db = db.cpu().numpy()
+    assert np.all(db[1] == 0) and stb[1]["iters"] == 0
+    assert len({s["iters"] for s in stb}) >= 2  # the slots stop at different iterations
+    for r in (0, 2, 3, 4):
+        ds, _, sts, _ = plan.solve(inc[r:r + 1], tol=1e-10, fp64=fp64, solver=code, want_field=False)
+        assert np.array_equal(ds.cpu().numpy()[0], db[r]), r
+        for k in ("iters", "matvecs_fp32", "matvecs_fp64", "refinements"):
+            assert sts[0][k] == stb[r][k], (r, k)
+        assert sts[0]["rel_residual"] == stb[r]["rel_residual"]
+    plan.close()
+
+
 def test_identity_medium_gives_zero_density(vie):
     n = 12
     coef = gen.identity_field(n)
