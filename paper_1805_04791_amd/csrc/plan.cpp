@@ -662,8 +662,6 @@ int graph_or_eager(vie_plan* pl, const Geom& g, bool fp64, int nrhs, const vie_p
     return run(s);
   if (!pl->gstream) {
     HIPCHK(pl, hipStreamCreateWithFlags(&pl->gstream, hipStreamNonBlocking));
-    HIPCHK(pl, hipEventCreateWithFlags(&pl->gev_in, hipEventDisableTiming));
-    HIPCHK(pl, hipEventCreateWithFlags(&pl->gev_out, hipEventDisableTiming));
   }
   auto it = pl->graphs.find(key);
   if (it == pl->graphs.end()) {
@@ -684,11 +682,10 @@ int graph_or_eager(vie_plan* pl, const Geom& g, bool fp64, int nrhs, const vie_p
     if (ei != hipSuccess) return hip_fail(pl, ei, "hipGraphInstantiate");
     it = pl->graphs.emplace(key, ex).first;
   }
-  HIPCHK(pl, hipEventRecord(pl->gev_in, s));
-  HIPCHK(pl, hipStreamWaitEvent(pl->gstream, pl->gev_in, 0));
-  HIPCHK(pl, hipGraphLaunch(it->second, pl->gstream));
-  HIPCHK(pl, hipEventRecord(pl->gev_out, pl->gstream));
-  HIPCHK(pl, hipStreamWaitEvent(s, pl->gev_out, 0));
+  // replayed on the caller's stream itself: captured on the plan's stream
+  // (so that nothing else of the caller's stream is recorded), run in order
+  // with the caller's work without an event hop per apply
+  HIPCHK(pl, hipGraphLaunch(it->second, s));
   pl->graph_launches++;
   return VIE_OK;
 }
@@ -720,8 +717,6 @@ void destroy_plan(vie_plan* pl) {
   std::lock_guard<std::recursive_mutex> lk(hip_mutex());
   vie::clear_graphs(pl);
   if (pl->gstream) (void)hipStreamSynchronize(pl->gstream);
-  if (pl->gev_in) (void)hipEventDestroy(pl->gev_in);
-  if (pl->gev_out) (void)hipEventDestroy(pl->gev_out);
   if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
   for (auto& r : pl->prof) {
     (void)hipEventDestroy(r.a);

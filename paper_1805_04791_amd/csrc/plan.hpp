@@ -116,7 +116,6 @@ struct vie_plan {
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
   hipStream_t gstream = nullptr;
-  hipEvent_t gev_in = nullptr, gev_out = nullptr;
   bool use_graphs = true;
   long graph_launches = 0;
 
