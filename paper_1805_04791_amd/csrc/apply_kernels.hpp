@@ -54,7 +54,9 @@ struct ZArgs {
 // XCD b % 8).  The nb right-hand sides of one (ky, kx-tile) slice read the
 // same table slice, so they are given consecutive launch slots on one XCD and
 // the slice is re-read from that XCD's L2.  Requires (pxy / T) * pxy % 8 == 0.
-template <typename R, int P1, int P2, int C, int MUL>
+// TT > 0: the tile width a.T == TT is known at compile time, so every LDS
+// offset of the exchanges is an instruction immediate.
+template <typename R, int P1, int P2, int C, int MUL, int TT = 0>
 __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* buf, const cx<R>* __restrict__ tab, ZArgs a,
                                                             const cx<R>* __restrict__ twg) {
   constexpr int P = P1 * P2;
@@ -71,13 +73,14 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
   cx<R>* tw = reinterpret_cast<cx<R>*>(smem_raw);
   cx<R>* lds = tw + P;
   load_twiddles<R, P>(tw, twg);
+  const int T = TT > 0 ? TT : a.T;
   int col, j;
-  Layout<false>::lane(threadIdx.x, a.T, J, col, j);
+  Layout<false>::lane(threadIdx.x, T, J, col, j);
   const long slice = long(k / unsigned(a.nb)) * 8 + xcd;
   const long rhs = long(k % unsigned(a.nb));
   const int tile = int(slice % a.ntiles);
   const int ky = int(slice / a.ntiles);
-  const int kx = tile * a.T + col;
+  const int kx = tile * T + col;
   const bool valid = kx < a.pxy;
   const long PP = long(a.pxy) * a.pxy;
   cx<R>* base = buf + rhs * a.rhs_stride + long(ky) * a.pxy + kx;
@@ -85,11 +88,13 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
   // kUpfront: all inputs of the block in flight at once
   constexpr int CU = kUpfront<R> ? C : 1;
   cx<R> in[CU][H1];
+  // z = P2 n1 + j: one 64-bit step of P2 planes per n1
+  const long zstep = long(P2) * PP;
   auto load_comp = [&](int c, cx<R>(&dst)[H1]) {
-    const cx<R>* src = base + c * a.comp_stride;
+    const cx<R>* src = base + c * a.comp_stride + long(j) * PP;
     static_for<0, H1>([&](auto n1) {
       const int z = P2 * n1 + j;
-      dst[n1] = (valid && j < P2 && z < a.nz) ? src[long(z) * PP] : czero<R>();
+      dst[n1] = (valid && j < P2 && z < a.nz) ? src[decltype(n1)::value * zstep] : czero<R>();
     });
   };
   if constexpr (kUpfront<R>) static_for<0, C>([&](auto c) { load_comp(c, in[c]); });
@@ -107,7 +112,7 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
       else
         u[n1] = czero<R>();
     });
-    fft_fwd_core<R, P1, P2, false>(u, twr, lds, col, j, a.T, X[c]);
+    fft_fwd_core<R, P1, P2, false>(u, twr, lds, col, j, T, X[c]);
   });
 
   if (j < P1 && valid) {
@@ -177,9 +182,10 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
 
   // outputs z < nz <= N: only m2 < P1 / 2 of the last step are ever stored
   static_for<0, C>([&](auto c) {
-    cx<R>* dst = base + c * a.comp_stride;
+    cx<R>* dst = base + c * a.comp_stride + long(j) * PP;  // z = j + P2 m2
     fft_inv_CD<R, P1, P2, false, P1 / 2>(
-        X[c], [&](auto, int z, cx<R> v) { dst[long(z) * PP] = v; }, a.nz, lds, twr, col, j, a.T, valid);
+        X[c], [&](auto m2, int, cx<R> v) { dst[decltype(m2)::value * zstep] = v; }, a.nz, lds, twr, col, j, T,
+        valid);
   });
 }
 

@@ -158,10 +158,19 @@ struct LenImpl {
         (long(a.ntiles) * a.pxy) % 8 != 0)
       return hipErrorInvalidValue;
     const size_t lds = pass_lds_bytes<R, P1, P2, false>(a.T);
+    // the solver's usual tile width has its own compiled kernel
+    constexpr int TC = std::is_same<R, float>::value ? 16 : 8;
+    const dim3 grid{unsigned(nblocks)}, block{unsigned(a.T * J)};
     if (mul == MUL_SYM3) {
-      k_zpass<R, P1, P2, 3, MUL_SYM3><<<dim3(unsigned(nblocks)), dim3(a.T * J), lds, s>>>(buf, tab, a, tw);
+      if (a.T == TC)
+        k_zpass<R, P1, P2, 3, MUL_SYM3, TC><<<grid, block, lds, s>>>(buf, tab, a, tw);
+      else
+        k_zpass<R, P1, P2, 3, MUL_SYM3><<<grid, block, lds, s>>>(buf, tab, a, tw);
     } else if (mul == MUL_MAX6) {
-      k_zpass<R, P1, P2, 6, MUL_MAX6><<<dim3(unsigned(nblocks)), dim3(a.T * J), lds, s>>>(buf, tab, a, tw);
+      if (a.T == TC)
+        k_zpass<R, P1, P2, 6, MUL_MAX6, TC><<<grid, block, lds, s>>>(buf, tab, a, tw);
+      else
+        k_zpass<R, P1, P2, 6, MUL_MAX6><<<grid, block, lds, s>>>(buf, tab, a, tw);
     } else {
       // potentials and the reduced Maxwell H field: FP64 only
       if constexpr (std::is_same<R, double>::value) {

@@ -38,9 +38,10 @@ DEVICE_HEADERS = ("cx.hpp", "dft.hpp", "fft.hpp", "apply_kernels.hpp", "lens.hpp
 
 
 def source_digest() -> str:
-    """sha256 over the device sources (names and contents, sorted)."""
+    """sha256 over the sources the apply kernels are compiled from (the shared
+    device headers and the per-length files; names and contents, sorted)."""
     h = hashlib.sha256()
-    paths = [os.path.join(CSRC, f) for f in DEVICE_HEADERS] + glob.glob(os.path.join(CSRC, "*.hip"))
+    paths = [os.path.join(CSRC, f) for f in DEVICE_HEADERS] + glob.glob(os.path.join(CSRC, "len_*.hip"))
     for path in sorted(paths):
         h.update(os.path.basename(path).encode())
         with open(path, "rb") as f:
