@@ -17,7 +17,8 @@
 // Right-hand sides are advanced together in fused launches, but every
 // decision (re-orthogonalisation, convergence, inner cycle length, budget) is
 // taken per right-hand side and every reduction has a fixed order, so a
-// right-hand side gets bitwise the same answer alone or in a batch.
+// right-hand side gets bitwise the same answer alone or in a batch.  Slots
+// that have stopped are skipped by the launches (device flags per slot).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -120,7 +121,6 @@ struct Batch {
   int nblk;
 };
 
-// red[r][0..nv] <- (conj(V_i) . w_r, ||w_r||^2), copied to the host
 // Device flags of the right-hand sides that take part in the next launches
 // (kernels skip the others entirely), or null when all do or the batch is
 // too large to flag; *nact = how many take part.
@@ -151,6 +151,8 @@ const int* set_active(const Batch& b, const std::vector<bool>& active, int* nact
   return pl->actd;
 }
 
+// red[r][0..nv] <- (conj(V_i) . w_r, ||w_r||^2), copied to the host (slots
+// flagged off in act are skipped and their entries are meaningless)
 template <typename TV, typename TW>
 int dots_host(const Batch& b, const TV* V, const TW* w, int nv, const int* act = nullptr, int nact = -1) {
   vie_plan* pl = b.pl;
@@ -428,44 +430,49 @@ int bicgstab_run(const Batch& b, bool fp64, const std::vector<double>& rnorm0, c
   std::vector<bool> active = active_in;
   c128* rhat = pl->V;
   c128* v = pl->V + b.vs;
-  c128* p = pl->V + 2 * b.vs;
-  c128* sv = pl->V + 3 * b.vs;
+  c128* p = pl->V + 2 * b.vs;  // v, p consecutive: one two-vector combine forms p
+  c128* sv = pl->V + 3 * b.vs; // p, s consecutive: one two-vector combine updates x
   c128* t = pl->V + 4 * b.vs;
+  for (int r = 0; r < nb; ++r)
+    if (!(rnorm0[zu(r)] > 0)) active[zu(r)] = false;
+  // Slots that are not active are skipped by every launch (as in gmres_cycle).
   std::vector<cd> none;
   std::vector<double> one(static_cast<size_t>(nb), 1.0), zero(zu(nb), 0.0);
   const c128* nov = nullptr;
-  int rc = combine_host(b, nov, pl->rw, rhat, 0, none, one);
-  if (!rc) rc = combine_host(b, nov, pl->rw, p, 0, none, zero);  // p = 0
-  if (!rc) rc = combine_host(b, nov, pl->rw, v, 0, none, zero);  // v = 0
+  std::vector<int> c0 = counts_of(active, 0), c1 = counts_of(active, 1), c2 = counts_of(active, 2);
+  int rc = combine_host(b, nov, pl->rw, rhat, 0, none, one, &c0);    // rhat = r
+  if (!rc) rc = combine_host(b, nov, pl->rw, p, 0, none, zero, &c0);  // p = 0
+  if (!rc) rc = combine_host(b, nov, pl->rw, v, 0, none, zero, &c0);  // v = 0
   if (rc) return rc;
   std::vector<cd> rho(static_cast<size_t>(nb), 1.0), alpha(zu(nb), 1.0), omg(zu(nb), 1.0);
-  for (int r = 0; r < nb; ++r)
-    if (!(rnorm0[zu(r)] > 0)) active[zu(r)] = false;
   const int max_steps = 100000;
   for (int it = 0; it < max_steps; ++it) {
     bool any = false;
     for (int r = 0; r < nb; ++r) any = any || active[zu(r)];
     if (!any) break;
+    int nact = 0;
+    const int* act = set_active(b, active, &nact, &rc);
+    if (rc) return rc;
+    c1 = counts_of(active, 1);
+    c2 = counts_of(active, 2);
     // rho_new = (rhat, r)
-    rc = dots_host(b, rhat, pl->rw, 1);
+    rc = dots_host(b, rhat, pl->rw, 1, act, nact);
     if (rc) return rc;
     std::vector<cd> cP(zu(nb) * 2, cd(0, 0));
     std::vector<cd> rho_new(static_cast<size_t>(nb));
     for (int r = 0; r < nb; ++r) {
-      rho_new[zu(r)] = red_at(b, r, 0, 2);
       if (!active[zu(r)]) continue;
+      rho_new[zu(r)] = red_at(b, r, 0, 2);
       const cd beta = (rho_new[zu(r)] / rho[zu(r)]) * (alpha[zu(r)] / omg[zu(r)]);
       // p = r + beta (p - omega v) = r - (v (beta omega) + p (-beta))
       cP[zu(r) * 2 + 0] = beta * omg[zu(r)];
       cP[zu(r) * 2 + 1] = -beta;
     }
-    std::vector<double> sc(static_cast<size_t>(nb));
-    for (int r = 0; r < nb; ++r) sc[zu(r)] = active[zu(r)] ? 1.0 : 0.0;
-    rc = combine_host(b, v, pl->rw, p, 2, cP, sc);
+    rc = combine_host(b, v, pl->rw, p, 2, cP, one, &c2);
     if (rc) return rc;
-    rc = apply_graph(pl, pl->box, fp64, p, p, nullptr, v, nb, MODE_MATVEC, b.s);
+    rc = apply_graph(pl, pl->box, fp64, p, p, nullptr, v, nb, MODE_MATVEC, b.s, act, nact);
     if (rc) return rc;
-    rc = dots_host(b, rhat, v, 1);
+    rc = dots_host(b, rhat, v, 1, act, nact);
     if (rc) return rc;
     std::vector<cd> cS(static_cast<size_t>(nb), cd(0, 0));
     for (int r = 0; r < nb; ++r) {
@@ -474,11 +481,11 @@ int bicgstab_run(const Batch& b, bool fp64, const std::vector<double>& rnorm0, c
       alpha[zu(r)] = std::abs(den) > 0 ? rho_new[zu(r)] / den : cd(0, 0);
       cS[zu(r)] = alpha[zu(r)];
     }
-    rc = combine_host(b, v, pl->rw, sv, 1, cS, sc);  // s = r - alpha v
+    rc = combine_host(b, v, pl->rw, sv, 1, cS, one, &c1);  // s = r - alpha v
     if (rc) return rc;
-    rc = apply_graph(pl, pl->box, fp64, sv, sv, nullptr, t, nb, MODE_MATVEC, b.s);
+    rc = apply_graph(pl, pl->box, fp64, sv, sv, nullptr, t, nb, MODE_MATVEC, b.s, act, nact);
     if (rc) return rc;
-    rc = dots_host(b, sv, t, 1);  // conj(s).t and ||t||^2
+    rc = dots_host(b, sv, t, 1, act, nact);  // conj(s).t and ||t||^2
     if (rc) return rc;
     std::vector<cd> cX(zu(nb) * 2, cd(0, 0)), cR(zu(nb), cd(0, 0));
     for (int r = 0; r < nb; ++r) {
@@ -496,45 +503,13 @@ int bicgstab_run(const Batch& b, bool fp64, const std::vector<double>& rnorm0, c
       else
         st[zu(r)].mv32 += 2;
     }
-    rc = combine_host(b, p, pl->xw, pl->xw, 2, cX, one);  // x += alpha p + omega s
+    rc = combine_host(b, p, pl->xw, pl->xw, 2, cX, one, &c2);  // x += alpha p + omega s
     if (rc) return rc;
-    // r = s - omega t (frozen slots keep r)
-    for (int r = 0; r < nb; ++r) sc[zu(r)] = 1.0;
-    {
-      std::vector<cd> cRr(static_cast<size_t>(nb), cd(0, 0));
-      for (int r = 0; r < nb; ++r) cRr[zu(r)] = cR[zu(r)];
-      // slots not active: r <- r (use w = r and coefficient 0 via a second call)
-      rc = combine_host(b, t, sv, pl->ww, 1, cRr, sc);
-      if (rc) return rc;
-    }
-    rc = dots_host(b, nov, pl->ww, 0);
+    rc = combine_host(b, t, sv, pl->rw, 1, cR, one, &c1);  // r = s - omega t
     if (rc) return rc;
-    std::vector<double> nr(static_cast<size_t>(nb));
-    for (int r = 0; r < nb; ++r) nr[zu(r)] = std::sqrt(std::max(0.0, red_at(b, r, 0, 1).real()));
-    // copy the new residual of active slots into rw
-    std::vector<double> keep(static_cast<size_t>(nb));
-    for (int r = 0; r < nb; ++r) keep[zu(r)] = active[zu(r)] ? 1.0 : 0.0;
-    // rw = active ? ww : rw  -> rw = ww*keep + rw*(1-keep): two combines keep arithmetic exact
-    for (int r = 0; r < nb; ++r) {
-      if (!active[zu(r)]) continue;
-      (void)r;
-    }
-    rc = VIE_OK;
-    {
-      // slots that are active take ww; inactive slots keep rw: done with a copy
-      // per active slot range (contiguous slots are copied in one call)
-      int r = 0;
-      while (r < nb) {
-        if (!active[zu(r)]) {
-          ++r;
-          continue;
-        }
-        int e = r;
-        while (e < nb && active[zu(e)]) ++e;
-        HIPCHK(pl, launch_copy(pl->ww + long(r) * b.L, pl->rw + long(r) * b.L, long(e - r) * b.L, b.s));
-        r = e;
-      }
-    }
+    std::vector<double> nr;
+    rc = norms(b, pl->rw, nr, act, nact);
+    if (rc) return rc;
     for (int r = 0; r < nb; ++r) {
       if (!active[zu(r)]) continue;
       RhsState& S = st[zu(r)];
