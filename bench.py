@@ -2,7 +2,7 @@
 """Headline benchmark: solves/s of 128^3 anisotropic Helmholtz to 1e-8 relative
 error, FP32-mixed batched solver vs the plain FP64 solver, with p50/p99 latency.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--nrhs B] [--n 128]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--nrhs B] [--n 128] [--workload NAME]
 
 Workload (helmholtz128): grid 128^3 on [-1,1]^3, omega = 8 pi (8 wavelengths
 across the box), eps^{-1}(x) = I + b(x)(A + 0.05 i I) with a seeded symmetric
@@ -11,6 +11,12 @@ seeded directions (gradient of exp(i omega d.x) as incident field).
 A step is one batched mixed-precision solve of the B right-hand sides to a
 true relative residual of 1e-9 (error <= 1e-8); inputs are resident in HBM
 before the timed region.  Prints one JSON line.
+
+--workload measures the other configurations instead (same JSON layout):
+  laplace32    anisotropic Laplace 32^3, eps = I + b A, E0 = z; FP64 to 1e-10
+  helmholtz64  anisotropic Helmholtz 64^3, omega = 4 pi; FP64 to 1e-10
+  maxwell128   full Maxwell 128^3 (eps and mu), omega = 8 pi; mixed to 1e-9
+  batched96    Helmholtz 96^3, omega = 6 pi, 64 plane waves per step; mixed to 1e-9
 """
 
 from __future__ import annotations
@@ -35,21 +41,32 @@ MI355X_HBM_PEAK_GBS = 8000.0
 # library is compiled without.
 MI355X_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 METRIC = "solves/s to 1e-8 rel err (128³ Helmholtz), mixed vs FP64; p50/p99 latency"
+# name: (right-hand sides per step, true relative residual, the solver `value` reports)
+WORKLOADS = {"helmholtz128": (8, 1e-9, "mixed"), "laplace32": (1, 1e-10, "fp64"),
+             "helmholtz64": (8, 1e-10, "fp64"), "maxwell128": (8, 1e-9, "mixed"),
+             "batched96": (64, 1e-9, "mixed")}
 
 
 def pct(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
 
 
-def cpu_baseline(n: int, omega: float, matvecs_per_solve: float, budget_s: float = 30.0):
+def make_problem(workload: str, n: int, nrhs: int):
+    from vie_inputs import generators as gen
+    if workload == "helmholtz128":
+        omega = 8.0 * math.pi * n / 128.0 if n != 128 else 8.0 * math.pi
+        return gen.helmholtz_problem(n, omega, "helmholtz128", nrhs=nrhs)
+    return gen.config_problem(workload, nrhs=nrhs)
+
+
+def cpu_baseline(workload: str, n: int, matvecs_per_solve: float):
     """The oracle (NumPy FP64, window FFT route) timed on the host: one plan
     setup and one matvec at the benchmark's grid, scaled to solves/s with the
     GPU FP64 solver's matvec count."""
     from oracle import operator as op
-    from vie_inputs import generators as gen
-    prob = gen.helmholtz_problem(n, omega, "helmholtz128", nrhs=1)
+    prob = make_problem(workload, n, 1)
     t0 = time.perf_counter()
-    A = op.Operator(prob.kind, prob.coef, prob.omega)
+    A = op.Operator(prob.kind, prob.coef, prob.omega, mu=prob.mu)
     setup = time.perf_counter() - t0
     t0 = time.perf_counter()
     A.apply(prob.inc[0])
@@ -69,9 +86,10 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=128)
-    ap.add_argument("--nrhs", type=int, default=8, help="right-hand sides per batched step")
-    ap.add_argument("--tol", type=float, default=1e-9)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="helmholtz128")
+    ap.add_argument("--n", type=int, default=128, help="grid of the helmholtz128 workload")
+    ap.add_argument("--nrhs", type=int, default=0, help="right-hand sides per batched step (0: the workload's)")
+    ap.add_argument("--tol", type=float, default=0.0, help="true relative residual (0: the workload's)")
     ap.add_argument("--restart", type=int, default=40)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--latency-solves", type=int, default=8, help="single-RHS mixed solves for p50/p99")
@@ -105,19 +123,22 @@ def main(argv=None):
         del src, dst
         print(f"[bench] calibration copy: {args.calibrate_copy_mib} MiB read and written, 3 times",
               file=sys.stderr, flush=True)
-    n, B = args.n, args.nrhs
-    omega = 8.0 * math.pi * n / 128.0 if n != 128 else 8.0 * math.pi
-    prob = gen.helmholtz_problem(n, omega, "helmholtz128", nrhs=B)
+    wl = args.workload
+    B = args.nrhs or WORKLOADS[wl][0]
+    tol = args.tol or WORKLOADS[wl][1]
+    primary_fp64 = WORKLOADS[wl][2] == "fp64"
+    prob = make_problem(wl, args.n, B)
+    n, omega = prob.n, prob.omega
     dev = torch.device("cuda:0")
     inc = torch.from_numpy(prob.inc).to(dev)
     torch.cuda.synchronize()
 
-    plan = vie.Plan(vie.HELMHOLTZ, prob.coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=B)
-    print(f"[bench] plan ready: n={n} nrhs={B} omega={omega:.4f} "
+    plan = vie.Plan(prob.kind, prob.coef, omega=omega, mu=prob.mu, precision=vie.PREC_MIXED, max_rhs=B)
+    print(f"[bench] plan ready: {wl} n={n} nrhs={B} omega={omega:.4f} "
           f"max||H||={plan.info()['max_contrast_norm']:.3f}", file=sys.stderr, flush=True)
 
-    def solve(x_inc, fp64=False):
-        return plan.solve(x_inc, tol=args.tol, restart=args.restart, fp64=fp64, want_field=False)
+    def solve(x_inc, fp64=primary_fp64):
+        return plan.solve(x_inc, tol=tol, restart=args.restart, fp64=fp64, want_field=False)
 
     for _ in range(args.warmup):
         solve(inc)
@@ -143,20 +164,22 @@ def main(argv=None):
     solves = args.steps * B
     value = solves / total
 
-    # ---- plain FP64 GPU solver on the same batch
+    # ---- the other solver on the same batch: plain FP64 (or mixed, when the
+    # workload's own figure is the FP64 solver's)
     fp64 = {}
     if not args.no_fp64 and args.fp64_steps > 0:
         ts = []
         for k in range(args.fp64_steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            d64, _, st64, _ = solve(inc, fp64=True)
+            d64, _, st64, _ = solve(inc, fp64=not primary_fp64)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
         err = float(torch.linalg.vector_norm(d_mixed - d64) / torch.linalg.vector_norm(d64))
-        fp64 = {"fp64_solves_per_s": B * len(ts) / sum(ts),
-                "fp64_ms_per_step": 1e3 * sum(ts) / len(ts),
-                "fp64_matvecs_per_solve": float(np.mean([s["matvecs_fp64"] for s in st64])),
+        other = "mixed" if primary_fp64 else "fp64"
+        fp64 = {f"{other}_solves_per_s": B * len(ts) / sum(ts),
+                f"{other}_ms_per_step": 1e3 * sum(ts) / len(ts),
+                f"{other}_matvecs_per_solve": float(np.mean([s["matvecs_fp64"] + s["matvecs_fp32"] for s in st64])),
                 "mixed_vs_fp64_rel_diff": err}
 
     # ---- single right-hand-side latency
@@ -177,7 +200,8 @@ def main(argv=None):
     # HBM bytes per launch from the committed counter summary of this kernel
     # and workload, if the device sources are unchanged since it was taken
     from paper_1805_04791_amd import profiling
-    tr = profiling.read_traffic(os.path.join(ROOT, "profiles", f"{fam}.helmholtz{n}.traffic.md"))
+    tag = f"helmholtz{n}" if wl == "helmholtz128" else wl
+    tr = profiling.read_traffic(os.path.join(ROOT, "profiles", f"{fam}.{tag}.traffic.md"))
     digest = profiling.source_digest()
     traffic = tr[0] if tr is not None and tr[2] == digest else None
     if alu:
@@ -203,9 +227,12 @@ def main(argv=None):
         pts = 2.5 * pts / np.linalg.norm(pts, axis=1, keepdims=True)
         dirs = rng.standard_normal((256, 3))
         dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
-        for name, fn in (("potential", lambda: plan.potential(d_mixed)),
-                         ("fields_at_64_points", lambda: plan.fields_at(d_mixed, pts)),
-                         ("far_field_256_dirs", lambda: plan.far_field(d_mixed, dirs))):
+        calls = [("fields_at_64_points", lambda: plan.fields_at(d_mixed, pts))]
+        if prob.kind != vie.MAXWELL:
+            calls.insert(0, ("potential", lambda: plan.potential(d_mixed)))
+        if omega > 0:
+            calls.append(("far_field_256_dirs", lambda: plan.far_field(d_mixed, dirs)))
+        for name, fn in calls:
             fn()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -230,20 +257,27 @@ def main(argv=None):
 
     cpu = None
     if not args.no_cpu_baseline:
-        mv = fp64.get("fp64_matvecs_per_solve") or float(np.mean([s["matvecs_fp32"] + s["matvecs_fp64"]
-                                                                  for s in stats_all]))
+        mv = (float(np.mean([s["matvecs_fp64"] for s in stats_all])) if primary_fp64 else
+              fp64.get("fp64_matvecs_per_solve") or float(np.mean([s["matvecs_fp32"] + s["matvecs_fp64"]
+                                                                   for s in stats_all])))
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(n, omega, mv)
+        cpu = cpu_baseline(wl, args.n, mv)
 
+    if wl == "helmholtz128":
+        desc = (f"helmholtz{n}: anisotropic Helmholtz {n}^3, omega={omega:.6g}, "
+                f"eps^-1 = I + b(x)(A + 0.05i I), {B} seeded plane waves per step")
+    else:
+        desc = f"{wl}: {n}^3, omega={omega:.6g}, {B} right-hand sides per step, {prob.ncomp} unknowns per point"
     out = {
-        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC if wl == "helmholtz128" else f"solves/s to rel residual {tol:g} ({wl})",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * total / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "c64 FFT apply + c128 Krylov (mixed)",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128 (FP64 apply and Krylov)" if primary_fp64 else "c64 FFT apply + c128 Krylov (mixed)",
         "data": "synthetic",
-        "config": {"workload": f"helmholtz{n}: anisotropic Helmholtz {n}^3, omega={omega:.6g}, "
-                               f"eps^-1 = I + b(x)(A + 0.05i I), {B} seeded plane waves per step",
-                   "n": n, "omega": omega, "nrhs_per_step": B, "tol_true_residual": args.tol,
-                   "restart": args.restart, "solver": "GMRES + FP64 iterative refinement"},
+        "config": {"workload": desc, "n": n, "omega": omega, "nrhs_per_step": B, "tol_true_residual": tol,
+                   "restart": args.restart,
+                   "solver": "GMRES (FP64)" if primary_fp64 else "GMRES + FP64 iterative refinement"},
         "latency_ms": {"batch_p50": 1e3 * pct(step_s, 50), "batch_p99": 1e3 * pct(step_s, 99),
                        "single_p50": 1e3 * pct(lat, 50) if lat else None,
                        "single_p99": 1e3 * pct(lat, 99) if lat else None},
@@ -257,8 +291,10 @@ def main(argv=None):
         "kernels": breakdown,
         "cpu_baseline": cpu,
     }
-    if fp64:
+    if fp64 and not primary_fp64:
         out["speedup_mixed_vs_fp64"] = value / fp64["fp64_solves_per_s"]
+    elif fp64:
+        out["speedup_mixed_vs_fp64"] = fp64["mixed_solves_per_s"] / value
     print(json.dumps(out), flush=True)
     plan.close()
     return 0
