@@ -726,9 +726,7 @@ void destroy_plan(vie_plan* pl) {
   for (auto& a : pl->allocs) (void)hipFree(a.first);
   pl->allocs.clear();
   if (pl->red_host) (void)hipHostFree(pl->red_host);
-  if (pl->coef_host) (void)hipHostFree(pl->coef_host);
-  if (pl->scale_host) (void)hipHostFree(pl->scale_host);
-  if (pl->count_host) (void)hipHostFree(pl->count_host);
+  if (pl->stage_host) (void)hipHostFree(pl->stage_host);
   delete pl;
 }
 

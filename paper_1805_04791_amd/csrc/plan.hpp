@@ -91,13 +91,14 @@ struct vie_plan {
   vie::c128 *xw = nullptr, *bw = nullptr, *rw = nullptr, *ww = nullptr;
   vie::c128* partials = nullptr;  // [cap][nblk][m+2]
   vie::c128* red = nullptr;       // [cap][m+2]
-  vie::c128* coefd = nullptr;     // [cap][m+1]
-  double* scaled = nullptr;       // [cap]
   vie::c128* red_host = nullptr;  // pinned
-  vie::c128* coef_host = nullptr; // pinned
-  double* scale_host = nullptr;   // pinned
-  int* count_host = nullptr;      // pinned: coefficients used per right-hand side, 2 slots of [cap]
-  int* countd = nullptr;          // [2][cap]
+  // staging of the combine arguments, two slots used alternately (pinned on
+  // the host, mirrored on the device); a slot holds scale [cap] doubles,
+  // count [cap] ints and coefficients [cap][m + 2] complex, in that order, so
+  // that one copy of its used prefix carries them all
+  unsigned char* stage_host = nullptr;
+  unsigned char* stage_dev = nullptr;
+  size_t stage_bytes = 0, stage_off_count = 0, stage_off_coef = 0;
   int* actd = nullptr;            // [cap] flags of the right-hand sides still iterating (0 = skip)
   std::vector<int> act_last;      // the flags last written to actd
 

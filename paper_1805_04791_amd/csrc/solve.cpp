@@ -70,21 +70,16 @@ int ensure_krylov(vie_plan* pl, int cap, int m, hipStream_t s) {
   dev_free(pl, pl->ww);
   dev_free(pl, pl->partials);
   dev_free(pl, pl->red);
-  dev_free(pl, pl->coefd);
-  dev_free(pl, pl->scaled);
-  dev_free(pl, pl->countd);
+  dev_free(pl, pl->stage_dev);
   dev_free(pl, pl->actd);
-  pl->V = pl->xw = pl->bw = pl->rw = pl->ww = pl->partials = pl->red = pl->coefd = nullptr;
-  pl->scaled = nullptr;
-  pl->countd = pl->actd = nullptr;
+  pl->V = pl->xw = pl->bw = pl->rw = pl->ww = pl->partials = pl->red = nullptr;
+  pl->stage_dev = nullptr;
+  pl->actd = nullptr;
   pl->act_last.clear();
   if (pl->red_host) (void)hipHostFree(pl->red_host);
-  if (pl->coef_host) (void)hipHostFree(pl->coef_host);
-  if (pl->scale_host) (void)hipHostFree(pl->scale_host);
-  if (pl->count_host) (void)hipHostFree(pl->count_host);
-  pl->red_host = pl->coef_host = nullptr;
-  pl->scale_host = nullptr;
-  pl->count_host = nullptr;
+  if (pl->stage_host) (void)hipHostFree(pl->stage_host);
+  pl->red_host = nullptr;
+  pl->stage_host = nullptr;
   pl->kr_cap = pl->kr_m = 0;
   const size_t L = zu(pl->C) * zu(pl->box.np);  // vectors hold the support rows of the box
   const size_t nblk = zu(krylov_blocks(long(L)));
@@ -96,15 +91,15 @@ int ensure_krylov(vie_plan* pl, int cap, int m, hipStream_t s) {
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->ww), vec);
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->partials), sizeof(c128) * zu(cap) * nblk * zu(m + 2));
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->red), sizeof(c128) * zu(cap) * zu(m + 2));
-  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->coefd), 2 * sizeof(c128) * zu(cap) * zu(m + 2));
-  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->scaled), 2 * sizeof(double) * zu(cap));
-  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->countd), 2 * sizeof(int) * zu(cap));
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  pl->stage_off_count = sizeof(double) * zu(cap);
+  pl->stage_off_coef = up(pl->stage_off_count + sizeof(int) * zu(cap));
+  pl->stage_bytes = up(pl->stage_off_coef + sizeof(c128) * zu(cap) * zu(m + 2));
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->stage_dev), 2 * pl->stage_bytes);
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->actd), sizeof(int) * zu(cap));
   if (rc) return rc;
   HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->red_host), sizeof(c128) * zu(cap) * zu(m + 2)));
-  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->coef_host), 2 * sizeof(c128) * zu(cap) * zu(m + 2)));
-  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->scale_host), 2 * sizeof(double) * zu(cap)));
-  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->count_host), 2 * sizeof(int) * zu(cap)));
+  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->stage_host), 2 * pl->stage_bytes));
   pl->stage_epoch[0] = pl->stage_epoch[1] = -1;
   pl->kr_cap = cap;
   pl->kr_m = m;
@@ -193,13 +188,14 @@ int combine_host(const Batch& b, const TV* V, const TW* w, TO* out, int nv, cons
     pl->sync_count++;
   }
   pl->stage_epoch[slot] = pl->sync_count;
-  const size_t half_c = zu(pl->kr_cap) * zu(pl->kr_m + 2);
-  c128* ch = pl->coef_host + zu(slot) * half_c;
-  double* sh = pl->scale_host + zu(slot) * zu(pl->kr_cap);
-  c128* cdv = pl->coefd + zu(slot) * half_c;
-  double* sdv = pl->scaled + zu(slot) * zu(pl->kr_cap);
-  int* nh = pl->count_host + zu(slot) * zu(pl->kr_cap);
-  int* ndv = pl->countd + zu(slot) * zu(pl->kr_cap);
+  unsigned char* hb = pl->stage_host + zu(slot) * pl->stage_bytes;
+  unsigned char* db = pl->stage_dev + zu(slot) * pl->stage_bytes;
+  double* sh = reinterpret_cast<double*>(hb);
+  int* nh = reinterpret_cast<int*>(hb + pl->stage_off_count);
+  c128* ch = reinterpret_cast<c128*>(hb + pl->stage_off_coef);
+  const double* sdv = reinterpret_cast<const double*>(db);
+  const int* ndv = reinterpret_cast<const int*>(db + pl->stage_off_count);
+  const c128* cdv = reinterpret_cast<const c128*>(db + pl->stage_off_coef);
   for (int r = 0; r < b.nb; ++r) {
     for (int i = 0; i < stride; ++i) {
       const cd c = i < nv ? coef[zu(r) * zu(nv) + zu(i)] : cd(0.0, 0.0);
@@ -217,9 +213,9 @@ int combine_host(const Batch& b, const TV* V, const TW* w, TO* out, int nv, cons
       nrun += 1.0;
     }
   }
-  HIPCHK(pl, hipMemcpyAsync(cdv, ch, sizeof(c128) * zu(b.nb) * zu(stride), hipMemcpyHostToDevice, b.s));
-  HIPCHK(pl, hipMemcpyAsync(sdv, sh, sizeof(double) * zu(b.nb), hipMemcpyHostToDevice, b.s));
-  if (counts) HIPCHK(pl, hipMemcpyAsync(ndv, nh, sizeof(int) * zu(b.nb), hipMemcpyHostToDevice, b.s));
+  // one copy: scales, counts and the used coefficients
+  const size_t used = pl->stage_off_coef + sizeof(c128) * zu(b.nb) * zu(stride);
+  HIPCHK(pl, hipMemcpyAsync(db, hb, used, hipMemcpyHostToDevice, b.s));
   const int tok = prof_begin(pl, b.s);
   HIPCHK(pl, launch_combine(V, b.vs, b.L, w, out, b.L, nv, cdv, sdv, b.nb, b.s, counts ? ndv : nullptr));
   prof_end(pl, FAM_COMBINE, tok, b.s, (nvec * sizeof(TV) + nrun * (sizeof(TW) + sizeof(TO))) * double(b.L),
