@@ -68,17 +68,33 @@ def cpu_baseline(workload: str, n: int, matvecs_per_solve: float):
     t0 = time.perf_counter()
     A = op.Operator(prob.kind, prob.coef, prob.omega, mu=prob.mu)
     setup = time.perf_counter() - t0
+    from oracle import tables as tb
     t0 = time.perf_counter()
     A.apply(prob.inc[0])
     mv = time.perf_counter() - t0
+    # the same matvec with one FFT worker
+    workers = tb.WORKERS
+    tb.WORKERS = 1
+    try:
+        t0 = time.perf_counter()
+        A.apply(prob.inc[0])
+        mv1 = time.perf_counter() - t0
+    finally:
+        tb.WORKERS = workers
     solve_s = mv * matvecs_per_solve
-    from oracle import tables as tb
-    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": tb.WORKERS, "kind": "oracle",
-            "sample": (f"one FP64 matvec of the oracle at {n}^3 ({mv:.2f} s; scipy.fft with "
-                       f"{tb.WORKERS} workers, the rest single-threaded numpy; table setup {setup:.1f} s "
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": (f"one FP64 matvec of the oracle at {prob.n}^3 ({mv:.2f} s; scipy.fft with "
+                       f"{workers} workers, the rest single-threaded numpy; table setup {setup:.1f} s "
                        f"not counted) x {matvecs_per_solve:.1f} matvecs per solve (the GPU FP64 "
                        f"GMRES count for the same right-hand sides)"),
-            "matvec_s": mv, "setup_s": setup}
+            "matvec_s": mv, "matvec_s_1_worker": mv1, "value_1_worker": 1.0 / (mv1 * matvecs_per_solve),
+            "setup_s": setup, "cpu_model": model}
 
 
 def main(argv=None):
