@@ -203,6 +203,16 @@ struct XArgs {
   const int* act = nullptr;  // optional: rows of right-hand side r are skipped when act[r] == 0
 };
 
+// Blocks of a k_xinv launch.  With xcd_order the ceil(bz by / T) row tiles of
+// each right-hand side are padded to a multiple of 8 (the padding blocks
+// exit at once), so that tile t of every right-hand side lands on XCD t % 8.
+__host__ __device__ inline long xinv_blocks(const XArgs& a) {
+  const long NN = long(a.bz) * a.by;
+  if (!a.xcd_order) return (a.nrows + a.T - 1) / a.T;
+  const long nt = (NN + a.T - 1) / a.T;
+  return (nt + 7) / 8 * 8 * a.nb;
+}
+
 // Rows (rhs, z, y) of the data box: inverse x transform of every component,
 // then the pointwise combine.  Vectors J, B, out are [rhs][C][np]: the dense
 // box [bz][by][bx], or only the support samples of each row (a.rows),
@@ -223,26 +233,27 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
   const long NN = long(a.bz) * a.by;  // rows per right-hand side
   // xcd_order: block b runs on XCD b % 8; the nb right-hand sides of one
   // (z, y) row tile share H, so they take consecutive slots on one XCD
-  long tile_id = blockIdx.x;
+  // rows [row0, row1) of the flattened (rhs, z, y) rows
+  long row0, row1;
   if (a.xcd_order) {
     const unsigned xcd = blockIdx.x % 8u, k = blockIdx.x / 8u;
     const long slice = long(k / unsigned(a.nb)) * 8 + xcd;
     const long r = long(k % unsigned(a.nb));
-    tile_id = r * (NN / a.T) + slice;
+    if (slice * a.T >= NN) return;  // padding block
+    row0 = r * NN + slice * a.T;
+    row1 = r * NN + (slice * a.T + a.T < NN ? slice * a.T + a.T : NN);
+  } else {
+    row0 = long(blockIdx.x) * a.T;
+    row1 = row0 + a.T < a.nrows ? row0 + a.T : a.nrows;
   }
-  if (a.act) {
-    // the whole block belongs to one inactive right-hand side
-    const long first = tile_id * a.T;
-    const long last = (first + a.T < a.nrows ? first + a.T : a.nrows) - 1;
-    if (first / NN == last / NN && !a.act[first / NN]) return;
-  }
+  if (a.act && (row0 / NN == (row1 - 1) / NN) && !a.act[row0 / NN]) return;  // one inactive right-hand side
   cx<R>* tw = reinterpret_cast<cx<R>*>(smem_raw);
   cx<R>* lds = tw + P;
   load_twiddles<R, P>(tw, twg);
   int col, j;
   Layout<true>::lane(threadIdx.x, a.T, J, col, j);
-  const long row = tile_id * a.T + col;
-  const bool valid = row < a.nrows && (!a.act || a.act[row / NN]);
+  const long row = row0 + col;
+  const bool valid = row < row1 && (!a.act || a.act[row / NN]);
   const long rhs = valid ? row / NN : 0;
   const long zy = valid ? row % NN : 0;
   const long hrow = (long(a.z0) + zy / a.by) * N + (a.y0 + zy % a.by);  // (z, y) in the grid

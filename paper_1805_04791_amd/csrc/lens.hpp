@@ -131,7 +131,7 @@ struct LenImpl {
   }
   static hipError_t xinv_v32(int C, const cx<R>* A, XArgs a, const c64* J_, const cx<R>* H, const cx<R>* Hmu,
                              c64* out, const cx<R>* tw, hipStream_t s) {
-    const long blocks = (a.nrows + a.T - 1) / a.T;
+    const long blocks = xinv_blocks(a);
     if (C == 3)
       k_xinv<R, P1, P2, 3, MODE_MATVEC, c64><<<dim3(unsigned(blocks)), dim3(a.T * J), pass_lds_bytes<R, P1, P2, true>(a.T), s>>>(A, a, J_, nullptr, H, Hmu, out, tw);
     else if (C == 6)
@@ -189,7 +189,7 @@ struct LenImpl {
   template <int C, int MODE>
   static void xinv_launch(const cx<R>* A, XArgs a, const c128* J_, const c128* B, const cx<R>* H, const cx<R>* Hmu,
                           c128* out, const cx<R>* tw, hipStream_t s) {
-    const long blocks = (a.nrows + a.T - 1) / a.T;
+    const long blocks = xinv_blocks(a);
     k_xinv<R, P1, P2, C, MODE><<<dim3(unsigned(blocks)), dim3(a.T * J), pass_lds_bytes<R, P1, P2, true>(a.T), s>>>(A, a, J_, B, H, Hmu, out, tw);
   }
   static hipError_t xinv(int C, int mode, const cx<R>* A, XArgs a, const c128* J_, const c128* B, const cx<R>* H,

@@ -304,7 +304,7 @@ hipError_t pass_xinv(const ApplyCall<R>& c, const TV* addv, const c128* bvec, TV
                      hipStream_t s) {
   const vie_plan* pl = c.pl;
   const long NN = long(c.g.bz) * c.g.by;
-  const int xcd = (NN % T == 0) && ((NN / T) % 8 == 0) ? 1 : 0;
+  const int xcd = 1;  // tiles of all right-hand sides that share H run back to back on one XCD
   XArgs a{T,      long(c.nb) * NN, pl->n,  pl->n3, c.nb,   xcd,  c.g.bx,
           c.g.by, c.g.bz,          c.g.x0, c.g.y0, c.g.z0, c.g.np, c.g.rows, c.act};
   const cx<R>* H;
