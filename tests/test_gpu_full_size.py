@@ -180,3 +180,34 @@ def test_batched_96_64_rhs(vie):
     d64, _, _, _ = plan.solve(prob.inc[63:64], tol=1e-11, fp64=True, want_field=False)
     assert rel(d[63], d64.cpu().numpy()[0]) < 1e-8
     plan.close()
+
+
+def test_largest_grid_160(vie):
+    """The largest supported grid (160^3, the top of the serving mix): the
+    Helmholtz recipe at omega = 10 pi.  The whole-grid apply runs on length
+    320 along every axis, the solver on the support box (length 256 along x
+    and y, 320 along z) with tables from the 640-point precompute.  FP64
+    apply against the oracle at samples, FP32 apply against FP64, and a
+    mixed solve of 2 right-hand sides through the oracle's residual."""
+    n = 160
+    prob = gen.helmholtz_problem(n, 10 * math.pi, "helmholtz128", nrhs=2)
+    orc = SampledOracle(prob.kind, prob.coef, prob.omega)
+    plan = vie.Plan(prob.kind, prob.coef, omega=prob.omega, precision=vie.PREC_MIXED, max_rhs=2)
+    assert plan.info()["box_P"] == 256
+    x = gen.random_density((1, 3, n, n, n), gen.rng_for(gen.CONFIG_IDS["test"], 801))
+    y64 = plan.apply(x, vie.APPLY_FP64).cpu().numpy()[0]
+    pts = sample_points(np.ones((n, n, n), dtype=bool), 6, 4)
+    got = np.concatenate([y64[:, z, yy, xx] for (z, yy, xx) in pts])
+    ref = np.concatenate([orc.apply_at(x[0], p) for p in pts])
+    assert rel(got, ref) < 1e-11
+    y32 = plan.apply(x).cpu().numpy()[0]
+    assert rel(y32, y64) < 1e-5
+    d, _, st, rc = plan.solve(prob.inc, tol=1e-9, want_field=False)
+    assert rc == vie.OK and all(s["rel_residual"] <= 1e-9 for s in st)
+    d = d.cpu().numpy()
+    spts = sample_points(support(orc.H), 6, 5)
+    for r in range(2):
+        b = np.concatenate([orc.rhs_at(prob.inc[r], p) for p in spts])
+        res = b - np.concatenate([orc.apply_at(d[r], p) for p in spts])
+        assert np.linalg.norm(res) <= 1e-7 * np.linalg.norm(b)
+    plan.close()
