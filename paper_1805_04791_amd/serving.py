@@ -15,6 +15,12 @@ The server
   merges their right-hand sides into one fused multi-RHS solve;
 * records arrival -> completion latency per request.
 
+The stream's inputs are generated on the host ahead of their arrival times
+by a thread pool, within a host-memory budget that also counts the inputs
+of requests still queued or on the device; when the budget is spent the
+feeder waits, and the wait shows in the latency (measured from the nominal
+arrival time).
+
 Each right-hand side is solved with the same arithmetic whatever else runs
 beside it (per-RHS convergence decisions, fixed-order reductions, tile
 choices that do not change the per-pencil arithmetic), so a result is the
@@ -57,6 +63,16 @@ class Request:
     key: str = ""                           # plan key; derived from the medium if empty
     make: Optional[Callable] = None
     full: bool = False
+    host_bytes: int = 0                     # input bytes charged to the host budget
+
+    def input_bytes(self) -> int:
+        """Host bytes of the request's inputs (estimated before they exist)."""
+        c = 6 if (self.full or self.mu is not None) else 3
+        tensors = 9 * (2 if (self.full or self.mu is not None) else 1)
+        return (tensors + self.nrhs * c) * self.n ** 3 * 16
+
+    def release(self):
+        self.coef = self.inc = self.mu = None
 
     def materialise(self):
         if self.coef is None and self.make is not None:
@@ -149,7 +165,8 @@ class PlanCache:
 
 class Server:
     def __init__(self, budget_bytes: Optional[int] = None, workers: int = 3, restart: int = 20,
-                 max_batch: int = 16, plan_cache: int = 4, precision: Optional[int] = None):
+                 max_batch: int = 16, plan_cache: int = 4, precision: Optional[int] = None,
+                 keep_results: bool = True, gen_workers: int = 8, host_budget_bytes: int = 32 * 10 ** 9):
         import torch
         from . import vie
         self.vie = vie
@@ -172,6 +189,10 @@ class Server:
         self.inflight = 0
         self.max_inflight = 0
         self.errors: List[str] = []
+        self.keep_results = keep_results
+        self.gen_workers = gen_workers
+        self.host = Admission(host_budget_bytes)
+        self.feeder_late = 0.0
 
     # ---- footprint -----------------------------------------------------------
     def footprint(self, reqs: List[Request]) -> int:
@@ -239,7 +260,7 @@ class Server:
                     inc = np.concatenate([q.inc for q in sel])
                     dens, _, stats, rc = plan.solve(inc, tol=min(q.tol for q in sel), restart=self.restart,
                                                     want_field=False, stream=stream)
-                    dens = dens.cpu().numpy()
+                    dens = dens.cpu().numpy() if self.keep_results else None
                     stream.synchronize()
                     self.cache.put(r.key, plan)
                 done = self.now()
@@ -247,38 +268,74 @@ class Server:
                 with self.rlock:
                     for q in sel:
                         k = q.nrhs
-                        self.results.append(Result(q.id, dens[off:off + k], stats[off:off + k], q.arrival,
-                                                   admitted, done, [o.id for o in sel if o.id != q.id]))
+                        self.results.append(Result(q.id, dens[off:off + k] if dens is not None else None,
+                                                   stats[off:off + k], q.arrival, admitted, done,
+                                                   [o.id for o in sel if o.id != q.id]))
                         off += k
             except Exception as exc:  # keep serving; report at the end
                 self.errors.append(f"request {sel[0].id}: {exc}")
             finally:
+                for q in sel:
+                    q.release()
+                    self.host.give(q.host_bytes)
                 self.admission.give(fp)
                 with self.qlock:
                     self.inflight -= 1
                     self.qlock.notify_all()
 
     def run(self, stream_of: Callable[[], List[Request]], realtime: bool = True) -> List[Result]:
-        """Feed the requests at their arrival times (or all at once) and serve them."""
+        """Feed the requests at their arrival times (or all at once) and serve them.
+
+        Inputs are generated ahead by a thread pool while the host budget
+        allows; request i itself waits for budget (freed as earlier requests
+        finish) before it is generated."""
+        from concurrent.futures import ThreadPoolExecutor
         reqs = sorted(stream_of(), key=lambda r: r.arrival)
         threads = [threading.Thread(target=self._worker, daemon=True) for _ in range(self.workers)]
+        pool = ThreadPoolExecutor(max_workers=max(1, self.gen_workers))
+        futures = {}
+        nxt = 0
+
+        def start(j: int, block: bool) -> bool:
+            r = reqs[j]
+            b = r.input_bytes()
+            with self.host.lock:
+                while not self.host.fits(b):
+                    if not block:
+                        return False
+                    self.host.lock.wait(timeout=0.05)
+                self.host.take(b)
+            r.host_bytes = b
+            futures[j] = pool.submit(r.materialise)
+            return True
+
         self.t0 = time.perf_counter()
         for t in threads:
             t.start()
-        for r in reqs:
-            if realtime:
-                delay = r.arrival - self.now()
-                if delay > 0:
-                    time.sleep(delay)
-            else:
-                r.arrival = self.now()
-            self.submit(r.materialise())
-        with self.qlock:
-            self.closed = True
-            self.qlock.notify_all()
-        for t in threads:
-            t.join()
-        self.cache.clear()
+        try:
+            for i, r in enumerate(reqs):
+                if nxt == i:
+                    start(i, True)
+                    nxt += 1
+                while nxt < len(reqs) and nxt - i <= 4 * max(1, self.gen_workers) and start(nxt, False):
+                    nxt += 1
+                futures.pop(i).result()
+                if realtime:
+                    delay = r.arrival - self.now()
+                    if delay > 0:
+                        time.sleep(delay)
+                    self.feeder_late = max(self.feeder_late, -delay)
+                else:
+                    r.arrival = self.now()
+                self.submit(r)
+        finally:
+            pool.shutdown(wait=True)
+            with self.qlock:
+                self.closed = True
+                self.qlock.notify_all()
+            for t in threads:
+                t.join()
+            self.cache.clear()
         return sorted(self.results, key=lambda x: x.id)
 
     def summary(self, results: List[Result]) -> dict:
@@ -294,6 +351,7 @@ class Server:
                 "latency_max_ms": 1e3 * float(lat.max()),
                 "max_inflight": self.max_inflight, "peak_admitted_GB": self.admission.peak / 1e9,
                 "budget_GB": self.admission.budget / 1e9, "plan_cache_hits": self.cache.hits,
+                "host_peak_GB": self.host.peak / 1e9, "feeder_late_max_s": self.feeder_late,
                 "errors": self.errors[:5]}
 
 
@@ -322,12 +380,16 @@ def main(argv=None):
     ap.add_argument("--max-rhs", type=int, default=16)
     ap.add_argument("--workers", type=int, default=3)
     ap.add_argument("--budget-gb", type=float, default=0.0)
+    ap.add_argument("--host-budget-gb", type=float, default=32.0, help="host memory for generated inputs")
+    ap.add_argument("--gen-workers", type=int, default=8, help="threads generating the stream's inputs")
     args = ap.parse_args(argv)
     grids = tuple(int(g) for g in args.grids.split(","))
     t = time.perf_counter()
     reqs = requests_from_generator(args.requests, args.rate, grids, args.max_rhs)
     print(f"[serve] generated {len(reqs)} requests in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
-    srv = Server(int(args.budget_gb * 1e9) if args.budget_gb > 0 else None, workers=args.workers)
+    srv = Server(int(args.budget_gb * 1e9) if args.budget_gb > 0 else None, workers=args.workers,
+                 keep_results=False, gen_workers=args.gen_workers,
+                 host_budget_bytes=int(args.host_budget_gb * 1e9))
     res = srv.run(lambda: reqs)
     out = srv.summary(res)
     out.update({"rate": args.rate, "grids": list(grids), "workers": args.workers})

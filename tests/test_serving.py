@@ -75,6 +75,52 @@ def test_request_key_from_medium():
     assert a.key == b.key != c.key
 
 
+def test_feeder_keeps_generated_inputs_within_the_host_budget():
+    """The feeder generates inputs ahead of arrival but never holds more than
+    the host budget (plus one request when nothing else is held); every
+    request is served and its arrays are released afterwards."""
+    from paper_1805_04791_amd import serving
+
+    n, nrhs = 8, 2
+    one = Request(0, 1, n, 2.0, nrhs).input_bytes()
+    held = []
+    lock = threading.Lock()
+
+    class FakeServer(serving.Server):
+        def _worker(self):
+            import time
+            while True:
+                sel, fp = self._take()
+                if sel is None:
+                    return
+                time.sleep(0.01)     # the device is slower than the stream
+                with self.rlock:
+                    for q in sel:
+                        assert q.inc is not None and q.inc.shape == (nrhs, 3, n, n, n)
+                        self.results.append(serving.Result(q.id, None, [{"status": 0}] * q.nrhs, q.arrival,
+                                                           self.now(), self.now()))
+                for q in sel:
+                    with lock:
+                        held.append(q)
+                    q.release()
+                    self.host.give(q.host_bytes)
+                self.admission.give(fp)
+                with self.qlock:
+                    self.inflight -= 1
+                    self.qlock.notify_all()
+
+    def make():
+        return (np.zeros((9, n, n, n), complex), None, np.zeros((nrhs, 3, n, n, n), complex))
+
+    reqs = [Request(i, 1, n, 2.0, nrhs, arrival=0.001 * i, key=f"k{i}", make=make) for i in range(40)]
+    srv = FakeServer(budget_bytes=10 ** 12, workers=2, keep_results=False, gen_workers=4,
+                     host_budget_bytes=3 * one)
+    res = srv.run(lambda: reqs)
+    assert [r.id for r in res] == list(range(40))
+    assert srv.host.peak <= 3 * one and srv.host.used == 0
+    assert all(q.coef is None and q.inc is None for q in held)
+
+
 @pytest.mark.gpu
 def test_results_alone_equal_results_in_the_mix():
     torch = pytest.importorskip("torch")
