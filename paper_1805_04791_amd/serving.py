@@ -16,10 +16,10 @@ The server
 * records arrival -> completion latency per request.
 
 The stream's inputs are generated on the host ahead of their arrival times
-by a thread pool, within a host-memory budget that also counts the inputs
-of requests still queued or on the device; when the budget is spent the
-feeder waits, and the wait shows in the latency (measured from the nominal
-arrival time).
+by a thread pool (and placed in pinned memory), within a host-memory budget
+that also counts the inputs of requests still queued or on the device; when
+the budget is spent the feeder waits, and the wait shows in the latency
+(measured from the nominal arrival time).
 
 Each right-hand side is solved with the same arithmetic whatever else runs
 beside it (per-RHS convergence decisions, fixed-order reductions, tile
@@ -73,6 +73,15 @@ class Request:
 
     def release(self):
         self.coef = self.inc = self.mu = None
+
+    def pin(self):
+        """Move the generated inputs to pinned host memory (torch tensors), so
+        that the worker's copies to the device run at full link speed."""
+        import torch
+        conv = lambda a: a if a is None or isinstance(a, torch.Tensor) else torch.from_numpy(
+            np.ascontiguousarray(a)).pin_memory()
+        self.coef, self.mu, self.inc = conv(self.coef), conv(self.mu), conv(self.inc)
+        return self
 
     def materialise(self):
         if self.coef is None and self.make is not None:
@@ -166,7 +175,8 @@ class PlanCache:
 class Server:
     def __init__(self, budget_bytes: Optional[int] = None, workers: int = 3, restart: int = 20,
                  max_batch: int = 16, plan_cache: int = 4, precision: Optional[int] = None,
-                 keep_results: bool = True, gen_workers: int = 8, host_budget_bytes: int = 32 * 10 ** 9):
+                 keep_results: bool = True, gen_workers: int = 8, host_budget_bytes: int = 32 * 10 ** 9,
+                 pinned_inputs: bool = False):
         import torch
         from . import vie
         self.vie = vie
@@ -190,9 +200,12 @@ class Server:
         self.max_inflight = 0
         self.errors: List[str] = []
         self.keep_results = keep_results
+        self.pinned_inputs = pinned_inputs
         self.gen_workers = gen_workers
         self.host = Admission(host_budget_bytes)
         self.feeder_late = 0.0
+        self.plan_s = 0.0       # summed over workers: plan creation (contrast, tables)
+        self.solve_s = 0.0      # and the solves
 
     # ---- footprint -----------------------------------------------------------
     def footprint(self, reqs: List[Request]) -> int:
@@ -252,17 +265,29 @@ class Server:
                 with torch.cuda.stream(stream):
                     r = sel[0]
                     plan = self.cache.get(r.key)
+                    t_plan = time.perf_counter()
                     if plan is None:
                         # worker threads allocate and synchronise while others
                         # solve, which stream capture would forbid
                         plan = vie.Plan(r.kind, r.coef, omega=r.omega, mu=r.mu, precision=self.precision,
                                         max_rhs=self.max_batch, stream=stream, graphs=False)
-                    inc = np.concatenate([q.inc for q in sel])
+                        stream.synchronize()
+                    t_solve = time.perf_counter()
+                    if len(sel) == 1:
+                        inc = sel[0].inc
+                    elif isinstance(sel[0].inc, torch.Tensor):
+                        inc = torch.cat([q.inc for q in sel])
+                    else:
+                        inc = np.concatenate([q.inc for q in sel])
                     dens, _, stats, rc = plan.solve(inc, tol=min(q.tol for q in sel), restart=self.restart,
                                                     want_field=False, stream=stream)
                     dens = dens.cpu().numpy() if self.keep_results else None
                     stream.synchronize()
+                    t_end = time.perf_counter()
                     self.cache.put(r.key, plan)
+                    with self.rlock:
+                        self.plan_s += t_solve - t_plan
+                        self.solve_s += t_end - t_solve
                 done = self.now()
                 off = 0
                 with self.rlock:
@@ -306,7 +331,7 @@ class Server:
                     self.host.lock.wait(timeout=0.05)
                 self.host.take(b)
             r.host_bytes = b
-            futures[j] = pool.submit(r.materialise)
+            futures[j] = pool.submit(lambda r=r: r.materialise().pin() if self.pinned_inputs else r.materialise())
             return True
 
         self.t0 = time.perf_counter()
@@ -352,6 +377,7 @@ class Server:
                 "max_inflight": self.max_inflight, "peak_admitted_GB": self.admission.peak / 1e9,
                 "budget_GB": self.admission.budget / 1e9, "plan_cache_hits": self.cache.hits,
                 "host_peak_GB": self.host.peak / 1e9, "feeder_late_max_s": self.feeder_late,
+                "worker_plan_s": self.plan_s, "worker_solve_s": self.solve_s,
                 "errors": self.errors[:5]}
 
 
@@ -382,6 +408,7 @@ def main(argv=None):
     ap.add_argument("--budget-gb", type=float, default=0.0)
     ap.add_argument("--host-budget-gb", type=float, default=32.0, help="host memory for generated inputs")
     ap.add_argument("--gen-workers", type=int, default=8, help="threads generating the stream's inputs")
+    ap.add_argument("--pageable", action="store_true", help="keep the generated inputs in pageable memory")
     args = ap.parse_args(argv)
     grids = tuple(int(g) for g in args.grids.split(","))
     t = time.perf_counter()
@@ -389,7 +416,7 @@ def main(argv=None):
     print(f"[serve] generated {len(reqs)} requests in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     srv = Server(int(args.budget_gb * 1e9) if args.budget_gb > 0 else None, workers=args.workers,
                  keep_results=False, gen_workers=args.gen_workers,
-                 host_budget_bytes=int(args.host_budget_gb * 1e9))
+                 host_budget_bytes=int(args.host_budget_gb * 1e9), pinned_inputs=not args.pageable)
     res = srv.run(lambda: reqs)
     out = srv.summary(res)
     out.update({"rate": args.rate, "grids": list(grids), "workers": args.workers})
