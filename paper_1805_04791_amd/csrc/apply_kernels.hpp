@@ -218,12 +218,14 @@ __host__ __device__ inline long xinv_blocks(const XArgs& a) {
 // box [bz][by][bx], or only the support samples of each row (a.rows),
 // J and out stored as TV (complex128, or complex64 for the FP32 Krylov basis
 // of the mixed solver), B as complex128; H, Hmu [9][n^3] on the whole grid.
-template <typename R, int P1, int P2, int C, int MODE, typename TV = c128>
+// TO: storage of out (TV by default; complex64 for the FP32 apply's output
+// in the mixed solver, which carries FP32 values only).
+template <typename R, int P1, int P2, int C, int MODE, typename TV = c128, typename TO = TV>
 __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R>* __restrict__ A, XArgs a, const TV* __restrict__ Jv,
                                                const c128* __restrict__ Bv, const cx<R>* __restrict__ H,
-                                               const cx<R>* __restrict__ Hmu, TV* __restrict__ out,
+                                               const cx<R>* __restrict__ Hmu, TO* __restrict__ out,
                                                const cx<R>* __restrict__ twg) {
-  using S = decltype(TV::re);
+  using S = decltype(TO::re);
   constexpr int P = P1 * P2;
   constexpr int J = P1 > P2 ? P1 : P2;
   static_assert(P1 % 2 == 0, "the cropped inverse assumes bx <= P/2 with P1 even");

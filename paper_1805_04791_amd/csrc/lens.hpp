@@ -83,6 +83,9 @@ struct LenOps {
   hipError_t (*contig_fwd_v32)(MemLoad<c64>, MemStore<cx<R>>, Geo, long ngroups, const cx<R>*, hipStream_t) = nullptr;
   hipError_t (*xinv_v32)(int C, const cx<R>*, XArgs, const c64*, const cx<R>*, const cx<R>*, c64*, const cx<R>*,
                          hipStream_t) = nullptr;
+  // the FP32 matvec reading complex128 vectors and writing complex64 (float only, MODE_MATVEC)
+  hipError_t (*xinv_w32)(int C, const cx<R>*, XArgs, const c128*, const cx<R>*, const cx<R>*, c64*, const cx<R>*,
+                         hipStream_t) = nullptr;
   // precompute: inverse x pass of length M fed by the symbol (double only)
   hipError_t (*symbol_inv)(SymbolSrc, MemStore<c128>, Geo, long ngroups, const c128*, hipStream_t) = nullptr;
 };
@@ -136,6 +139,17 @@ struct LenImpl {
       k_xinv<R, P1, P2, 3, MODE_MATVEC, c64><<<dim3(unsigned(blocks)), dim3(a.T * J), pass_lds_bytes<R, P1, P2, true>(a.T), s>>>(A, a, J_, nullptr, H, Hmu, out, tw);
     else if (C == 6)
       k_xinv<R, P1, P2, 6, MODE_MATVEC, c64><<<dim3(unsigned(blocks)), dim3(a.T * J), pass_lds_bytes<R, P1, P2, true>(a.T), s>>>(A, a, J_, nullptr, H, Hmu, out, tw);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  static hipError_t xinv_w32(int C, const cx<R>* A, XArgs a, const c128* J_, const cx<R>* H, const cx<R>* Hmu,
+                             c64* out, const cx<R>* tw, hipStream_t s) {
+    const long blocks = xinv_blocks(a);
+    if (C == 3)
+      k_xinv<R, P1, P2, 3, MODE_MATVEC, c128, c64><<<dim3(unsigned(blocks)), dim3(a.T * J), pass_lds_bytes<R, P1, P2, true>(a.T), s>>>(A, a, J_, nullptr, H, Hmu, out, tw);
+    else if (C == 6)
+      k_xinv<R, P1, P2, 6, MODE_MATVEC, c128, c64><<<dim3(unsigned(blocks)), dim3(a.T * J), pass_lds_bytes<R, P1, P2, true>(a.T), s>>>(A, a, J_, nullptr, H, Hmu, out, tw);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
@@ -231,6 +245,7 @@ struct LenImpl {
       if constexpr (std::is_same<R, float>::value) {
         o.contig_fwd_v32 = &contig_fwd_v32;
         o.xinv_v32 = &xinv_v32;
+        o.xinv_w32 = &xinv_w32;
       }
     }
     if constexpr (SYMBOL && std::is_same<R, double>::value) o.symbol_inv = &symbol_inv;

@@ -299,8 +299,10 @@ hipError_t pass_yinv(const ApplyCall<R>& c, int T, hipStream_t s) {
   return c.ops->strided(true, src, dst, g, long(c.nb) * pl->C * c.g.bz, c.tw, s);
 }
 
-template <typename R, typename TV>
-hipError_t pass_xinv(const ApplyCall<R>& c, const TV* addv, const c128* bvec, TV* out, int mode, int T,
+// TV: storage of J (the input), TO: of the output (complex64 output from
+// complex128 input: the FP32 matvec of the mixed solver)
+template <typename R, typename TV, typename TO = TV>
+hipError_t pass_xinv(const ApplyCall<R>& c, const TV* addv, const c128* bvec, TO* out, int mode, int T,
                      hipStream_t s) {
   const vie_plan* pl = c.pl;
   const long NN = long(c.g.bz) * c.g.by;
@@ -316,8 +318,11 @@ hipError_t pass_xinv(const ApplyCall<R>& c, const TV* addv, const c128* bvec, TV
     H = pl->H64;
     Hmu = pl->Hmu64;
   }
-  if constexpr (std::is_same<TV, c128>::value) {
+  if constexpr (std::is_same<TV, c128>::value && std::is_same<TO, c128>::value) {
     return c.ops->xinv(pl->C, mode, c.A, a, addv, bvec, H, Hmu, out, c.tw, s);
+  } else if constexpr (std::is_same<TV, c128>::value) {
+    if (mode != MODE_MATVEC || !c.ops->xinv_w32) return hipErrorInvalidValue;
+    return c.ops->xinv_w32(pl->C, c.A, a, addv, H, Hmu, out, c.tw, s);
   } else {
     if (mode != MODE_MATVEC) return hipErrorInvalidValue;
     return c.ops->xinv_v32(pl->C, c.A, a, addv, H, Hmu, out, c.tw, s);
@@ -377,8 +382,8 @@ int pick_tile(vie_plan* pl, int P1, int P2, bool contig, int maxthreads, int col
 
 int tune_key(int nb, const Geom& g) { return bucket_of(nb) + (g.id << 20) + ((g.mul + 1) << 24); }
 
-template <typename R, typename TV>
-int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStream_t s, Tune* t) {
+template <typename R, typename TV, typename TO = TV>
+int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStream_t s, Tune* t) {
   const int idx = std::is_same<R, double>::value ? 1 : 0;
   const int key = tune_key(c.nb, c.g);
   auto it = pl->tune[idx].find(key);
@@ -428,9 +433,10 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStre
     rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, P, [&](int T) { return pass_yinv<R>(c, T, s); }, s, &d.ty_inv);
     if (rc) return rc;
     // the raw convolution for complex128 vectors (any J), the matvec for complex64
-    const int xmode = std::is_same<TV, c128>::value ? MODE_CONV : MODE_MATVEC;
+    const int xmode = std::is_same<TV, c128>::value && std::is_same<TO, c128>::value ? MODE_CONV : MODE_MATVEC;
     rc = pick_tile<R>(pl, P1, P2, true, fmax, P,
-                      [&](int T) { return pass_xinv<R, TV>(c, in, nullptr, out, xmode, T, s); }, s, &d.tx_inv);
+                      [&](int T) { return pass_xinv<R, TV, TO>(c, in, nullptr, out, xmode, T, s); }, s,
+                      &d.tx_inv);
     if (rc) return rc;
   }
   d.tuned = true;
@@ -444,8 +450,8 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TV* out, hipStre
 
 // act (device, optional): per right-hand side, 0 = skip it (its output is
 // left as it was); nact = the number of non-zero flags, for the byte counts
-template <typename R, typename TV>
-int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, const c128* bvec, TV* out,
+template <typename R, typename TV, typename TO = TV>
+int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, const c128* bvec, TO* out,
                 int nrhs, int mode, hipStream_t s, const int* act = nullptr, int nact = -1) {
   const Spec& sp = *geom.sp;
   const LenOps<R>* ops = len_ops<R>(sp.Pxy);
@@ -454,6 +460,8 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     return fail(pl, VIE_E_SIZE, "no compiled FFT lengths " + std::to_string(sp.Pxy) + ", " + std::to_string(sp.Pz));
   if (!std::is_same<TV, c128>::value && (!ops->contig_fwd_v32 || !ops->xinv_v32))
     return fail(pl, VIE_E_STATE, "complex64 vectors need the FP32 apply");
+  if (!std::is_same<TO, TV>::value && (!ops->xinv_w32 || mode != MODE_MATVEC))
+    return fail(pl, VIE_E_STATE, "complex64 output needs the FP32 matvec");
   const int idx = std::is_same<R, double>::value ? 1 : 0;
   const int chunk = std::max(1, std::min(nrhs, pl->max_rhs));
   int rc = ensure_workspace<R>(pl, chunk);
@@ -477,20 +485,20 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
                    nb,  geom};
     const long off = long(r0) * L;
     const TV* inr = in + off;
-    TV* outr = out + off;
+    TO* outr = out + off;
     Tune t;
-    rc = get_tune<R, TV>(pl, c, inr, outr, s, &t);
+    rc = get_tune<R, TV, TO>(pl, c, inr, outr, s, &t);
     if (rc) return rc;
     c.act = act ? act + r0 : nullptr;
     const int nrun = (act && nact >= 0 && nrhs <= chunk) ? nact : nb;  // right-hand sides computed
     const int f0 = std::is_same<R, double>::value ? FAM_XFWD64 : FAM_XFWD32;
     // algorithmic bytes: every operand read or written once per launch
-    const double cr = double(sizeof(cx<R>)), c16 = double(sizeof(TV));
+    const double cr = double(sizeof(cx<R>)), c16 = double(sizeof(TV)), co = double(sizeof(TO));
     const double vN3 = double(nrun) * pl->C * double(geom.np);
     const double vN2P = double(nrun) * pl->C * geom.bz * geom.by * sp.Pxy, vNP2 = vN2P / geom.by * sp.Pxy;
     const double hb = 9.0 * double(geom.np) * cr * (pl->full ? 2 : 1);
     const double xinv_b = vN2P * cr + hb * (mode == MODE_MATVEC || mode == MODE_RESIDUAL) +
-                          vN3 * c16 * (1 + (mode != MODE_CONV)) + vN3 * sizeof(c128) * (mode == MODE_RESIDUAL);
+                          vN3 * (co + c16 * (mode != MODE_CONV)) + vN3 * sizeof(c128) * (mode == MODE_RESIDUAL);
     // nominal flops: 5 P log2 P per transformed pencil of length P; 66 per
     // frequency point for the 3x3 multiply (216 for the 6x6 Maxwell block);
     // 72 per point and 3-component half for the combine
@@ -514,7 +522,8 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     HIPCHK(pl, pass_yinv<R>(c, t.ty_inv, s));
     prof_end(pl, f0 + 3, tok, s, (vN2P + vNP2) * cr, rows_y * fft_row);
     tok = prof_begin(pl, s);
-    HIPCHK(pl, (pass_xinv<R, TV>(c, addv ? addv + off : inr, bvec ? bvec + off : nullptr, outr, mode, t.tx_inv, s)));
+    HIPCHK(pl, (pass_xinv<R, TV, TO>(c, addv ? addv + off : inr, bvec ? bvec + off : nullptr, outr, mode, t.tx_inv,
+                                     s)));
     prof_end(pl, f0 + 4, tok, s, xinv_b, rows_x * fft_row + comb_f);
   }
   return VIE_OK;
@@ -642,6 +651,15 @@ int apply_any(vie_plan* pl, const Geom& g, const c64* in, c64* out, int nrhs, hi
   return apply_typed<float, c64>(pl, g, in, in, nullptr, out, nrhs, MODE_MATVEC, s);
 }
 
+int apply_any(vie_plan* pl, const Geom& g, const c128* in, c64* out, int nrhs, hipStream_t s, const int* act,
+              int nact) {
+  if (g.sp == &pl->sg) {
+    const int rc = ensure_grid_spec(pl, s);
+    if (rc) return rc;
+  }
+  return apply_typed<float, c128, c64>(pl, g, in, in, nullptr, out, nrhs, MODE_MATVEC, s, act, nact);
+}
+
 void clear_graphs(vie_plan* pl) {
   for (auto& kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
   pl->graphs.clear();
@@ -694,9 +712,17 @@ int graph_or_eager(vie_plan* pl, const Geom& g, bool fp64, int nrhs, const vie_p
 
 int apply_graph(vie_plan* pl, const Geom& g, bool fp64, const c128* in, const c128* addv, const c128* bvec,
                 c128* out, int nrhs, int mode, hipStream_t s, const int* act, int nact) {
-  const vie_plan::GraphKey key{fp64 ? 1 : 0, mode, nrhs, g.id, in, addv, bvec, out, act};
+  const vie_plan::GraphKey key{fp64 ? 1 : 0, mode, nrhs, g.id, in, addv, bvec, out, act, 0};
   return graph_or_eager(pl, g, fp64, nrhs, key, s, [&](hipStream_t st) {
     return apply_any(pl, g, fp64, in, addv, bvec, out, nrhs, mode, st, act, nact);
+  });
+}
+
+int apply_graph(vie_plan* pl, const Geom& g, const c128* in, c64* out, int nrhs, hipStream_t s, const int* act,
+                int nact) {
+  const vie_plan::GraphKey key{0, MODE_MATVEC, nrhs, g.id, in, in, nullptr, out, act, 1};
+  return graph_or_eager(pl, g, false, nrhs, key, s, [&](hipStream_t st) {
+    return apply_any(pl, g, in, out, nrhs, st, act, nact);
   });
 }
 

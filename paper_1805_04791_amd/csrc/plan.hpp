@@ -110,9 +110,10 @@ struct vie_plan {
   struct GraphKey {
     int fp64, mode, nb, geom;
     const void *in, *addv, *bvec, *out, *act;
+    int out64;  // 1: the output is stored as complex64
     bool operator<(const GraphKey& o) const {
-      return std::tie(fp64, mode, nb, geom, in, addv, bvec, out, act) <
-             std::tie(o.fp64, o.mode, o.nb, o.geom, o.in, o.addv, o.bvec, o.out, o.act);
+      return std::tie(fp64, mode, nb, geom, in, addv, bvec, out, act, out64) <
+             std::tie(o.fp64, o.mode, o.nb, o.geom, o.in, o.addv, o.bvec, o.out, o.act, o.out64);
     }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -178,6 +179,12 @@ int ensure_grid_spec(vie_plan* pl, hipStream_t s);
 int ensure_div_spec(vie_plan* pl, hipStream_t s);
 // FP32 matvec y = A x with x, y stored as complex64
 int apply_any(vie_plan* pl, const Geom& g, const c64* in, c64* out, int nrhs, hipStream_t s);
+// FP32 matvec with x stored as complex128 and y as complex64 (the values are
+// FP32 results either way), eager or from a captured graph
+int apply_any(vie_plan* pl, const Geom& g, const c128* in, c64* out, int nrhs, hipStream_t s, const int* act,
+              int nact);
+int apply_graph(vie_plan* pl, const Geom& g, const c128* in, c64* out, int nrhs, hipStream_t s,
+                const int* act = nullptr, int nact = -1);
 void clear_graphs(vie_plan* pl);
 
 // kernel families timed by vie_profile

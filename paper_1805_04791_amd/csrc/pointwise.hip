@@ -466,6 +466,8 @@ hipError_t launch_dots(const TV* V, long vstride, long rstride, const TW* w, lon
 }
 template hipError_t launch_dots<c128, c128>(const c128*, long, long, const c128*, long, int, int, int, c128*,
                                             hipStream_t, const int*);
+template hipError_t launch_dots<c128, c64>(const c128*, long, long, const c64*, long, int, int, int, c128*,
+                                           hipStream_t, const int*);
 
 
 hipError_t launch_reduce(const c128* partials, int nrhs, int nblk, int nv1, c128* out, hipStream_t s,
@@ -487,6 +489,8 @@ hipError_t launch_combine(const TV* V, long vstride, long rstride, const TW* w, 
   template hipError_t launch_combine<TV, TW, TO>(const TV*, long, long, const TW*, TO*, long, int, const c128*, \
                                                  const double*, int, hipStream_t, const int*);
 VIE_COMBINE_INST(c128, c128, c128)
+VIE_COMBINE_INST(c128, c64, c128)
+VIE_COMBINE_INST(c128, c64, c64)
 #undef VIE_COMBINE_INST
 
 hipError_t launch_set_flags(const unsigned long long (&words)[4], int nb, int* out, hipStream_t s) {

@@ -252,6 +252,10 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
   vie_plan* pl = b.pl;
   c128* basis = pl->V;
   c128* wv = pl->ww;
+  // FP32 inner cycles: w = A v_j holds FP32 values and is stored as complex64
+  // (half the traffic of its write, of the multi-dot and of the combine)
+  c64* wv32 = reinterpret_cast<c64*>(pl->ww);
+  const bool w32 = !fp64;
   const int nb = b.nb;
   std::vector<bool> active = active_in;
   std::vector<int> jend(static_cast<size_t>(nb), 0);
@@ -288,10 +292,11 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
     int nact = 0;
     const int* act = set_active(b, active, &nact, &rc);
     if (rc) return rc;
-    rc = apply_graph(pl, pl->box, fp64, Vj, Vj, nullptr, wv, nb, MODE_MATVEC, b.s, act, nact);
+    rc = w32 ? apply_graph(pl, pl->box, Vj, wv32, nb, b.s, act, nact)
+             : apply_graph(pl, pl->box, fp64, Vj, Vj, nullptr, wv, nb, MODE_MATVEC, b.s, act, nact);
     if (rc) return rc;
     const int nv = j + 1;
-    rc = dots_host(b, basis, wv, nv, act, nact);
+    rc = w32 ? dots_host(b, basis, wv32, nv, act, nact) : dots_host(b, basis, wv, nv, act, nact);
     if (rc) return rc;
     cnt = counts_of(active, nv);
     bool any_reorth = false;
@@ -314,9 +319,10 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
       for (int i = 0; i < nv; ++i) hcol[zu(r) * zu(nv + 1) + zu(i)] = h1[zu(r) * zu(nv) + zu(i)];
     if (any_reorth) {
       std::vector<double> one(static_cast<size_t>(nb), 1.0);
-      rc = combine_host(b, basis, wv, wv, nv, h1, one, &cnt);  // w <- w - V h1
+      // w <- w - V h1
+      rc = w32 ? combine_host(b, basis, wv32, wv32, nv, h1, one, &cnt) : combine_host(b, basis, wv, wv, nv, h1, one, &cnt);
       if (rc) return rc;
-      rc = dots_host(b, basis, wv, nv, act, nact);
+      rc = w32 ? dots_host(b, basis, wv32, nv, act, nact) : dots_host(b, basis, wv, nv, act, nact);
       if (rc) return rc;
       for (int r = 0; r < nb; ++r) {
         double beta2;
@@ -336,7 +342,8 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
         hcol[zu(r) * zu(nv + 1) + zu(nv)] = beta;
         scale[zu(r)] = (active[zu(r)] && beta > 1e-300) ? 1.0 / beta : 0.0;
       }
-      rc = combine_host(b, basis, wv, Vn, nv, coef2, scale, &cnt);
+      rc = w32 ? combine_host(b, basis, wv32, Vn, nv, coef2, scale, &cnt)
+               : combine_host(b, basis, wv, Vn, nv, coef2, scale, &cnt);
       if (rc) return rc;
     } else {
       for (int r = 0; r < nb; ++r) {
@@ -344,7 +351,7 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
         hcol[zu(r) * zu(nv + 1) + zu(nv)] = beta;
         scale[zu(r)] = (active[zu(r)] && beta > 1e-300) ? 1.0 / beta : 0.0;
       }
-      rc = combine_host(b, basis, wv, Vn, nv, h1, scale, &cnt);
+      rc = w32 ? combine_host(b, basis, wv32, Vn, nv, h1, scale, &cnt) : combine_host(b, basis, wv, Vn, nv, h1, scale, &cnt);
       if (rc) return rc;
     }
     // Givens update per active slot
