@@ -35,7 +35,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MI355X_HBM_PEAK_GBS = 8000.0
-# Vector ALU peak reachable by this build: 256 CUs x 4 SIMDs x 16 lanes x
+# Vector ALU peak reachable by this library: 256 CUs x 4 SIMDs x 16 lanes x
 # 2 flops (FMA) x 2.4 GHz.  FP64 and FP32 alike: the published 157.3 TFLOP/s
 # FP32 figure counts packed (two-per-lane) FP32 instructions, which the
 # library is compiled without.
@@ -118,7 +118,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: this library has no multi-GPU path "
               "(right-hand sides and requests would shard across GPUs with no exchange).",
               file=sys.stderr)
         return 2
