@@ -74,14 +74,19 @@ class Request:
     def release(self):
         self.coef = self.inc = self.mu = None
 
-    def pin(self):
+    def pin(self) -> bool:
         """Move the generated inputs to pinned host memory (torch tensors), so
-        that the worker's copies to the device run at full link speed."""
+        that the worker's copies to the device run at full link speed.  When
+        pinned memory is exhausted the inputs stay pageable (returns False)."""
         import torch
         conv = lambda a: a if a is None or isinstance(a, torch.Tensor) else torch.from_numpy(
             np.ascontiguousarray(a)).pin_memory()
-        self.coef, self.mu, self.inc = conv(self.coef), conv(self.mu), conv(self.inc)
-        return self
+        try:
+            coef, mu, inc = conv(self.coef), conv(self.mu), conv(self.inc)
+        except RuntimeError:
+            return False
+        self.coef, self.mu, self.inc = coef, mu, inc
+        return True
 
     def materialise(self):
         if self.coef is None and self.make is not None:
@@ -201,6 +206,7 @@ class Server:
         self.errors: List[str] = []
         self.keep_results = keep_results
         self.pinned_inputs = pinned_inputs
+        self.pin_fallbacks = 0
         self.gen_workers = gen_workers
         self.host = Admission(host_budget_bytes)
         self.feeder_late = 0.0
@@ -308,6 +314,13 @@ class Server:
                     self.inflight -= 1
                     self.qlock.notify_all()
 
+    def _prepare(self, r: Request):
+        r.materialise()
+        if self.pinned_inputs and not r.pin():
+            with self.rlock:
+                self.pin_fallbacks += 1
+        return r
+
     def run(self, stream_of: Callable[[], List[Request]], realtime: bool = True) -> List[Result]:
         """Feed the requests at their arrival times (or all at once) and serve them.
 
@@ -331,7 +344,7 @@ class Server:
                     self.host.lock.wait(timeout=0.05)
                 self.host.take(b)
             r.host_bytes = b
-            futures[j] = pool.submit(lambda r=r: r.materialise().pin() if self.pinned_inputs else r.materialise())
+            futures[j] = pool.submit(self._prepare, r)
             return True
 
         self.t0 = time.perf_counter()
@@ -378,6 +391,7 @@ class Server:
                 "budget_GB": self.admission.budget / 1e9, "plan_cache_hits": self.cache.hits,
                 "host_peak_GB": self.host.peak / 1e9, "feeder_late_max_s": self.feeder_late,
                 "worker_plan_s": self.plan_s, "worker_solve_s": self.solve_s,
+                "pinned_fallbacks": self.pin_fallbacks,
                 "errors": self.errors[:5]}
 
 
@@ -406,7 +420,7 @@ def main(argv=None):
     ap.add_argument("--max-rhs", type=int, default=16)
     ap.add_argument("--workers", type=int, default=3)
     ap.add_argument("--budget-gb", type=float, default=0.0)
-    ap.add_argument("--host-budget-gb", type=float, default=32.0, help="host memory for generated inputs")
+    ap.add_argument("--host-budget-gb", type=float, default=24.0, help="host memory for generated inputs")
     ap.add_argument("--gen-workers", type=int, default=8, help="threads generating the stream's inputs")
     ap.add_argument("--pageable", action="store_true", help="keep the generated inputs in pageable memory")
     args = ap.parse_args(argv)

@@ -155,24 +155,26 @@ def rot2(phi):
 
 
 def _rotated_field(X, Y, diag: np.ndarray) -> np.ndarray:
-    """R(x) diag R(x)^T with R(x) = R2(pi x) R1(pi y), as [3][3][n][n][n]."""
-    R = np.einsum("ab...,bc...->ac...", rot2(np.pi * X), rot1(np.pi * Y))
+    """R(x) diag R(x)^T with R(x) = R2(pi x) R1(pi y), as [3][3][1][n][n]:
+    it depends on (x, y) only, so it is formed on one z plane and broadcast."""
+    X2, Y2 = X[:1], Y[:1]
+    R = np.einsum("ab...,bc...->ac...", rot2(np.pi * X2), rot1(np.pi * Y2))
     return np.einsum("ab...,b,cb...->ac...", R, diag, R)
 
 
-def maxwell_medium(n: int, rng: np.random.Generator):
+def maxwell_medium(n: int, rng: np.random.Generator, with_mu: bool = True):
     """eps = I + b R (D_eps + 0.05i) R^T, mu = I + b R (D_mu + 0.02i) R^T.
 
     R(x) = R2(pi x) R1(pi y) (the rotation field of the paper's dense medium).
     Draw order: D_eps (3 uniforms in [0, 1]), D_mu (3 uniforms in [0, 0.5]).
-    Returns (eps, mu).
+    Returns (eps, mu) (mu None without with_mu; the draws are the same).
     """
     d_eps = rng.uniform(0.0, 1.0, 3)
     d_mu = rng.uniform(0.0, 0.5, 3)
     X, Y, Z = grid_coords(n)
     b = bump(X, Y, Z)
     eps = tensor_field(1.0, b, _rotated_field(X, Y, d_eps + 0.05j))
-    mu = tensor_field(1.0, b, _rotated_field(X, Y, d_mu + 0.02j))
+    mu = tensor_field(1.0, b, _rotated_field(X, Y, d_mu + 0.02j)) if with_mu else None
     return eps, mu
 
 
@@ -222,21 +224,37 @@ def constant_field(n: int, E0) -> np.ndarray:
     return out
 
 
+def plane_phase(n: int, omega: float, d: np.ndarray, origin: float = -1.0, h: Optional[float] = None):
+    """exp(i omega d.x) on the grid, [n][n][n] (z, y, x), as the product of its
+    three one-dimensional factors."""
+    t = grid_axis(n, origin, h)
+    ex, ey, ez = (np.exp(1j * omega * d[a] * t) for a in range(3))
+    return ez[:, None, None] * ey[None, :, None] * ex[None, None, :]
+
+
 def plane_wave_gradient(n: int, omega: float, d: np.ndarray, origin: float = -1.0,
-                        h: Optional[float] = None) -> np.ndarray:
-    """grad of phi_inc = exp(i omega d.x): i omega d exp(i omega d.x), as [3][n][n][n]."""
-    X, Y, Z = grid_coords(n, origin, h)
-    ph = np.exp(1j * omega * (d[0] * X + d[1] * Y + d[2] * Z))
-    return np.ascontiguousarray(np.stack([1j * omega * d[a] * ph for a in range(3)]))
+                        h: Optional[float] = None, out: Optional[np.ndarray] = None) -> np.ndarray:
+    """grad of phi_inc = exp(i omega d.x): i omega d exp(i omega d.x), as [3][n][n][n]
+    (written into `out` when given)."""
+    ph = plane_phase(n, omega, d, origin, h)
+    if out is None:
+        out = np.empty((3, n, n, n), dtype=np.complex128)
+    for a in range(3):
+        np.multiply(ph, 1j * omega * d[a], out=out[a])
+    return out
 
 
 def plane_wave_em(n: int, omega: float, d: np.ndarray, p: np.ndarray, origin: float = -1.0,
-                  h: Optional[float] = None) -> np.ndarray:
-    """[E_inc; H_inc] = [p; d x p] exp(i omega d.x) as [6][n][n][n] (free-space, eps = mu = 1)."""
-    X, Y, Z = grid_coords(n, origin, h)
-    ph = np.exp(1j * omega * (d[0] * X + d[1] * Y + d[2] * Z))
+                  h: Optional[float] = None, with_h: bool = True) -> np.ndarray:
+    """[E_inc; H_inc] = [p; d x p] exp(i omega d.x) as [6][n][n][n] (free-space,
+    eps = mu = 1); [3][n][n][n] (E only) without with_h."""
+    ph = plane_phase(n, omega, d, origin, h)
     q = np.cross(d, p)
-    return np.ascontiguousarray(np.stack([p[a] * ph for a in range(3)] + [q[a] * ph for a in range(3)]))
+    coefs = list(p) + (list(q) if with_h else [])
+    out = np.empty((len(coefs), n, n, n), dtype=np.complex128)
+    for a, c in enumerate(coefs):
+        np.multiply(ph, c, out=out[a])
+    return out
 
 
 def random_polarisation(rng: np.random.Generator, d: np.ndarray) -> np.ndarray:
@@ -405,23 +423,23 @@ def serving_problem(req: dict) -> Problem:
     """
     rng = rng_for(CONFIG_IDS["serving"], req["item"])
     n, kind, omega, nrhs = req["n"], req["kind"], req["omega"], req["nrhs"]
+    inc = np.empty((nrhs, 3, n, n, n), dtype=np.complex128)
     if kind == KIND_LAPLACE:
         coef = laplace_medium(n, rng)
-        incs = []
-        for _ in range(nrhs):
+        for r in range(nrhs):
             E0 = random_unit(rng)
-            incs.append(constant_field(n, E0))
-        mu = None
+            for a in range(3):
+                inc[r, a] = E0[a]
     elif kind == KIND_HELMHOLTZ:
         coef = helmholtz_medium(n, rng)
-        incs = [plane_wave_gradient(n, omega, random_unit(rng)) for _ in range(nrhs)]
-        mu = None
+        for r in range(nrhs):
+            plane_wave_gradient(n, omega, random_unit(rng), out=inc[r])
     else:
-        coef, _ = maxwell_medium(n, rng)
-        incs = []
-        for _ in range(nrhs):
+        coef, _ = maxwell_medium(n, rng, with_mu=False)
+        for r in range(nrhs):
             d = random_unit(rng)
             p = random_polarisation(rng, d)
-            incs.append(plane_wave_em(n, omega, d, p)[:3])
-        mu = None
-    return Problem(kind, n, omega, coef, mu, np.stack(incs), 1e-8, f"req{req['id']}", 2.0 / n)
+            ph = plane_phase(n, omega, d)
+            for a in range(3):
+                np.multiply(ph, p[a], out=inc[r, a])
+    return Problem(kind, n, omega, coef, None, inc, 1e-8, f"req{req['id']}", 2.0 / n)
