@@ -203,7 +203,7 @@ int vie_destroy(vie_plan *pl);
 int vie_plan_info(const vie_plan *pl, double *out, int nout);
 
 /* Copies the FP64 kernel-transform tables into host memory:
- * complex128 [n+1][n+1][ne][nxp] (z, y, entry, x-octant index padded to nxp),
+ * complex128 [n+1][n+1][nxp][ne] (z, y, x-octant index padded to nxp, entry),
  * the transform of the windowed kernel on the 2n grid at frequencies
  * q in [0, n]^3, scaled by (2n)^-3 (curl entries also by i omega).
  * host_bytes must be at least the size reported in *needed. */

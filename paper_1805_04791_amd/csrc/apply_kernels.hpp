@@ -15,7 +15,10 @@
 //             (eq. represent_Maxwell_reduced).
 // The tables hold one octant q in [0, n]^3 of the 2n-periodic transform; the
 // other octants follow from the parity of each entry (odd in s_a for the
-// off-diagonal entries ab and for curl component a).
+// off-diagonal entries ab and for curl component a).  Layout
+// [qz][qy][qx < nxp][entry]: the entries of one frequency point are adjacent,
+// so a thread reads them with a few wide loads (three 16-byte loads for the
+// six FP32 entries of MUL_SYM3).
 //
 // Pointwise combine (eqs. intLap, contractionK with the derived sign,
 // contraction_Maxwell_reduced, intM):
@@ -56,8 +59,18 @@ struct ZArgs {
 // the slice is re-read from that XCD's L2.  Requires (pxy / T) * pxy % 8 == 0.
 // TT > 0: the tile width a.T == TT is known at compile time, so every LDS
 // offset of the exchanges is an instruction immediate.
+// Minimum waves per SIMD the register allocation of k_zpass must allow: the
+// FP64 three-component pass needs a little over 256 registers when left
+// alone, which allows one wave; held to 256 (a few bytes of spill) it runs
+// two and is faster.
+template <typename R, int C>
+constexpr int zpass_min_waves() {
+  return (sizeof(R) == 8 && C == 3) ? 2 : 1;
+}
+
 template <typename R, int P1, int P2, int C, int MUL, int TT = 0>
-__global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* buf, const cx<R>* __restrict__ tab, ZArgs a,
+__global__ void __launch_bounds__((fused_max_threads<R, C>()))
+__attribute__((amdgpu_waves_per_eu(zpass_min_waves<R, C>()))) k_zpass(cx<R>* buf, const cx<R>* __restrict__ tab, ZArgs a,
                                                             const cx<R>* __restrict__ twg) {
   constexpr int P = P1 * P2;
   constexpr int J = P1 > P2 ? P1 : P2;
@@ -116,8 +129,8 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
   });
 
   if (j < P1 && valid) {
-    // table geometry follows from P: octant [0, N]^3, rows of NXP (N + 1
-    // padded to 16) per entry, NE entries per (qz, qy)
+    // table geometry follows from P: octant [0, N]^3, (qz, qy) rows of NXP
+    // (N + 1 padded to 16) points of NE adjacent entries
     constexpr int N = P / 2;
     constexpr int NXP = ((N + 1 + 15) / 16) * 16;
     constexpr int NE = mul_entries(MUL);
@@ -129,7 +142,7 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
     const R sy = ky > Nxy ? R(-1) : R(1);
     const R sx = kx > Nxy ? R(-1) : R(1);
     const R sxy = sx * sy;
-    const cx<R>* tb = tab + (fy * ROW + fx);  // offsets below 2^31 elements
+    const cx<R>* tb = tab + (fy * ROW + fx * NE);  // offsets below 2^31 elements
     static_for<0, P2>([&](auto k2) {
       // kz = j + P1 k2 < N exactly when k2 < P2 / 2.  The entries odd in s_z
       // vanish on the plane kz = N, so taking the folded side there is exact.
@@ -139,7 +152,7 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
       const int fz = upper ? P - kz : kz;
       const cx<R>* t = tb + fz * ((N + 1) * ROW);
       if constexpr (MUL == MUL_DIV || MUL == MUL_CURLH) {
-        const cx<R> dx = sx * t[0], dy = sy * t[NXP], dz = sz * t[2 * NXP];
+        const cx<R> dx = sx * t[0], dy = sy * t[1], dz = sz * t[2];
         const cx<R> x0 = X[0][k2], x1 = X[1][k2], x2 = X[2][k2];
         if constexpr (MUL == MUL_DIV) {
           X[0][k2] = dx * x0 + dy * x1 + dz * x2;
@@ -153,17 +166,17 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_zpass(cx<R>* bu
           X[2][k2] = {w * w2.im, -w * w2.re};
         }
       } else {
-        const cx<R> kxx = t[0], kyy = t[NXP], kzz = t[2 * NXP];
-        const cx<R> kxy = sxy * t[3 * NXP];
-        const cx<R> kxz = (sx * sz) * t[4 * NXP];
-        const cx<R> kyz = (sy * sz) * t[5 * NXP];
+        const cx<R> kxx = t[0], kyy = t[1], kzz = t[2];
+        const cx<R> kxy = sxy * t[3];
+        const cx<R> kxz = (sx * sz) * t[4];
+        const cx<R> kyz = (sy * sz) * t[5];
         if constexpr (MUL == MUL_SYM3) {
           const cx<R> x0 = X[0][k2], x1 = X[1][k2], x2 = X[2][k2];
           X[0][k2] = kxx * x0 + kxy * x1 + kxz * x2;
           X[1][k2] = kxy * x0 + kyy * x1 + kyz * x2;
           X[2][k2] = kxz * x0 + kyz * x1 + kzz * x2;
         } else {
-          const cx<R> cxv = sx * t[6 * NXP], cyv = sy * t[7 * NXP], czv = sz * t[8 * NXP];
+          const cx<R> cxv = sx * t[6], cyv = sy * t[7], czv = sz * t[8];
           const cx<R> j0 = X[0][k2], j1 = X[1][k2], j2 = X[2][k2];
           const cx<R> m0 = X[3][k2], m1 = X[4][k2], m2 = X[5][k2];
           // c x m and c x j

@@ -396,10 +396,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const c128* __restrict__ bu
   const double sc = 1.0 / (double(Q) * double(Q) * double(Z));
   const long V = long(Z) * Q * Q;
   for (long t = long(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
-    const int qx = int(t % nxp);
-    long r = t / nxp;
-    const int e = int(r % ne);
-    r /= ne;
+    // layout [qz][qy][qx < nxp][e]: the entries of one frequency point adjacent
+    const int e = int(t % ne);
+    long r = t / ne;
+    const int qx = int(r % nxp);
+    r /= nxp;
     const int qy = int(r % n1);
     const int qz = int(r / n1);
     c128 v = {0.0, 0.0};

@@ -297,7 +297,8 @@ class Plan:
         return d
 
     def tables(self) -> np.ndarray:
-        """FP64 octant tables as complex128 [n+1][n+1][ne][nxp]."""
+        """FP64 octant tables as complex128 [n+1][n+1][ne][nxp] (a transposed
+        view of the library's [n+1][n+1][nxp][ne])."""
         need = ctypes.c_long()
         nxp = ctypes.c_int()
         ne = ctypes.c_int()
@@ -307,7 +308,7 @@ class Plan:
         self._check(self.lib.vie_copy_tables(self._h, arr.ctypes.data, need.value, None, None, None),
                     "vie_copy_tables")
         n1 = self.n + 1
-        return arr.reshape(n1, n1, ne.value, nxp.value)
+        return arr.reshape(n1, n1, nxp.value, ne.value).transpose(0, 1, 3, 2)
 
     def contrast(self) -> np.ndarray:
         k = 2 if self.ncomp == 6 else 1
