@@ -51,14 +51,9 @@ struct ZArgs {
   int pxy;          // x and y transform length (<= P): columns (ky, kx) in [0, pxy)^2
   double omega;     // MUL_CURLH: the factor -i omega
   const int* act = nullptr;  // optional: right-hand side r is skipped when act[r] == 0
+  int pair_ky = 0;  // 1: slices ky and pxy - ky of a tile back to back on one XCD (needs (pxy/2) ntiles % 8 == 0)
 };
 
-// Block order: blocks are dealt round-robin to the 8 XCDs (block b runs on
-// XCD b % 8).  The nb right-hand sides of one (ky, kx-tile) slice read the
-// same table slice, so they are given consecutive launch slots on one XCD and
-// the slice is re-read from that XCD's L2.  Requires (pxy / T) * pxy % 8 == 0.
-// TT > 0: the tile width a.T == TT is known at compile time, so every LDS
-// offset of the exchanges is an instruction immediate.
 // Minimum waves per SIMD the register allocation of k_zpass must allow: the
 // FP64 three-component pass needs a little over 256 registers when left
 // alone, which allows one wave; held to 256 (a few bytes of spill) it runs
@@ -68,6 +63,16 @@ constexpr int zpass_min_waves() {
   return (sizeof(R) == 8 && C == 3) ? 2 : 1;
 }
 
+// Block order: blocks are dealt round-robin to the 8 XCDs (block b runs on
+// XCD b % 8).  The nb right-hand sides of one (ky, kx-tile) slice read the
+// same table slice, so they are given consecutive launch slots on one XCD and
+// the slice is re-read from that XCD's L2.  Requires (pxy / T) * pxy % 8 == 0.
+// With pair_ky the slices (ky, tile) and (pxy - ky, tile), which read the
+// same folded table rows, follow each other on one XCD (ky = 0 is paired
+// with ky = pxy / 2): slice s of XCD-order is member s % 16 / 8 of pair
+// (s / 16) * 8 + s % 8.
+// TT > 0: the tile width a.T == TT is known at compile time, so every LDS
+// offset of the exchanges is an instruction immediate.
 template <typename R, int P1, int P2, int C, int MUL, int TT = 0>
 __global__ void __launch_bounds__((fused_max_threads<R, C>()))
 __attribute__((amdgpu_waves_per_eu(zpass_min_waves<R, C>()))) k_zpass(cx<R>* buf, const cx<R>* __restrict__ tab, ZArgs a,
@@ -91,8 +96,17 @@ __attribute__((amdgpu_waves_per_eu(zpass_min_waves<R, C>()))) k_zpass(cx<R>* buf
   Layout<false>::lane(threadIdx.x, T, J, col, j);
   const long slice = long(k / unsigned(a.nb)) * 8 + xcd;
   const long rhs = long(k % unsigned(a.nb));
-  const int tile = int(slice % a.ntiles);
-  const int ky = int(slice / a.ntiles);
+  int tile, ky;
+  if (a.pair_ky) {
+    const int within = int(slice % 16);
+    const long pair = (slice / 16) * 8 + within % 8;
+    const int pk = int(pair / a.ntiles);
+    tile = int(pair % a.ntiles);
+    ky = within < 8 ? pk : (pk == 0 ? a.pxy / 2 : a.pxy - pk);
+  } else {
+    tile = int(slice % a.ntiles);
+    ky = int(slice / a.ntiles);
+  }
   const int kx = tile * T + col;
   const bool valid = kx < a.pxy;
   const long PP = long(a.pxy) * a.pxy;

@@ -284,6 +284,7 @@ hipError_t pass_z(const ApplyCall<R>& c, const cx<R>* tab, int T, hipStream_t s)
   ZArgs a{T,      int(ntiles), int(Pz / 2),           int(Pz), c.g.sp->nxp, c.g.sp->ne, bz * Q * Q,
           long(pl->C) * bz * Q * Q, c.nb, int(bz), int(Q), pl->omega, c.act};
   if (ntiles * Q % 8 != 0) return hipErrorInvalidValue;  // XCD block order: slices in groups of 8
+  a.pair_ky = (Q % 2 == 0 && (Q / 2) * ntiles % 8 == 0) ? 1 : 0;
   const long nblocks = ntiles * Q * c.nb;
   return c.opsz->zpass(geom_mul(pl, c.g), c.B, tab, a, nblocks, c.twz, s);
 }
