@@ -107,6 +107,8 @@ def main(argv=None):
     ap.add_argument("--nrhs", type=int, default=0, help="right-hand sides per batched step (0: the workload's)")
     ap.add_argument("--tol", type=float, default=0.0, help="true relative residual (0: the workload's)")
     ap.add_argument("--restart", type=int, default=40)
+    ap.add_argument("--inner-tol", type=float, default=0.0,
+                    help="relative residual reduction of each FP32 inner cycle (0: the library's, 1e-5)")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--latency-solves", type=int, default=20, help="single-RHS mixed solves for p50/p99")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -154,7 +156,8 @@ def main(argv=None):
           f"max||H||={plan.info()['max_contrast_norm']:.3f}", file=sys.stderr, flush=True)
 
     def solve(x_inc, fp64=primary_fp64):
-        return plan.solve(x_inc, tol=tol, restart=args.restart, fp64=fp64, want_field=False)
+        return plan.solve(x_inc, tol=tol, restart=args.restart, inner_tol=args.inner_tol, fp64=fp64,
+                          want_field=False)
 
     for _ in range(args.warmup):
         solve(inc)
