@@ -236,6 +236,32 @@ def test_short_box_transform_equals_full_length(vie, monkeypatch):
     full.close()
 
 
+def test_z_block_order_with_and_without_slice_pairing(vie, monkeypatch):
+    """The z pass runs the mirrored slices (ky, P - ky) of a column tile back
+    to back on one XCD when (P / 2) * tiles is a multiple of 8, and in plain
+    order otherwise.  At P = 120, z tiles of 16 (8 tiles) are paired, tiles of
+    8 (FP64) and 24 (FP32) are not; the solves agree."""
+    n = 64
+    coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 18)
+    inc = plane_waves(n, omega, 2, 40)
+    out = {}
+    for name, tiles64, tiles32 in (("paired", "8,8,16,8,8", "8,24,16,24,8"),
+                                   ("plain", "8,8,8,8,8", "8,24,24,24,8")):
+        monkeypatch.setenv("VIE_TILES_FP64", tiles64)
+        monkeypatch.setenv("VIE_TILES", tiles32)
+        plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2)
+        assert plan.info()["box_P"] == 120
+        out[name] = []
+        for fp64, tol in ((True, 1e-12), (False, 1e-10)):
+            d, _, st, rc = plan.solve(inc, tol=tol, fp64=fp64, want_field=False)
+            assert rc == 0
+            out[name].append(d.cpu().numpy())
+        plan.close()
+    for k, err in ((0, 1e-11), (1, 1e-9)):
+        for r in range(2):
+            assert rel(out["paired"][k][r], out["plain"][k][r]) < err
+
+
 def test_x0_outside_support_rows_is_ignored(vie):
     """A warm start is restricted to the support rows: values elsewhere
     cannot change the solution (the equation fixes J = 0 there)."""
