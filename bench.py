@@ -278,6 +278,19 @@ def main(argv=None):
     roof["copy_GBs"] = copy_gbs
     roof["hbm_frac_of_copy"] = roof["hbm_GBs"] / copy_gbs
 
+    # the whole FFT matvec of the timed solver (its five passes, in the
+    # precision the Krylov iteration applies): algorithmic bytes over time
+    suffix = "_fp64" if primary_fp64 else "_fp32"
+    passes = [v for k, v in prof.items() if k.startswith("fft_") and k.endswith(suffix)]
+    matvec = None
+    if passes:
+        mv_ms, mv_by = sum(v[0] for v in passes), sum(v[2] for v in passes)
+        mv_n = max(v[1] for v in passes)
+        matvec = {"precision": suffix[1:], "passes": len(passes), "us_per_apply": 1e3 * mv_ms / mv_n,
+                  "bytes_per_apply": mv_by / mv_n, "hbm_GBs": mv_by / (mv_ms * 1e-3) / 1e9}
+        matvec["frac_of_hbm_peak"] = matvec["hbm_GBs"] / MI355X_HBM_PEAK_GBS
+        matvec["frac_of_copy"] = matvec["hbm_GBs"] / copy_gbs
+
     cpu = None
     if not args.no_cpu_baseline:
         mv = (float(np.mean([s["matvecs_fp64"] for s in stats_all])) if primary_fp64 else
@@ -310,6 +323,7 @@ def main(argv=None):
         "max_rel_residual": float(max(s["rel_residual"] for s in stats_all)),
         **fp64,
         "roofline": roof,
+        "matvec": matvec,
         "postprocess_ms_per_batch": post,
         "kernels": breakdown,
         "cpu_baseline": cpu,
