@@ -228,7 +228,6 @@ struct XArgs {
   long np;          // points per component of the vectors
   const int* rows;  // support rows (xa, len, off) per (z, y) row, or null: dense box
   const int* act = nullptr;  // optional: rows of right-hand side r are skipped when act[r] == 0
-  const int* ywin = nullptr; // optional (with rows): rows outside [ywin[2 z], ywin[2 z + 1]) are not read
 };
 
 // Blocks of a k_xinv launch.  With xcd_order the ceil(bz by / T) row tiles of
@@ -287,17 +286,15 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
   const long rhs = valid ? row / NN : 0;
   const long zy = valid ? row % NN : 0;
   const long hrow = (long(a.z0) + zy / a.by) * N + (a.y0 + zy % a.by);  // (z, y) in the grid
-  // rows outside the y-interval of their plane have no support samples (no
-  // output) and were not written by the y inverse: not read
-  const bool inwin = valid && (!a.ywin || (int(zy % a.by) >= a.ywin[2 * (zy / a.by)] &&
-                                           int(zy % a.by) < a.ywin[2 * (zy / a.by) + 1]));
+  // a row without support samples has no output: its spectrum is not read
+  const bool need = valid && (!a.rows || a.rows[3 * zy + 1] > 0);
 
   // kUpfront: all spectral inputs of the row in flight at once
   constexpr int CU = kUpfront<R> ? C : 1;
   cx<R> X[CU][P2];
   auto load_comp = [&](int c, cx<R>(&dst)[P2]) {
     const cx<R>* src = A + ((rhs * C + c) * NN + zy) * P;
-    static_for<0, P2>([&](auto k2) { dst[k2] = (inwin && j < P1) ? src[j + P1 * k2] : czero<R>(); });
+    static_for<0, P2>([&](auto k2) { dst[k2] = (need && j < P1) ? src[j + P1 * k2] : czero<R>(); });
   };
   if constexpr (kUpfront<R>) static_for<0, C>([&](auto c) { load_comp(c, X[c]); });
   __syncthreads();

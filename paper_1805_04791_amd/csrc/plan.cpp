@@ -310,7 +310,6 @@ hipError_t pass_xinv(const ApplyCall<R>& c, const TV* addv, const c128* bvec, TO
   const int xcd = 1;  // tiles of all right-hand sides that share H run back to back on one XCD
   XArgs a{T,      long(c.nb) * NN, pl->n,  pl->n3, c.nb,   xcd,  c.g.bx,
           c.g.by, c.g.bz,          c.g.x0, c.g.y0, c.g.z0, c.g.np, c.g.rows, c.act};
-  a.ywin = c.g.ywin;
   const cx<R>* H;
   const cx<R>* Hmu;
   if constexpr (std::is_same<R, float>::value) {
@@ -498,9 +497,9 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     const double cr = double(sizeof(cx<R>)), c16 = double(sizeof(TV)), co = double(sizeof(TO));
     const double vN3 = double(nrun) * pl->C * double(geom.np);
     // rows of the x-transformed array: every (z, y) row of the box, of which
-    // the x inverse reads only those inside their plane's y window
+    // the x inverse reads only those holding support points
     const double vN2P = double(nrun) * pl->C * geom.bz * geom.by * sp.Pxy, vNP2 = vN2P / geom.by * sp.Pxy;
-    const double vN2Pw = geom.ywin ? double(nrun) * pl->C * double(geom.nwin) * sp.Pxy : vN2P;
+    const double vN2Pw = geom.rows ? double(nrun) * pl->C * double(geom.rows_nz) * sp.Pxy : vN2P;
     const double hb = 9.0 * double(geom.np) * cr * (pl->full ? 2 : 1);
     const double xinv_b = vN2Pw * cr + hb * (mode == MODE_MATVEC || mode == MODE_RESIDUAL) +
                           vN3 * (co + c16 * (mode != MODE_CONV)) + vN3 * sizeof(c128) * (mode == MODE_RESIDUAL);
@@ -835,32 +834,14 @@ int build_rows(vie_plan* pl, hipStream_t s) {
     h3[size_t(3 * r + 2)] = int(off);
     off += h2[size_t(2 * r + 1)];
   }
-  // per z plane, the y-interval of its non-empty rows
-  const int by = pl->box.by, bz = pl->box.bz;
-  std::vector<int> hw(size_t(2 * bz), 0);
-  long nwin = 0;
-  for (int z = 0; z < bz; ++z) {
-    int ya = -1, ye = -1;
-    for (int y = 0; y < by; ++y)
-      if (h2[size_t(2 * (long(z) * by + y) + 1)] > 0) {
-        if (ya < 0) ya = y;
-        ye = y + 1;
-      }
-    if (ya < 0) ya = ye = 0;
-    hw[size_t(2 * z)] = ya;
-    hw[size_t(2 * z + 1)] = ye;
-    nwin += ye - ya;
-  }
-  rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->ywin_d), sizeof(int) * hw.size());
-  if (rc) return rc;
+  long nonempty = 0;
+  for (long r = 0; r < nr; ++r) nonempty += h2[size_t(2 * r + 1)] > 0 ? 1 : 0;
   HIPCHK(pl, hipMemcpyAsync(pl->rows_d, h3.data(), sizeof(int) * h3.size(), hipMemcpyHostToDevice, s));
-  HIPCHK(pl, hipMemcpyAsync(pl->ywin_d, hw.data(), sizeof(int) * hw.size(), hipMemcpyHostToDevice, s));
   HIPCHK(pl, hipStreamSynchronize(s));
   dev_free(pl, xalen);
   pl->box.rows = pl->rows_d;
   pl->box.np = off;
-  pl->box.ywin = pl->ywin_d;
-  pl->box.nwin = nwin;
+  pl->box.rows_nz = nonempty;
   return VIE_OK;
 }
 

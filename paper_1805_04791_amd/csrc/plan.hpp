@@ -41,11 +41,7 @@ struct Geom {
   const int* rows = nullptr; // support rows (xa, len, off) per (z, y) row; null: dense box
   long np = 0;               // points per component of the vectors
   int mul = -1;              // spectral multiply (MUL_*); -1: the plan's operator
-  // with rows: per z of the box, [ya, ye) = the y-interval of the non-empty
-  // support rows (ya = ye when the plane has none); the rows outside it have
-  // no support samples, so the last inverse x pass does not read them
-  const int* ywin = nullptr;
-  long nwin = 0;             // sum over z of ye - ya
+  long rows_nz = 0;          // with rows: (z, y) rows holding at least one support point
 };
 inline Box box_of(const Geom& g, int n) { return Box{n, g.bx, g.by, g.bz, g.x0, g.y0, g.z0, g.rows, g.np}; }
 
@@ -71,7 +67,6 @@ struct vie_plan {
   vie::Geom grid, box;  // whole grid; the solver's: bounding box of supp(H) (and H_mu), support rows
   bool use_box = true;
   int* rows_d = nullptr;  // device (xa, len, off) per (z, y) row of the box
-  int* ywin_d = nullptr;  // device [ya, ye) per z of the box (Geom::ywin)
   hipStream_t last_stream = nullptr;  // stream of the latest call (synchronised by vie_destroy)
   int device = 0;
   size_t max_lds = 65536;
