@@ -178,10 +178,19 @@ int vie_field(vie_plan *pl, const double *density, const double *inc, double *fi
 int vie_solve(vie_plan *pl, const double *inc, double *density, double *field, int nrhs,
               const vie_solve_opts *opts, vie_solve_stats *stats, void *hip_stream);
 
-/* Synchronises the stream of the plan's latest call, then frees the plan and
- * all its device memory.  Work on other streams that uses the plan must have
- * completed.  vie_destroy(NULL) is a no-op. */
+/* Synchronises the stream of the plan's latest call, then frees the plan.
+ * Work on other streams that uses the plan must have completed.  Its device
+ * blocks (and small pinned host buffers) go to a process-wide cache from
+ * which later plans of about the same sizes take their memory (at most
+ * 48 GiB kept; a hipFree would wait for the whole device); an allocation
+ * that cannot be met frees the cache of its device and retries.
+ * vie_destroy(NULL) is a no-op. */
 int vie_destroy(vie_plan *pl);
+
+/* Frees the library's cache of released device blocks and pinned host
+ * buffers (e.g. before handing the memory to another allocator).  Returns the
+ * device bytes that were cached.  Thread-safe; plans in use are unaffected. */
+long vie_release_cached_memory(void);
 
 /* Introspection (host pointers).
  * vie_plan_info: out[0] = n, out[1] = components c, out[2] = P (= 2n),

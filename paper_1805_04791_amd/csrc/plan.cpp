@@ -47,15 +47,156 @@ std::recursive_mutex& hip_mutex() {
   return m;
 }
 
+// Device blocks released by plans are kept for reuse by later allocations of
+// about the same size: a hipFree waits for the whole device, which would
+// serialise plans created and destroyed while others compute (a serving
+// loop).  A block enters the cache only after the work queued on the
+// releasing plan's streams has completed.  All of this under hip_mutex().
+namespace {
+struct FreeBlock {
+  void* p;
+  size_t bytes;
+  int device;
+};
+std::vector<FreeBlock>& free_blocks() {
+  static std::vector<FreeBlock> v;
+  return v;
+}
+size_t g_cached_bytes = 0;
+constexpr size_t kCacheLimit = size_t(48) << 30;  // bytes kept for reuse at most
+std::vector<std::pair<void*, size_t>>& free_host_blocks() {
+  static std::vector<std::pair<void*, size_t>> v;
+  return v;
+}
+size_t g_cached_host_bytes = 0;
+constexpr size_t kHostCacheLimit = size_t(256) << 20;
+
+size_t round_block(size_t b) {
+  const size_t g = b < (size_t(64) << 20) ? (size_t(64) << 10) : (size_t(2) << 20);
+  return (b + g - 1) / g * g;
+}
+
+}  // namespace
+
+size_t cached_bytes() { return g_cached_bytes; }
+
+void release_all_cached() {
+  release_cached(-1);
+  for (auto& b : free_host_blocks()) (void)hipHostFree(b.first);
+  free_host_blocks().clear();
+  g_cached_host_bytes = 0;
+}
+
+int host_alloc(vie_plan* pl, void** p, size_t bytes) {
+  std::lock_guard<std::recursive_mutex> lk(hip_mutex());
+  *p = nullptr;
+  bytes = (std::max<size_t>(bytes, 1) + 4095) / 4096 * 4096;
+  auto& v = free_host_blocks();
+  long best = -1;
+  for (size_t i = 0; i < v.size(); ++i)
+    if (v[i].second >= bytes && v[i].second - bytes <= bytes / 4 &&
+        (best < 0 || v[i].second < v[size_t(best)].second))
+      best = long(i);
+  if (best >= 0) {
+    *p = v[size_t(best)].first;
+    bytes = v[size_t(best)].second;
+    g_cached_host_bytes -= bytes;
+    v.erase(v.begin() + best);
+  } else {
+    const hipError_t e = hipHostMalloc(p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return fail(pl, VIE_E_NOMEM, "hipHostMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  pl->host_allocs.push_back({*p, bytes});
+  return VIE_OK;
+}
+
+void host_free(vie_plan* pl, void* p) {
+  if (!p) return;
+  std::lock_guard<std::recursive_mutex> lk(hip_mutex());
+  for (size_t i = 0; i < pl->host_allocs.size(); ++i) {
+    if (pl->host_allocs[i].first == p) {
+      const size_t bytes = pl->host_allocs[i].second;
+      pl->host_allocs.erase(pl->host_allocs.begin() + long(i));
+      quiesce(pl);
+      if (g_cached_host_bytes + bytes > kHostCacheLimit) {
+        (void)hipHostFree(p);
+      } else {
+        free_host_blocks().push_back({p, bytes});
+        g_cached_host_bytes += bytes;
+      }
+      return;
+    }
+  }
+}
+
+// frees the cached blocks of `device` (all devices when device < 0)
+void release_cached(int device) {
+  auto& v = free_blocks();
+  for (size_t i = 0; i < v.size();) {
+    if (device < 0 || v[i].device == device) {
+      int cur = -1;
+      (void)hipGetDevice(&cur);
+      if (cur != v[i].device) (void)hipSetDevice(v[i].device);
+      (void)hipFree(v[i].p);
+      if (cur >= 0 && cur != v[i].device) (void)hipSetDevice(cur);
+      g_cached_bytes -= v[i].bytes;
+      v.erase(v.begin() + long(i));
+    } else {
+      ++i;
+    }
+  }
+}
+
+// a block no queued work uses any more: cached, or freed beyond the limit
+void give_block(void* p, size_t bytes, int device) {
+  if (g_cached_bytes + bytes > kCacheLimit) {
+    (void)hipFree(p);
+    return;
+  }
+  free_blocks().push_back({p, bytes, device});
+  g_cached_bytes += bytes;
+}
+
+// waits for the work the plan has queued (its latest stream and its graph stream)
+void quiesce(vie_plan* pl) {
+  (void)hipStreamSynchronize(pl->last_stream);
+  if (pl->gstream) (void)hipStreamSynchronize(pl->gstream);
+}
+
 int dev_alloc(vie_plan* pl, void** p, size_t bytes) {
   std::lock_guard<std::recursive_mutex> lk(hip_mutex());
   *p = nullptr;
   if (bytes == 0) bytes = 256;
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return fail(pl, VIE_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  bytes = round_block(bytes);
+  // the smallest cached block of this device that is at most 1.25x the request
+  auto& v = free_blocks();
+  long best = -1;
+  for (size_t i = 0; i < v.size(); ++i)
+    if (v[i].device == pl->device && v[i].bytes >= bytes && v[i].bytes - bytes <= bytes / 4 &&
+        (best < 0 || v[i].bytes < v[size_t(best)].bytes))
+      best = long(i);
+  if (best >= 0) {
+    *p = v[size_t(best)].p;
+    bytes = v[size_t(best)].bytes;
+    g_cached_bytes -= bytes;
+    v.erase(v.begin() + best);
+  } else {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      // give the cached blocks back and try once more
+      (void)hipGetLastError();
+      release_cached(pl->device);
+      e = hipMalloc(p, bytes);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return fail(pl, VIE_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
   }
   pl->allocs.push_back({*p, bytes});
   pl->dev_bytes += bytes;
@@ -67,12 +208,14 @@ void dev_free(vie_plan* pl, void* p) {
   std::lock_guard<std::recursive_mutex> lk(hip_mutex());
   for (size_t i = 0; i < pl->allocs.size(); ++i) {
     if (pl->allocs[i].first == p) {
-      pl->dev_bytes -= pl->allocs[i].second;
+      const size_t bytes = pl->allocs[i].second;
+      pl->dev_bytes -= bytes;
       pl->allocs.erase(pl->allocs.begin() + long(i));
-      break;
+      quiesce(pl);
+      give_block(p, bytes, pl->device);
+      return;
     }
   }
-  (void)hipFree(p);
 }
 
 static hipEvent_t take_event(vie_plan* pl) {
@@ -746,17 +889,18 @@ void destroy_plan(vie_plan* pl) {
   if (!pl) return;
   std::lock_guard<std::recursive_mutex> lk(hip_mutex());
   vie::clear_graphs(pl);
-  if (pl->gstream) (void)hipStreamSynchronize(pl->gstream);
+  quiesce(pl);
   if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
+  pl->gstream = nullptr;
   for (auto& r : pl->prof) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
   for (auto e : pl->ev_pool) (void)hipEventDestroy(e);
-  for (auto& a : pl->allocs) (void)hipFree(a.first);
+  for (auto& a : pl->allocs) give_block(a.first, a.second, pl->device);
   pl->allocs.clear();
-  if (pl->red_host) (void)hipHostFree(pl->red_host);
-  if (pl->stage_host) (void)hipHostFree(pl->stage_host);
+  host_free(pl, pl->red_host);
+  host_free(pl, pl->stage_host);
   delete pl;
 }
 
@@ -1019,6 +1163,13 @@ int vie_destroy(vie_plan* pl) {
   (void)hipStreamSynchronize(pl->last_stream);
   destroy_plan(pl);
   return VIE_OK;
+}
+
+long vie_release_cached_memory(void) {
+  std::lock_guard<std::recursive_mutex> lk(vie::hip_mutex());
+  const long bytes = long(vie::cached_bytes());
+  vie::release_all_cached();
+  return bytes;
 }
 
 int vie_apply(vie_plan* pl, const double* x, double* y, int nrhs, unsigned flags, void* hip_stream) {

@@ -105,6 +105,7 @@ struct vie_plan {
 
   size_t dev_bytes = 0;
   std::vector<std::pair<void*, size_t>> allocs;
+  std::vector<std::pair<void*, size_t>> host_allocs;  // pinned host blocks (host_alloc)
   std::string err;
 
   // captured applies: key (fp64, mode, nb, in, addv, bvec, out) -> graph
@@ -155,6 +156,16 @@ std::string& last_create_error();
 // allocation helpers (record bytes on the plan)
 int dev_alloc(vie_plan* pl, void** p, size_t bytes);
 void dev_free(vie_plan* pl, void* p);
+// the library's cache of released device blocks (callers hold hip_mutex())
+void quiesce(vie_plan* pl);
+void give_block(void* p, size_t bytes, int device);
+void release_cached(int device);
+void release_all_cached();
+size_t cached_bytes();
+// pinned host memory through a cache of the same kind (hipHostFree, too,
+// waits for the device)
+int host_alloc(vie_plan* pl, void** p, size_t bytes);
+void host_free(vie_plan* pl, void* p);
 int fail(vie_plan* pl, int code, const std::string& msg);
 int hip_fail(vie_plan* pl, hipError_t e, const char* what);
 

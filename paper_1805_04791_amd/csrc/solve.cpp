@@ -76,8 +76,8 @@ int ensure_krylov(vie_plan* pl, int cap, int m, hipStream_t s) {
   pl->stage_dev = nullptr;
   pl->actd = nullptr;
   pl->act_last.clear();
-  if (pl->red_host) (void)hipHostFree(pl->red_host);
-  if (pl->stage_host) (void)hipHostFree(pl->stage_host);
+  host_free(pl, pl->red_host);
+  host_free(pl, pl->stage_host);
   pl->red_host = nullptr;
   pl->stage_host = nullptr;
   pl->kr_cap = pl->kr_m = 0;
@@ -98,8 +98,9 @@ int ensure_krylov(vie_plan* pl, int cap, int m, hipStream_t s) {
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->stage_dev), 2 * pl->stage_bytes);
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->actd), sizeof(int) * zu(cap));
   if (rc) return rc;
-  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->red_host), sizeof(c128) * zu(cap) * zu(m + 2)));
-  HIPCHK(pl, hipHostMalloc(reinterpret_cast<void**>(&pl->stage_host), 2 * pl->stage_bytes));
+  rc = host_alloc(pl, reinterpret_cast<void**>(&pl->red_host), sizeof(c128) * zu(cap) * zu(m + 2));
+  if (!rc) rc = host_alloc(pl, reinterpret_cast<void**>(&pl->stage_host), 2 * pl->stage_bytes);
+  if (rc) return rc;
   pl->stage_epoch[0] = pl->stage_epoch[1] = -1;
   pl->kr_cap = cap;
   pl->kr_m = m;

@@ -15,10 +15,13 @@ The server
   merges their right-hand sides into one fused multi-RHS solve;
 * records arrival -> completion latency per request.
 
-The stream's inputs are generated on the host ahead of their arrival times
-by a thread pool (and placed in pinned memory), within a host-memory budget
-that also counts the inputs of requests still queued or on the device; when
-the budget is spent the feeder waits, and the wait shows in the latency
+The stream's inputs: by default each request's random draws are made on
+the host ahead of its arrival time and its arrays (medium, incident fields)
+are built on the device by the worker that serves it, on the worker's stream.
+With ``--inputs host`` the arrays themselves are generated on the host by a
+thread pool (and placed in pinned memory), within a host-memory budget that
+also counts the inputs of requests still queued or on the device; when the
+budget is spent the feeder waits, and the wait shows in the latency
 (measured from the nominal arrival time).
 
 Each right-hand side is solved with the same arithmetic whatever else runs
@@ -64,6 +67,8 @@ class Request:
     make: Optional[Callable] = None
     full: bool = False
     host_bytes: int = 0                     # input bytes charged to the host budget
+    recipe_fn: Optional[Callable] = None    # the request's random draws (device-side inputs)
+    recipe: Optional[dict] = None
 
     def input_bytes(self) -> int:
         """Host bytes of the request's inputs (estimated before they exist)."""
@@ -73,6 +78,7 @@ class Request:
 
     def release(self):
         self.coef = self.inc = self.mu = None
+        self.recipe = None
 
     def pin(self) -> bool:
         """Move the generated inputs to pinned host memory (torch tensors), so
@@ -99,6 +105,47 @@ class Request:
                 h.update(np.ascontiguousarray(self.mu).view(np.uint8))
             self.key = f"{self.kind}:{self.n}:{self.omega!r}:{h.hexdigest()[:16]}"
         return self
+
+
+def device_inputs(recipe: dict, device):
+    """The arrays of a serving recipe evaluated with torch on ``device``:
+    coef = I + bump(x) M as [9][n][n][n] and the incident fields
+    [nrhs][3][n][n][n], complex128, in the operation order of the host
+    generator (the exponentials may differ from NumPy's in the last bit)."""
+    import torch
+    n = recipe["n"]
+    f64, c128 = torch.float64, torch.complex128
+    t = torch.as_tensor(recipe["axis"], dtype=f64, device=device)
+    X, Y, Z = t.view(1, 1, n), t.view(1, n, 1), t.view(n, 1, 1)
+    radius = 0.8
+    q = (X * X + Y * Y + Z * Z) / (radius * radius)
+    inside = q < 1.0
+    qs = torch.where(inside, q, torch.zeros_like(q))
+    b = torch.where(inside, torch.exp(1.0 - 1.0 / (1.0 - qs)), torch.zeros_like(q))
+    M = torch.as_tensor(np.asarray(recipe["matrix"], dtype=np.complex128), device=device)
+    coef = torch.empty((3, 3, n, n, n), dtype=c128, device=device)
+    for a in range(3):
+        for c in range(3):
+            coef[a, c] = b * M[a, c]
+            if a == c:
+                coef[a, c] += 1.0
+    coef = coef.reshape(9, n, n, n)
+    nrhs = recipe["nrhs"]
+    inc = torch.empty((nrhs, 3, n, n, n), dtype=c128, device=device)
+    axis = np.asarray(recipe["axis"])
+    for r in range(nrhs):
+        w = recipe["waves"][r]
+        if recipe["phased"]:
+            d = recipe["dirs"][r]
+            ex, ey, ez = (torch.as_tensor(np.exp(1j * recipe["omega"] * d[k] * axis), device=device)
+                          for k in range(3))
+            ph = ez.view(n, 1, 1) * ey.view(1, n, 1) * ex.view(1, 1, n)
+            for a in range(3):
+                torch.mul(ph, complex(w[a]), out=inc[r, a])
+        else:
+            for a in range(3):
+                inc[r, a].fill_(complex(w[a]))
+    return coef, None, inc
 
 
 @dataclass
@@ -181,7 +228,7 @@ class Server:
     def __init__(self, budget_bytes: Optional[int] = None, workers: int = 3, restart: int = 20,
                  max_batch: int = 16, plan_cache: int = 4, precision: Optional[int] = None,
                  keep_results: bool = True, gen_workers: int = 8, host_budget_bytes: int = 32 * 10 ** 9,
-                 pinned_inputs: bool = False):
+                 pinned_inputs: bool = False, device_inputs: bool = True):
         import torch
         from . import vie
         self.vie = vie
@@ -207,6 +254,10 @@ class Server:
         self.keep_results = keep_results
         self.pinned_inputs = pinned_inputs
         self.pin_fallbacks = 0
+        # requests carrying a recipe are drawn on the host and built on the
+        # device by their worker (no host copy of the arrays)
+        self.device_inputs = device_inputs
+        self.device = torch.device("cuda")
         self.gen_workers = gen_workers
         self.host = Admission(host_budget_bytes)
         self.feeder_late = 0.0
@@ -269,6 +320,9 @@ class Server:
             admitted = self.now()
             try:
                 with torch.cuda.stream(stream):
+                    for q in sel:
+                        if q.coef is None and q.recipe is not None:
+                            q.coef, q.mu, q.inc = device_inputs(q.recipe, self.device)
                     r = sel[0]
                     plan = self.cache.get(r.key)
                     t_plan = time.perf_counter()
@@ -315,6 +369,9 @@ class Server:
                     self.qlock.notify_all()
 
     def _prepare(self, r: Request):
+        if self.device_inputs and r.recipe_fn is not None:
+            r.recipe = r.recipe_fn()
+            return r
         r.materialise()
         if self.pinned_inputs and not r.pin():
             with self.rlock:
@@ -336,7 +393,7 @@ class Server:
 
         def start(j: int, block: bool) -> bool:
             r = reqs[j]
-            b = r.input_bytes()
+            b = 0 if (self.device_inputs and r.recipe_fn is not None) else r.input_bytes()
             with self.host.lock:
                 while not self.host.fits(b):
                     if not block:
@@ -391,7 +448,7 @@ class Server:
                 "budget_GB": self.admission.budget / 1e9, "plan_cache_hits": self.cache.hits,
                 "host_peak_GB": self.host.peak / 1e9, "feeder_late_max_s": self.feeder_late,
                 "worker_plan_s": self.plan_s, "worker_solve_s": self.solve_s,
-                "pinned_fallbacks": self.pin_fallbacks,
+                "pinned_fallbacks": self.pin_fallbacks, "device_inputs": self.device_inputs,
                 "errors": self.errors[:5]}
 
 
@@ -408,7 +465,8 @@ def requests_from_generator(count: int, rate: float, grids=None, max_rhs: int = 
             p = gen.serving_problem(rq)
             return p.coef, p.mu, p.inc
         out.append(Request(rq["id"], rq["kind"], rq["n"], rq["omega"], rq["nrhs"], arrival=rq["arrival"],
-                           key=f"req{rq['item']}", make=make))
+                           key=f"req{rq['item']}", make=make,
+                           recipe_fn=lambda rq=rq: gen.serving_recipe(rq)))
     return out
 
 
@@ -423,6 +481,8 @@ def main(argv=None):
     ap.add_argument("--host-budget-gb", type=float, default=24.0, help="host memory for generated inputs")
     ap.add_argument("--gen-workers", type=int, default=8, help="threads generating the stream's inputs")
     ap.add_argument("--pageable", action="store_true", help="keep the generated inputs in pageable memory")
+    ap.add_argument("--inputs", choices=("device", "host"), default="device",
+                    help="build each request's arrays on the device from its random draws, or on the host")
     args = ap.parse_args(argv)
     grids = tuple(int(g) for g in args.grids.split(","))
     t = time.perf_counter()
@@ -430,7 +490,8 @@ def main(argv=None):
     print(f"[serve] generated {len(reqs)} requests in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     srv = Server(int(args.budget_gb * 1e9) if args.budget_gb > 0 else None, workers=args.workers,
                  keep_results=False, gen_workers=args.gen_workers,
-                 host_budget_bytes=int(args.host_budget_gb * 1e9), pinned_inputs=not args.pageable)
+                 host_budget_bytes=int(args.host_budget_gb * 1e9), pinned_inputs=not args.pageable,
+                 device_inputs=args.inputs == "device")
     res = srv.run(lambda: reqs)
     out = srv.summary(res)
     out.update({"rate": args.rate, "grids": list(grids), "workers": args.workers})

@@ -57,7 +57,8 @@ class SolveStats(ctypes.Structure):
 EXPORTS = ["vie_plan_create", "vie_apply", "vie_rhs", "vie_field", "vie_solve", "vie_destroy",
            "vie_plan_info", "vie_copy_tables", "vie_copy_contrast", "vie_status_string",
            "vie_last_error", "vie_supported_n", "vie_profile", "vie_profile_read", "vie_profile_family",
-           "vie_footprint_bytes", "vie_potential", "vie_field_h", "vie_fields_at", "vie_far_field"]
+           "vie_footprint_bytes", "vie_potential", "vie_field_h", "vie_fields_at", "vie_far_field",
+           "vie_release_cached_memory"]
 
 _lib = None
 
@@ -97,6 +98,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.vie_far_field.argtypes = [vp, vp, ci, vp, ci, vp, vp]
     L.vie_footprint_bytes.argtypes = [ci, ci, ci, ci, ci]
     L.vie_footprint_bytes.restype = ctypes.c_long
+    L.vie_release_cached_memory.argtypes = []
+    L.vie_release_cached_memory.restype = ctypes.c_long
     for name in ("vie_plan_create", "vie_apply", "vie_rhs", "vie_field", "vie_solve", "vie_destroy",
                  "vie_plan_info", "vie_copy_tables", "vie_copy_contrast", "vie_supported_n",
                  "vie_profile", "vie_profile_read", "vie_potential", "vie_field_h", "vie_fields_at",
@@ -104,6 +107,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         getattr(L, name).restype = ci
     _lib = L
     return L
+
+
+def release_cached_memory() -> int:
+    """Frees the library's cache of device blocks released by destroyed plans
+    (and of their pinned host buffers); returns the device bytes it held."""
+    return int(load_library().vie_release_cached_memory())
 
 
 def _torch():

@@ -122,7 +122,8 @@ def test_feeder_keeps_generated_inputs_within_the_host_budget():
 
 
 @pytest.mark.gpu
-def test_results_alone_equal_results_in_the_mix():
+@pytest.mark.parametrize("device_inputs", [True, False], ids=["device-inputs", "host-inputs"])
+def test_results_alone_equal_results_in_the_mix(device_inputs):
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -130,18 +131,20 @@ def test_results_alone_equal_results_in_the_mix():
     reqs = requests_from_generator(10, rate=1e6, grids=(16, 24, 32), max_rhs=4)
     # two requests share a medium (and so a plan) to exercise merged batches
     dup = requests_from_generator(1, rate=1e6, grids=(16, 24, 32), max_rhs=4)[0]
-    dup.id, dup.key, dup.make = 99, reqs[0].key, reqs[0].make
+    dup.id, dup.key, dup.make, dup.recipe_fn = 99, reqs[0].key, reqs[0].make, reqs[0].recipe_fn
     dup.kind, dup.n, dup.omega, dup.nrhs = reqs[0].kind, reqs[0].n, reqs[0].omega, reqs[0].nrhs
+
+    def fresh(r):
+        return Request(r.id, r.kind, r.n, r.omega, r.nrhs, key=r.key, make=r.make, recipe_fn=r.recipe_fn)
+
     alone = {}
     for r in reqs:
-        srv = Server(workers=1)
-        res = srv.run(lambda r=r: [Request(r.id, r.kind, r.n, r.omega, r.nrhs, key=r.key, make=r.make)],
-                      realtime=False)
+        srv = Server(workers=1, device_inputs=device_inputs)
+        res = srv.run(lambda r=r: [fresh(r)], realtime=False)
         assert not srv.errors, srv.errors
         alone[r.id] = res[0].density
-    srv = Server(workers=3)
-    mix = srv.run(lambda: [Request(r.id, r.kind, r.n, r.omega, r.nrhs, key=r.key, make=r.make)
-                           for r in reqs + [dup]], realtime=False)
+    srv = Server(workers=3, device_inputs=device_inputs)
+    mix = srv.run(lambda: [fresh(r) for r in reqs + [dup]], realtime=False)
     assert not srv.errors, srv.errors
     assert len(mix) == len(reqs) + 1
     for res in mix:
@@ -151,3 +154,20 @@ def test_results_alone_equal_results_in_the_mix():
         assert all(s["status"] == 0 and s["rel_residual"] <= 1e-9 for s in res.stats)
     s = srv.summary(mix)
     assert s["max_inflight"] >= 1 and s["rhs_converged"] == s["rhs_solved"]
+
+
+def test_device_recipe_matches_host_generator():
+    """The serving recipe evaluated with torch (on the CPU here) gives the host
+    generator's arrays, to the rounding of the exponentials, for every kind."""
+    torch = pytest.importorskip("torch")
+    from paper_1805_04791_amd.serving import device_inputs
+    from vie_inputs import generators as gen
+    kinds = set()
+    for rq in gen.serving_requests(12, 5.0, (16, 24), 3):
+        p = gen.serving_problem(rq)
+        coef, mu, inc = device_inputs(gen.serving_recipe(rq), torch.device("cpu"))
+        assert mu is None
+        assert np.abs(coef.numpy() - p.coef).max() <= 1e-14 * np.abs(p.coef).max()
+        assert np.abs(inc.numpy() - p.inc).max() <= 1e-14 * np.abs(p.inc).max()
+        kinds.add(rq["kind"])
+    assert kinds == {0, 1, 2}

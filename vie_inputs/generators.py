@@ -66,6 +66,13 @@ def grid_coords(n: int, origin: float = -1.0, h: Optional[float] = None):
     return X, Y, Z
 
 
+def grid_coords_plane(n: int, origin: float = -1.0, h: Optional[float] = None):
+    """X, Y, Z of the z = 0 plane, shape (1, n, n) indexed [z][y][x]."""
+    t = grid_axis(n, origin, h)
+    Z, Y, X = np.meshgrid(t[:1], t, t, indexing="ij")
+    return X, Y, Z
+
+
 def bump(X, Y, Z, radius: float = 0.8) -> np.ndarray:
     """C-infinity bump exp(1 - 1/(1 - |x|^2/radius^2)) inside the ball, 0 outside; b(0) = 1."""
     q = (X * X + Y * Y + Z * Z) / (radius * radius)
@@ -115,29 +122,34 @@ def identity_field(n: int) -> np.ndarray:
 # media recipes
 # ----------------------------------------------------------------------------
 
-def laplace_medium(n: int, rng: np.random.Generator) -> np.ndarray:
-    """eps(x) = I + b(x) A, A = Q diag(lam) Q^T, lam ~ U[0.5, 2].
-
-    Draw order: lam (3 uniforms), then Q (9 normals).
-    """
+def laplace_matrix(rng: np.random.Generator) -> np.ndarray:
+    """A = Q diag(lam) Q^T, lam ~ U[0.5, 2]; draw order: lam (3 uniforms), then Q (9 normals)."""
     lam = rng.uniform(0.5, 2.0, 3)
     q = random_rotation(rng)
-    A = q @ np.diag(lam) @ q.T
+    return (q @ np.diag(lam) @ q.T).astype(np.complex128)
+
+
+def laplace_medium(n: int, rng: np.random.Generator) -> np.ndarray:
+    """eps(x) = I + b(x) A with A from ``laplace_matrix``."""
+    A = laplace_matrix(rng)
     X, Y, Z = grid_coords(n)
-    return tensor_field(1.0, bump(X, Y, Z), A.astype(np.complex128))
+    return tensor_field(1.0, bump(X, Y, Z), A)
+
+
+def helmholtz_matrix(rng: np.random.Generator, norm: float = 0.5, loss: float = 0.05) -> np.ndarray:
+    """A + i*loss*I, A = norm * S/||S||_2, S = sym(G), G standard normal; draw order: G (9 normals)."""
+    g = rng.standard_normal((3, 3))
+    s = 0.5 * (g + g.T)
+    A = norm * s / np.max(np.abs(np.linalg.eigvalsh(s)))
+    return A + 1j * loss * np.eye(3)
 
 
 def helmholtz_medium(n: int, rng: np.random.Generator, norm: float = 0.5,
                      loss: float = 0.05) -> np.ndarray:
-    """eps^{-1}(x) = I + b(x) (A + i*loss*I), A = norm * S/||S||_2, S = sym(G), G standard normal.
-
-    Draw order: G (9 normals).
-    """
-    g = rng.standard_normal((3, 3))
-    s = 0.5 * (g + g.T)
-    A = norm * s / np.max(np.abs(np.linalg.eigvalsh(s)))
+    """eps^{-1}(x) = I + b(x) M with M from ``helmholtz_matrix``."""
+    M = helmholtz_matrix(rng, norm, loss)
     X, Y, Z = grid_coords(n)
-    return tensor_field(1.0, bump(X, Y, Z), A + 1j * loss * np.eye(3))
+    return tensor_field(1.0, bump(X, Y, Z), M)
 
 
 def rot1(theta):
@@ -414,6 +426,47 @@ def serving_requests(count: int = 2000, rate: float = 10.0, grids=SERVING_GRIDS,
     return reqs
 
 
+def serving_recipe(req: dict) -> dict:
+    """The random draws of one serving request, in the order ``serving_problem``
+    makes them, and the small factors its arrays are built from:
+
+    * ``matrix``: [3][3] (Laplace, Helmholtz) or [3][3][1][n][n] (Maxwell,
+      R(x, y) diag R^T on one z plane), so that coef = I + bump(x) * matrix;
+    * ``waves``: per right-hand side the three components' constant factors,
+      multiplied by the separable phase exp(i omega d.x) (``phased``) or not
+      (Laplace: constant fields);
+    * ``dirs``: the directions d of the phases.
+    """
+    rng = rng_for(CONFIG_IDS["serving"], req["item"])
+    n, kind, omega, nrhs = req["n"], req["kind"], req["omega"], req["nrhs"]
+    out = {"kind": kind, "n": n, "omega": omega, "nrhs": nrhs, "axis": grid_axis(n)}
+    waves, dirs = [], []
+    if kind == KIND_LAPLACE:
+        out["matrix"] = laplace_matrix(rng)
+        for r in range(nrhs):
+            waves.append(random_unit(rng))
+        out["phased"] = False
+    elif kind == KIND_HELMHOLTZ:
+        out["matrix"] = helmholtz_matrix(rng)
+        for r in range(nrhs):
+            d = random_unit(rng)
+            dirs.append(d)
+            waves.append(1j * omega * d)
+        out["phased"] = True
+    else:
+        d_eps = rng.uniform(0.0, 1.0, 3)
+        rng.uniform(0.0, 0.5, 3)  # D_mu, drawn and unused (mu = I)
+        X, Y, _ = grid_coords_plane(n)
+        out["matrix"] = _rotated_field(X, Y, d_eps + 0.05j)
+        for r in range(nrhs):
+            d = random_unit(rng)
+            dirs.append(d)
+            waves.append(random_polarisation(rng, d))
+        out["phased"] = True
+    out["waves"], out["dirs"] = waves, dirs
+    return out
+
+
 def serving_problem(req: dict) -> Problem:
     """Materialise the medium and right-hand sides of one serving request.
 
@@ -421,25 +474,18 @@ def serving_problem(req: dict) -> Problem:
     Helmholtz and Maxwell configurations; Maxwell with mu = I).  Then per
     right-hand side: a direction (and polarisation for Maxwell).
     """
-    rng = rng_for(CONFIG_IDS["serving"], req["item"])
-    n, kind, omega, nrhs = req["n"], req["kind"], req["omega"], req["nrhs"]
+    rc = serving_recipe(req)
+    n, kind, omega, nrhs = rc["n"], rc["kind"], rc["omega"], rc["nrhs"]
+    X, Y, Z = grid_coords(n)
+    coef = tensor_field(1.0, bump(X, Y, Z), rc["matrix"])
     inc = np.empty((nrhs, 3, n, n, n), dtype=np.complex128)
-    if kind == KIND_LAPLACE:
-        coef = laplace_medium(n, rng)
-        for r in range(nrhs):
-            E0 = random_unit(rng)
+    for r in range(nrhs):
+        w = rc["waves"][r]
+        if rc["phased"]:
+            ph = plane_phase(n, omega, rc["dirs"][r])
             for a in range(3):
-                inc[r, a] = E0[a]
-    elif kind == KIND_HELMHOLTZ:
-        coef = helmholtz_medium(n, rng)
-        for r in range(nrhs):
-            plane_wave_gradient(n, omega, random_unit(rng), out=inc[r])
-    else:
-        coef, _ = maxwell_medium(n, rng, with_mu=False)
-        for r in range(nrhs):
-            d = random_unit(rng)
-            p = random_polarisation(rng, d)
-            ph = plane_phase(n, omega, d)
+                np.multiply(ph, w[a], out=inc[r, a])
+        else:
             for a in range(3):
-                np.multiply(ph, p[a], out=inc[r, a])
+                inc[r, a] = w[a]
     return Problem(kind, n, omega, coef, None, inc, 1e-8, f"req{req['id']}", 2.0 / n)
