@@ -228,7 +228,7 @@ class Server:
     def __init__(self, budget_bytes: Optional[int] = None, workers: int = 3, restart: int = 20,
                  max_batch: int = 16, plan_cache: int = 4, precision: Optional[int] = None,
                  keep_results: bool = True, gen_workers: int = 8, host_budget_bytes: int = 32 * 10 ** 9,
-                 pinned_inputs: bool = False, device_inputs: bool = True):
+                 pinned_inputs: bool = False, device_inputs: bool = True, progress: int = 0):
         import torch
         from . import vie
         self.vie = vie
@@ -257,6 +257,7 @@ class Server:
         # requests carrying a recipe are drawn on the host and built on the
         # device by their worker (no host copy of the arrays)
         self.device_inputs = device_inputs
+        self.progress = progress  # a line on stderr every `progress` finished requests (0: none)
         self.device = torch.device("cuda")
         self.gen_workers = gen_workers
         self.host = Admission(host_budget_bytes)
@@ -357,6 +358,9 @@ class Server:
                                                    stats[off:off + k], q.arrival, admitted, done,
                                                    [o.id for o in sel if o.id != q.id]))
                         off += k
+                        if self.progress and len(self.results) % self.progress == 0:
+                            print(f"[serve] {len(self.results)} requests done at {done:.1f} s", file=sys.stderr,
+                                  flush=True)
             except Exception as exc:  # keep serving; report at the end
                 self.errors.append(f"request {sel[0].id}: {exc}")
             finally:
@@ -491,7 +495,7 @@ def main(argv=None):
     srv = Server(int(args.budget_gb * 1e9) if args.budget_gb > 0 else None, workers=args.workers,
                  keep_results=False, gen_workers=args.gen_workers,
                  host_budget_bytes=int(args.host_budget_gb * 1e9), pinned_inputs=not args.pageable,
-                 device_inputs=args.inputs == "device")
+                 device_inputs=args.inputs == "device", progress=100)
     res = srv.run(lambda: reqs)
     out = srv.summary(res)
     out.update({"rate": args.rate, "grids": list(grids), "workers": args.workers})
