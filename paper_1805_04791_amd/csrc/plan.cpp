@@ -114,6 +114,16 @@ int host_alloc(vie_plan* pl, void** p, size_t bytes) {
   return VIE_OK;
 }
 
+// a pinned block no queued work uses any more: cached, or freed beyond the limit
+void give_host_block(void* p, size_t bytes) {
+  if (g_cached_host_bytes + bytes > kHostCacheLimit) {
+    (void)hipHostFree(p);
+    return;
+  }
+  free_host_blocks().push_back({p, bytes});
+  g_cached_host_bytes += bytes;
+}
+
 void host_free(vie_plan* pl, void* p) {
   if (!p) return;
   std::lock_guard<std::recursive_mutex> lk(hip_mutex());
@@ -122,12 +132,7 @@ void host_free(vie_plan* pl, void* p) {
       const size_t bytes = pl->host_allocs[i].second;
       pl->host_allocs.erase(pl->host_allocs.begin() + long(i));
       quiesce(pl);
-      if (g_cached_host_bytes + bytes > kHostCacheLimit) {
-        (void)hipHostFree(p);
-      } else {
-        free_host_blocks().push_back({p, bytes});
-        g_cached_host_bytes += bytes;
-      }
+      give_host_block(p, bytes);
       return;
     }
   }
@@ -887,9 +892,12 @@ bool n_supported(int n) {
 
 void destroy_plan(vie_plan* pl) {
   if (!pl) return;
+  // wait for the plan's own work before taking the library lock: the stream
+  // may be another thread's, still busy, and the lock would stall every
+  // allocation meanwhile
+  quiesce(pl);
   std::lock_guard<std::recursive_mutex> lk(hip_mutex());
   vie::clear_graphs(pl);
-  quiesce(pl);
   if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
   pl->gstream = nullptr;
   for (auto& r : pl->prof) {
@@ -899,8 +907,8 @@ void destroy_plan(vie_plan* pl) {
   for (auto e : pl->ev_pool) (void)hipEventDestroy(e);
   for (auto& a : pl->allocs) give_block(a.first, a.second, pl->device);
   pl->allocs.clear();
-  host_free(pl, pl->red_host);
-  host_free(pl, pl->stage_host);
+  for (auto& a : pl->host_allocs) give_host_block(a.first, a.second);
+  pl->host_allocs.clear();
   delete pl;
 }
 
@@ -1160,8 +1168,7 @@ int vie_plan_create(const vie_problem* p, void* hip_stream, vie_plan** out) {
 
 int vie_destroy(vie_plan* pl) {
   if (!pl) return VIE_OK;
-  (void)hipStreamSynchronize(pl->last_stream);
-  destroy_plan(pl);
+  destroy_plan(pl);  // synchronises the plan's latest stream first
   return VIE_OK;
 }
 

@@ -166,6 +166,7 @@ size_t cached_bytes();
 // waits for the device)
 int host_alloc(vie_plan* pl, void** p, size_t bytes);
 void host_free(vie_plan* pl, void* p);
+void give_host_block(void* p, size_t bytes);
 int fail(vie_plan* pl, int code, const std::string& msg);
 int hip_fail(vie_plan* pl, hipError_t e, const char* what);
 
