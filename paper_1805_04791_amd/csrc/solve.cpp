@@ -243,7 +243,10 @@ int norms(const Batch& b, const c128* v, std::vector<double>& out, const int* ac
 
 // One GMRES(m) cycle on A d = r (r in rw, x += d in xw).  target[r]: absolute
 // residual at which slot r stops; active[r]: slot takes part; budget[r]:
-// matvecs it may still spend.
+// matvecs it may still spend.  A slot's update x += V y is made in the
+// iteration where it stops (target, breakdown, budget or the cycle's last),
+// in place of the basis vector it would not use, so the basis is read once
+// less per cycle.
 // The basis stays complex128 in the FP32 inner cycles too: rounding it to
 // complex64 acts as a unit roundoff of 6e-8 in the classical Gram-Schmidt
 // bound above, and orthogonality is gone once the residual has dropped by
@@ -259,7 +262,6 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
   const bool w32 = !fp64;
   const int nb = b.nb;
   std::vector<bool> active = active_in;
-  std::vector<int> jend(static_cast<size_t>(nb), 0);
   std::vector<double> scale(static_cast<size_t>(nb));
   std::vector<cd> none;
   // V_0 = r / ||r||
@@ -343,19 +345,16 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
         hcol[zu(r) * zu(nv + 1) + zu(nv)] = beta;
         scale[zu(r)] = (active[zu(r)] && beta > 1e-300) ? 1.0 / beta : 0.0;
       }
-      rc = w32 ? combine_host(b, basis, wv32, Vn, nv, coef2, scale, &cnt)
-               : combine_host(b, basis, wv, Vn, nv, coef2, scale, &cnt);
-      if (rc) return rc;
     } else {
       for (int r = 0; r < nb; ++r) {
         const double beta = std::sqrt(std::max(wp2[zu(r)], 0.0));
         hcol[zu(r) * zu(nv + 1) + zu(nv)] = beta;
         scale[zu(r)] = (active[zu(r)] && beta > 1e-300) ? 1.0 / beta : 0.0;
       }
-      rc = w32 ? combine_host(b, basis, wv32, Vn, nv, h1, scale, &cnt) : combine_host(b, basis, wv, Vn, nv, h1, scale, &cnt);
-      if (rc) return rc;
     }
-    // Givens update per active slot
+    // Givens update per active slot: it needs only the new Hessenberg column,
+    // so whether the slot stops here is known before V_{j+1} is formed
+    std::vector<bool> finish(static_cast<size_t>(nb), false);
     for (int r = 0; r < nb; ++r) {
       if (!active[zu(r)]) continue;
       RhsState& S = st[zu(r)];
@@ -393,36 +392,59 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
       cd& gj1 = g[zu(r)][zu(j + 1)];
       gj1 = -std::conj(sgn) * gj;
       gj = c * gj;
-      jend[zu(r)] = j + 1;
       const double est = std::abs(gj1);
       const bool breakdown = !(hcol[zu(r) * zu(nv + 1) + zu(nv)].real() > 1e-300);
       if (trace_on())
         std::fprintf(stderr, "[vie] gmres%s rhs %d j %d est/r0 %.3e beta %.3e wp2/w2 %.3e reorth %d\n",
                      fp64 ? "64" : "32", r, j, est / rnorm[zu(r)], hcol[zu(r) * zu(nv + 1) + zu(nv)].real(),
                      wp2[zu(r)] / w2[zu(r)], int(reorth[zu(r)]));
-      if (est <= target[zu(r)] || breakdown || S.mv32 + S.mv64 >= budget[zu(r)]) active[zu(r)] = false;
+      // a slot stops on its target, a breakdown or its budget, and the cycle
+      // ends for all at its last iteration
+      finish[zu(r)] = est <= target[zu(r)] || breakdown || S.mv32 + S.mv64 >= budget[zu(r)] || j == m - 1;
+    }
+    // continuing slots: V_{j+1} = (w - V h) / beta
+    std::vector<int> cnt_next(static_cast<size_t>(nb), -1), cnt_x(zu(nb), -1);
+    bool any_next = false, any_x = false;
+    for (int r = 0; r < nb; ++r) {
+      if (!active[zu(r)]) continue;
+      if (finish[zu(r)]) {
+        cnt_x[zu(r)] = nv;
+        any_x = true;
+      } else {
+        cnt_next[zu(r)] = nv;
+        any_next = true;
+      }
+    }
+    if (any_next) {
+      const std::vector<cd>& vc = any_reorth ? coef2 : h1;
+      rc = w32 ? combine_host(b, basis, wv32, Vn, nv, vc, scale, &cnt_next)
+               : combine_host(b, basis, wv, Vn, nv, vc, scale, &cnt_next);
+      if (rc) return rc;
+    }
+    // finishing slots: x += V y over their j + 1 basis vectors (instead of a
+    // V_{j+1} they will not use), y from the triangular system R y = g
+    if (any_x) {
+      std::vector<cd> coef(zu(nb) * zu(nv), cd(0, 0));
+      for (int r = 0; r < nb; ++r) {
+        if (cnt_x[zu(r)] < 0) continue;
+        const int k = nv;
+        std::vector<cd> y(static_cast<size_t>(k));
+        const std::vector<cd>& H = Hs[zu(r)];
+        for (int i = k - 1; i >= 0; --i) {
+          cd acc = g[zu(r)][zu(i)];
+          for (int q = i + 1; q < k; ++q) acc -= H[zu(q) * zu(m + 1) + zu(i)] * y[zu(q)];
+          const cd d = H[zu(i) * zu(m + 1) + zu(i)];
+          y[zu(i)] = std::abs(d) > 0 ? acc / d : cd(0, 0);
+        }
+        for (int i = 0; i < k; ++i) coef[zu(r) * zu(nv) + zu(i)] = -y[zu(i)];
+        active[zu(r)] = false;
+      }
+      std::vector<double> one(static_cast<size_t>(nb), 1.0);
+      rc = combine_host(b, static_cast<const c128*>(basis), pl->xw, pl->xw, nv, coef, one, &cnt_x);
+      if (rc) return rc;
     }
   }
-  // x += V y with y from the triangular systems
-  int nvmax = 0;
-  for (int r = 0; r < nb; ++r) nvmax = std::max(nvmax, jend[zu(r)]);
-  if (nvmax == 0) return VIE_OK;
-  std::vector<cd> coef(zu(nb) * zu(nvmax), cd(0, 0));
-  for (int r = 0; r < nb; ++r) {
-    const int k = jend[zu(r)];
-    std::vector<cd> y(static_cast<size_t>(k));
-    const std::vector<cd>& H = Hs[zu(r)];
-    for (int i = k - 1; i >= 0; --i) {
-      cd acc = g[zu(r)][zu(i)];
-      for (int q = i + 1; q < k; ++q) acc -= H[zu(q) * zu(m + 1) + zu(i)] * y[zu(q)];
-      const cd d = H[zu(i) * zu(m + 1) + zu(i)];
-      y[zu(i)] = std::abs(d) > 0 ? acc / d : cd(0, 0);
-    }
-    for (int i = 0; i < k; ++i) coef[zu(r) * zu(nvmax) + zu(i)] = -y[zu(i)];
-  }
-  std::vector<double> one(static_cast<size_t>(nb), 1.0);
-  for (int r = 0; r < nb; ++r) cnt[zu(r)] = jend[zu(r)] > 0 ? jend[zu(r)] : -1;
-  return combine_host(b, static_cast<const c128*>(basis), pl->xw, pl->xw, nvmax, coef, one, &cnt);
+  return VIE_OK;
 }
 
 // Bi-CGStab on A d = r (r in rw, d accumulated into xw).  Work vectors in the
