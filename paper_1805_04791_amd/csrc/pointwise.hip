@@ -367,6 +367,24 @@ __global__ void __launch_bounds__(kBlock) k_combine(const TV* __restrict__ V, lo
   }
 }
 
+template <typename TV, typename TW, typename TO>
+__global__ void __launch_bounds__(kBlock) k_combine_args(const TV* __restrict__ V, long vstride, long rstride,
+                                                         const TW* w, TO* out, long L, int nv, CombineArgs a) {
+  const int rhs = blockIdx.y;
+  const int nvr = a.count[rhs] < nv ? a.count[rhs] : nv;
+  if (nvr < 0) return;
+  const TW* wr = w + rhs * rstride;
+  TO* outr = out + rhs * rstride;
+  const TV* Vr = V + rhs * rstride;
+  const c128* cr = a.coef + rhs * (nv > 0 ? nv : 1);
+  const double sc = a.scale[rhs];
+  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < L; e += long(gridDim.x) * blockDim.x) {
+    c128 acc = cvt<double>(wr[e]);
+    for (int i = 0; i < nvr; ++i) acc = acc - cvt<double>(Vr[long(i) * vstride + e]) * cr[i];
+    outr[e] = cvt<decltype(TO::re)>(sc * acc);
+  }
+}
+
 struct FlagWords {
   unsigned long long w[4];
 };
@@ -493,6 +511,23 @@ VIE_COMBINE_INST(c128, c128, c128)
 VIE_COMBINE_INST(c128, c64, c128)
 VIE_COMBINE_INST(c128, c64, c64)
 #undef VIE_COMBINE_INST
+
+template <typename TV, typename TW, typename TO>
+hipError_t launch_combine_args(const TV* V, long vstride, long rstride, const TW* w, TO* out, long L, int nv,
+                               const CombineArgs& a, int nrhs, hipStream_t s) {
+  if (nrhs < 1 || nrhs > kArgRhs || nrhs * (nv > 0 ? nv : 1) > kArgCoef) return hipErrorInvalidValue;
+  long bx = (L + kBlock - 1) / kBlock;
+  if (bx > 2048) bx = 2048;
+  k_combine_args<TV, TW, TO><<<dim3(unsigned(bx), nrhs), kBlock, 0, s>>>(V, vstride, rstride, w, out, L, nv, a);
+  return hipGetLastError();
+}
+#define VIE_COMBINE_ARGS_INST(TV, TW, TO)                                                                       \
+  template hipError_t launch_combine_args<TV, TW, TO>(const TV*, long, long, const TW*, TO*, long, int,        \
+                                                      const CombineArgs&, int, hipStream_t);
+VIE_COMBINE_ARGS_INST(c128, c128, c128)
+VIE_COMBINE_ARGS_INST(c128, c64, c128)
+VIE_COMBINE_ARGS_INST(c128, c64, c64)
+#undef VIE_COMBINE_ARGS_INST
 
 hipError_t launch_set_flags(const unsigned long long (&words)[4], int nb, int* out, hipStream_t s) {
   if (nb < 1 || nb > kMaxFlagged) return hipErrorInvalidValue;

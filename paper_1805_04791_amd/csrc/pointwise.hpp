@@ -60,6 +60,19 @@ template <typename TV, typename TW, typename TO>
 hipError_t launch_combine(const TV* V, long vstride, long rstride, const TW* w, TO* out, long L, int nv,
                           const c128* coef, const double* scale, int nrhs, hipStream_t s,
                           const int* count = nullptr);
+// The same combine with its coefficients, scales and counts passed as kernel
+// arguments (no staging copy before the launch), for up to kArgRhs right-hand
+// sides and kArgCoef coefficients in all ([rhs][stride], stride = max(nv, 1)).
+constexpr int kArgRhs = 8;
+constexpr int kArgCoef = 160;
+struct CombineArgs {
+  double scale[kArgRhs];
+  int count[kArgRhs];  // < 0: skip the right-hand side
+  c128 coef[kArgCoef];
+};
+template <typename TV, typename TW, typename TO>
+hipError_t launch_combine_args(const TV* V, long vstride, long rstride, const TW* w, TO* out, long L, int nv,
+                               const CombineArgs& a, int nrhs, hipStream_t s);
 // out[r] = bit r of words[0..3] (r < nb <= kMaxFlagged), as 0 / 1
 constexpr int kMaxFlagged = 256;
 hipError_t launch_set_flags(const unsigned long long (&words)[4], int nb, int* out, hipStream_t s);

@@ -180,6 +180,33 @@ int combine_host(const Batch& b, const TV* V, const TW* w, TO* out, int nv, cons
                  const std::vector<double>& scale, const std::vector<int>* counts = nullptr) {
   vie_plan* pl = b.pl;
   const int stride = std::max(nv, 1);
+  // vectors read per right-hand side (for the byte counts)
+  double nvec = 0.0, nrun = 0.0;
+  for (int r = 0; r < b.nb; ++r) {
+    const int k = counts ? std::min((*counts)[zu(r)], nv) : nv;
+    if (k >= 0) {
+      nvec += k;
+      nrun += 1.0;
+    }
+  }
+  const double bytes = (nvec * sizeof(TV) + nrun * (sizeof(TW) + sizeof(TO))) * double(b.L);
+  const double flops = (8.0 * nvec + 2.0 * nrun) * double(b.L);
+  if (b.nb <= kArgRhs && b.nb * stride <= kArgCoef) {
+    // small batches: the coefficients travel as kernel arguments
+    CombineArgs a;
+    for (int r = 0; r < b.nb; ++r) {
+      a.scale[r] = scale[zu(r)];
+      a.count[r] = counts ? std::min((*counts)[zu(r)], nv) : nv;
+      for (int i = 0; i < stride; ++i) {
+        const cd c = i < nv ? coef[zu(r) * zu(nv) + zu(i)] : cd(0.0, 0.0);
+        a.coef[r * stride + i] = {c.real(), c.imag()};
+      }
+    }
+    const int tok = prof_begin(pl, b.s);
+    HIPCHK(pl, launch_combine_args(V, b.vs, b.L, w, out, b.L, nv, a, b.nb, b.s));
+    prof_end(pl, FAM_COMBINE, tok, b.s, bytes, flops);
+    return VIE_OK;
+  }
   // two staging slots used alternately; a slot is rewritten only after the
   // stream has been synchronised since its copies were queued
   const int slot = pl->stage_next;
@@ -204,23 +231,14 @@ int combine_host(const Batch& b, const TV* V, const TW* w, TO* out, int nv, cons
     }
     sh[r] = scale[zu(r)];
   }
-  // vectors read per right-hand side (for the byte counts)
-  double nvec = 0.0, nrun = 0.0;
-  for (int r = 0; r < b.nb; ++r) {
-    const int k = counts ? std::min((*counts)[zu(r)], nv) : nv;
-    if (counts) nh[r] = k;
-    if (k >= 0) {
-      nvec += k;
-      nrun += 1.0;
-    }
-  }
+  for (int r = 0; r < b.nb; ++r)
+    if (counts) nh[r] = std::min((*counts)[zu(r)], nv);
   // one copy: scales, counts and the used coefficients
   const size_t used = pl->stage_off_coef + sizeof(c128) * zu(b.nb) * zu(stride);
   HIPCHK(pl, hipMemcpyAsync(db, hb, used, hipMemcpyHostToDevice, b.s));
   const int tok = prof_begin(pl, b.s);
   HIPCHK(pl, launch_combine(V, b.vs, b.L, w, out, b.L, nv, cdv, sdv, b.nb, b.s, counts ? ndv : nullptr));
-  prof_end(pl, FAM_COMBINE, tok, b.s, (nvec * sizeof(TV) + nrun * (sizeof(TW) + sizeof(TO))) * double(b.L),
-           (8.0 * nvec + 2.0 * nrun) * double(b.L));
+  prof_end(pl, FAM_COMBINE, tok, b.s, bytes, flops);
   return VIE_OK;
 }
 
