@@ -76,10 +76,18 @@ typedef enum {
 #define VIE_PTR_HOST 0x1u        /* coef / mu are host pointers (default: device pointers) */
 #define VIE_STRICT_MEDIUM 0x2u   /* fail with VIE_E_MEDIUM when max ||H(x)||_2 >= 1 (Lemma 1) */
 #define VIE_NO_GRAPHS 0x4u       /* never replay solver applies from captured hipGraphs.  Capture
-                                    (on by default; VIE_GRAPHS=0 in the environment also turns it
-                                    off) forbids, in every thread of the process, HIP calls that
-                                    allocate, free or synchronise the device; hosts whose other
-                                    threads make such calls while a plan solves set this flag. */
+                                    (on by default) forbids, in every thread of the process, HIP
+                                    calls that allocate, free or synchronise the device; hosts whose
+                                    other threads make such calls while a plan solves set this flag. */
+/* Unknowns of the solver.  By default they are the support rows of H (in
+ * each (z, y) row of the bounding box of supp(H), the x-interval from the
+ * first to the last point where H != 0; the integral equation gives J = 0
+ * wherever H = 0) and its x and y transforms have the shortest compiled
+ * length >= 2 max(bx, by).  These flags widen that, for comparisons; the
+ * discrete operator is the same. */
+#define VIE_WHOLE_GRID 0x8u      /* the solver works on the whole n^3 grid with 2n-point transforms */
+#define VIE_DENSE_BOX 0x10u      /* unknowns: every point of the bounding box (no support rows) */
+#define VIE_FULL_LENGTH 0x20u    /* the solver's x and y transforms have length 2n */
 
 /*
  * The problem statement of the paper (Introduction and Section 5): a grid,
@@ -200,14 +208,14 @@ long vie_release_cached_memory(void);
  * out[8..10] = corner (x0, y0, z0) and out[11..13] = extent (bx, by, bz) of
  * the box the solver works on: the bounding box of the points where H (or
  * H_mu) is non-zero, outside which the density vanishes (a single point if
- * H = 0 everywhere; the whole grid when VIE_BOX=0 is set in the
- * environment at plan creation), out[14] = the solver's unknown points per
- * component: in each (z, y) row of the box, the x-interval from the first to
- * the last point where H (or H_mu) is non-zero (the whole box with
- * VIE_ROWS=0, the whole grid with VIE_BOX=0), out[15] = the periodic
- * transform length along x and y of the solver's applies: the shortest
- * compiled length >= 2 max(bx, by) and <= 2n (2n with VIE_PBOX=0; along z
- * always 2n); its kernel tables are the transform of the kernel windowed to
+ * H = 0 everywhere; the whole grid with the plan flag VIE_WHOLE_GRID),
+ * out[14] = the solver's unknown points per component: in each (z, y) row
+ * of the box, the x-interval from the first to the last point where H (or
+ * H_mu) is non-zero (the whole box with VIE_DENSE_BOX, the whole grid with
+ * VIE_WHOLE_GRID), out[15] = the periodic transform length along x and y of
+ * the solver's applies: the shortest compiled length >= 2 max(bx, by) and
+ * <= 2n (2n with VIE_FULL_LENGTH or VIE_WHOLE_GRID; along z always 2n); its
+ * kernel tables are the transform of the kernel windowed to
  * |m_a| <= length_a/2 - 1. */
 int vie_plan_info(const vie_plan *pl, double *out, int nout);
 

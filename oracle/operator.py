@@ -158,17 +158,50 @@ class Convolver:
             self.curl = [window_transform(K) for K in self.curl] if with_curl else None
         self._conv = {"direct": conv_direct, "window": conv_fft_window_hat, "mgrid": conv_fft_mgrid}[route]
 
-    def sym_apply(self, J: np.ndarray) -> np.ndarray:
-        """U_a = sum_b K^{ab} * J_b."""
+    def spectra(self, J: np.ndarray):
+        """Window route: the transform of each zero-padded component on the 2n grid."""
+        n, P = self.n, 2 * self.n
+        out = []
+        for b in range(J.shape[0]):
+            fp = np.zeros((P, P, P), dtype=np.complex128)
+            fp[:n, :n, :n] = J[b]
+            out.append(tb.fftn(fp))
+        return out
+
+    def _crop_inverse(self, spec: np.ndarray) -> np.ndarray:
+        n = self.n
+        return tb.ifftn(spec)[:n, :n, :n]
+
+    def sym_apply(self, J: np.ndarray, Jh=None) -> np.ndarray:
+        """U_a = sum_b K^{ab} * J_b.  Window route: by the convolution theorem,
+        U_a = crop IFFT(sum_b K^_ab J^_b) with J^_b = FFT(pad J_b) (Jh: these
+        transforms, when already computed)."""
         U = np.zeros(J.shape, dtype=np.complex128)
+        if self.route == "window":
+            Jh = self.spectra(J) if Jh is None else Jh
+            for a in range(3):
+                acc = self.sym[_sym_index(a, 0)] * Jh[0]
+                for b in (1, 2):
+                    acc += self.sym[_sym_index(a, b)] * Jh[b]
+                U[a] = self._crop_inverse(acc)
+            return U
         for a in range(3):
             for b in range(3):
                 U[a] += self._conv(self.sym[_sym_index(a, b)], J[b])
         return U
 
-    def curl_apply(self, J: np.ndarray) -> np.ndarray:
-        """W_a = sum_bc eps_abc C_b * J_c."""
+    def curl_apply(self, J: np.ndarray, Jh=None) -> np.ndarray:
+        """W_a = sum_bc eps_abc C_b * J_c (window route: one inverse transform per a)."""
         W = np.zeros(J.shape, dtype=np.complex128)
+        if self.route == "window":
+            Jh = self.spectra(J) if Jh is None else Jh
+            for a in range(3):
+                acc = np.zeros_like(Jh[0])
+                for (p, b, c), sgn in LEVI.items():
+                    if p == a:
+                        acc += sgn * (self.curl[b] * Jh[c])
+                W[a] = self._crop_inverse(acc)
+            return W
         for (a, b, c), sgn in LEVI.items():
             W[a] += sgn * self._conv(self.curl[b], J[c])
         return W
@@ -199,14 +232,18 @@ class Operator:
     def ncomp(self) -> int:
         return 6 if self.full else 3
 
+    def _spectra(self, v):
+        return self.conv.spectra(v) if self.conv.route == "window" else None
+
     def apply(self, x: np.ndarray) -> np.ndarray:
         if not self.full:
             U = self.conv.sym_apply(x)
             return x - pointwise(self.H, x + 2.0 * U)
         w = self.omega
         J, M = x[:3], x[3:]
-        UJ, UM = self.conv.sym_apply(J), self.conv.sym_apply(M)
-        WJ, WM = self.conv.curl_apply(J), self.conv.curl_apply(M)
+        Jh, Mh = self._spectra(J), self._spectra(M)
+        UJ, UM = self.conv.sym_apply(J, Jh), self.conv.sym_apply(M, Mh)
+        WJ, WM = self.conv.curl_apply(J, Jh), self.conv.curl_apply(M, Mh)
         yJ = J - pointwise(self.H, J + 2.0 * UJ + 2j * w * WM)
         yM = M - pointwise(self.Hmu, M + 2.0 * UM - 2j * w * WJ)
         return np.concatenate([yJ, yM])
@@ -221,6 +258,7 @@ class Operator:
             return inc + self.conv.sym_apply(x)
         w = self.omega
         J, M = x[:3], x[3:]
-        E = inc[:3] + self.conv.sym_apply(J) + 1j * w * self.conv.curl_apply(M)
-        Hf = inc[3:] + self.conv.sym_apply(M) - 1j * w * self.conv.curl_apply(J)
+        Jh, Mh = self._spectra(J), self._spectra(M)
+        E = inc[:3] + self.conv.sym_apply(J, Jh) + 1j * w * self.conv.curl_apply(M, Mh)
+        Hf = inc[3:] + self.conv.sym_apply(M, Mh) - 1j * w * self.conv.curl_apply(J, Jh)
         return np.concatenate([E, Hf])

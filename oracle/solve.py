@@ -6,7 +6,9 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
   the exact discrete solution.
 * ``gmres``: restarted GMRES (the paper names GMRES beside Bi-CGStab as a
   suitable unpreconditioned iteration, Introduction and Discussion).  Arnoldi
-  with modified Gram-Schmidt; the small least-squares problem is solved with
+  with classical Gram-Schmidt applied twice (as stable as the modified
+  variant; the basis is a matrix, so each pass is two matrix-vector
+  products); the small least-squares problem is solved with
   ``numpy.linalg.lstsq`` at every step; stops on the true relative residual
   ||b - A x|| / ||b|| <= tol, x0 = 0.
 * ``bicgstab``: unpreconditioned Bi-CGStab as used in the numerical section.
@@ -56,16 +58,19 @@ def gmres(apply, b: np.ndarray, tol: float = 1e-13, restart: int = 100, maxiter:
         info["history"].append(rel)
         if rel <= tol or info["matvecs"] >= maxiter:
             break
-        V = [r / beta]
-        Hh = np.zeros((restart + 1, restart), dtype=np.complex128)
+        m = min(restart, max(1, maxiter - info["matvecs"]))
+        V = np.empty((m + 1, b.size), dtype=np.complex128)
+        V[0] = (r / beta).ravel()
+        Hh = np.zeros((m + 1, m), dtype=np.complex128)
         k = 0
         y = np.zeros(0)
-        for j in range(restart):
-            w = apply(V[j])
+        for j in range(m):
+            w = apply(V[j].reshape(b.shape)).ravel()
             info["matvecs"] += 1
-            for i in range(j + 1):
-                Hh[i, j] = np.vdot(V[i], w)
-                w = w - Hh[i, j] * V[i]
+            for _ in range(2):                  # classical Gram-Schmidt, twice
+                h = np.conj(V[:j + 1] @ np.conj(w))  # h_i = (V_i, w)
+                w = w - V[:j + 1].T @ h
+                Hh[:j + 1, j] += h
             Hh[j + 1, j] = _norm(w)
             rhs = np.zeros(j + 2, dtype=np.complex128)
             rhs[0] = beta
@@ -74,9 +79,8 @@ def gmres(apply, b: np.ndarray, tol: float = 1e-13, restart: int = 100, maxiter:
             k = j + 1
             if est <= 0.5 * tol * bnorm or Hh[j + 1, j] == 0 or info["matvecs"] >= maxiter:
                 break
-            V.append(w / Hh[j + 1, j])
-        for i in range(k):
-            x = x + y[i] * V[i]
+            V[j + 1] = w / Hh[j + 1, j]
+        x = x + (V[:k].T @ y[:k]).reshape(b.shape)
     info["rel_residual"] = rel
     info["converged"] = rel <= tol
     return x, info

@@ -33,21 +33,14 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def cflags(defines=()):
-    return ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-fPIC", "-x", "hip"] + \
-        [f"-D{d}" for d in defines] + [
+def cflags():
+    return ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-fPIC", "-x", "hip",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wno-unused-command-line-argument", "-I", INCLUDE, "-I", CSRC]
 
 
-def sources(only_lens=None):
-    out = []
-    for f in sorted(os.listdir(CSRC)):
-        if f.endswith((".hip", ".cpp")):
-            if only_lens is not None and f.startswith("len_") and int(f[4:].split(".")[0]) not in only_lens:
-                continue
-            out.append(os.path.join(CSRC, f))
-    return out
+def sources():
+    return [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith((".hip", ".cpp"))]
 
 
 def headers():
@@ -63,8 +56,8 @@ def _needs(src, obj, newest_header):
     return os.path.getmtime(src) > t or newest_header > t
 
 
-def _compile(src, obj, defines=()):
-    cmd = [hipcc()] + cflags(defines) + ["-c", src, "-o", obj]
+def _compile(src, obj):
+    cmd = [hipcc()] + cflags() + ["-c", src, "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (p.stdout + p.stderr).splitlines()
                      if "packed-fp32-ops" not in l and l.strip())
@@ -73,22 +66,21 @@ def _compile(src, obj, defines=()):
     return os.path.basename(src)
 
 
-def build(jobs: int = 0, incremental: bool = False, verbose: bool = True, defines=(), only_lens=None,
-          out: str = LIB, build_dir: str = BUILD) -> str:
-    """Compile and link; `defines`, `only_lens`, `out` and `build_dir` serve
-    experimental variants built outside the package."""
-    os.makedirs(build_dir, exist_ok=True)
-    srcs = sources(only_lens)
-    objs = [os.path.join(build_dir, os.path.basename(s) + ".o") for s in srcs]
+def build(jobs: int = 0, incremental: bool = False, verbose: bool = True) -> str:
+    """Compile every source (only the out-of-date ones with `incremental`) and link."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = sources()
+    objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in srcs]
     newest = max(os.path.getmtime(h) for h in headers())
     todo = [(s, o) for s, o in zip(srcs, objs) if not incremental or _needs(s, o, newest)]
     if jobs <= 0:
         jobs = min(16, max(1, len(os.sched_getaffinity(0))))
     if todo:
         with ThreadPoolExecutor(max_workers=jobs) as ex:
-            for name in ex.map(lambda so: _compile(*so, defines=defines), todo):
+            for name in ex.map(lambda so: _compile(*so), todo):
                 if verbose:
                     print(f"  compiled {name}", flush=True)
+    out = LIB
     tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     p = subprocess.run(cmd, capture_output=True, text=True)

@@ -126,7 +126,7 @@ __attribute__((amdgpu_waves_per_eu(zpass_min_waves<R, C>()))) k_zpass(cx<R>* buf
   };
   if constexpr (kUpfront<R>) static_for<0, C>([&](auto c) { load_comp(c, in[c]); });
   __syncthreads();
-  ThreadTw<R, P1, P2, kRegTwiddles<R>> twr;
+  ThreadTw<R, P1, P2> twr;
   twr.init(tw, j);
 
   cx<R> X[C][P2];
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
   };
   if constexpr (kUpfront<R>) static_for<0, C>([&](auto c) { load_comp(c, X[c]); });
   __syncthreads();
-  ThreadTw<R, P1, P2, kRegTwiddles<R>> twr;
+  ThreadTw<R, P1, P2> twr;
   twr.init(tw, j);
 
   cx<R> U[C][NV];

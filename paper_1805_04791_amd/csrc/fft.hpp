@@ -33,17 +33,11 @@ struct scalar_of<cx<R>> {
   using type = R;
 };
 
-// Kernel variants.  kUpfront<R>: the fused z / x-inverse passes issue the
-// loads of all components before the first transform (more bytes in flight,
-// more VGPRs; FP32 only).  kRegTwiddles<R>: per-thread twiddles held in
-// registers.
-#ifndef VIE_ZVAR
-#define VIE_ZVAR 1
-#endif
+// The fused z / x-inverse passes in FP32 issue the loads of all components
+// before the first transform (more bytes in flight for the same occupancy);
+// the FP64 ones load one component at a time to stay within their registers.
 template <typename R>
-constexpr bool kUpfront = (VIE_ZVAR & 1) != 0 && sizeof(R) == 4;
-template <typename R>
-constexpr bool kRegTwiddles = (VIE_ZVAR & 2) != 0 && sizeof(R) == 4;
+constexpr bool kUpfront = sizeof(R) == 4;
 
 // largest block of each kernel family (the tile choice keeps T*J within it)
 constexpr int kPassMaxThreads = 512;
@@ -166,27 +160,20 @@ __host__ __device__ constexpr int lds_elems_per_col(bool contig) {
   return P2 * (P1 + 1) > P1 * (P2 + 1) ? P2 * (P1 + 1) : P1 * (P2 + 1);
 }
 
-// Twiddles W_P^{j i} of thread j.  Step A multiplies by W_P^{n2 k1} (n2 = j,
-// k1 < P1) and step C by W_P^{-m1 k1} (k1 = j, m1 < P2 <= P1); j i < P in both.
-// REG: the P1 values are copied to registers once per block (fewer LDS reads,
-// more VGPRs); otherwise they are read from the LDS table when needed.
-template <typename R, int P1, int P2, bool REG>
+// Twiddles W_P^{j i} of thread j, read from the LDS table when needed.  Step A
+// multiplies by W_P^{n2 k1} (n2 = j, k1 < P1) and step C by W_P^{-m1 k1}
+// (k1 = j, m1 < P2 <= P1); j i < P in both.
+template <typename R, int P1, int P2>
 struct ThreadTw {
-  static constexpr int P = P1 * P2;
-  cx<R> r[REG ? P1 : 1];
   const cx<R>* t;
   int j;
   __device__ __forceinline__ void init(const cx<R>* tw, int jj) {
     t = tw;
     j = jj;
-    if constexpr (REG) static_for<0, P1>([&](auto i) { r[i] = tw[(jj * i) % P]; });
   }
   template <int I>
   __device__ __forceinline__ cx<R> get() const {
-    if constexpr (REG)
-      return r[I];
-    else
-      return t[j * I];
+    return t[j * I];
   }
 };
 
@@ -293,7 +280,7 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<R, P1, P2, CONTIG, INV>()))) k
   const auto col_src = src.column(g, valid ? c : 0);
   if constexpr (!INV) fft_load<R, P1, P2>([&](int n) { return col_src.template load<R>(n); }, geo.nin, j, valid, u);
   __syncthreads();
-  ThreadTw<R, P1, P2, kRegTwiddles<R>> twr;
+  ThreadTw<R, P1, P2> twr;
   twr.init(tw, j);
   cx<R> X[P2];
   if constexpr (!INV) {

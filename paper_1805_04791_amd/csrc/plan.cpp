@@ -1024,7 +1024,7 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   pl->max_rhs = p->max_rhs;
   pl->flags = p->flags;
   pl->n3 = long(p->n) * p->n * p->n;
-  pl->use_graphs = env_flag("VIE_GRAPHS", true) && !(p->flags & VIE_NO_GRAPHS);
+  pl->use_graphs = !(p->flags & VIE_NO_GRAPHS);
   pl->last_stream = s;
   HIPCHK(pl, hipGetDevice(&pl->device));
   {
@@ -1092,11 +1092,11 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   }
   pl->box = Geom{&pl->sb, hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1, lo[0], lo[1], lo[2], 1, nullptr, 0};
   pl->box.np = long(pl->box.bx) * pl->box.by * pl->box.bz;
-  pl->use_box = env_flag("VIE_BOX", true);
+  pl->use_box = !(p->flags & VIE_WHOLE_GRID);
   if (!pl->use_box) {
     pl->box = pl->grid;
     pl->box.sp = &pl->sb;
-  } else if (env_flag("VIE_ROWS", true)) {
+  } else if (!(p->flags & VIE_DENSE_BOX)) {
     rc = build_rows(pl, s);
     if (rc) return rc;
   }
@@ -1108,7 +1108,7 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   // twiddles and kernel tables: the whole grid's, and the box's when shorter
   // (the whole grid's are built at its first use when they differ: a solve
   // without field output never needs them)
-  const int pb = pl->use_box && env_flag("VIE_PBOX", true) ? box_length(pl) : pl->P;
+  const int pb = pl->use_box && !(p->flags & VIE_FULL_LENGTH) ? box_length(pl) : pl->P;
   rc = make_spec(pl, pl->P, pb, pl->sym_set, pl->ne, pl->sb, s);
   if (rc) return rc;
   if (pb == pl->P) pl->sg = pl->sb;

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libvie.so")
 LAPLACE, HELMHOLTZ, MAXWELL = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 PTR_HOST, STRICT_MEDIUM, NO_GRAPHS = 0x1, 0x2, 0x4
+WHOLE_GRID, DENSE_BOX, FULL_LENGTH = 0x8, 0x10, 0x20
 APPLY_FP64, APPLY_FP32, APPLY_CONV, APPLY_C64 = 0x1, 0x2, 0x4, 0x8
 SOLVER_GMRES, SOLVER_BICGSTAB = 0, 1
 SOLVE_X0, SOLVE_FP64 = 0x1, 0x2
@@ -151,11 +152,12 @@ class Plan:
 
     kind: LAPLACE (coef = eps), HELMHOLTZ (coef = eps^{-1}) or MAXWELL
     (coef = eps, optional mu).  coef / mu: complex arrays [9][n][n][n].
+    flags: further vie_problem flags (WHOLE_GRID, DENSE_BOX, FULL_LENGTH, ...).
     """
 
     def __init__(self, kind: int, coef, omega: float = 0.0, mu=None, h: Optional[float] = None,
                  precision: int = PREC_MIXED, max_rhs: int = 1, strict: bool = False,
-                 device: str = "cuda", stream=None, graphs: bool = True):
+                 device: str = "cuda", stream=None, graphs: bool = True, flags: int = 0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the volume-integral-equation library runs on MI355X only")
@@ -177,7 +179,7 @@ class Plan:
         p.mu = mu_d.data_ptr() if mu_d is not None else None
         p.precision = int(precision)
         p.max_rhs = int(max_rhs)
-        p.flags = (STRICT_MEDIUM if strict else 0) | (0 if graphs else NO_GRAPHS)
+        p.flags = (STRICT_MEDIUM if strict else 0) | (0 if graphs else NO_GRAPHS) | int(flags)
         handle = ctypes.c_void_p()
         rc = self.lib.vie_plan_create(ctypes.byref(p), _stream_ptr(stream), ctypes.byref(handle))
         if rc != OK:

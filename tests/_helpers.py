@@ -15,9 +15,17 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
-def medium(kind: int, n: int, seed_item: int = 0, full: bool = False):
-    """(coef, mu, omega) of a small test problem of the given kind."""
+def medium(kind: int, n: int, seed_item: int = 0, full: bool = False, sheared: bool = False):
+    """(coef, mu, omega) of a small test problem of the given kind.  sheared:
+    non-symmetric tensors (a rotation composed with a shear; for full Maxwell
+    both eps and mu), so that H and H^T differ at every point of the bump."""
     rng = gen.rng_for(gen.CONFIG_IDS["test"], 100 + seed_item)
+    if sheared:
+        coef = gen.sheared_medium(n, rng)
+        if kind == op.KIND_LAPLACE:
+            return coef, None, 0.0
+        mu = gen.sheared_medium(n, rng, norm=0.3) if full else None
+        return coef, mu, 3.0 * math.pi
     if kind == op.KIND_LAPLACE:
         return gen.laplace_medium(n, rng), None, 0.0
     if kind == op.KIND_HELMHOLTZ:

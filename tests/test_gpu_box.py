@@ -156,16 +156,14 @@ def test_offcentre_box_full_maxwell_matches_oracle(vie):
     plan.close()
 
 
-def test_restricted_solve_equals_whole_grid_solve(vie, monkeypatch):
+def test_restricted_solve_equals_whole_grid_solve(vie):
     n = 24
     coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 15)
     inc = plane_waves(n, omega, 3, 10)
-    monkeypatch.setenv("VIE_BOX", "0")
-    whole = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
-    monkeypatch.delenv("VIE_BOX")
-    monkeypatch.setenv("VIE_ROWS", "0")
-    dense = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
-    monkeypatch.delenv("VIE_ROWS")
+    whole = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3,
+                     flags=vie.WHOLE_GRID)
+    dense = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3,
+                     flags=vie.DENSE_BOX)
     rows = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
     assert whole.info()["box"] == (0, 0, 0, n, n, n) and whole.info()["unknown_points"] == n ** 3
     box = dense.info()["box"]
@@ -215,15 +213,15 @@ def test_short_box_transform_matches_oracle(vie, n, radius):
     plan.close()
 
 
-def test_short_box_transform_equals_full_length(vie, monkeypatch):
+def test_short_box_transform_equals_full_length(vie):
     """n = 64, bump of radius 0.8: the solver's transform length along x and y
     is 120 (not 128); solves agree with those on the 2n grid."""
     n = 64
     coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 18)
     inc = plane_waves(n, omega, 2, 40)
     short = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2)
-    monkeypatch.setenv("VIE_PBOX", "0")
-    full = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2)
+    full = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2,
+                    flags=vie.FULL_LENGTH)
     assert short.info()["box_P"] < 2 * n and full.info()["box_P"] == 2 * n
     for fp64, tol, err in ((True, 1e-12, 1e-10), (False, 1e-10, 1e-9)):
         ds, _, ss, _ = short.solve(inc, tol=tol, fp64=fp64, want_field=False)

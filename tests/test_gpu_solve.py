@@ -73,6 +73,26 @@ def test_fp64_and_mixed_solves_match_oracle(vie, name, kind, full):
     plan.close()
 
 
+@pytest.mark.parametrize("name,kind,full", [("helmholtz_sheared", op.KIND_HELMHOLTZ, False),
+                                            ("maxwell_full_sheared", op.KIND_MAXWELL, True)])
+def test_sheared_medium_solves_match_oracle(vie, name, kind, full):
+    """Non-symmetric media (H != H^T): FP64 and mixed solves against the oracle."""
+    n = 16
+    coef, mu, omega = medium(kind, n, 5, full, sheared=True)
+    inc = incident(kind, n, omega, 2, full, item=20)
+    A = op.Operator(kind, coef, omega, mu=mu)
+    ref = [sv.gmres(A.apply, A.rhs(inc[r]), tol=1e-13)[0] for r in range(2)]
+    plan = vie.Plan(kind, coef, omega=omega, mu=mu, precision=vie.PREC_MIXED, max_rhs=2)
+    d64, _, st64, rc64 = plan.solve(inc, tol=1e-12, fp64=True, want_field=False)
+    d32, _, st32, rc32 = plan.solve(inc, tol=1e-9, want_field=False)
+    assert rc64 == vie.OK and rc32 == vie.OK
+    d64, d32 = d64.cpu().numpy(), d32.cpu().numpy()
+    for r in range(2):
+        assert rel(d64[r], ref[r]) < 1e-10
+        assert rel(d32[r], ref[r]) < 1e-8
+    plan.close()
+
+
 def test_bicgstab_matches_oracle(vie):
     n = 16
     coef, mu, omega = medium(op.KIND_HELMHOLTZ, n, 4)
@@ -169,15 +189,13 @@ def test_resume_from_x0_and_noconv(vie):
     plan.close()
 
 
-def test_graph_replay_equals_eager(vie, monkeypatch):
+def test_graph_replay_equals_eager(vie):
     """Solver applies replayed from captured hipGraphs give bitwise the eager
     results, over several solves (replays) with eager work in between."""
     n = 24
     coef, mu, omega = medium(op.KIND_HELMHOLTZ, n, 7)
     inc = incident(op.KIND_HELMHOLTZ, n, omega, 3, False, item=40)
-    monkeypatch.setenv("VIE_GRAPHS", "0")
-    eager = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
-    monkeypatch.setenv("VIE_GRAPHS", "1")
+    eager = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3, graphs=False)
     graph = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
     ref, _, _, _ = eager.solve(inc, tol=1e-10, want_field=False)
     ref = ref.cpu().numpy()
@@ -191,3 +209,4 @@ def test_graph_replay_equals_eager(vie, monkeypatch):
     assert eager.info()["graph_launches"] == 0
     eager.close()
     graph.close()
+

@@ -60,6 +60,95 @@ def test_contrast_rotation_covariant():
     assert np.allclose(H, Q @ np.diag((d - 1) / (d + 1)) @ Q.T, atol=1e-15)
 
 
+def shear_field(n):
+    """a = I + e_x e_y^T at every point: the hand-computed contrast (eq. rhodef) is
+    H = (a + I)^{-1}(a - I) = [[1/2, -1/4, 0], [0, 1/2, 0], [0, 0, 1/2]] e_x e_y^T
+      = (1/2) e_x e_y^T,
+    so H v = (v_y / 2, 0, 0) while H^T v = (0, v_x / 2, 0)."""
+    a = np.eye(3)
+    a[0, 1] = 1.0
+    return gen.tensor_field(0.0, np.ones((n, n, n)), a.astype(np.complex128))
+
+
+def test_contrast_orientation_hand_computed():
+    n = 6
+    H = op.contrast(shear_field(n))
+    want = np.zeros((3, 3))
+    want[0, 1] = 0.5
+    assert np.array_equal(H.reshape(3, 3, -1)[:, :, 17], want)
+    v = np.zeros((3, n, n, n), dtype=np.complex128)
+    v[1] = 2.0 - 4.0j                        # v = (0, 2 - 4i, 0)
+    v[0] = 1.0                               # ... + (1, 0, 0): H^T would pick this one
+    Hv = op.pointwise(H, v)
+    assert np.array_equal(Hv[0], np.full((n, n, n), 1.0 - 2.0j))
+    assert np.array_equal(Hv[1], np.zeros((n, n, n))) and np.array_equal(Hv[2], np.zeros((n, n, n)))
+
+
+@pytest.mark.parametrize("kind,full", [(op.KIND_LAPLACE, False), (op.KIND_HELMHOLTZ, False),
+                                       (op.KIND_MAXWELL, False), (op.KIND_MAXWELL, True)])
+def test_operator_orientation_of_contrast(kind, full):
+    """With H = (1/2) e_x e_y^T, A J = J - H (J + 2 U) leaves the y and z
+    components of J untouched and changes x by -(J_y + 2 U_y)/2; the right-hand
+    side 2 H g is (g_y, 0, 0).  Full Maxwell: the same for the M half with
+    H_mu = (1/2) e_x e_y^T."""
+    n = 8
+    coef = shear_field(n)
+    omega = 0.0 if kind == op.KIND_LAPLACE else 2.0
+    A = op.Operator(kind, coef, omega, mu=coef if full else None)
+    c = 6 if full else 3
+    x = gen.random_density((c, n, n, n), np.random.default_rng(11))
+    y = A.apply(x)
+    Z = A.field(x, np.zeros_like(x)) if full else A.conv.sym_apply(x)
+    for h in range(c // 3):
+        J, Y, U = x[3 * h:3 * h + 3], y[3 * h:3 * h + 3], Z[3 * h:3 * h + 3]
+        assert np.array_equal(Y[1], J[1]) and np.array_equal(Y[2], J[2])
+        assert rel(Y[0], J[0] - 0.5 * (J[1] + 2.0 * U[1])) < 1e-15
+    g = gen.random_density((c, n, n, n), np.random.default_rng(12))
+    b = A.rhs(g)
+    for h in range(c // 3):
+        assert np.array_equal(b[3 * h], g[3 * h + 1])
+        assert not b[3 * h + 1].any() and not b[3 * h + 2].any()
+
+
+def _field_of(mats):
+    """[9][n][1][1] field holding one 3x3 matrix per x point."""
+    m = np.stack(mats, axis=-1)              # [3][3][n]
+    return m.reshape(9, 1, 1, -1).astype(np.complex128)
+
+
+def test_contrast_norm_is_spectral_norm():
+    """Lemma 1 is stated for ||H(x)||_2.  For normal H (unitarily
+    diagonalisable) the norm is max |lambda|; for the nilpotent (1/2) e_x e_y^T
+    it is 1/2 although every eigenvalue is 0; for a rank-one u v^H it is
+    |u| |v|.  The largest entry, the Frobenius norm or the spectral radius
+    each fail at least one of these."""
+    rng = np.random.default_rng(21)
+    g = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    U, _ = np.linalg.qr(g)                   # unitary
+    lam = np.array([0.3 * np.exp(0.4j), -0.7, 0.55j])
+    normal = U @ np.diag(lam) @ U.conj().T
+    assert abs(op.contrast_norm_max(_field_of([normal])) - 0.7) < 1e-14
+    nil = np.zeros((3, 3))
+    nil[0, 1] = 0.5
+    assert abs(op.contrast_norm_max(_field_of([nil])) - 0.5) < 1e-15
+    u = np.array([0.3, 0.4j, 0.0])
+    v = np.array([0.6, 0.0, 0.8j])
+    assert abs(op.contrast_norm_max(_field_of([np.outer(u, v.conj())])) - 0.5) < 1e-15
+    # the maximum over points
+    assert abs(op.contrast_norm_max(_field_of([nil, normal, 0.1 * np.eye(3)])) - 0.7) < 1e-14
+
+
+def test_lemma1_accretive_and_not():
+    """H = (a + I)^{-1}(a - I) is a contraction exactly when the Hermitian part
+    of a is positive definite (Lemma 1's hypothesis): a sheared non-symmetric
+    medium passes; a tensor with an indefinite Hermitian part does not."""
+    n = 10
+    c = gen.sheared_medium(n, gen.rng_for(gen.CONFIG_IDS["test"], 3))
+    assert op.contrast_norm_max(op.contrast(c)) < 1.0
+    a = np.array([[1.0, 3.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])   # a + a^T indefinite
+    assert op.contrast_norm_max(op.contrast(_field_of([a]))) > 1.0
+
+
 @pytest.mark.parametrize("name", ["laplace", "helmholtz", "maxwell"])
 def test_lemma1_contrast_is_contraction(name):
     n = 20

@@ -10,6 +10,7 @@
   truncated-kernel method promises for resolved data (Section 5).
 """
 
+import itertools
 import math
 
 import numpy as np
@@ -47,6 +48,23 @@ def test_routes_agree(kind, omega):
         assert np.linalg.norm(a - c) <= 1e-13 * np.linalg.norm(a)
 
 
+@pytest.mark.parametrize("kind,omega", [("grad", 0.0), ("grad", 2.5), ("D", 2.5)])
+def test_vector_routes_agree(kind, omega):
+    """The window route's vector apply (each component transformed once,
+    U_a = crop IFFT(sum_b K^_ab J^_b)) equals the direct sum of every (a, b)
+    pair; the same for the curl W_a = sum_bc eps_abc C_b * J_c."""
+    n, h = 6, 2.0 / 6
+    J = gen.random_density((3, n, n, n), np.random.default_rng(8))
+    curl = kind == "D"
+    win = op.Convolver(kind, n, h, omega, "window", with_curl=curl)
+    dsum = op.Convolver(kind, n, h, omega, "direct", with_curl=curl)
+    a, b = win.sym_apply(J), dsum.sym_apply(J)
+    assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
+    if curl:
+        a, b = win.curl_apply(J), dsum.curl_apply(J)
+        assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
+
+
 def test_direct_sum_at_single_point():
     n, h = 6, 1.0 / 3
     K = tb.kernel_tables("grad", n, h, 2.0)[3]
@@ -54,6 +72,51 @@ def test_direct_sum_at_single_point():
     full = op.conv_direct(K, f)
     for p in [(0, 0, 0), (5, 2, 1), (3, 5, 4)]:
         assert abs(op.conv_direct_at(K, f, p) - full[p]) < 1e-13 * np.abs(full).max()
+
+
+@pytest.mark.parametrize("kind,omega", [("grad", 0.0), ("grad", 3.0), ("D", 3.0), ("curl", 3.0)])
+def test_nyquist_samples_are_averages(kind, omega):
+    """Reading of Section 5's cut-off: a sample on a plane k_a = -M/2 is the
+    average of the symbol over s_a = -pi/h and s_a = +pi/h (edges: over the 4
+    sign choices, the corner: over 8).  Evaluated point by point from the
+    symbol functions (themselves pinned by quadrature), at plane, edge and
+    corner samples; the entries odd in a Nyquist axis come out zero there."""
+    from oracle import symbol as sym
+    n, h = 5, 0.4
+    M = tb.default_M(n)
+    R = tb.default_R(n, h)
+    F = tb.sampled_symbol(kind, n, h, omega)
+    fn = sym.symbol_set(kind)
+    ds = 2.0 * math.pi / (M * h)
+    k = tb.freq_integers(M)
+    nyq = M // 2                              # FFT index of k = -M/2
+    cases = [(3, 7, nyq), (nyq, 2, 15), (11, nyq, 4),        # planes (z, y, x index)
+             (nyq, nyq, 6), (1, nyq, nyq), (nyq, 9, nyq),    # edges
+             (nyq, nyq, nyq)]                                  # corner
+    for iz, iy, ix in cases:
+        base = np.array([k[ix], k[iy], k[iz]], dtype=np.float64) * ds      # (s_x, s_y, s_z)
+        axes = [a for a, i in enumerate((ix, iy, iz)) if i == nyq]
+        ref = np.zeros(len(F), dtype=np.complex128)
+        for signs in itertools.product((-1.0, 1.0), repeat=len(axes)):
+            s = base.copy()
+            for a, sg in zip(axes, signs):
+                s[a] = sg * math.pi / h
+            vals = fn(np.array([s[0]]), np.array([s[1]]), np.array([s[2]]), omega, R)
+            ref += np.array([v[0] for v in vals])
+        ref /= 2 ** len(axes)
+        got = np.array([F[e][iz, iy, ix] for e in range(len(F))])
+        mag = max(abs(v[0]) for v in fn(np.array([base[0]]), np.array([base[1]]), np.array([base[2]]),
+                                        omega, R))
+        assert np.allclose(got, ref, rtol=1e-14, atol=1e-14 * mag)
+        par = [sym.parity(kind, e) for e in range(len(F))]
+        for e in range(len(F)):
+            if any(par[e][a] < 0 for a in axes):
+                assert abs(got[e]) <= 1e-15 * mag
+            else:
+                # an even entry is unchanged by the averaging: F(-pi/h) itself
+                s = base.copy()
+                vals = fn(np.array([s[0]]), np.array([s[1]]), np.array([s[2]]), omega, R)
+                assert abs(got[e] - vals[e][0]) <= 1e-14 * max(abs(vals[e][0]), 1e-300)
 
 
 @pytest.mark.parametrize("kind", ["grad", "D", "curl"])

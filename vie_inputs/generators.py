@@ -152,6 +152,29 @@ def helmholtz_medium(n: int, rng: np.random.Generator, norm: float = 0.5,
     return tensor_field(1.0, bump(X, Y, Z), M)
 
 
+def sheared_matrix(rng: np.random.Generator, norm: float = 0.5, shear: float = 0.8,
+                   loss: float = 0.05) -> np.ndarray:
+    """A non-symmetric 3x3 matrix: a rotation composed with a shear, scaled to
+    spectral norm ``norm``, plus i*loss*I.  N = Q S with Q from
+    ``random_rotation`` and S = I + shear e_x e_y^T.  Draw order: Q (9 normals).
+    With norm <= 0.5 the symmetric part of I + b N stays positive definite for
+    0 <= b <= 1, so the contrast is a contraction (Lemma 1)."""
+    q = random_rotation(rng)
+    s = np.eye(3)
+    s[0, 1] = shear
+    N = q @ s
+    N = norm * N / np.linalg.norm(N, 2)
+    return N + 1j * loss * np.eye(3)
+
+
+def sheared_medium(n: int, rng: np.random.Generator, norm: float = 0.5) -> np.ndarray:
+    """I + b(x) N with N from ``sheared_matrix``: a tensor field that is not
+    (complex-)symmetric at any point of the bump, so that H and H^T differ."""
+    N = sheared_matrix(rng, norm)
+    X, Y, Z = grid_coords(n)
+    return tensor_field(1.0, bump(X, Y, Z), N)
+
+
 def rot1(theta):
     """Rotation about the first axis (Section 5, dense medium)."""
     c, s = np.cos(theta), np.sin(theta)
