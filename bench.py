@@ -8,9 +8,15 @@ Workload (helmholtz128): grid 128^3 on [-1,1]^3, omega = 8 pi (8 wavelengths
 across the box), eps^{-1}(x) = I + b(x)(A + 0.05 i I) with a seeded symmetric
 A of norm 0.5 and the C-infinity bump b of radius 0.8, plane waves along B
 seeded directions (gradient of exp(i omega d.x) as incident field).
-A step is one batched mixed-precision solve of the B right-hand sides to a
-true relative residual of 1e-9 (error <= 1e-8); inputs are resident in HBM
-before the timed region.  Prints one JSON line.
+A step is one batched mixed-precision solve of the B right-hand sides (64 by
+default) to a true relative residual of 1e-9 (error <= 1e-8); inputs are
+resident in HBM before the timed region, which runs with kernel timing off
+(the solver's applies replay from captured hipGraphs).  The per-kernel
+HIP-event times (and the roofline of the dominant kernel) come from a second,
+profiled pass over the same steps.  The oracle leg (CPU) times the oracle's
+matvec for the CPU baseline and checks the timed batch against the oracle:
+the oracle's true residual of the GPU solutions, and one oracle GMRES solve
+to 1e-13 compared element by element (err_vs_oracle).  Prints one JSON line.
 
 --workload measures the other configurations instead (same JSON layout):
   laplace32    anisotropic Laplace 32^3, eps = I + b A, E0 = z; FP64 to 1e-10
@@ -35,14 +41,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MI355X_HBM_PEAK_GBS = 8000.0
-# Vector ALU peak reachable by this library: 256 CUs x 4 SIMDs x 16 lanes x
-# 2 flops (FMA) x 2.4 GHz.  FP64 and FP32 alike: the published 157.3 TFLOP/s
-# FP32 figure counts packed (two-per-lane) FP32 instructions, which the
-# library is compiled without.
-MI355X_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Published vector peaks (256 CUs, 2.4 GHz): FP32 157.3 TFLOP/s (counting the
+# two-per-lane packed FMA), FP64 78.6 TFLOP/s.  The library is compiled
+# without packed FP32, so its FP32 kernels can issue at most half the
+# published FP32 rate (78.6 TFLOP/s of FMAs); both are reported.
+MI355X_FP32_PEAK_TFLOPS = 157.3
+MI355X_FP64_PEAK_TFLOPS = 78.6
+MI355X_FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 METRIC = "solves/s to 1e-8 rel err (128³ Helmholtz), mixed vs FP64; p50/p99 latency"
 # name: (right-hand sides per step, true relative residual, the solver `value` reports)
-WORKLOADS = {"helmholtz128": (8, 1e-9, "mixed"), "laplace32": (1, 1e-10, "fp64"),
+WORKLOADS = {"helmholtz128": (64, 1e-9, "mixed"), "laplace32": (1, 1e-10, "fp64"),
              "helmholtz64": (8, 1e-10, "fp64"), "maxwell128": (8, 1e-9, "mixed"),
              "batched96": (64, 1e-9, "mixed")}
 
@@ -59,42 +67,74 @@ def make_problem(workload: str, n: int, nrhs: int):
     return gen.config_problem(workload, nrhs=nrhs)
 
 
-def cpu_baseline(workload: str, n: int, matvecs_per_solve: float):
-    """The oracle (NumPy FP64, window FFT route) timed on the host: one plan
-    setup and one matvec at the benchmark's grid, scaled to solves/s with the
-    GPU FP64 solver's matvec count."""
+def cpu_model():
+    """The host CPU's model name as lscpu reports it (else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        return None
+
+
+def oracle_leg(workload: str, n: int, matvecs_per_solve: float, inc, dens, dens64, residual_rhs):
+    """The oracle (NumPy FP64, window FFT route) on the host.
+
+    * CPU baseline: one plan setup and one matvec at the benchmark's grid,
+      scaled to solves/s with the GPU FP64 solver's matvec count; the same
+      matvec with one FFT worker.
+    * Parity of the timed batch: the oracle's true relative residual
+      ||b - A x|| / ||b|| of the GPU mixed solutions of the right-hand sides
+      `residual_rhs`, and one oracle GMRES solve (right-hand side 0, to a
+      residual of 1e-13) against the GPU mixed and FP64 solutions of the same
+      right-hand side, element by element (relative l2)."""
     from oracle import operator as op
+    from oracle import solve as sv
+    from oracle import tables as tb
     prob = make_problem(workload, n, 1)
     t0 = time.perf_counter()
     A = op.Operator(prob.kind, prob.coef, prob.omega, mu=prob.mu)
     setup = time.perf_counter() - t0
-    from oracle import tables as tb
     t0 = time.perf_counter()
-    A.apply(prob.inc[0])
+    A.apply(inc[0])
     mv = time.perf_counter() - t0
-    # the same matvec with one FFT worker
     workers = tb.WORKERS
     tb.WORKERS = 1
     try:
         t0 = time.perf_counter()
-        A.apply(prob.inc[0])
+        A.apply(inc[0])
         mv1 = time.perf_counter() - t0
     finally:
         tb.WORKERS = workers
     solve_s = mv * matvecs_per_solve
-    model = None
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
-    except OSError:
-        pass
-    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": workers, "kind": "oracle",
-            "sample": (f"one FP64 matvec of the oracle at {prob.n}^3 ({mv:.2f} s; scipy.fft with "
-                       f"{workers} workers, the rest single-threaded numpy; table setup {setup:.1f} s "
-                       f"not counted) x {matvecs_per_solve:.1f} matvecs per solve (the GPU FP64 "
-                       f"GMRES count for the same right-hand sides)"),
-            "matvec_s": mv, "matvec_s_1_worker": mv1, "value_1_worker": 1.0 / (mv1 * matvecs_per_solve),
-            "setup_s": setup, "cpu_model": model}
+    cpu = {"value": 1.0 / solve_s, "unit": "solves/s", "cores": workers, "kind": "oracle",
+           "sample": (f"one FP64 matvec of the oracle at {prob.n}^3 ({mv:.2f} s; scipy.fft with "
+                      f"{workers} workers, the rest numpy; table setup {setup:.1f} s not counted) x "
+                      f"{matvecs_per_solve:.1f} matvecs per solve (the GPU FP64 GMRES count for the same "
+                      f"right-hand sides)"),
+           "matvec_s": mv, "matvec_s_1_worker": mv1, "value_1_worker": 1.0 / (mv1 * matvecs_per_solve),
+           "setup_s": setup, "cpu_model": cpu_model()}
+    t0 = time.perf_counter()
+    res = []
+    for r in residual_rhs:
+        b = A.rhs(inc[r])
+        res.append(float(np.linalg.norm(b - A.apply(dens[r])) / np.linalg.norm(b)))
+    x0, info = sv.gmres(A.apply, A.rhs(inc[0]), tol=1e-13, restart=100)
+    ref = float(np.linalg.norm(x0))
+    parity = {"oracle_rel_residual_max": max(res), "oracle_residual_rhs": list(residual_rhs),
+              "err_vs_oracle": float(np.linalg.norm(dens[0] - x0)) / ref,
+              "err_vs_oracle_fp64": float(np.linalg.norm(dens64[0] - x0)) / ref if dens64 is not None else None,
+              "oracle_solve": {"rhs": 0, "tol": 1e-13, "matvecs": info["matvecs"],
+                               "rel_residual": info["rel_residual"]},
+              "oracle_parity_s": time.perf_counter() - t0}
+    return cpu, parity
 
 
 def main(argv=None):
@@ -110,8 +150,10 @@ def main(argv=None):
     ap.add_argument("--inner-tol", type=float, default=0.0,
                     help="relative residual reduction of each FP32 inner cycle (0: the library's, 1e-5)")
     ap.add_argument("--fp64-steps", type=int, default=2)
-    ap.add_argument("--latency-solves", type=int, default=20, help="single-RHS mixed solves for p50/p99")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-solves", type=int, default=30, help="single-RHS mixed solves for p50/p99")
+    ap.add_argument("--profile-steps", type=int, default=2,
+                    help="steps of the second pass, timed per kernel with HIP events (0: none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (CPU baseline and parity)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-post", action="store_true", help="skip timing the post-processing calls")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -163,8 +205,8 @@ def main(argv=None):
         solve(inc)
     torch.cuda.synchronize()
 
-    # ---- timed region: K batched mixed solves, kernels timed with HIP events
-    plan.profile(True)
+    # ---- timed region: K batched mixed solves (kernel timing off, so the
+    # solver's applies replay from their captured hipGraphs)
     step_s, stats_all = [], []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
@@ -174,18 +216,33 @@ def main(argv=None):
         torch.cuda.synchronize()
         step_s.append(time.perf_counter() - t0)
         stats_all.extend(st)
-        print(f"[bench] step {k}: {step_s[-1]*1e3:.1f} ms, iters {[s['iters'] for s in st]}",
+        print(f"[bench] step {k}: {step_s[-1]*1e3:.1f} ms, iters {[s['iters'] for s in st][:8]}",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all
-    prof = plan.profile_read()
-    plan.profile(False)
     solves = args.steps * B
     value = solves / total
+
+    # ---- profiled pass over the same steps: per-kernel HIP events on the
+    # launch stream (eager launches), algorithmic bytes and nominal flops
+    prof = {}
+    prof_step_ms = None
+    if args.profile_steps > 0:
+        plan.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.profile_steps):
+            solve(inc)
+        torch.cuda.synchronize()
+        prof_step_ms = 1e3 * (time.perf_counter() - t0) / args.profile_steps
+        prof = plan.profile_read()
+        plan.profile(False)
+        print(f"[bench] profiled pass: {prof_step_ms:.1f} ms per step", file=sys.stderr, flush=True)
 
     # ---- the other solver on the same batch: plain FP64 (or mixed, when the
     # workload's own figure is the FP64 solver's)
     fp64 = {}
+    d64_host = None
     if not args.no_fp64 and args.fp64_steps > 0:
         ts = []
         for k in range(args.fp64_steps):
@@ -195,6 +252,7 @@ def main(argv=None):
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
         err = float(torch.linalg.vector_norm(d_mixed - d64) / torch.linalg.vector_norm(d64))
+        d64_host = d64.cpu().numpy()
         other = "mixed" if primary_fp64 else "fp64"
         fp64 = {f"{other}_solves_per_s": B * len(ts) / sum(ts),
                 f"{other}_ms_per_step": 1e3 * sum(ts) / len(ts),
@@ -214,32 +272,42 @@ def main(argv=None):
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
 
-    # ---- roofline of the dominant kernel family (HIP events, algorithmic
-    # bytes and nominal flops): ALU-bound when its arithmetic intensity is
-    # above the ridge point peak_flops / peak_bandwidth
-    fam, (ms, cnt, by, fl) = max(prof.items(), key=lambda kv: kv[1][0])
-    ridge = MI355X_VALU_PEAK_TFLOPS * 1e12 / (MI355X_HBM_PEAK_GBS * 1e9)
-    alu = fl / by > ridge
-    # HBM bytes per launch from the committed counter summary of this kernel
-    # and workload, if the device sources are unchanged since it was taken
-    from paper_1805_04791_amd import profiling
-    tag = f"helmholtz{n}" if wl == "helmholtz128" else wl
-    tr = profiling.read_traffic(os.path.join(ROOT, "profiles", f"{fam}.{tag}.traffic.md"))
-    digest = profiling.source_digest()
-    traffic = tr[0] if tr is not None and tr[2] == digest else None
-    if alu:
-        achieved, peak, unit = fl / (ms * 1e-3) / 1e12, MI355X_VALU_PEAK_TFLOPS, "TFLOP/s"
-    else:
-        achieved, peak, unit = by / (ms * 1e-3) / 1e9, MI355X_HBM_PEAK_GBS, "GB/s"
-    roof = {"bound": "alu" if alu else "hbm", "kernel": fam, "achieved": achieved, "peak": peak,
-            "unit": unit, "frac": achieved / peak, "traffic": traffic,
-            "avg_launch_us": 1e3 * ms / cnt, "bytes_per_launch": by / cnt, "flops_per_launch": fl / cnt,
-            "flop_per_byte": fl / by, "ridge_flop_per_byte": ridge,
-            "hbm_GBs": by / (ms * 1e-3) / 1e9, "source_digest": digest}
-    breakdown = {k: {"ms": v[0], "launches": v[1],
-                     "GB/s": v[2] / (v[0] * 1e-3) / 1e9 if v[0] > 0 else None,
-                     "TFLOP/s": v[3] / (v[0] * 1e-3) / 1e12 if v[0] > 0 else None}
-                 for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
+    # ---- roofline of the dominant kernel family (HIP events of the profiled
+    # pass, algorithmic bytes, nominal flops): compute-bound when its
+    # arithmetic intensity exceeds the ridge of the published peaks of its
+    # precision, else HBM-bound; the byte rate against 8 TB/s is reported
+    # either way
+    roof, breakdown = None, {}
+    if prof:
+        fam, (ms, cnt, by, fl) = max(prof.items(), key=lambda kv: kv[1][0])
+        fp32 = fam.endswith("_fp32")
+        peak_tf = MI355X_FP32_PEAK_TFLOPS if fp32 else MI355X_FP64_PEAK_TFLOPS
+        ridge = peak_tf * 1e12 / (MI355X_HBM_PEAK_GBS * 1e9)
+        alu = fl / by > ridge
+        from paper_1805_04791_amd import profiling
+        tag = f"helmholtz{n}" if wl == "helmholtz128" else wl
+        tr = profiling.read_traffic(os.path.join(ROOT, "profiles", f"{fam}.{tag}.traffic.md"))
+        digest = profiling.source_digest()
+        traffic = tr[0] if tr is not None and tr[2] == digest else None
+        hbm_gbs = by / (ms * 1e-3) / 1e9
+        tflops = fl / (ms * 1e-3) / 1e12
+        if alu:
+            achieved, peak, unit = tflops, peak_tf, "TFLOP/s"
+        else:
+            achieved, peak, unit = hbm_gbs, MI355X_HBM_PEAK_GBS, "GB/s"
+        roof = {"bound": "alu" if alu else "hbm", "kernel": fam, "achieved": achieved, "peak": peak,
+                "unit": unit, "frac": achieved / peak, "traffic": traffic,
+                "avg_launch_us": 1e3 * ms / cnt, "bytes_per_launch": by / cnt, "flops_per_launch": fl / cnt,
+                "flop_per_byte": fl / by, "ridge_flop_per_byte": ridge,
+                "hbm_GBs": hbm_gbs, "hbm_frac": hbm_gbs / MI355X_HBM_PEAK_GBS,
+                "valu_nominal_TFLOPs": tflops, "valu_frac_published": tflops / peak_tf,
+                "valu_frac_unpacked": tflops / (MI355X_FP32_UNPACKED_TFLOPS if fp32 else MI355X_FP64_PEAK_TFLOPS),
+                "timing": f"HIP events on the launch stream, {args.profile_steps} profiled steps",
+                "source_digest": digest}
+        breakdown = {k: {"ms": v[0], "launches": v[1],
+                         "GB/s": v[2] / (v[0] * 1e-3) / 1e9 if v[0] > 0 else None,
+                         "TFLOP/s": v[3] / (v[0] * 1e-3) / 1e12 if v[0] > 0 else None}
+                     for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
 
     # post-processing of the batch's densities: potential on the grid, fields at
     # 64 points outside the support, far-field patterns in 256 directions
@@ -275,8 +343,9 @@ def main(argv=None):
     torch.cuda.synchronize()
     copy_gbs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
-    roof["copy_GBs"] = copy_gbs
-    roof["hbm_frac_of_copy"] = roof["hbm_GBs"] / copy_gbs
+    if roof:
+        roof["copy_GBs"] = copy_gbs
+        roof["hbm_frac_of_copy"] = roof["hbm_GBs"] / copy_gbs
 
     # the whole FFT matvec of the timed solver (its five passes, in the
     # precision the Krylov iteration applies): algorithmic bytes over time
@@ -291,13 +360,19 @@ def main(argv=None):
         matvec["frac_of_hbm_peak"] = matvec["hbm_GBs"] / MI355X_HBM_PEAK_GBS
         matvec["frac_of_copy"] = matvec["hbm_GBs"] / copy_gbs
 
-    cpu = None
+    cpu, parity = None, {}
     if not args.no_cpu_baseline:
         mv = (float(np.mean([s["matvecs_fp64"] for s in stats_all])) if primary_fp64 else
               fp64.get("fp64_matvecs_per_solve") or float(np.mean([s["matvecs_fp32"] + s["matvecs_fp64"]
                                                                    for s in stats_all])))
-        print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(wl, args.n, mv)
+        print("[bench] oracle leg (CPU): baseline timing and parity of the timed batch ...",
+              file=sys.stderr, flush=True)
+        # the oracle's residual of every right-hand side of the batch, or of 8
+        # seeded ones of a larger batch
+        rr = list(range(B)) if B <= 8 else sorted(int(i) for i in np.random.default_rng(5).choice(B, 8, replace=False))
+        cpu, parity = oracle_leg(wl, args.n, mv, prob.inc, d_mixed.cpu().numpy(), d64_host, rr)
+        print(f"[bench] oracle: err {parity['err_vs_oracle']:.2e}, residual max "
+              f"{parity['oracle_rel_residual_max']:.2e}", file=sys.stderr, flush=True)
 
     if wl == "helmholtz128":
         desc = (f"helmholtz{n}: anisotropic Helmholtz {n}^3, omega={omega:.6g}, "
@@ -322,10 +397,12 @@ def main(argv=None):
         "matvecs_fp64_per_solve": float(np.mean([s["matvecs_fp64"] for s in stats_all])),
         "max_rel_residual": float(max(s["rel_residual"] for s in stats_all)),
         **fp64,
+        **parity,
         "roofline": roof,
         "matvec": matvec,
         "postprocess_ms_per_batch": post,
         "kernels": breakdown,
+        "profiled_ms_per_step": prof_step_ms,
         "cpu_baseline": cpu,
     }
     if fp64 and not primary_fp64:

@@ -186,6 +186,46 @@ int vie_field(vie_plan *pl, const double *density, const double *inc, double *fi
 int vie_solve(vie_plan *pl, const double *inc, double *density, double *field, int nrhs,
               const vie_solve_opts *opts, vie_solve_stats *stats, void *hip_stream);
 
+/* Continuous batching: the solve of vie_solve (the integral equations in
+ * the header comment, GMRES or Bi-CGStab with FP64 true-residual refinement)
+ * run step by step on a batch of `capacity` slots (1..256) of one plan, so
+ * that right-hand sides can join while others are being solved and leave as
+ * soon as they are done.  One batch per plan; vie_solve returns VIE_E_STATE
+ * while it is open.  Each slot's arithmetic is independent of the other
+ * slots, of its position and of when it joined: a right-hand side gets
+ * bitwise the result vie_solve gives it alone with the same options.
+ *
+ * vie_batch_open:  opens the batch with the options of vie_solve (opts may be
+ *                  NULL: its defaults); sizes the Krylov workspace for it.
+ * vie_batch_add:   nrhs incident fields (device, [nrhs][c][n^3] as in
+ *                  vie_solve; x0 NULL or initial densities of the same
+ *                  layout) take free slots, written to slots[0..nrhs-1]; they
+ *                  start iterating at the next vie_batch_step.  The inputs are
+ *                  read before the call returns (it synchronises the stream).
+ *                  VIE_E_ARG if fewer than nrhs slots are free.
+ * vie_batch_step:  one outer cycle (an inner GMRES cycle of `restart`
+ *                  iterations or a Bi-CGStab run, then the FP64 true
+ *                  residual) for every slot still iterating; *nactive =
+ *                  slots still iterating after it.  Synchronises the stream.
+ * vie_batch_done:  host arrays: the finished slots not yet taken (up to
+ *                  max_slots of them in slots, their count in *ndone) and the
+ *                  free slots (*nfree).
+ * vie_batch_take:  writes a finished slot's density (device, [c][n^3], zero
+ *                  outside the support rows) and, if field is not NULL, the
+ *                  total field (then inc is its incident field [c][n^3]),
+ *                  fills *stats (seconds: from its vie_batch_add to the step
+ *                  that finished it; may be NULL) and frees the slot.
+ *                  Returns VIE_OK or VIE_W_NOCONV (the slot's status).
+ * vie_batch_close: frees the batch (slots still holding right-hand sides are
+ *                  dropped); the plan stays valid. */
+int vie_batch_open(vie_plan *pl, int capacity, const vie_solve_opts *opts, void *hip_stream);
+int vie_batch_add(vie_plan *pl, const double *inc, const double *x0, int nrhs, int *slots, void *hip_stream);
+int vie_batch_step(vie_plan *pl, int *nactive, void *hip_stream);
+int vie_batch_done(vie_plan *pl, int *slots, int max_slots, int *ndone, int *nfree);
+int vie_batch_take(vie_plan *pl, int slot, double *density, double *field, const double *inc,
+                   vie_solve_stats *stats, void *hip_stream);
+int vie_batch_close(vie_plan *pl);
+
 /* Synchronises the stream of the plan's latest call, then frees the plan.
  * Work on other streams that uses the plan must have completed.  Its device
  * blocks (and small pinned host buffers) go to a process-wide cache from

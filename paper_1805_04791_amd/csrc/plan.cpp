@@ -897,6 +897,7 @@ void destroy_plan(vie_plan* pl) {
   // allocation meanwhile
   quiesce(pl);
   std::lock_guard<std::recursive_mutex> lk(hip_mutex());
+  vie::close_session(pl);
   vie::clear_graphs(pl);
   if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
   pl->gstream = nullptr;

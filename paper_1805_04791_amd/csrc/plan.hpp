@@ -15,6 +15,8 @@
 
 namespace vie {
 
+struct SolveSession;  // an open batch of solver slots (solve.cpp)
+
 // Extent of the data an apply works on: the whole grid, or the bounding box
 // of the support of H (the Krylov vectors vanish outside it exactly).
 // Spectral data of one periodic grid: transform length Pz along z and Pxy
@@ -90,6 +92,7 @@ struct vie_plan {
   vie::c128* V = nullptr;  // [(m+1)][cap][L]
   int kr_cap = 0, kr_m = 0;
   vie::c128 *xw = nullptr, *bw = nullptr, *rw = nullptr, *ww = nullptr;
+  vie::c128* xbest = nullptr;  // per slot: the iterate with the smallest true residual so far
   vie::c128* partials = nullptr;  // [cap][nblk][m+2]
   vie::c128* red = nullptr;       // [cap][m+2]
   vie::c128* red_host = nullptr;  // pinned
@@ -101,6 +104,7 @@ struct vie_plan {
   unsigned char* stage_dev = nullptr;
   size_t stage_bytes = 0, stage_off_count = 0, stage_off_coef = 0;
   int* actd = nullptr;            // [cap] flags of the right-hand sides still iterating (0 = skip)
+  vie::SolveSession* session = nullptr;  // the open batch of slots (vie_solve, vie_batch_*)
   std::vector<int> act_last;      // the flags last written to actd
 
   size_t dev_bytes = 0;
@@ -213,5 +217,7 @@ void prof_end(vie_plan* pl, int fam, int token, hipStream_t s, double bytes, dou
 
 int solve_batch(vie_plan* pl, const c128* inc, c128* density, c128* field, int nrhs, const vie_solve_opts& o,
                 vie_solve_stats* stats, hipStream_t s);
+// frees the plan's open batch, if any
+void close_session(vie_plan* pl);
 
 }  // namespace vie

@@ -15,16 +15,25 @@
 // ||r|| / ||b|| <= tol.  Plain FP64 runs the same loop with the FP64 apply.
 //
 // Right-hand sides are advanced together in fused launches, but every
-// decision (re-orthogonalisation, convergence, inner cycle length, budget) is
-// taken per right-hand side and every reduction has a fixed order, so a
-// right-hand side gets bitwise the same answer alone or in a batch.  Slots
-// that have stopped are skipped by the launches (device flags per slot).
+// decision (re-orthogonalisation, convergence, stagnation, inner cycle
+// length, budget) is taken per right-hand side, every launch touches a slot
+// only with that slot's own coefficients, and every reduction has a fixed
+// order, so a right-hand side gets bitwise the same answer alone or in a
+// batch.  Slots that have stopped are skipped by the launches (device flags
+// per slot).
+//
+// Stagnation: a slot whose true residual has not fallen below 0.9 times its
+// value of kStallMatvecs (or 3 restart cycles, if longer) matvecs earlier
+// stops with VIE_W_NOCONV.  A slot that stops without reaching its target
+// (stagnation, budget, a non-finite residual) returns the iterate with the
+// smallest true residual it had.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <complex>
+#include <limits>
 #include <vector>
 
 #include "apply_kernels.hpp"
@@ -52,7 +61,13 @@ struct RhsState {
   double bnorm = 0, rnorm = 0;
   bool done = false, conv = false;
   int iters = 0, mv32 = 0, mv64 = 0, refine = 0;
+  double best = 0;            // smallest true residual so far (its iterate is in xbest)
+  double ref = 0;             // stagnation reference: true residual at matvec count ref_mv
+  int ref_mv = 0;
+  int matvecs() const { return mv32 + mv64; }
 };
+
+constexpr int kStallMatvecs = 300;
 
 // Work vectors for batches of `cap` right-hand sides and bases of m + 1 vectors.
 int ensure_krylov(vie_plan* pl, int cap, int m, hipStream_t s) {
@@ -68,11 +83,12 @@ int ensure_krylov(vie_plan* pl, int cap, int m, hipStream_t s) {
   dev_free(pl, pl->bw);
   dev_free(pl, pl->rw);
   dev_free(pl, pl->ww);
+  dev_free(pl, pl->xbest);
   dev_free(pl, pl->partials);
   dev_free(pl, pl->red);
   dev_free(pl, pl->stage_dev);
   dev_free(pl, pl->actd);
-  pl->V = pl->xw = pl->bw = pl->rw = pl->ww = pl->partials = pl->red = nullptr;
+  pl->V = pl->xw = pl->bw = pl->rw = pl->ww = pl->xbest = pl->partials = pl->red = nullptr;
   pl->stage_dev = nullptr;
   pl->actd = nullptr;
   pl->act_last.clear();
@@ -89,6 +105,7 @@ int ensure_krylov(vie_plan* pl, int cap, int m, hipStream_t s) {
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->bw), vec);
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->rw), vec);
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->ww), vec);
+  if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->xbest), vec);
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->partials), sizeof(c128) * zu(cap) * nblk * zu(m + 2));
   if (!rc) rc = dev_alloc(pl, reinterpret_cast<void**>(&pl->red), sizeof(c128) * zu(cap) * zu(m + 2));
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
@@ -179,6 +196,7 @@ template <typename TV, typename TW, typename TO>
 int combine_host(const Batch& b, const TV* V, const TW* w, TO* out, int nv, const std::vector<cd>& coef,
                  const std::vector<double>& scale, const std::vector<int>* counts = nullptr) {
   vie_plan* pl = b.pl;
+  if (b.L <= 0) return VIE_OK;  // no unknowns (H = 0 everywhere): nothing to combine
   const int stride = std::max(nv, 1);
   // vectors read per right-hand side (for the byte counts)
   double nvec = 0.0, nrun = 0.0;
@@ -255,7 +273,11 @@ int norms(const Batch& b, const c128* v, std::vector<double>& out, const int* ac
   int rc = dots_host(b, static_cast<const c128*>(nullptr), v, 0, act, nact);
   if (rc) return rc;
   out.resize(zu(b.nb));
-  for (int r = 0; r < b.nb; ++r) out[zu(r)] = std::sqrt(std::max(0.0, red_at(b, r, 0, 1).real()));
+  for (int r = 0; r < b.nb; ++r) {
+    // a NaN sum stays NaN (std::max would turn it into 0, i.e. "b = 0")
+    const double v = red_at(b, r, 0, 1).real();
+    out[zu(r)] = std::isnan(v) ? v : std::sqrt(std::max(0.0, v));
+  }
   return VIE_OK;
 }
 
@@ -319,7 +341,6 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
     const int nv = j + 1;
     rc = w32 ? dots_host(b, basis, wv32, nv, act, nact) : dots_host(b, basis, wv, nv, act, nact);
     if (rc) return rc;
-    cnt = counts_of(active, nv);
     bool any_reorth = false;
     for (int r = 0; r < nb; ++r) {
       double p = 0;
@@ -340,8 +361,13 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
       for (int i = 0; i < nv; ++i) hcol[zu(r) * zu(nv + 1) + zu(i)] = h1[zu(r) * zu(nv) + zu(i)];
     if (any_reorth) {
       std::vector<double> one(static_cast<size_t>(nb), 1.0);
-      // w <- w - V h1
-      rc = w32 ? combine_host(b, basis, wv32, wv32, nv, h1, one, &cnt) : combine_host(b, basis, wv, wv, nv, h1, one, &cnt);
+      // w <- w - V h1 for the slots that re-orthogonalise only (the others
+      // form V_{j+1} from their own w and h1 below, exactly as alone)
+      std::vector<int> cnt_re(static_cast<size_t>(nb), -1);
+      for (int r = 0; r < nb; ++r)
+        if (reorth[zu(r)]) cnt_re[zu(r)] = nv;
+      rc = w32 ? combine_host(b, basis, wv32, wv32, nv, h1, one, &cnt_re)
+               : combine_host(b, basis, wv, wv, nv, h1, one, &cnt_re);
       if (rc) return rc;
       rc = w32 ? dots_host(b, basis, wv32, nv, act, nact) : dots_host(b, basis, wv, nv, act, nact);
       if (rc) return rc;
@@ -434,7 +460,12 @@ int gmres_cycle(const Batch& b, bool fp64, int m, const std::vector<double>& rno
       }
     }
     if (any_next) {
-      const std::vector<cd>& vc = any_reorth ? coef2 : h1;
+      // per slot: the second-pass coefficients on the re-orthogonalised w,
+      // else the first-pass ones on the original w
+      std::vector<cd> vc(h1);
+      for (int r = 0; r < nb; ++r)
+        if (reorth[zu(r)])
+          for (int i = 0; i < nv; ++i) vc[zu(r) * zu(nv) + zu(i)] = coef2[zu(r) * zu(nv) + zu(i)];
       rc = w32 ? combine_host(b, basis, wv32, Vn, nv, vc, scale, &cnt_next)
                : combine_host(b, basis, wv, Vn, nv, vc, scale, &cnt_next);
       if (rc) return rc;
@@ -566,131 +597,361 @@ int bicgstab_run(const Batch& b, bool fp64, const std::vector<double>& rnorm0, c
 
 }  // namespace
 
-int solve_batch(vie_plan* pl, const c128* inc, c128* density, c128* field, int nrhs, const vie_solve_opts& o,
-                vie_solve_stats* stats, hipStream_t s) {
+// ---------------------------------------------------------------------------
+// Solver sessions: a batch of `cap` slots on the plan's Krylov workspace.
+// Right-hand sides join free slots at any cycle boundary (session_add), every
+// step advances all slots still iterating by one outer cycle (an inner GMRES
+// cycle or Bi-CGStab run and the FP64 true residual), and finished slots are
+// read out and freed (session_take) while the others continue.  vie_solve is
+// a session filled with one chunk of right-hand sides at a time; the
+// continuous-batching calls (vie_batch_*) expose it.  Each slot's arithmetic
+// does not depend on the others, on its position, or on when it joined.
+// ---------------------------------------------------------------------------
+struct SolveSession {
+  vie_solve_opts o{};
+  bool mixed = false;
+  bool user = false;  // opened through vie_batch_open
+  int m = 0, cap = 0;
+  long L = 0;
+  std::vector<RhsState> st;
+  std::vector<char> used;  // the slot holds a right-hand side not yet taken
+  std::vector<std::chrono::steady_clock::time_point> t_add, t_done;
+};
+
+namespace {
+
+Batch batch_of(vie_plan* pl, const SolveSession& S, hipStream_t s) {
+  return Batch{pl, s, S.cap, S.L, long(pl->kr_cap) * S.L, krylov_blocks(S.L)};
+}
+
+bool ends(const RhsState& S) { return S.done; }
+
+}  // namespace
+
+void close_session(vie_plan* pl) {
+  delete pl->session;
+  pl->session = nullptr;
+}
+
+int open_session(vie_plan* pl, int cap, const vie_solve_opts& o, bool user, hipStream_t s) {
+  if (pl->session) return fail(pl, VIE_E_STATE, "a batch is already open on this plan");
+  if (cap < 1 || cap > kMaxFlagged) return fail(pl, VIE_E_ARG, "batch capacity must be in [1, 256]");
   const bool mixed = pl->precision == VIE_PREC_MIXED && !(o.flags & VIE_SOLVE_FP64);
   const int m = o.solver == VIE_SOLVER_BICGSTAB ? 5 : std::max(1, o.restart);
+  int rc = ensure_krylov(pl, cap, std::max(m, 5), s);
+  if (rc) return rc;
+  SolveSession* S = new (std::nothrow) SolveSession();
+  if (!S) return fail(pl, VIE_E_NOMEM, "session");
+  S->o = o;
+  S->mixed = mixed;
+  S->user = user;
+  S->m = m;
+  S->cap = cap;
   // Outside supp(H) the equation gives J = 0 exactly, so the unknowns are
   // the points of supp(H): per (z, y) row of its bounding box, the x-interval
   // from the first to the last support point.  U is needed only there too.
-  const long L = long(pl->C) * pl->box.np;
+  S->L = long(pl->C) * pl->box.np;
+  S->st.assign(zu(cap), RhsState{});
+  for (auto& x : S->st) x.done = true;
+  S->used.assign(zu(cap), 0);
+  S->t_add.resize(zu(cap));
+  S->t_done.resize(zu(cap));
+  pl->session = S;
+  return VIE_OK;
+}
+
+// Right-hand sides k of inc (whole-grid layout [k][C][n^3]) into free slots
+// (written to slots[0..k-1]); x0: optional initial densities of the same layout.
+int session_add(vie_plan* pl, const c128* inc, const c128* x0, int k, int* slots, hipStream_t s) {
+  SolveSession* S = pl->session;
+  const long L = S->L;
+  const long Lg = long(pl->C) * pl->n3;
+  const Box box = box_of(pl->box, pl->n);
+  std::vector<int> sl;
+  for (int r = 0; r < S->cap && int(sl.size()) < k; ++r)
+    if (!S->used[zu(r)]) sl.push_back(r);
+  if (int(sl.size()) < k) return fail(pl, VIE_E_ARG, "not enough free slots in the batch");
+  Batch b = batch_of(pl, *S, s);
+  std::vector<bool> fresh(zu(S->cap), false);
+  for (int i = 0; i < k; ++i) {
+    const int r = sl[zu(i)];
+    fresh[zu(r)] = true;
+    // b = 2 H g
+    HIPCHK(pl, launch_rhs(pl->H64, pl->Hmu64, inc + long(i) * Lg, pl->bw + long(r) * L, 1, pl->C, box, s));
+    if (x0) {
+      HIPCHK(pl, launch_gather(x0 + long(i) * Lg, pl->xw + long(r) * L, pl->C, box, s));
+    } else {
+      HIPCHK(pl, launch_fill(pl->xw + long(r) * L, L, c128{0.0, 0.0}, s));
+      HIPCHK(pl, launch_copy(pl->bw + long(r) * L, pl->rw + long(r) * L, L, s));
+    }
+  }
+  int rc = VIE_OK, nact = 0;
+  const int* act = set_active(b, fresh, &nact, &rc);
+  if (rc) return rc;
+  std::vector<double> bnorm, rnorm;
+  rc = norms(b, pl->bw, bnorm, act, nact);
+  if (rc) return rc;
+  if (x0) {
+    rc = apply_any(pl, pl->box, true, pl->xw, pl->xw, pl->bw, pl->rw, S->cap, MODE_RESIDUAL, s, act, nact);
+    if (rc) return rc;
+  }
+  rc = norms(b, pl->rw, rnorm, act, nact);
+  if (rc) return rc;
+  const auto now = std::chrono::steady_clock::now();
+  std::vector<int> c0(zu(S->cap), -1);
+  for (int i = 0; i < k; ++i) {
+    const int r = sl[zu(i)];
+    RhsState& T = S->st[zu(r)];
+    T = RhsState{};
+    T.bnorm = bnorm[zu(r)];
+    T.rnorm = T.best = T.ref = rnorm[zu(r)];
+    if (x0) T.mv64++;
+    if (!std::isfinite(T.bnorm) || !std::isfinite(T.rnorm)) {
+      // a non-finite incident field (or initial guess): nothing to iterate on
+      T.done = true;
+    } else if (!(T.bnorm > 0)) {
+      // b = 0: x = 0 is exact
+      T.done = T.conv = true;
+      T.rnorm = 0;
+    } else if (T.rnorm <= S->o.tol * T.bnorm) {
+      T.done = T.conv = true;
+    }
+    S->used[zu(r)] = 1;
+    S->t_add[zu(r)] = S->t_done[zu(r)] = now;
+    c0[zu(r)] = 0;
+    if (slots) slots[i] = r;
+  }
+  // the best iterate so far of every new slot: its initial one
+  std::vector<double> one(zu(S->cap), 1.0);
+  std::vector<cd> none;
+  const c128* nov = nullptr;
+  return combine_host(b, nov, pl->xw, pl->xbest, 0, none, one, &c0);
+}
+
+// One outer cycle for every slot still iterating; *nactive = slots still
+// iterating afterwards.
+int session_step(vie_plan* pl, hipStream_t s, int* nactive) {
+  SolveSession* Sx = pl->session;
+  const vie_solve_opts& o = Sx->o;
+  const int nb = Sx->cap, m = Sx->m;
+  std::vector<RhsState>& st = Sx->st;
+  Batch b = batch_of(pl, *Sx, s);
+  int rc = VIE_OK;
+  std::vector<double> target(zu(nb)), rnorm(zu(nb));
+  std::vector<bool> active(zu(nb));
+  std::vector<int> budget(zu(nb));
+  bool any = false;
+  for (int r = 0; r < nb; ++r) {
+    const RhsState& S = st[zu(r)];
+    active[zu(r)] = Sx->used[zu(r)] && !ends(S);
+    any = any || active[zu(r)];
+    const double inner = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+    target[zu(r)] = Sx->mixed ? std::max(inner * S.rnorm, 0.3 * o.tol * S.bnorm) : 0.5 * o.tol * S.bnorm;
+    budget[zu(r)] = std::max(1, o.max_iters - 1);
+    rnorm[zu(r)] = active[zu(r)] ? S.rnorm : 0.0;
+  }
+  if (any) {
+    if (o.solver == VIE_SOLVER_BICGSTAB)
+      rc = bicgstab_run(b, !Sx->mixed, rnorm, target, st, active, budget);
+    else
+      rc = gmres_cycle(b, !Sx->mixed, m, rnorm, target, st, active, budget);
+    if (rc) return rc;
+    // true residual with the FP64 operator, for the slots that iterated
+    int nlive = 0;
+    const int* act = set_active(b, active, &nlive, &rc);
+    if (rc) return rc;
+    rc = apply_graph(pl, pl->box, true, pl->xw, pl->xw, pl->bw, pl->rw, nb, MODE_RESIDUAL, s, act, nlive);
+    if (rc) return rc;
+    rc = norms(b, pl->rw, rnorm, act, nlive);
+    if (rc) return rc;
+    const int stall_mv = std::max(kStallMatvecs, 3 * m);
+    std::vector<int> keep(zu(nb), -1), restore(zu(nb), -1);
+    bool any_keep = false, any_restore = false;
+    const auto now = std::chrono::steady_clock::now();
+    for (int r = 0; r < nb; ++r) {
+      if (!active[zu(r)]) continue;
+      RhsState& S = st[zu(r)];
+      S.mv64++;
+      S.refine++;
+      S.rnorm = rnorm[zu(r)];
+      const bool finite = std::isfinite(S.rnorm);
+      if (finite && S.rnorm < S.best) {
+        S.best = S.rnorm;
+        keep[zu(r)] = 0;
+        any_keep = true;
+      }
+      if (finite && S.rnorm <= 0.9 * S.ref) {
+        S.ref = S.rnorm;
+        S.ref_mv = S.matvecs();
+      }
+      if (finite && S.rnorm <= o.tol * S.bnorm) {
+        S.done = S.conv = true;
+      } else if (!finite || S.matvecs() >= o.max_iters || S.matvecs() - S.ref_mv >= stall_mv) {
+        // budget spent, stagnation or a non-finite residual: the best iterate
+        S.done = true;
+        if (!(S.rnorm <= S.best)) {
+          restore[zu(r)] = 0;
+          any_restore = true;
+          S.rnorm = S.best;
+        }
+      }
+      if (S.done) Sx->t_done[zu(r)] = now;
+    }
+    std::vector<double> one(zu(nb), 1.0);
+    std::vector<cd> none;
+    const c128* nov = nullptr;
+    if (any_keep) {
+      rc = combine_host(b, nov, pl->xw, pl->xbest, 0, none, one, &keep);
+      if (rc) return rc;
+    }
+    if (any_restore) {
+      rc = combine_host(b, nov, pl->xbest, pl->xw, 0, none, one, &restore);
+      if (rc) return rc;
+    }
+  }
+  int left = 0;
+  for (int r = 0; r < nb; ++r) left += (Sx->used[zu(r)] && !ends(st[zu(r)])) ? 1 : 0;
+  if (nactive) *nactive = left;
+  return VIE_OK;
+}
+
+void fill_stats(const RhsState& S, double secs, vie_solve_stats* x) {
+  x->status = S.conv ? VIE_OK : VIE_W_NOCONV;
+  x->iters = S.iters;
+  x->matvecs_fp32 = S.mv32;
+  x->matvecs_fp64 = S.mv64;
+  x->refinements = S.refine;
+  x->rel_residual = !std::isfinite(S.bnorm) ? std::numeric_limits<double>::quiet_NaN()
+                                            : (S.bnorm > 0 ? S.rnorm / S.bnorm : 0.0);
+  x->seconds = secs;
+}
+
+int solve_batch(vie_plan* pl, const c128* inc, c128* density, c128* field, int nrhs, const vie_solve_opts& o,
+                vie_solve_stats* stats, hipStream_t s) {
+  if (pl->session) return fail(pl, VIE_E_STATE, "vie_solve: a continuous batch is open on this plan");
   const long Lg = long(pl->C) * pl->n3;
   const Box box = box_of(pl->box, pl->n);
   const int cap = std::max(1, std::min(nrhs, pl->max_rhs));
-  int rc = ensure_krylov(pl, cap, std::max(m, 5), s);
+  int rc = open_session(pl, cap, o, false, s);
   if (rc) return rc;
+  SolveSession* S = pl->session;
   int status = VIE_OK;
-  for (int r0 = 0; r0 < nrhs; r0 += cap) {
+  for (int r0 = 0; r0 < nrhs && !rc; r0 += cap) {
     const auto t0 = std::chrono::steady_clock::now();
     const int nb = std::min(cap, nrhs - r0);
-    Batch b{pl, s, nb, L, long(pl->kr_cap) * L, krylov_blocks(L)};
     const long off = long(r0) * Lg;
-    // b = 2 H g
-    HIPCHK(pl, launch_rhs(pl->H64, pl->Hmu64, inc + off, pl->bw, nb, pl->C, box, s));
-    std::vector<double> bnorm, rnorm;
-    rc = norms(b, pl->bw, bnorm);
-    if (rc) return rc;
-    if (o.flags & VIE_SOLVE_X0) {
-      HIPCHK(pl, launch_gather(density + off, pl->xw, long(nb) * pl->C, box, s));
-      rc = apply_any(pl, pl->box, true, pl->xw, pl->xw, pl->bw, pl->rw, nb, MODE_RESIDUAL, s);
-      if (rc) return rc;
-    } else {
-      HIPCHK(pl, launch_fill(pl->xw, long(nb) * L, c128{0.0, 0.0}, s));
-      HIPCHK(pl, launch_copy(pl->bw, pl->rw, long(nb) * L, s));
+    std::vector<int> slots(zu(nb));
+    rc = session_add(pl, inc + off, (o.flags & VIE_SOLVE_X0) ? density + off : nullptr, nb, slots.data(), s);
+    int left = 1;
+    while (!rc && left > 0) rc = session_step(pl, s, &left);
+    if (rc) break;
+    // slots 0..nb-1 (the session was empty): one launch for the chunk
+    hipError_t e = launch_scatter(pl->xw, density + off, long(nb) * pl->C, box, s);
+    if (e != hipSuccess) {
+      rc = hip_fail(pl, e, "launch_scatter");
+      break;
     }
-    rc = norms(b, pl->rw, rnorm);
-    if (rc) return rc;
-    std::vector<RhsState> st(static_cast<size_t>(nb));
-    for (int r = 0; r < nb; ++r) {
-      st[zu(r)].bnorm = bnorm[zu(r)];
-      st[zu(r)].rnorm = rnorm[zu(r)];
-      if (o.flags & VIE_SOLVE_X0) st[zu(r)].mv64++;
-      if (!(bnorm[zu(r)] > 0)) {
-        // b = 0: x = 0 is exact
-        st[zu(r)].done = st[zu(r)].conv = true;
-        st[zu(r)].rnorm = 0;
-      } else if (rnorm[zu(r)] <= o.tol * bnorm[zu(r)]) {
-        st[zu(r)].done = st[zu(r)].conv = true;
-      }
-    }
-    std::vector<double> prev(rnorm);
-    int stall = 0;
-    for (int outer = 0; outer < 10000; ++outer) {
-      bool any = false;
-      for (int r = 0; r < nb; ++r) any = any || !st[zu(r)].done;
-      if (!any) break;
-      std::vector<double> target(static_cast<size_t>(nb));
-      std::vector<bool> active(static_cast<size_t>(nb));
-      std::vector<int> budget(static_cast<size_t>(nb));
-      for (int r = 0; r < nb; ++r) {
-        const RhsState& S = st[zu(r)];
-        active[zu(r)] = !S.done;
-        const double inner = o.inner_tol > 0 ? o.inner_tol : 1e-5;
-        target[zu(r)] = mixed ? std::max(inner * S.rnorm, 0.3 * o.tol * S.bnorm) : 0.5 * o.tol * S.bnorm;
-        budget[zu(r)] = std::max(1, o.max_iters - 1);
-        if (S.done) rnorm[zu(r)] = 0.0;
-      }
-      if (o.solver == VIE_SOLVER_BICGSTAB)
-        rc = bicgstab_run(b, !mixed, rnorm, target, st, active, budget);
-      else
-        rc = gmres_cycle(b, !mixed, m, rnorm, target, st, active, budget);
-      if (rc) return rc;
-      // true residual with the FP64 operator, for the slots still iterating
-      std::vector<bool> live(static_cast<size_t>(nb));
-      for (int r = 0; r < nb; ++r) live[zu(r)] = !st[zu(r)].done;
-      int nlive = 0;
-      const int* act = set_active(b, live, &nlive, &rc);
-      if (rc) return rc;
-      rc = apply_graph(pl, pl->box, true, pl->xw, pl->xw, pl->bw, pl->rw, nb, MODE_RESIDUAL, s, act, nlive);
-      if (rc) return rc;
-      rc = norms(b, pl->rw, rnorm, act, nlive);
-      if (rc) return rc;
-      bool progressed = false;
-      for (int r = 0; r < nb; ++r) {
-        RhsState& S = st[zu(r)];
-        if (S.done) continue;
-        S.mv64++;
-        S.refine++;
-        S.rnorm = rnorm[zu(r)];
-        if (S.rnorm < 0.9 * prev[zu(r)]) progressed = true;
-        prev[zu(r)] = S.rnorm;
-        if (S.rnorm <= o.tol * S.bnorm) {
-          S.done = S.conv = true;
-        } else if (S.mv32 + S.mv64 >= o.max_iters || !std::isfinite(S.rnorm)) {
-          S.done = true;
-        }
-      }
-      stall = progressed ? 0 : stall + 1;
-      if (stall >= 3) {
-        for (int r = 0; r < nb; ++r) st[zu(r)].done = true;
-      }
-    }
-    HIPCHK(pl, launch_scatter(pl->xw, density + off, long(nb) * pl->C, box, s));
     if (field) {
       rc = apply_any(pl, pl->grid, true, density + off, inc + off, nullptr, field + off, nb, MODE_FIELD, s);
-      if (rc) return rc;
+      if (rc) break;
     }
-    HIPCHK(pl, hipStreamSynchronize(s));
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      rc = hip_fail(pl, e, "hipStreamSynchronize");
+      break;
+    }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (int r = 0; r < nb; ++r) {
-      const RhsState& S = st[zu(r)];
-      if (!S.conv) status = VIE_W_NOCONV;
-      if (stats) {
-        vie_solve_stats& x = stats[r0 + r];
-        x.status = S.conv ? VIE_OK : VIE_W_NOCONV;
-        x.iters = S.iters;
-        x.matvecs_fp32 = S.mv32;
-        x.matvecs_fp64 = S.mv64;
-        x.refinements = S.refine;
-        x.rel_residual = S.bnorm > 0 ? S.rnorm / S.bnorm : 0.0;
-        x.seconds = secs;
-      }
+      const RhsState& T = S->st[zu(r)];
+      if (!T.conv) status = VIE_W_NOCONV;
+      if (stats) fill_stats(T, secs, &stats[r0 + r]);
+      S->used[zu(r)] = 0;
     }
   }
-  return status;
+  close_session(pl);
+  return rc ? rc : status;
 }
 
 }  // namespace vie
+
+using vie::SolveSession;
+
+extern "C" int vie_batch_open(vie_plan* pl, int capacity, const vie_solve_opts* opts, void* hip_stream) {
+  if (!pl) return VIE_E_ARG;
+  vie_solve_opts o{1e-10, 2000, 40, 0.0, VIE_SOLVER_GMRES, 0u};
+  if (opts) o = *opts;
+  if (!(o.tol > 0) || o.max_iters < 1 || o.restart < 1 || o.restart > 1000 ||
+      (o.solver != VIE_SOLVER_GMRES && o.solver != VIE_SOLVER_BICGSTAB))
+    return vie::fail(pl, VIE_E_ARG, "vie_batch_open: invalid options");
+  pl->last_stream = static_cast<hipStream_t>(hip_stream);
+  return vie::open_session(pl, capacity, o, true, static_cast<hipStream_t>(hip_stream));
+}
+
+extern "C" int vie_batch_add(vie_plan* pl, const double* inc, const double* x0, int nrhs, int* slots,
+                             void* hip_stream) {
+  if (!pl) return VIE_E_ARG;
+  if (!pl->session || !pl->session->user) return vie::fail(pl, VIE_E_STATE, "vie_batch_add: no open batch");
+  if (!inc || nrhs < 1) return vie::fail(pl, VIE_E_ARG, "vie_batch_add: null pointer or nrhs < 1");
+  pl->last_stream = static_cast<hipStream_t>(hip_stream);
+  return vie::session_add(pl, reinterpret_cast<const vie::c128*>(inc), reinterpret_cast<const vie::c128*>(x0),
+                          nrhs, slots, static_cast<hipStream_t>(hip_stream));
+}
+
+extern "C" int vie_batch_step(vie_plan* pl, int* nactive, void* hip_stream) {
+  if (!pl) return VIE_E_ARG;
+  if (!pl->session || !pl->session->user) return vie::fail(pl, VIE_E_STATE, "vie_batch_step: no open batch");
+  pl->last_stream = static_cast<hipStream_t>(hip_stream);
+  return vie::session_step(pl, static_cast<hipStream_t>(hip_stream), nactive);
+}
+
+extern "C" int vie_batch_done(vie_plan* pl, int* slots, int max_slots, int* ndone, int* nfree) {
+  if (!pl) return VIE_E_ARG;
+  if (!pl->session || !pl->session->user) return vie::fail(pl, VIE_E_STATE, "vie_batch_done: no open batch");
+  SolveSession* S = pl->session;
+  int d = 0, f = 0;
+  for (int r = 0; r < S->cap; ++r) {
+    if (!S->used[size_t(r)]) {
+      ++f;
+    } else if (S->st[size_t(r)].done) {
+      if (slots && d < max_slots) slots[d] = r;
+      ++d;
+    }
+  }
+  if (ndone) *ndone = d;
+  if (nfree) *nfree = f;
+  return VIE_OK;
+}
+
+extern "C" int vie_batch_take(vie_plan* pl, int slot, double* density, double* field, const double* inc,
+                              vie_solve_stats* stats, void* hip_stream) {
+  if (!pl) return VIE_E_ARG;
+  if (!pl->session || !pl->session->user) return vie::fail(pl, VIE_E_STATE, "vie_batch_take: no open batch");
+  SolveSession* S = pl->session;
+  if (slot < 0 || slot >= S->cap || !S->used[size_t(slot)] || !S->st[size_t(slot)].done)
+    return vie::fail(pl, VIE_E_ARG, "vie_batch_take: the slot holds no finished right-hand side");
+  if (!density || (field && !inc)) return vie::fail(pl, VIE_E_ARG, "vie_batch_take: null density (or inc with field)");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  pl->last_stream = s;
+  auto* d = reinterpret_cast<vie::c128*>(density);
+  HIPCHK(pl, vie::launch_scatter(pl->xw + long(slot) * S->L, d, pl->C, vie::box_of(pl->box, pl->n), s));
+  if (field) {
+    const int rc = vie::apply_any(pl, pl->grid, true, d, reinterpret_cast<const vie::c128*>(inc), nullptr,
+                                  reinterpret_cast<vie::c128*>(field), 1, vie::MODE_FIELD, s);
+    if (rc) return rc;
+  }
+  const vie::RhsState& T = S->st[size_t(slot)];
+  if (stats)
+    vie::fill_stats(T, std::chrono::duration<double>(S->t_done[size_t(slot)] - S->t_add[size_t(slot)]).count(), stats);
+  S->used[size_t(slot)] = 0;
+  return T.conv ? VIE_OK : VIE_W_NOCONV;
+}
+
+extern "C" int vie_batch_close(vie_plan* pl) {
+  if (!pl) return VIE_E_ARG;
+  if (!pl->session || !pl->session->user) return vie::fail(pl, VIE_E_STATE, "vie_batch_close: no open batch");
+  vie::close_session(pl);
+  return VIE_OK;
+}
 
 extern "C" int vie_solve(vie_plan* pl, const double* inc, double* density, double* field, int nrhs,
                          const vie_solve_opts* opts, vie_solve_stats* stats, void* hip_stream) {

@@ -3,17 +3,23 @@
 Requests (a medium, a frequency and 1..k incident waves) arrive as a stream.
 The server
 
-* estimates each request's device footprint with the library's own formula
-  (vie_footprint_bytes) and admits it only while the admitted total fits the
-  HBM budget; requests that do not fit wait, and smaller later requests may
-  overtake a large one at the head of the queue;
-* keeps plans (contrast + kernel tables + Krylov bases) resident in a small
-  cache keyed by (kind, n, omega, medium digest): a request for a cached plan
-  skips the precompute;
-* runs several workers, each on its own HIP stream, so admitted requests
-  overlap on the device; when queued requests share a plan key a worker
-  merges their right-hand sides into one fused multi-RHS solve;
-* records arrival -> completion latency per request.
+* keeps plans (contrast, kernel tables, Krylov workspace) resident in a
+  cache keyed by (kind, n, omega, medium digest); a request for a cached
+  plan skips the precompute;
+* serves each plan key with one worker on its own HIP stream: the worker
+  opens a batch of solver slots on the plan (the library's vie_batch_*
+  calls) and, at every cycle boundary of the running solve, lets queued
+  requests with the same key join the free slots; finished right-hand sides
+  leave at once and a request completes when all of its right-hand sides
+  have; different keys are served by other workers at the same time, so
+  their work overlaps on the device;
+* admits by device footprint (the library's own formula, vie_footprint_bytes):
+  every resident plan (serving or cached) and the input/output arrays of the
+  admitted requests count against the HBM budget; idle cached plans are
+  evicted (least recently used first) when a new plan needs the room, and a
+  request whose plan alone exceeds the budget is refused with an error;
+* records arrival -> completion latency per request, and counts the joins
+  into running solves and the plan-cache hits.
 
 The stream's inputs: by default each request's random draws are made on
 the host ahead of its arrival time and its arrays (medium, incident fields)
@@ -25,11 +31,11 @@ budget is spent the feeder waits, and the wait shows in the latency
 (measured from the nominal arrival time).
 
 Each right-hand side is solved with the same arithmetic whatever else runs
-beside it (per-RHS convergence decisions, fixed-order reductions, tile
-choices that do not change the per-pencil arithmetic), so a result is the
-same alone and in the mix.
+beside it (per-slot decisions, fixed-order reductions, tile choices that do
+not change the per-pencil arithmetic), so a result is bitwise the same alone
+and in the mix, whenever it joins.
 
-    python -m paper_1805_04791_amd.serving --requests 200 --rate 20
+    python -m paper_1805_04791_amd.serving --requests 200 --rate 20 [--media 8]
 """
 
 from __future__ import annotations
@@ -151,12 +157,13 @@ def device_inputs(recipe: dict, device):
 @dataclass
 class Result:
     id: int
-    density: np.ndarray
+    density: Optional[np.ndarray]
     stats: list
     arrival: float
     admitted: float
     done: float
-    merged_with: List[int] = field(default_factory=list)
+    joined_running: bool = False   # joined a batch while other right-hand sides were iterating
+    error: str = ""
 
     @property
     def latency(self) -> float:
@@ -164,7 +171,9 @@ class Result:
 
 
 class Admission:
-    """Admission control by device footprint (host-only logic)."""
+    """Admission control by device footprint (host-only logic).  A request is
+    admitted only while the admitted total stays within the budget; nothing
+    larger than the budget is ever admitted."""
 
     def __init__(self, budget_bytes: int):
         self.budget = int(budget_bytes)
@@ -173,7 +182,10 @@ class Admission:
         self.lock = threading.Condition()
 
     def fits(self, nbytes: int) -> bool:
-        return self.used + nbytes <= self.budget or self.used == 0
+        return self.used + nbytes <= self.budget
+
+    def can_ever_fit(self, nbytes: int) -> bool:
+        return nbytes <= self.budget
 
     def take(self, nbytes: int):
         self.used += nbytes
@@ -186,49 +198,80 @@ class Admission:
 
 
 class PlanCache:
-    """Resident plans keyed by request key; a plan is checked out by one worker at a time."""
+    """Idle resident plans keyed by request key, least recently used first; a
+    plan is checked out by one worker at a time.  Each entry remembers the
+    device bytes charged for it, released to ``on_evict`` when it is closed."""
 
-    def __init__(self, capacity: int):
+    def __init__(self, capacity: int, on_evict: Optional[Callable[[int], None]] = None):
         self.capacity = capacity
-        self.free: "OrderedDict[str, object]" = OrderedDict()
+        self.free: "OrderedDict[str, tuple]" = OrderedDict()
         self.lock = threading.Lock()
         self.hits = 0
         self.misses = 0
+        self.on_evict = on_evict
+
+    def _close(self, entries):
+        # outside self.lock: on_evict takes the admission lock, which callers
+        # may hold while they ask this cache for room
+        for plan, nbytes in entries:
+            plan.close()
+            if self.on_evict:
+                self.on_evict(nbytes)
 
     def get(self, key: str):
+        """(plan, charged bytes) or None."""
         with self.lock:
-            plan = self.free.pop(key, None)
-            if plan is None:
+            entry = self.free.pop(key, None)
+            if entry is None:
                 self.misses += 1
             else:
                 self.hits += 1
-            return plan
+            return entry
 
-    def put(self, key: str, plan):
+    def contains(self, key: str) -> bool:
+        with self.lock:
+            return key in self.free
+
+    def put(self, key: str, plan, nbytes: int = 0):
+        victims = []
         with self.lock:
             if self.capacity <= 0:
-                plan.close()
-                return
-            old = self.free.pop(key, None)
-            if old is not None:
-                old.close()
-            self.free[key] = plan
-            while len(self.free) > self.capacity:
-                _, victim = self.free.popitem(last=False)
-                victim.close()
+                victims.append((plan, nbytes))
+            else:
+                old = self.free.pop(key, None)
+                if old is not None:
+                    victims.append(old)
+                self.free[key] = (plan, nbytes)
+                while len(self.free) > self.capacity:
+                    victims.append(self.free.popitem(last=False)[1])
+        self._close(victims)
+
+    def evict_one(self, keep: str = "") -> bool:
+        """Closes the least recently used idle plan (not `keep`); False if none."""
+        victim = None
+        with self.lock:
+            for k in list(self.free.keys()):
+                if k != keep:
+                    victim = self.free.pop(k)
+                    break
+        if victim is None:
+            return False
+        self._close([victim])
+        return True
 
     def clear(self):
         with self.lock:
-            for p in self.free.values():
-                p.close()
+            victims = list(self.free.values())
             self.free.clear()
+        self._close(victims)
 
 
 class Server:
     def __init__(self, budget_bytes: Optional[int] = None, workers: int = 3, restart: int = 20,
                  max_batch: int = 16, plan_cache: int = 4, precision: Optional[int] = None,
                  keep_results: bool = True, gen_workers: int = 8, host_budget_bytes: int = 32 * 10 ** 9,
-                 pinned_inputs: bool = False, device_inputs: bool = True, progress: int = 0):
+                 pinned_inputs: bool = False, device_inputs: bool = True, progress: int = 0,
+                 tol: float = 1e-9):
         import torch
         from . import vie
         self.vie = vie
@@ -237,13 +280,15 @@ class Server:
             free, total = torch.cuda.mem_get_info()
             budget_bytes = int(0.7 * free)
         self.admission = Admission(budget_bytes)
-        self.cache = PlanCache(plan_cache)
+        self.cache = PlanCache(plan_cache, on_evict=self.admission.give)
         self.workers = workers
         self.restart = restart
         self.max_batch = max_batch
+        self.tol = tol
         self.precision = vie.PREC_MIXED if precision is None else precision
         self.queue: List[Request] = []
         self.qlock = threading.Condition()
+        self.serving = set()          # keys whose batch is open on some worker
         self.results: List[Result] = []
         self.rlock = threading.Lock()
         self.t0 = time.perf_counter()
@@ -263,16 +308,22 @@ class Server:
         self.host = Admission(host_budget_bytes)
         self.feeder_late = 0.0
         self.plan_s = 0.0       # summed over workers: plan creation (contrast, tables)
-        self.solve_s = 0.0      # and the solves
+        self.solve_s = 0.0      # and the batched solves
+        self.plans_created = 0
+        self.joins = 0          # right-hand sides added to a batch
+        self.joins_running = 0  # ... while other right-hand sides of the batch were iterating
+        self.batches = 0
+        self.refused = 0
 
     # ---- footprint -----------------------------------------------------------
-    def footprint(self, reqs: List[Request]) -> int:
-        r = reqs[0]
-        nb = min(self.max_batch, sum(q.nrhs for q in reqs))
-        fp = self.vie.footprint_bytes(r.kind, r.n, r.full, nb, self.restart)
-        # inputs and outputs of the merged batch
-        fp += 2 * sum(q.nrhs * (6 if q.full else 3) * q.n ** 3 * 16 for q in reqs)
-        return int(fp)
+    def plan_bytes(self, r: Request) -> int:
+        """Device bytes of a plan with a batch of max_batch slots."""
+        return int(self.vie.footprint_bytes(r.kind, r.n, r.full, self.max_batch, self.restart))
+
+    @staticmethod
+    def io_bytes(r: Request) -> int:
+        """The request's incident fields and densities on the device."""
+        return 2 * r.nrhs * (6 if r.full else 3) * r.n ** 3 * 16
 
     # ---- stream ----------------------------------------------------------------
     def now(self) -> float:
@@ -283,94 +334,184 @@ class Server:
             self.queue.append(req)
             self.qlock.notify_all()
 
-    def _take(self):
-        """Oldest admissible request plus queued requests with the same key."""
+    def _refuse(self, q: Request, why: str):
+        with self.rlock:
+            self.refused += 1
+            self.errors.append(f"request {q.id}: {why}")
+            self.results.append(Result(q.id, None, [], q.arrival, self.now(), self.now(), error=why))
+        q.release()
+        self.host.give(q.host_bytes)
+
+    def _claim(self):
+        """The oldest queued request whose key no worker is serving and whose
+        plan and arrays fit the device budget (evicting idle cached plans for
+        room): (request, its cached (plan, charged bytes) checked out, or None
+        and the plan bytes charged for a new plan)."""
         with self.qlock:
             while True:
                 if self.closed and not self.queue:
-                    return None, 0
-                for i, r in enumerate(self.queue):
-                    group = [r] + [q for q in self.queue[i + 1:] if q.key == r.key]
-                    nb = 0
-                    sel = []
-                    for q in group:
-                        if nb + q.nrhs > self.max_batch and sel:
-                            break
-                        sel.append(q)
-                        nb += q.nrhs
-                    fp = self.footprint(sel)
+                    return None, None, 0
+                for q in list(self.queue):
+                    if q.key in self.serving:
+                        continue
+                    if q.nrhs > self.max_batch:
+                        self.queue.remove(q)
+                        self._refuse(q, f"{q.nrhs} right-hand sides exceed the batch capacity {self.max_batch}")
+                        continue
+                    cached = self.cache.contains(q.key)
+                    need = (0 if cached else self.plan_bytes(q)) + self.io_bytes(q)
+                    if not self.admission.can_ever_fit(need):
+                        self.queue.remove(q)
+                        self._refuse(q, f"footprint {need / 1e9:.1f} GB exceeds the device budget "
+                                        f"{self.admission.budget / 1e9:.1f} GB")
+                        continue
                     with self.admission.lock:
-                        if self.admission.fits(fp):
-                            self.admission.take(fp)
-                            for q in sel:
-                                self.queue.remove(q)
+                        while not self.admission.fits(need) and self.cache.evict_one(keep=q.key):
+                            pass
+                        if self.admission.fits(need):
+                            entry = self.cache.get(q.key) if cached else None
+                            if cached and entry is None:
+                                continue  # evicted meanwhile: look again
+                            self.admission.take(need)
+                            self.queue.remove(q)
+                            self.serving.add(q.key)
                             self.inflight += 1
                             self.max_inflight = max(self.max_inflight, self.inflight)
-                            return sel, fp
-                # nothing fits: wait for a release or an arrival
+                            return q, entry, need - self.io_bytes(q)
+                    break  # the oldest admissible key must wait for memory: keep the order
                 self.qlock.wait(timeout=0.05)
+
+    def _joiners(self, key: str, free: int) -> List[Request]:
+        """Queued requests of `key`, oldest first, while they fit the free slots
+        and the device budget (their arrays); the first that does not fit stops
+        the scan, so requests of one key keep their order."""
+        out = []
+        with self.qlock:
+            for q in list(self.queue):
+                if q.key != key:
+                    continue
+                if q.nrhs > free:
+                    break
+                with self.admission.lock:
+                    if not self.admission.fits(self.io_bytes(q)):
+                        break
+                    self.admission.take(self.io_bytes(q))
+                self.queue.remove(q)
+                out.append(q)
+                free -= q.nrhs
+        return out
+
+    def _inputs(self, q: Request):
+        if q.coef is None and q.recipe is not None:
+            q.coef, q.mu, q.inc = device_inputs(q.recipe, self.device)
 
     def _worker(self):
         torch = self.torch
         vie = self.vie
         stream = torch.cuda.Stream()
         while True:
-            sel, fp = self._take()
-            if sel is None:
+            first, entry, plan_charge = self._claim()
+            if first is None:
                 return
-            admitted = self.now()
+            key = first.key
+            plan, charged = None, plan_charge
+            # request id -> [request, admitted time, densities, stats, slots left, joined while running]
+            open_reqs = {}
+            slot_of = {}    # slot -> (request id, index within the request)
             try:
                 with torch.cuda.stream(stream):
-                    for q in sel:
-                        if q.coef is None and q.recipe is not None:
-                            q.coef, q.mu, q.inc = device_inputs(q.recipe, self.device)
-                    r = sel[0]
-                    plan = self.cache.get(r.key)
+                    self._inputs(first)
                     t_plan = time.perf_counter()
-                    if plan is None:
+                    if entry is not None:
+                        plan, charged = entry[0], entry[1]
+                    else:
                         # worker threads allocate and synchronise while others
                         # solve, which stream capture would forbid
-                        plan = vie.Plan(r.kind, r.coef, omega=r.omega, mu=r.mu, precision=self.precision,
-                                        max_rhs=self.max_batch, stream=stream, graphs=False)
+                        plan = vie.Plan(first.kind, first.coef, omega=first.omega, mu=first.mu,
+                                        precision=self.precision, max_rhs=self.max_batch, stream=stream,
+                                        graphs=False)
                         stream.synchronize()
+                        with self.rlock:
+                            self.plans_created += 1
                     t_solve = time.perf_counter()
-                    if len(sel) == 1:
-                        inc = sel[0].inc
-                    elif isinstance(sel[0].inc, torch.Tensor):
-                        inc = torch.cat([q.inc for q in sel])
-                    else:
-                        inc = np.concatenate([q.inc for q in sel])
-                    dens, _, stats, rc = plan.solve(inc, tol=min(q.tol for q in sel), restart=self.restart,
-                                                    want_field=False, stream=stream)
-                    dens = dens.cpu().numpy() if self.keep_results else None
-                    stream.synchronize()
-                    t_end = time.perf_counter()
-                    self.cache.put(r.key, plan)
+                    plan.batch_open(self.max_batch, tol=self.tol, restart=self.restart, stream=stream)
                     with self.rlock:
                         self.plan_s += t_solve - t_plan
-                        self.solve_s += t_end - t_solve
-                done = self.now()
-                off = 0
-                with self.rlock:
-                    for q in sel:
-                        k = q.nrhs
-                        self.results.append(Result(q.id, dens[off:off + k] if dens is not None else None,
-                                                   stats[off:off + k], q.arrival, admitted, done,
-                                                   [o.id for o in sel if o.id != q.id]))
-                        off += k
-                        if self.progress and len(self.results) % self.progress == 0:
-                            print(f"[serve] {len(self.results)} requests done at {done:.1f} s", file=sys.stderr,
-                                  flush=True)
+                        self.batches += 1
+                    pending = [first]
+                    used = 0
+                    while True:
+                        for q in pending:
+                            self._inputs(q)
+                            slots = plan.batch_add(q.inc, stream=stream)
+                            open_reqs[q.id] = [q, self.now(), [None] * q.nrhs, [None] * q.nrhs, q.nrhs, used > 0]
+                            for i, sl in enumerate(slots):
+                                slot_of[sl] = (q.id, i)
+                            with self.rlock:
+                                self.joins += q.nrhs
+                                if used > 0:
+                                    self.joins_running += q.nrhs
+                            used += q.nrhs
+                            q.inc = q.coef = q.mu = None   # read by batch_add (it synchronised)
+                        if used == 0:
+                            # nothing left: release the key atomically with the last
+                            # look at the queue, so a late request starts a new batch
+                            with self.qlock:
+                                pending = self._joiners(key, self.max_batch)
+                                if not pending:
+                                    self.serving.discard(key)
+                                    self.inflight -= 1
+                                    self.qlock.notify_all()
+                                    break
+                            continue
+                        plan.batch_step(stream=stream)
+                        done, nfree = plan.batch_done()
+                        for sl in done:
+                            d, _, st, rc = plan.batch_take(sl, stream=stream)
+                            rid, i = slot_of.pop(sl)
+                            o = open_reqs[rid]
+                            o[2][i] = d
+                            o[3][i] = st
+                            o[4] -= 1
+                            used -= 1
+                            if o[4] == 0:
+                                self._finish(open_reqs.pop(rid), stream)
+                        pending = self._joiners(key, self.max_batch - used)
+                    plan.batch_close()
+                    with self.rlock:
+                        self.solve_s += time.perf_counter() - t_solve
+                self.cache.put(key, plan, charged)
+                plan = None
             except Exception as exc:  # keep serving; report at the end
-                self.errors.append(f"request {sel[0].id}: {exc}")
-            finally:
-                for q in sel:
-                    q.release()
-                    self.host.give(q.host_bytes)
-                self.admission.give(fp)
+                self.errors.append(f"key {key}: {exc}")
+                for o in open_reqs.values():
+                    self.admission.give(self.io_bytes(o[0]))
+                    o[0].release()
+                    self.host.give(o[0].host_bytes)
+                if plan is not None:
+                    plan.close()
+                self.admission.give(charged)
                 with self.qlock:
-                    self.inflight -= 1
+                    if key in self.serving:
+                        self.serving.discard(key)
+                        self.inflight -= 1
                     self.qlock.notify_all()
+
+    def _finish(self, o, stream):
+        q, admitted, dens, stats, _, joined = o
+        dens_h = None
+        if self.keep_results:
+            dens_h = self.torch.stack(dens).cpu().numpy()
+        else:
+            stream.synchronize()
+        done = self.now()
+        self.admission.give(self.io_bytes(q))
+        q.release()
+        self.host.give(q.host_bytes)
+        with self.rlock:
+            self.results.append(Result(q.id, dens_h, stats, q.arrival, admitted, done, joined))
+            if self.progress and len(self.results) % self.progress == 0:
+                print(f"[serve] {len(self.results)} requests done at {done:.1f} s", file=sys.stderr, flush=True)
 
     def _prepare(self, r: Request):
         if self.device_inputs and r.recipe_fn is not None:
@@ -453,24 +594,29 @@ class Server:
                 "host_peak_GB": self.host.peak / 1e9, "feeder_late_max_s": self.feeder_late,
                 "worker_plan_s": self.plan_s, "worker_solve_s": self.solve_s,
                 "pinned_fallbacks": self.pin_fallbacks, "device_inputs": self.device_inputs,
-                "errors": self.errors[:5]}
+                "plans_created": self.plans_created, "batches": self.batches,
+                "joins_rhs": self.joins, "joins_into_running_rhs": self.joins_running,
+                "requests_joined_running": sum(1 for r in results if r.joined_running),
+                "refused": self.refused, "errors": self.errors[:5]}
 
 
-def requests_from_generator(count: int, rate: float, grids=None, max_rhs: int = 16) -> List[Request]:
+def requests_from_generator(count: int, rate: float, grids=None, max_rhs: int = 16, media: int = 0) -> List[Request]:
     """The seeded serving stream (Poisson arrivals; Laplace / Helmholtz / Maxwell mix).
 
     Media and incident fields are generated when each request arrives; every
-    request has its own medium (key = its seed)."""
+    request has its own medium (key = its seed), or, with media > 0, one of a
+    pool of `media` scatterers (key = the pool entry), so that plans repeat
+    and requests join running batches."""
     from vie_inputs import generators as gen
     grids = grids or gen.SERVING_GRIDS
     out = []
-    for rq in gen.serving_requests(count, rate, grids, max_rhs):
+    for rq in gen.serving_requests(count, rate, grids, max_rhs, media=media):
         def make(rq=rq):
             p = gen.serving_problem(rq)
             return p.coef, p.mu, p.inc
+        key = f"pool{rq['medium_item']}" if "medium_item" in rq else f"req{rq['item']}"
         out.append(Request(rq["id"], rq["kind"], rq["n"], rq["omega"], rq["nrhs"], arrival=rq["arrival"],
-                           key=f"req{rq['item']}", make=make,
-                           recipe_fn=lambda rq=rq: gen.serving_recipe(rq)))
+                           key=key, make=make, recipe_fn=lambda rq=rq: gen.serving_recipe(rq)))
     return out
 
 
@@ -485,12 +631,14 @@ def main(argv=None):
     ap.add_argument("--host-budget-gb", type=float, default=24.0, help="host memory for generated inputs")
     ap.add_argument("--gen-workers", type=int, default=8, help="threads generating the stream's inputs")
     ap.add_argument("--pageable", action="store_true", help="keep the generated inputs in pageable memory")
+    ap.add_argument("--media", type=int, default=0,
+                    help="draw the scatterers from a pool of this many (0: every request its own)")
     ap.add_argument("--inputs", choices=("device", "host"), default="device",
                     help="build each request's arrays on the device from its random draws, or on the host")
     args = ap.parse_args(argv)
     grids = tuple(int(g) for g in args.grids.split(","))
     t = time.perf_counter()
-    reqs = requests_from_generator(args.requests, args.rate, grids, args.max_rhs)
+    reqs = requests_from_generator(args.requests, args.rate, grids, args.max_rhs, media=args.media)
     print(f"[serve] generated {len(reqs)} requests in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     srv = Server(int(args.budget_gb * 1e9) if args.budget_gb > 0 else None, workers=args.workers,
                  keep_results=False, gen_workers=args.gen_workers,
@@ -498,7 +646,7 @@ def main(argv=None):
                  device_inputs=args.inputs == "device", progress=100)
     res = srv.run(lambda: reqs)
     out = srv.summary(res)
-    out.update({"rate": args.rate, "grids": list(grids), "workers": args.workers})
+    out.update({"rate": args.rate, "grids": list(grids), "workers": args.workers, "media": args.media})
     print(json.dumps(out), flush=True)
     return 0
 

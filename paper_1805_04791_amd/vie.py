@@ -59,7 +59,8 @@ EXPORTS = ["vie_plan_create", "vie_apply", "vie_rhs", "vie_field", "vie_solve", 
            "vie_plan_info", "vie_copy_tables", "vie_copy_contrast", "vie_status_string",
            "vie_last_error", "vie_supported_n", "vie_profile", "vie_profile_read", "vie_profile_family",
            "vie_footprint_bytes", "vie_potential", "vie_field_h", "vie_fields_at", "vie_far_field",
-           "vie_release_cached_memory"]
+           "vie_release_cached_memory", "vie_batch_open", "vie_batch_add", "vie_batch_step", "vie_batch_done",
+           "vie_batch_take", "vie_batch_close"]
 
 _lib = None
 
@@ -99,12 +100,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.vie_far_field.argtypes = [vp, vp, ci, vp, ci, vp, vp]
     L.vie_footprint_bytes.argtypes = [ci, ci, ci, ci, ci]
     L.vie_footprint_bytes.restype = ctypes.c_long
+    ip = ctypes.POINTER(ci)
+    L.vie_batch_open.argtypes = [vp, ci, ctypes.POINTER(SolveOpts), vp]
+    L.vie_batch_add.argtypes = [vp, vp, vp, ci, ip, vp]
+    L.vie_batch_step.argtypes = [vp, ip, vp]
+    L.vie_batch_done.argtypes = [vp, ip, ci, ip, ip]
+    L.vie_batch_take.argtypes = [vp, ci, vp, vp, vp, ctypes.POINTER(SolveStats), vp]
+    L.vie_batch_close.argtypes = [vp]
     L.vie_release_cached_memory.argtypes = []
     L.vie_release_cached_memory.restype = ctypes.c_long
     for name in ("vie_plan_create", "vie_apply", "vie_rhs", "vie_field", "vie_solve", "vie_destroy",
                  "vie_plan_info", "vie_copy_tables", "vie_copy_contrast", "vie_supported_n",
                  "vie_profile", "vie_profile_read", "vie_potential", "vie_field_h", "vie_fields_at",
-                 "vie_far_field"):
+                 "vie_far_field", "vie_batch_open", "vie_batch_add", "vie_batch_step", "vie_batch_done",
+                 "vie_batch_take", "vie_batch_close"):
         getattr(L, name).restype = ci
     _lib = L
     return L
@@ -295,6 +304,54 @@ class Plan:
                                 _stream_ptr(stream))
         self._check(rc, "vie_solve")
         return dens, fld, [s.as_dict() for s in st], rc
+
+    # -- continuous batching (one open batch per plan) ------------------------------
+    def batch_open(self, capacity: int, tol: float = 1e-10, max_iters: int = 2000, restart: int = 40,
+                   inner_tol: float = 0.0, solver: int = SOLVER_GMRES, fp64: bool = False, stream=None):
+        """Open a batch of `capacity` solver slots on this plan (vie_batch_open)."""
+        o = SolveOpts(float(tol), int(max_iters), int(restart), float(inner_tol), int(solver),
+                      SOLVE_FP64 if fp64 else 0)
+        self._check(self.lib.vie_batch_open(self._h, int(capacity), ctypes.byref(o), _stream_ptr(stream)),
+                    "vie_batch_open")
+
+    def batch_add(self, inc, x0=None, stream=None) -> list:
+        """Right-hand sides [k][c][n][n][n] join free slots at the next cycle; returns the slots."""
+        inc = self._vec(inc, "inc")
+        x = self._vec(x0, "x0") if x0 is not None else None
+        k = inc.shape[0]
+        slots = (ctypes.c_int * k)()
+        self._check(self.lib.vie_batch_add(self._h, inc.data_ptr(), x.data_ptr() if x is not None else None, k,
+                                           slots, _stream_ptr(stream)), "vie_batch_add")
+        return list(slots)
+
+    def batch_step(self, stream=None) -> int:
+        """One outer cycle of every slot still iterating; returns how many still iterate."""
+        n = ctypes.c_int()
+        self._check(self.lib.vie_batch_step(self._h, ctypes.byref(n), _stream_ptr(stream)), "vie_batch_step")
+        return n.value
+
+    def batch_done(self):
+        """(finished slots not yet taken, free slots)."""
+        cap = 256
+        slots = (ctypes.c_int * cap)()
+        nd, nf = ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.vie_batch_done(self._h, slots, cap, ctypes.byref(nd), ctypes.byref(nf)), "vie_batch_done")
+        return list(slots[:min(nd.value, cap)]), nf.value
+
+    def batch_take(self, slot: int, inc=None, want_field: bool = False, stream=None):
+        """Density (and total field) of a finished slot, which is freed: (density, field, stats, status)."""
+        torch = _torch()
+        d = torch.empty((self.ncomp, self.n, self.n, self.n), dtype=torch.complex128, device=self.device)
+        f = torch.empty_like(d) if want_field else None
+        i = self._vec(inc, "inc") if want_field else None
+        st = SolveStats()
+        rc = self.lib.vie_batch_take(self._h, int(slot), d.data_ptr(), f.data_ptr() if f is not None else None,
+                                     i.data_ptr() if i is not None else None, ctypes.byref(st), _stream_ptr(stream))
+        self._check(rc, "vie_batch_take")
+        return d, f, st.as_dict(), rc
+
+    def batch_close(self):
+        self._check(self.lib.vie_batch_close(self._h), "vie_batch_close")
 
     def info(self) -> dict:
         out = (ctypes.c_double * 16)()

@@ -210,3 +210,66 @@ def test_graph_replay_equals_eager(vie):
     eager.close()
     graph.close()
 
+
+def test_reorthogonalising_slots_batch_equals_alone(vie):
+    """Inner FP32 cycles asked for a deep reduction (1e-8) re-orthogonalise once
+    their residual estimate passes 1e-6 of the cycle's start, at an iteration
+    that differs per right-hand side; the second pass is applied to those slots
+    only, so every result is bitwise its solve alone."""
+    n = 16
+    coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 9)
+    inc = incident(op.KIND_HELMHOLTZ, n, omega, 3, False, item=60)
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
+    d, _, st, rc = plan.solve(inc, tol=1e-11, inner_tol=1e-8, want_field=False)
+    assert rc == vie.OK
+    d = d.cpu().numpy()
+    for r in range(3):
+        ds, _, ss, _ = plan.solve(inc[r:r + 1], tol=1e-11, inner_tol=1e-8, want_field=False)
+        assert np.array_equal(ds.cpu().numpy()[0], d[r])
+        assert ss[0]["iters"] == st[r]["iters"]
+    plan.close()
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_stagnating_slots_stop_on_their_own(vie, fp64):
+    """An unreachable tolerance: every slot stagnates at its own rounding floor
+    and stops after its own window of matvecs without a 10% decrease, with
+    VIE_W_NOCONV and its best iterate; batch and alone agree bitwise."""
+    n = 16
+    coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 10)
+    inc = incident(op.KIND_HELMHOLTZ, n, omega, 2, False, item=70)
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2)
+    kw = dict(tol=1e-18, restart=20, max_iters=5000, fp64=fp64, want_field=False)
+    d, _, st, rc = plan.solve(inc, **kw)
+    assert rc == vie.W_NOCONV
+    d = d.cpu().numpy()
+    for r in range(2):
+        assert st[r]["status"] == vie.W_NOCONV
+        assert st[r]["matvecs_fp32"] + st[r]["matvecs_fp64"] < 4000          # stopped well before the budget
+        assert st[r]["rel_residual"] < 1e-12                                 # the best iterate's residual
+        ds, _, ss, _ = plan.solve(inc[r:r + 1], **kw)
+        assert np.array_equal(ds.cpu().numpy()[0], d[r])
+        assert ss[0]["matvecs_fp32"] == st[r]["matvecs_fp32"] and ss[0]["matvecs_fp64"] == st[r]["matvecs_fp64"]
+        assert ss[0]["rel_residual"] == st[r]["rel_residual"]
+    plan.close()
+
+
+def test_nan_in_incident_field(vie):
+    """A NaN in one right-hand side's incident field: that slot stops at once
+    (status VIE_W_NOCONV, residual NaN, density 0); the others in the batch are
+    solved and equal their solves alone bitwise."""
+    n = 16
+    coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 11)
+    inc = incident(op.KIND_HELMHOLTZ, n, omega, 3, False, item=80)
+    inc[1, 2, 8, 8, 8] = np.nan
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=3)
+    d, _, st, rc = plan.solve(inc, tol=1e-9, want_field=False)
+    assert rc == vie.W_NOCONV
+    d = d.cpu().numpy()
+    assert st[1]["status"] == vie.W_NOCONV and math.isnan(st[1]["rel_residual"])
+    assert st[1]["matvecs_fp32"] == 0 and not d[1].any()
+    for r in (0, 2):
+        assert st[r]["status"] == vie.OK and st[r]["rel_residual"] <= 1e-9
+        ds, _, ss, _ = plan.solve(inc[r:r + 1], tol=1e-9, want_field=False)
+        assert np.array_equal(ds.cpu().numpy()[0], d[r])
+    plan.close()

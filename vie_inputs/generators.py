@@ -426,19 +426,38 @@ SERVING_GRIDS = (32, 48, 64, 96, 128, 160)
 
 
 def serving_requests(count: int = 2000, rate: float = 10.0, grids=SERVING_GRIDS,
-                     max_rhs: int = 16, seed_item: int = 0):
+                     max_rhs: int = 16, seed_item: int = 0, media: int = 0):
     """Poisson stream of mixed solve requests.
 
     Draw order (one generator, item ``seed_item`` of the serving config):
     ``count`` exponential inter-arrival times (mean 1/rate), then per request:
     kind (integer in {0,1,2}), grid index, wavelengths w ~ U[2, 10], nrhs in {1..max_rhs}.
     The medium and incident waves of request r use item 1000 + r.
+
+    media > 0: the scatterers come from a pool of ``media`` entries instead,
+    so that requests repeat plans.  Entry j draws (kind, grid index, w) from
+    item 200000 + j, then its medium; request r draws, after its arrival
+    gap, the pool index (integer in [0, media)) and nrhs from the stream
+    generator, and its waves from item 1000 + r.
     """
     rng = rng_for(CONFIG_IDS["serving"], seed_item)
     gaps = rng.exponential(1.0 / rate, count)
     t = np.cumsum(gaps)
+    pool = []
+    for j in range(media):
+        prng = rng_for(CONFIG_IDS["serving"], 200000 + j)
+        kind = int(prng.integers(0, 3))
+        n = int(grids[int(prng.integers(0, len(grids)))])
+        w = float(prng.uniform(2.0, 10.0))
+        pool.append((kind, n, 0.0 if kind == KIND_LAPLACE else math.pi * w, 200000 + j))
     reqs = []
     for r in range(count):
+        if media > 0:
+            kind, n, omega, mitem = pool[int(rng.integers(0, media))]
+            nrhs = int(rng.integers(1, max_rhs + 1))
+            reqs.append({"id": r, "arrival": float(t[r]), "kind": kind, "n": n, "omega": omega,
+                         "nrhs": nrhs, "item": 1000 + r, "medium_item": mitem})
+            continue
         kind = int(rng.integers(0, 3))
         n = int(grids[int(rng.integers(0, len(grids)))])
         w = float(rng.uniform(2.0, 10.0))
@@ -460,25 +479,28 @@ def serving_recipe(req: dict) -> dict:
       (Laplace: constant fields);
     * ``dirs``: the directions d of the phases.
     """
+    # the medium from the pool entry's generator when the request has one,
+    # else from the request's own (then the waves follow in the same generator)
     rng = rng_for(CONFIG_IDS["serving"], req["item"])
+    mrng = rng_for(CONFIG_IDS["serving"], req["medium_item"]) if "medium_item" in req else rng
     n, kind, omega, nrhs = req["n"], req["kind"], req["omega"], req["nrhs"]
     out = {"kind": kind, "n": n, "omega": omega, "nrhs": nrhs, "axis": grid_axis(n)}
     waves, dirs = [], []
     if kind == KIND_LAPLACE:
-        out["matrix"] = laplace_matrix(rng)
+        out["matrix"] = laplace_matrix(mrng)
         for r in range(nrhs):
             waves.append(random_unit(rng))
         out["phased"] = False
     elif kind == KIND_HELMHOLTZ:
-        out["matrix"] = helmholtz_matrix(rng)
+        out["matrix"] = helmholtz_matrix(mrng)
         for r in range(nrhs):
             d = random_unit(rng)
             dirs.append(d)
             waves.append(1j * omega * d)
         out["phased"] = True
     else:
-        d_eps = rng.uniform(0.0, 1.0, 3)
-        rng.uniform(0.0, 0.5, 3)  # D_mu, drawn and unused (mu = I)
+        d_eps = mrng.uniform(0.0, 1.0, 3)
+        mrng.uniform(0.0, 0.5, 3)  # D_mu, drawn and unused (mu = I)
         X, Y, _ = grid_coords_plane(n)
         out["matrix"] = _rotated_field(X, Y, d_eps + 0.05j)
         for r in range(nrhs):
