@@ -88,6 +88,9 @@ typedef enum {
 #define VIE_WHOLE_GRID 0x8u      /* the solver works on the whole n^3 grid with 2n-point transforms */
 #define VIE_DENSE_BOX 0x10u      /* unknowns: every point of the bounding box (no support rows) */
 #define VIE_FULL_LENGTH 0x20u    /* the solver's x and y transforms have length 2n */
+#define VIE_GRID_TABLES 0x40u    /* build the whole grid's kernel tables at plan creation (otherwise
+                                    at the first vie_apply / vie_field when the solver's transform
+                                    is shorter than 2n); vie_apply_noalloc needs them */
 
 /*
  * The problem statement of the paper (Introduction and Section 5): a grid,
@@ -161,6 +164,29 @@ int vie_plan_create(const vie_problem *p, void *hip_stream, vie_plan **out);
  * The discrete operator of the integral equation (see the header comment).
  * x and y must not overlap. */
 int vie_apply(vie_plan *pl, const double *x, double *y, int nrhs, unsigned flags, void *hip_stream);
+
+/* Size of the device scratch of vie_apply_noalloc, per device (MiB). */
+#define VIE_NOALLOC_SCRATCH_MIB 128
+
+/* vie_apply without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, flags, layouts and results as
+ * vie_apply; the apply workspace is the library's static device scratch of
+ * VIE_NOALLOC_SCRATCH_MIB MiB per device (held from the first plan creation
+ * on a device until the process ends) instead of the plan's.  Nothing is
+ * allocated, freed or synchronised: no hipMalloc, no event, no tile
+ * measurement (tiles measured earlier by vie_apply for this batch size are
+ * reused, else fixed defaults).  The whole grid's kernel tables must exist:
+ * create the plan with VIE_GRID_TABLES, or call vie_apply once before
+ * (VIE_E_STATE otherwise).  Right-hand sides are processed in chunks of at
+ * most min(max_rhs, scratch / workspace per right-hand side); VIE_E_SIZE when
+ * one right-hand side alone needs more workspace than the scratch holds
+ * (C * n^2 * 2n + C * n * (2n)^2 complex values of the apply precision: e.g.
+ * n <= 64 in FP64 or n <= 96 in FP32 with c = 3).  Every call on one device
+ * shares its scratch, which keeps the last call's contents: calls that
+ * overlap in time on one device (other streams or threads) race and must be
+ * serialised by the caller. */
+int vie_apply_noalloc(vie_plan *pl, const double *x, double *y, int nrhs, unsigned flags, void *hip_stream);
 
 /* b = 2 H g (the right-hand side of the integral equation; for full Maxwell
  * [2 H_eps E_inc; 2 H_mu H_inc]).  Device pointers, [nrhs][c][n^3]. */

@@ -16,6 +16,17 @@
 
 using namespace vie;
 
+// Workspace of vie_apply_noalloc: device memory the library owns from load
+// time, so that the call allocates nothing.  Each device holds its own copy at
+// its own address (looked up once per device when the first plan is created
+// there); host code never passes the array's name to a kernel.
+static __device__ __align__(256) unsigned char scratch[size_t(VIE_NOALLOC_SCRATCH_MIB) << 20];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};  // under hip_mutex()
+}  // namespace
+
 namespace vie {
 
 template <typename R>
@@ -531,6 +542,35 @@ int pick_tile(vie_plan* pl, int P1, int P2, bool contig, int maxthreads, int col
 
 int tune_key(int nb, const Geom& g) { return bucket_of(nb) + (g.id << 20) + ((g.mul + 1) << 24); }
 
+// tiles chosen without measuring: about 256 threads per block, whole 128-byte
+// lines where the column count allows
+template <typename R>
+int default_tune(vie_plan* pl, const ApplyCall<R>& c, Tune* d) {
+  const int P1 = c.ops->P1, P2 = c.ops->P2, Z1 = c.opsz->P1, Z2 = c.opsz->P2;
+  const int P = P1 * P2;  // the x and y transform length; the z pass runs over P x P columns
+  d->tx_fwd = default_tile<R>(pl, P1, P2, true, kPassMaxThreads, P);
+  const int fmax = pl->C == 6 ? fused_max_threads<R, 6>() : fused_max_threads<R, 3>();
+  d->tx_inv = default_tile<R>(pl, P1, P2, true, fmax, P);
+  d->ty_fwd = d->ty_inv = default_tile<R>(pl, P1, P2, false, kPassMaxThreads, P);
+  d->tz = default_tile<R>(pl, Z1, Z2, false, fmax, P, true);
+  if (d->tx_fwd == 0 || d->tz == 0 || d->tx_inv == 0 || d->ty_fwd == 0)
+    return fail(pl, VIE_E_SIZE, "no tile shape fits the LDS limit");
+  return VIE_OK;
+}
+
+// the tiles measured earlier for this batch size and geometry, else the
+// defaults; measures nothing and records nothing (the allocation-free apply)
+template <typename R>
+int fixed_tune(vie_plan* pl, const ApplyCall<R>& c, Tune* t) {
+  const int idx = std::is_same<R, double>::value ? 1 : 0;
+  auto it = pl->tune[idx].find(tune_key(c.nb, c.g));
+  if (it != pl->tune[idx].end()) {
+    *t = it->second;
+    return VIE_OK;
+  }
+  return default_tune<R>(pl, c, t);
+}
+
 template <typename R, typename TV, typename TO = TV>
 int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStream_t s, Tune* t) {
   const int idx = std::is_same<R, double>::value ? 1 : 0;
@@ -542,13 +582,10 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStre
   }
   const int P1 = c.ops->P1, P2 = c.ops->P2, Z1 = c.opsz->P1, Z2 = c.opsz->P2;
   Tune d;
-  const int P = P1 * P2;  // the x and y transform length; the z pass runs over P x P columns
-  d.tx_fwd = default_tile<R>(pl, P1, P2, true, kPassMaxThreads, P);
+  int rc = default_tune<R>(pl, c, &d);
+  if (rc) return rc;
+  const int P = P1 * P2;
   const int fmax = pl->C == 6 ? fused_max_threads<R, 6>() : fused_max_threads<R, 3>();
-  d.tx_inv = default_tile<R>(pl, P1, P2, true, fmax, P);
-  d.ty_fwd = d.ty_inv = default_tile<R>(pl, P1, P2, false, kPassMaxThreads, P);
-  d.tz = default_tile<R>(pl, Z1, Z2, false, fmax, P, true);
-  if (d.tx_fwd == 0 || d.tz == 0 || d.tx_inv == 0 || d.ty_fwd == 0) return fail(pl, VIE_E_SIZE, "no tile shape fits the LDS limit");
   // VIE_TILES="xfwd,yfwd,z,yinv,xinv" pins the tiles of this FFT length and
   // precision (profiling runs that must repeat a measured launch shape)
   const char* pin = std::getenv(sizeof(R) == 8 ? "VIE_TILES_FP64" : "VIE_TILES");
@@ -572,7 +609,6 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStre
       tab = c.g.sp->tab32;
     else
       tab = c.g.sp->tab64;
-    int rc;
     rc = pick_tile<R>(pl, P1, P2, true, kPassMaxThreads, P, [&](int T) { return pass_xfwd<R, TV>(c, in, T, s); }, s, &d.tx_fwd);
     if (rc) return rc;
     rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, P, [&](int T) { return pass_yfwd<R>(c, T, s); }, s, &d.ty_fwd);
@@ -599,9 +635,19 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStre
 
 // act (device, optional): per right-hand side, 0 = skip it (its output is
 // left as it was); nact = the number of non-zero flags, for the byte counts
+// Caller-provided apply workspace (the allocation-free entry point): arrays A
+// and B for `cap` right-hand sides; tiles are not measured and no kernel is
+// timed.  Without it the plan's own workspace is used (grown on demand).
+struct FixedWork {
+  void* A;
+  void* B;
+  int cap;
+};
+
 template <typename R, typename TV, typename TO = TV>
 int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, const c128* bvec, TO* out,
-                int nrhs, int mode, hipStream_t s, const int* act = nullptr, int nact = -1) {
+                int nrhs, int mode, hipStream_t s, const int* act = nullptr, int nact = -1,
+                const FixedWork* fw = nullptr) {
   const Spec& sp = *geom.sp;
   const LenOps<R>* ops = len_ops<R>(sp.Pxy);
   const LenOps<R>* opsz = len_ops<R>(sp.Pz);
@@ -612,9 +658,20 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
   if (!std::is_same<TO, TV>::value && (!ops->xinv_w32 || mode != MODE_MATVEC))
     return fail(pl, VIE_E_STATE, "complex64 output needs the FP32 matvec");
   const int idx = std::is_same<R, double>::value ? 1 : 0;
-  const int chunk = std::max(1, std::min(nrhs, pl->max_rhs));
-  int rc = ensure_workspace<R>(pl, chunk);
-  if (rc) return rc;
+  int chunk = std::max(1, std::min(nrhs, pl->max_rhs));
+  cx<R>* wA;
+  cx<R>* wB;
+  if (fw) {
+    chunk = std::max(1, std::min(chunk, fw->cap));
+    wA = static_cast<cx<R>*>(fw->A);
+    wB = static_cast<cx<R>*>(fw->B);
+  } else {
+    const int rc = ensure_workspace<R>(pl, chunk);
+    if (rc) return rc;
+    wA = static_cast<cx<R>*>(pl->wsA[idx]);
+    wB = static_cast<cx<R>*>(pl->wsB[idx]);
+  }
+  int rc = VIE_OK;
   const cx<R>* tw;
   const cx<R>* twz;
   const cx<R>* tab;
@@ -630,13 +687,12 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
   const long L = long(pl->C) * geom.np;
   for (int r0 = 0; r0 < nrhs; r0 += chunk) {
     const int nb = std::min(chunk, nrhs - r0);
-    ApplyCall<R> c{pl,  ops, tw, opsz, twz, static_cast<cx<R>*>(pl->wsA[idx]), static_cast<cx<R>*>(pl->wsB[idx]),
-                   nb,  geom};
+    ApplyCall<R> c{pl, ops, tw, opsz, twz, wA, wB, nb, geom};
     const long off = long(r0) * L;
     const TV* inr = in + off;
     TO* outr = out + off;
     Tune t;
-    rc = get_tune<R, TV, TO>(pl, c, inr, outr, s, &t);
+    rc = fw ? fixed_tune<R>(pl, c, &t) : get_tune<R, TV, TO>(pl, c, inr, outr, s, &t);
     if (rc) return rc;
     c.act = act ? act + r0 : nullptr;
     const int nrun = (act && nact >= 0 && nrhs <= chunk) ? nact : nb;  // right-hand sides computed
@@ -661,19 +717,21 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     const int mul = geom_mul(pl, geom);
     const double mul_f = (mul == MUL_MAX6 ? 216.0 : (mul == MUL_SYM3 ? 66.0 : 24.0)) * pts;
     const double comb_f = (mode == MODE_CONV) ? 0.0 : 72.0 * vN3 / 3.0;
-    int tok = prof_begin(pl, s);
+    // the allocation-free path records no events (creating one may allocate)
+    const bool prof = !fw;
+    int tok = prof ? prof_begin(pl, s) : -1;
     HIPCHK(pl, (pass_xfwd<R, TV>(c, inr, t.tx_fwd, s)));
     prof_end(pl, f0 + 0, tok, s, vN3 * c16 + vN2P * cr, rows_x * fft_row);
-    tok = prof_begin(pl, s);
+    tok = prof ? prof_begin(pl, s) : -1;
     HIPCHK(pl, pass_yfwd<R>(c, t.ty_fwd, s));
     prof_end(pl, f0 + 1, tok, s, (vN2P + vNP2) * cr, rows_y * fft_row);
-    tok = prof_begin(pl, s);
+    tok = prof ? prof_begin(pl, s) : -1;
     HIPCHK(pl, pass_z<R>(c, tab, t.tz, s));
     prof_end(pl, f0 + 2, tok, s, 2.0 * vNP2 * cr + double(sp.tab_elems) * cr, 2.0 * rows_z * fft_row_z + mul_f);
-    tok = prof_begin(pl, s);
+    tok = prof ? prof_begin(pl, s) : -1;
     HIPCHK(pl, pass_yinv<R>(c, t.ty_inv, s));
     prof_end(pl, f0 + 3, tok, s, (vN2P + vNP2) * cr, rows_y * fft_row);
-    tok = prof_begin(pl, s);
+    tok = prof ? prof_begin(pl, s) : -1;
     HIPCHK(pl, (pass_xinv<R, TV, TO>(c, addv ? addv + off : inr, bvec ? bvec + off : nullptr, outr, mode, t.tx_inv,
                                      s)));
     prof_end(pl, f0 + 4, tok, s, xinv_b, rows_x * fft_row + comb_f);
@@ -1028,6 +1086,16 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   pl->use_graphs = !(p->flags & VIE_NO_GRAPHS);
   pl->last_stream = s;
   HIPCHK(pl, hipGetDevice(&pl->device));
+  if (pl->device < 0 || pl->device >= kMaxDevices) return fail(pl, VIE_E_DEVICE, "device index out of range");
+  {
+    // the device address of the scratch of vie_apply_noalloc, once per device
+    std::lock_guard<std::recursive_mutex> lk(hip_mutex());
+    if (!g_scratch_ptr[pl->device]) {
+      void* sp = nullptr;
+      HIPCHK(pl, hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)));
+      g_scratch_ptr[pl->device] = sp;
+    }
+  }
   {
     hipDeviceProp_t prop;
     HIPCHK(pl, hipGetDeviceProperties(&prop, pl->device));
@@ -1113,6 +1181,10 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   rc = make_spec(pl, pl->P, pb, pl->sym_set, pl->ne, pl->sb, s);
   if (rc) return rc;
   if (pb == pl->P) pl->sg = pl->sb;
+  if (p->flags & VIE_GRID_TABLES) {
+    rc = ensure_grid_spec(pl, s);
+    if (rc) return rc;
+  }
   return VIE_OK;
 }
 
@@ -1199,6 +1271,48 @@ int vie_apply(vie_plan* pl, const double* x, double* y, int nrhs, unsigned flags
   const c128* in = reinterpret_cast<const c128*>(x);
   return apply_any(pl, pl->grid, fp64, in, in, nullptr, reinterpret_cast<c128*>(y), nrhs, mode,
                    static_cast<hipStream_t>(hip_stream));
+}
+
+int vie_apply_noalloc(vie_plan* pl, const double* x, double* y, int nrhs, unsigned flags, void* hip_stream) {
+  if (!pl) return VIE_E_ARG;
+  if (!x || !y || nrhs < 1) return fail(pl, VIE_E_ARG, "vie_apply_noalloc: null pointer or nrhs < 1");
+  if ((flags & VIE_APPLY_FP64) && (flags & VIE_APPLY_FP32)) return fail(pl, VIE_E_ARG, "FP64 and FP32 both set");
+  if (x == y) return fail(pl, VIE_E_ARG, "vie_apply_noalloc: x and y must not overlap");
+  if (!pl->sg.tab64)
+    return fail(pl, VIE_E_STATE,
+                "vie_apply_noalloc: the whole grid's kernel tables are not built (create the plan with "
+                "VIE_GRID_TABLES, or call vie_apply once first)");
+  unsigned char* base = static_cast<unsigned char*>(g_scratch_ptr[pl->device]);
+  if (!base) return fail(pl, VIE_E_STATE, "vie_apply_noalloc: no scratch address for this device");
+  bool fp64 = pl->precision == VIE_PREC_FP64;
+  if (flags & VIE_APPLY_FP64) fp64 = true;
+  if (flags & VIE_APPLY_FP32) fp64 = false;
+  const int mode = (flags & VIE_APPLY_CONV) ? MODE_CONV : MODE_MATVEC;
+  if ((flags & VIE_APPLY_C64) && (fp64 || mode != MODE_MATVEC))
+    return fail(pl, VIE_E_ARG, "vie_apply_noalloc: complex64 vectors need the FP32 matvec (no FP64, no CONV)");
+  // workspace of one right-hand side (the arrays A and B of the whole grid)
+  const size_t N = size_t(pl->n), P = size_t(pl->P), C = size_t(pl->C);
+  const size_t el = fp64 ? sizeof(c128) : sizeof(c64);
+  const size_t a1 = el * C * N * N * P, b1 = el * C * N * P * P;
+  const size_t total = size_t(VIE_NOALLOC_SCRATCH_MIB) << 20;
+  const size_t cap = (total - 256) / (a1 + b1);
+  if (cap < 1)
+    return fail(pl, VIE_E_SIZE, "vie_apply_noalloc: one right-hand side needs " + std::to_string(a1 + b1) +
+                                    " bytes of workspace at n = " + std::to_string(pl->n) + ", more than the " +
+                                    std::to_string(total) + "-byte scratch");
+  const int ncap = int(std::min<size_t>(cap, 4096));
+  const FixedWork fw{base, base + (a1 * size_t(ncap) + 255) / 256 * 256, ncap};
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  pl->last_stream = s;
+  if (flags & VIE_APPLY_C64) {
+    const c64* in = reinterpret_cast<const c64*>(x);
+    return apply_typed<float, c64>(pl, pl->grid, in, in, nullptr, reinterpret_cast<c64*>(y), nrhs, MODE_MATVEC, s,
+                                   nullptr, -1, &fw);
+  }
+  const c128* in = reinterpret_cast<const c128*>(x);
+  c128* out = reinterpret_cast<c128*>(y);
+  return fp64 ? apply_typed<double, c128>(pl, pl->grid, in, in, nullptr, out, nrhs, mode, s, nullptr, -1, &fw)
+              : apply_typed<float, c128>(pl, pl->grid, in, in, nullptr, out, nrhs, mode, s, nullptr, -1, &fw);
 }
 
 int vie_rhs(vie_plan* pl, const double* inc, double* b, int nrhs, void* hip_stream) {

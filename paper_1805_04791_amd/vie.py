@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libvie.so")
 LAPLACE, HELMHOLTZ, MAXWELL = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 PTR_HOST, STRICT_MEDIUM, NO_GRAPHS = 0x1, 0x2, 0x4
-WHOLE_GRID, DENSE_BOX, FULL_LENGTH = 0x8, 0x10, 0x20
+WHOLE_GRID, DENSE_BOX, FULL_LENGTH, GRID_TABLES = 0x8, 0x10, 0x20, 0x40
+NOALLOC_SCRATCH_MIB = 128
 APPLY_FP64, APPLY_FP32, APPLY_CONV, APPLY_C64 = 0x1, 0x2, 0x4, 0x8
 SOLVER_GMRES, SOLVER_BICGSTAB = 0, 1
 SOLVE_X0, SOLVE_FP64 = 0x1, 0x2
@@ -55,7 +56,7 @@ class SolveStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-EXPORTS = ["vie_plan_create", "vie_apply", "vie_rhs", "vie_field", "vie_solve", "vie_destroy",
+EXPORTS = ["vie_plan_create", "vie_apply", "vie_apply_noalloc", "vie_rhs", "vie_field", "vie_solve", "vie_destroy",
            "vie_plan_info", "vie_copy_tables", "vie_copy_contrast", "vie_status_string",
            "vie_last_error", "vie_supported_n", "vie_profile", "vie_profile_read", "vie_profile_family",
            "vie_footprint_bytes", "vie_potential", "vie_field_h", "vie_fields_at", "vie_far_field",
@@ -76,6 +77,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     vp, ci, cd, cu = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint
     L.vie_plan_create.argtypes = [ctypes.POINTER(Problem), vp, ctypes.POINTER(vp)]
     L.vie_apply.argtypes = [vp, vp, vp, ci, cu, vp]
+    L.vie_apply_noalloc.argtypes = [vp, vp, vp, ci, cu, vp]
     L.vie_rhs.argtypes = [vp, vp, vp, ci, vp]
     L.vie_field.argtypes = [vp, vp, vp, vp, ci, vp]
     L.vie_solve.argtypes = [vp, vp, vp, vp, ci, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
@@ -109,7 +111,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.vie_batch_close.argtypes = [vp]
     L.vie_release_cached_memory.argtypes = []
     L.vie_release_cached_memory.restype = ctypes.c_long
-    for name in ("vie_plan_create", "vie_apply", "vie_rhs", "vie_field", "vie_solve", "vie_destroy",
+    for name in ("vie_plan_create", "vie_apply", "vie_apply_noalloc", "vie_rhs", "vie_field", "vie_solve", "vie_destroy",
                  "vie_plan_info", "vie_copy_tables", "vie_copy_contrast", "vie_supported_n",
                  "vie_profile", "vie_profile_read", "vie_potential", "vie_field_h", "vie_fields_at",
                  "vie_far_field", "vie_batch_open", "vie_batch_add", "vie_batch_step", "vie_batch_done",
@@ -224,6 +226,19 @@ class Plan:
         y = torch.empty_like(x)
         self._check(self.lib.vie_apply(self._h, x.data_ptr(), y.data_ptr(), x.shape[0], int(flags),
                                        _stream_ptr(stream)), "vie_apply")
+        return y
+
+    def apply_noalloc(self, x, y=None, flags: int = 0, stream=None):
+        """y = A x through vie_apply_noalloc (the library's static scratch as
+        workspace; nothing allocated by the call).  y may be given (reused)."""
+        torch = _torch()
+        x = self._vec(x)
+        if flags & APPLY_C64:
+            x = x.to(torch.complex64)
+        if y is None:
+            y = torch.empty_like(x)
+        self._check(self.lib.vie_apply_noalloc(self._h, x.data_ptr(), y.data_ptr(), x.shape[0], int(flags),
+                                               _stream_ptr(stream)), "vie_apply_noalloc")
         return y
 
     def rhs(self, inc, stream=None):

@@ -40,6 +40,7 @@ def test_host_only_calls():
     assert L.vie_supported_n(128) == 1
     assert L.vie_supported_n(7) == 0
     assert L.vie_destroy(None) == 0
+    assert L.vie_apply_noalloc(None, None, None, 1, 0, None) == vie.E_ARG
     # invalid problems are rejected before any device work
     p = vie.Problem()
     p.kind, p.n, p.h, p.omega, p.coef, p.precision, p.max_rhs = 1, 7, 0.1, 1.0, None, 0, 1
