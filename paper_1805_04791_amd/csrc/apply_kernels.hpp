@@ -52,6 +52,15 @@ struct ZArgs {
   double omega;     // MUL_CURLH: the factor -i omega
   const int* act = nullptr;  // optional: right-hand side r is skipped when act[r] == 0
   int pair_ky = 0;  // 1: slices ky and pxy - ky of a tile back to back on one XCD (needs (pxy/2) ntiles % 8 == 0)
+  // mirror groups (quad = 1): the four slices that read the same folded table
+  // rows run back to back on one XCD: ky and its mirror, each for the kx
+  // tile kx = fx (fx in [t T, t T + T), fx < pxy/2) and the mirrored tile
+  // kx = pxy - fx (fx in [t T + 1, t T + T], fx <= pxy/2).  ntx = tiles per
+  // side (ceil(pxy / 2 / T)), ngroups = (pxy / 2) ntx groups, padded to a
+  // multiple of 8 in the launch.
+  int quad = 0;
+  int ntx = 0;
+  long ngroups = 0;
 };
 
 // Minimum waves per SIMD the register allocation of k_zpass must allow: the
@@ -97,7 +106,28 @@ __attribute__((amdgpu_waves_per_eu(zpass_min_waves<R, C>()))) k_zpass(cx<R>* buf
   const long slice = long(k / unsigned(a.nb)) * 8 + xcd;
   const long rhs = long(k % unsigned(a.nb));
   int tile, ky;
-  if (a.pair_ky) {
+  int kx0 = 0, kxdir = 1, fxmin = 0, fxmax = a.pxy;  // column col of the block: kx = kx0 + kxdir col
+  if (a.quad) {
+    const long q = long(k / unsigned(a.nb));
+    const long grp = (q / 4) * 8 + xcd;
+    if (grp >= a.ngroups) return;  // padding
+    const int member = int(q % 4);
+    const int pk = int(grp / a.ntx);
+    const int t = int(grp % a.ntx);
+    ky = (member & 1) == 0 ? pk : (pk == 0 ? a.pxy / 2 : a.pxy - pk);
+    const int T0 = TT > 0 ? TT : a.T;
+    if (member < 2) {
+      kx0 = t * T0;          // fx = kx = t T + col < pxy / 2
+      fxmin = 0;
+      fxmax = a.pxy / 2 - 1;
+    } else {
+      kx0 = a.pxy - t * T0 - 1;  // fx = t T + col + 1 <= pxy / 2, kx = pxy - fx
+      kxdir = -1;
+      fxmin = 1;
+      fxmax = a.pxy / 2;
+    }
+    tile = t;
+  } else if (a.pair_ky) {
     const int within = int(slice % 16);
     const long pair = (slice / 16) * 8 + within % 8;
     const int pk = int(pair / a.ntiles);
@@ -107,10 +137,18 @@ __attribute__((amdgpu_waves_per_eu(zpass_min_waves<R, C>()))) k_zpass(cx<R>* buf
     tile = int(slice % a.ntiles);
     ky = int(slice / a.ntiles);
   }
-  const int kx = tile * T + col;
-  const bool valid = kx < a.pxy;
+  int kx;
+  bool valid;
+  if (a.quad) {
+    kx = kx0 + kxdir * col;
+    const int fx = kxdir > 0 ? kx : a.pxy - kx;
+    valid = fx >= fxmin && fx <= fxmax;
+  } else {
+    kx = tile * T + col;
+    valid = kx < a.pxy;
+  }
   const long PP = long(a.pxy) * a.pxy;
-  cx<R>* base = buf + rhs * a.rhs_stride + long(ky) * a.pxy + kx;
+  cx<R>* base = buf + rhs * a.rhs_stride + long(ky) * a.pxy + (valid ? kx : 0);
 
   // kUpfront: all inputs of the block in flight at once
   constexpr int CU = kUpfront<R> ? C : 1;

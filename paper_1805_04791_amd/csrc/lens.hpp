@@ -90,14 +90,18 @@ struct LenOps {
   hipError_t (*symbol_inv)(SymbolSrc, MemStore<c128>, Geo, long ngroups, const c128*, hipStream_t) = nullptr;
 };
 
-template <typename R>
-LenOps<R>* len_table();  // indexed by P, size kMaxLen + 1
+// Each length may be compiled with more than one split P = P1 x P2 (variant
+// 0: the one of the precompute; variant 1: an alternative the autotuner may
+// pick per pass).
 constexpr int kMaxLen = 640;
+constexpr int kMaxSplits = 2;
+template <typename R>
+LenOps<R>* len_table();  // [kMaxLen + 1][kMaxSplits]
 
 template <typename R>
-inline const LenOps<R>* len_ops(int P) {
-  if (P < 0 || P > kMaxLen) return nullptr;
-  const LenOps<R>* o = &len_table<R>()[P];
+inline const LenOps<R>* len_ops(int P, int variant = 0) {
+  if (P < 0 || P > kMaxLen || variant < 0 || variant >= kMaxSplits) return nullptr;
+  const LenOps<R>* o = &len_table<R>()[P * kMaxSplits + variant];
   return o->P == P ? o : nullptr;
 }
 
@@ -166,11 +170,23 @@ struct LenImpl {
   }
   static hipError_t zpass(int mul, cx<R>* buf, const cx<R>* tab, ZArgs a, long nblocks, const cx<R>* tw,
                           hipStream_t s) {
+    // the z fold needs P1 and P2 even
+    if constexpr (P1 % 2 != 0 || P2 % 2 != 0) {
+      (void)mul; (void)buf; (void)tab; (void)a; (void)nblocks; (void)tw; (void)s;
+      return hipErrorInvalidValue;
+    } else {
     // the kernel takes the table geometry from P
     if (2 * a.n != P || a.nxp != ((a.n + 1 + 15) / 16) * 16 || a.ne != mul_entries(mul) || 2 * a.nz > P ||
-        a.pxy > P || a.ntiles != (a.pxy + a.T - 1) / a.T || nblocks != long(a.ntiles) * a.pxy * a.nb ||
-        (long(a.ntiles) * a.pxy) % 8 != 0)
+        a.pxy > P || a.pxy % 2 != 0)
       return hipErrorInvalidValue;
+    if (a.quad) {
+      if (a.ntx != (a.pxy / 2 + a.T - 1) / a.T || a.ngroups != long(a.pxy / 2) * a.ntx ||
+          nblocks != (a.ngroups + 7) / 8 * 8 * 4 * a.nb)
+        return hipErrorInvalidValue;
+    } else if (a.ntiles != (a.pxy + a.T - 1) / a.T || nblocks != long(a.ntiles) * a.pxy * a.nb ||
+               (long(a.ntiles) * a.pxy) % 8 != 0) {
+      return hipErrorInvalidValue;
+    }
     const size_t lds = pass_lds_bytes<R, P1, P2, false>(a.T);
     // the solver's usual tile width has its own compiled kernel
     constexpr int TC = std::is_same<R, float>::value ? 16 : 8;
@@ -199,6 +215,7 @@ struct LenImpl {
       }
     }
     return hipGetLastError();
+    }
   }
   template <int C, int MODE>
   static void xinv_launch(const cx<R>* A, XArgs a, const c128* J_, const c128* B, const cx<R>* H, const cx<R>* Hmu,
@@ -231,8 +248,8 @@ struct LenImpl {
 
   // register the apply kernels and, for double, the precompute passes
   template <bool APPLY, bool SYMBOL>
-  static void register_all() {
-    LenOps<R>& o = len_table<R>()[P];
+  static void register_all(int variant = 0) {
+    LenOps<R>& o = len_table<R>()[P * kMaxSplits + variant];
     o.P = P;
     o.P1 = P1;
     o.P2 = P2;
@@ -263,6 +280,18 @@ struct LenImpl {
       vie::LenImpl<double, P1_, P2_>::register_all<APPLY_, SYMBOL_>();                 \
     }                                                                                \
   } reg_len_##P1_##x##P2_;                                                           \
+  }
+
+// Registers the split P1 x P2 of a length already registered with another
+// split, as variant 1 (apply kernels in FP32 and FP64 only).
+#define VIE_REGISTER_SPLIT(P1_, P2_)                                                  \
+  namespace {                                                                        \
+  struct RegSplit##P1_##x##P2_ {                                                     \
+    RegSplit##P1_##x##P2_() {                                                        \
+      vie::LenImpl<float, P1_, P2_>::register_all<true, false>(1);                   \
+      vie::LenImpl<double, P1_, P2_>::register_all<true, false>(1);                  \
+    }                                                                                \
+  } reg_split_##P1_##x##P2_;                                                         \
   }
 
 }  // namespace vie

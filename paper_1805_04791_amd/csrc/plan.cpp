@@ -31,7 +31,7 @@ namespace vie {
 
 template <typename R>
 LenOps<R>* len_table() {
-  static LenOps<R> t[kMaxLen + 1];
+  static LenOps<R> t[(kMaxLen + 1) * kMaxSplits];
   return t;
 }
 template LenOps<float>* len_table<float>();
@@ -408,7 +408,7 @@ struct ApplyCall {
 // x forward: rows (rhs, c, z, y) of the box, bx samples -> P; TV is the
 // storage of the input vectors (complex128, or complex64 in FP32 applies)
 template <typename R, typename TV>
-hipError_t pass_xfwd(const ApplyCall<R>& c, const TV* in, int T, hipStream_t s) {
+hipError_t pass_xfwd(const ApplyCall<R>& c, const LenOps<R>* ops, const TV* in, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
   const long nr = long(c.g.bz) * c.g.by;
   const long rows = long(c.nb) * pl->C * nr;
@@ -416,54 +416,65 @@ hipError_t pass_xfwd(const ApplyCall<R>& c, const TV* in, int T, hipStream_t s) 
   Geo g{T, int((rows + T - 1) / T), rows, c.g.bx, P, c.act, long(pl->C) * nr};
   MemStore<cx<R>> dst{c.A, 0, P, 1, 1.0, 0};
   if constexpr (std::is_same<TV, c128>::value) {
-    if (c.g.rows) return c.ops->contig_fwd_rows(RowLoad<c128>{in, c.g.rows, nr, c.g.np}, dst, g, 1, c.tw, s);
-    return c.ops->contig_fwd(MemLoad<c128>{in, 0, c.g.bx, 1}, dst, g, 1, c.tw, s);
+    if (c.g.rows) return ops->contig_fwd_rows(RowLoad<c128>{in, c.g.rows, nr, c.g.np}, dst, g, 1, c.tw, s);
+    return ops->contig_fwd(MemLoad<c128>{in, 0, c.g.bx, 1}, dst, g, 1, c.tw, s);
   } else {
     if (c.g.rows) return hipErrorInvalidValue;
-    return c.ops->contig_fwd_v32(MemLoad<c64>{in, 0, c.g.bx, 1}, dst, g, 1, c.tw, s);
+    return ops->contig_fwd_v32(MemLoad<c64>{in, 0, c.g.bx, 1}, dst, g, 1, c.tw, s);
   }
 }
 
 // y forward: A [rhs][c][bz][by][P] -> B [rhs][c][bz][P][P]
 template <typename R>
-hipError_t pass_yfwd(const ApplyCall<R>& c, int T, hipStream_t s) {
+hipError_t pass_yfwd(const ApplyCall<R>& c, const LenOps<R>* ops, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
   const long P = c.g.sp->Pxy, by = c.g.by;
   Geo g{T, int(P / T), P, int(by), int(P), c.act, long(pl->C) * c.g.bz * P};
   MemLoad<cx<R>> src{c.A, by * P, 1, P};
   MemStore<cx<R>> dst{c.B, P * P, 1, P, 1.0, 0};
-  return c.ops->strided(false, src, dst, g, long(c.nb) * pl->C * c.g.bz, c.tw, s);
+  return ops->strided(false, src, dst, g, long(c.nb) * pl->C * c.g.bz, c.tw, s);
 }
 
+// order 1: mirror groups (the four slices reading the same folded table rows
+// back to back on one XCD); order 0: slices (ky, tile), mirrored ky slices
+// paired when the slice count allows it
 template <typename R>
-hipError_t pass_z(const ApplyCall<R>& c, const cx<R>* tab, int T, hipStream_t s) {
+hipError_t pass_z(const ApplyCall<R>& c, const LenOps<R>* opsz, const cx<R>* tab, int T, int order, hipStream_t s) {
   const vie_plan* pl = c.pl;
   const long Pz = c.g.sp->Pz, Q = c.g.sp->Pxy, bz = c.g.bz;
   const long ntiles = (Q + T - 1) / T;  // the last tile may be partial
   ZArgs a{T,      int(ntiles), int(Pz / 2),           int(Pz), c.g.sp->nxp, c.g.sp->ne, bz * Q * Q,
           long(pl->C) * bz * Q * Q, c.nb, int(bz), int(Q), pl->omega, c.act};
-  if (ntiles * Q % 8 != 0) return hipErrorInvalidValue;  // XCD block order: slices in groups of 8
-  a.pair_ky = (Q % 2 == 0 && (Q / 2) * ntiles % 8 == 0) ? 1 : 0;
-  const long nblocks = ntiles * Q * c.nb;
-  return c.opsz->zpass(geom_mul(pl, c.g), c.B, tab, a, nblocks, c.twz, s);
+  long nblocks;
+  if (order == 1) {
+    a.quad = 1;
+    a.ntx = int((Q / 2 + T - 1) / T);
+    a.ngroups = (Q / 2) * a.ntx;
+    nblocks = (a.ngroups + 7) / 8 * 8 * 4 * c.nb;
+  } else {
+    if (ntiles * Q % 8 != 0) return hipErrorInvalidValue;  // XCD block order: slices in groups of 8
+    a.pair_ky = (Q % 2 == 0 && (Q / 2) * ntiles % 8 == 0) ? 1 : 0;
+    nblocks = ntiles * Q * c.nb;
+  }
+  return opsz->zpass(geom_mul(pl, c.g), c.B, tab, a, nblocks, c.twz, s);
 }
 
 // y inverse: B -> A, outputs y < by
 template <typename R>
-hipError_t pass_yinv(const ApplyCall<R>& c, int T, hipStream_t s) {
+hipError_t pass_yinv(const ApplyCall<R>& c, const LenOps<R>* ops, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
   const long P = c.g.sp->Pxy, by = c.g.by;
   Geo g{T, int(P / T), P, int(P), int(by), c.act, long(pl->C) * c.g.bz * P};
   MemLoad<cx<R>> src{c.B, P * P, 1, P};
   MemStore<cx<R>> dst{c.A, by * P, 1, P, 1.0, 0};
-  return c.ops->strided(true, src, dst, g, long(c.nb) * pl->C * c.g.bz, c.tw, s);
+  return ops->strided(true, src, dst, g, long(c.nb) * pl->C * c.g.bz, c.tw, s);
 }
 
 // TV: storage of J (the input), TO: of the output (complex64 output from
 // complex128 input: the FP32 matvec of the mixed solver)
 template <typename R, typename TV, typename TO = TV>
-hipError_t pass_xinv(const ApplyCall<R>& c, const TV* addv, const c128* bvec, TO* out, int mode, int T,
-                     hipStream_t s) {
+hipError_t pass_xinv(const ApplyCall<R>& c, const LenOps<R>* ops, const TV* addv, const c128* bvec, TO* out,
+                     int mode, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
   const long NN = long(c.g.bz) * c.g.by;
   const int xcd = 1;  // tiles of all right-hand sides that share H run back to back on one XCD
@@ -479,13 +490,13 @@ hipError_t pass_xinv(const ApplyCall<R>& c, const TV* addv, const c128* bvec, TO
     Hmu = pl->Hmu64;
   }
   if constexpr (std::is_same<TV, c128>::value && std::is_same<TO, c128>::value) {
-    return c.ops->xinv(pl->C, mode, c.A, a, addv, bvec, H, Hmu, out, c.tw, s);
+    return ops->xinv(pl->C, mode, c.A, a, addv, bvec, H, Hmu, out, c.tw, s);
   } else if constexpr (std::is_same<TV, c128>::value) {
-    if (mode != MODE_MATVEC || !c.ops->xinv_w32) return hipErrorInvalidValue;
-    return c.ops->xinv_w32(pl->C, c.A, a, addv, H, Hmu, out, c.tw, s);
+    if (mode != MODE_MATVEC || !ops->xinv_w32) return hipErrorInvalidValue;
+    return ops->xinv_w32(pl->C, c.A, a, addv, H, Hmu, out, c.tw, s);
   } else {
-    if (mode != MODE_MATVEC) return hipErrorInvalidValue;
-    return c.ops->xinv_v32(pl->C, c.A, a, addv, H, Hmu, out, c.tw, s);
+    if (mode != MODE_MATVEC || !ops->xinv_v32) return hipErrorInvalidValue;
+    return ops->xinv_v32(pl->C, c.A, a, addv, H, Hmu, out, c.tw, s);
   }
 }
 
@@ -508,9 +519,12 @@ int ensure_workspace(vie_plan* pl, int nb) {
 }
 
 // time one pass for each tile candidate and keep the fastest
+// best_ms (optional): the time of the chosen tile (3 launches); skip_unrunnable:
+// candidates whose launch is refused (an order that does not fit the tile
+// count) are skipped instead of failing the choice
 template <typename R, typename F>
 int pick_tile(vie_plan* pl, int P1, int P2, bool contig, int maxthreads, int cols, F&& run, hipStream_t s, int* out,
-              bool ragged = false) {
+              bool ragged = false, float* best_out = nullptr, bool skip_unrunnable = false) {
   hipEvent_t e0, e1;
   HIPCHK(pl, hipEventCreate(&e0));
   HIPCHK(pl, hipEventCreate(&e1));
@@ -521,7 +535,16 @@ int pick_tile(vie_plan* pl, int P1, int P2, bool contig, int maxthreads, int col
     any_full = any_full || tile_ok<R>(pl, P1, P2, T, contig, cols, maxthreads, true, ragged);
   for (int T : kTileChoices) {
     if (!tile_ok<R>(pl, P1, P2, T, contig, cols, maxthreads, any_full, ragged)) continue;
-    HIPCHK(pl, run(T));  // warm-up
+    if (skip_unrunnable) {
+      const hipError_t e = run(T);  // warm-up; a refused launch shape is skipped
+      if (e == hipErrorInvalidValue) {
+        (void)hipGetLastError();
+        continue;
+      }
+      HIPCHK(pl, e);
+    } else {
+      HIPCHK(pl, run(T));  // warm-up
+    }
     HIPCHK(pl, hipEventRecord(e0, s));
     for (int r = 0; r < 3; ++r) HIPCHK(pl, run(T));
     HIPCHK(pl, hipEventRecord(e1, s));
@@ -535,12 +558,37 @@ int pick_tile(vie_plan* pl, int P1, int P2, bool contig, int maxthreads, int col
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (best == 0) return fail(pl, VIE_E_SIZE, "no tile shape fits the LDS limit");
+  if (best == 0) {
+    if (skip_unrunnable) {
+      *out = 0;
+      return VIE_OK;
+    }
+    return fail(pl, VIE_E_SIZE, "no tile shape fits the LDS limit");
+  }
   *out = best;
+  if (best_out) *best_out = best_ms;
   return VIE_OK;
 }
 
 int tune_key(int nb, const Geom& g) { return bucket_of(nb) + (g.id << 20) + ((g.mul + 1) << 24); }
+
+// Tile choices measured by any plan of the process, so that later plans of
+// the same shape (a serving stream's requests on one grid) do not measure
+// again: keyed by precision, transform lengths, components, multiply, batch
+// bucket and the extent of the data box (and whether it holds support rows).
+using SharedTuneKey = std::tuple<int, int, int, int, int, int, int, int, int, int>;
+std::map<SharedTuneKey, Tune>& shared_tunes() {
+  static std::map<SharedTuneKey, Tune> m;
+  return m;
+}
+std::mutex& shared_tunes_mutex() {
+  static std::mutex m;
+  return m;
+}
+SharedTuneKey shared_key(const vie_plan* pl, int rsize, int nb, const Geom& g) {
+  return SharedTuneKey{rsize, g.sp->Pxy, g.sp->Pz, pl->C, g.mul < 0 ? (pl->full ? MUL_MAX6 : MUL_SYM3) : g.mul,
+                       bucket_of(nb), g.bx, g.by, g.bz, g.rows ? 1 : 0};
+}
 
 // tiles chosen without measuring: about 256 threads per block, whole 128-byte
 // lines where the column count allows
@@ -571,6 +619,22 @@ int fixed_tune(vie_plan* pl, const ApplyCall<R>& c, Tune* t) {
   return default_tune<R>(pl, c, t);
 }
 
+// the split variant v of the x/y length (Pxy) and of the z length usable for
+// vectors TV and outputs TO, or null
+template <typename R, typename TV, typename TO>
+const LenOps<R>* xy_ops(int P, int v) {
+  const LenOps<R>* o = len_ops<R>(P, v);
+  if (!o || !o->strided || !o->contig_fwd || !o->xinv) return nullptr;
+  if (!std::is_same<TV, c128>::value && (!o->contig_fwd_v32 || !o->xinv_v32)) return nullptr;
+  if (!std::is_same<TO, TV>::value && !o->xinv_w32) return nullptr;
+  return o;
+}
+template <typename R>
+const LenOps<R>* z_ops(int P, int v) {
+  const LenOps<R>* o = len_ops<R>(P, v);
+  return (o && o->zpass) ? o : nullptr;
+}
+
 template <typename R, typename TV, typename TO = TV>
 int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStream_t s, Tune* t) {
   const int idx = std::is_same<R, double>::value ? 1 : 0;
@@ -580,55 +644,160 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStre
     *t = it->second;
     return VIE_OK;
   }
-  const int P1 = c.ops->P1, P2 = c.ops->P2, Z1 = c.opsz->P1, Z2 = c.opsz->P2;
+  const SharedTuneKey skey = shared_key(pl, int(sizeof(R)), c.nb, c.g);
+  // VIE_TILES="xfwd,yfwd,z,yinv,xinv[,zorder]" pins the tiles (and the z
+  // pass's block order, 0 paired by default, 1 mirror groups) of this precision, and
+  // VIE_SPLITS="xfwd,yfwd,z,yinv,xinv" the split variant of each pass (where
+  // the length has it) with default tiles (profiling runs that must repeat a
+  // measured launch shape, and tests of every split); pinned choices are not
+  // shared with other plans
+  const char* pin = std::getenv(sizeof(R) == 8 ? "VIE_TILES_FP64" : "VIE_TILES");
+  const char* spin = std::getenv("VIE_SPLITS");
+  if (!pin && !spin) {
+    std::lock_guard<std::mutex> lk(shared_tunes_mutex());
+    auto sit = shared_tunes().find(skey);
+    if (sit != shared_tunes().end()) {
+      pl->tune[idx][key] = sit->second;
+      *t = sit->second;
+      return VIE_OK;
+    }
+  }
+  const int Pxy = c.g.sp->Pxy, Pz = c.g.sp->Pz;
+  const int fmax = pl->C == 6 ? fused_max_threads<R, 6>() : fused_max_threads<R, 3>();
   Tune d;
   int rc = default_tune<R>(pl, c, &d);
   if (rc) return rc;
-  const int P = P1 * P2;
-  const int fmax = pl->C == 6 ? fused_max_threads<R, 6>() : fused_max_threads<R, 3>();
-  // VIE_TILES="xfwd,yfwd,z,yinv,xinv" pins the tiles of this FFT length and
-  // precision (profiling runs that must repeat a measured launch shape)
-  const char* pin = std::getenv(sizeof(R) == 8 ? "VIE_TILES_FP64" : "VIE_TILES");
-  int pt[5];
-  if (pin && std::sscanf(pin, "%d,%d,%d,%d,%d", &pt[0], &pt[1], &pt[2], &pt[3], &pt[4]) == 5) {
-    const bool ok = tile_ok<R>(pl, P1, P2, pt[0], true, P, kPassMaxThreads, false) &&
-                    tile_ok<R>(pl, P1, P2, pt[1], false, P, kPassMaxThreads, false) &&
-                    tile_ok<R>(pl, Z1, Z2, pt[2], false, P, fmax, false, true) &&
-                    tile_ok<R>(pl, P1, P2, pt[3], false, P, kPassMaxThreads, false) &&
-                    tile_ok<R>(pl, P1, P2, pt[4], true, P, fmax, false);
+  int sv[5] = {0, 0, 0, 0, 0};
+  const int nsv = spin ? std::sscanf(spin, "%d,%d,%d,%d,%d", &sv[0], &sv[1], &sv[2], &sv[3], &sv[4]) : 0;
+  if (nsv == 5) {
+    // a pinned variant that a length does not have falls back to its split 0
+    for (int i = 0; i < 5; ++i) {
+      const bool has = i == 2 ? z_ops<R>(Pz, sv[i]) != nullptr : xy_ops<R, TV, TO>(Pxy, sv[i]) != nullptr;
+      if (!has) sv[i] = 0;
+    }
+    const LenOps<R>* o[5] = {xy_ops<R, TV, TO>(Pxy, sv[0]), xy_ops<R, TV, TO>(Pxy, sv[1]), z_ops<R>(Pz, sv[2]),
+                             xy_ops<R, TV, TO>(Pxy, sv[3]), xy_ops<R, TV, TO>(Pxy, sv[4])};
+    d.vx_fwd = sv[0];
+    d.vy_fwd = sv[1];
+    d.vz = sv[2];
+    d.vy_inv = sv[3];
+    d.vx_inv = sv[4];
+    d.tx_fwd = default_tile<R>(pl, o[0]->P1, o[0]->P2, true, kPassMaxThreads, Pxy);
+    d.ty_fwd = default_tile<R>(pl, o[1]->P1, o[1]->P2, false, kPassMaxThreads, Pxy);
+    d.tz = default_tile<R>(pl, o[2]->P1, o[2]->P2, false, fmax, Pxy, true);
+    d.ty_inv = default_tile<R>(pl, o[3]->P1, o[3]->P2, false, kPassMaxThreads, Pxy);
+    d.tx_inv = default_tile<R>(pl, o[4]->P1, o[4]->P2, true, fmax, Pxy);
+    if (!d.tx_fwd || !d.ty_fwd || !d.tz || !d.ty_inv || !d.tx_inv)
+      return fail(pl, VIE_E_SIZE, "no tile shape fits the LDS limit");
+  }
+  int pt[6] = {0, 0, 0, 0, 0, 0};
+  const int npin = pin ? std::sscanf(pin, "%d,%d,%d,%d,%d,%d", &pt[0], &pt[1], &pt[2], &pt[3], &pt[4], &pt[5]) : 0;
+  if (npin >= 5) {
+    const LenOps<R>* o[5] = {xy_ops<R, TV, TO>(Pxy, d.vx_fwd), xy_ops<R, TV, TO>(Pxy, d.vy_fwd), z_ops<R>(Pz, d.vz),
+                             xy_ops<R, TV, TO>(Pxy, d.vy_inv), xy_ops<R, TV, TO>(Pxy, d.vx_inv)};
+    const bool ok = tile_ok<R>(pl, o[0]->P1, o[0]->P2, pt[0], true, Pxy, kPassMaxThreads, false) &&
+                    tile_ok<R>(pl, o[1]->P1, o[1]->P2, pt[1], false, Pxy, kPassMaxThreads, false) &&
+                    tile_ok<R>(pl, o[2]->P1, o[2]->P2, pt[2], false, Pxy, fmax, false, true) &&
+                    tile_ok<R>(pl, o[3]->P1, o[3]->P2, pt[3], false, Pxy, kPassMaxThreads, false) &&
+                    tile_ok<R>(pl, o[4]->P1, o[4]->P2, pt[4], true, Pxy, fmax, false);
     if (!ok) return fail(pl, VIE_E_ARG, std::string("tiles pinned by the environment do not fit: ") + pin);
     d.tx_fwd = pt[0];
     d.ty_fwd = pt[1];
     d.tz = pt[2];
     d.ty_inv = pt[3];
     d.tx_inv = pt[4];
-  } else if (pl->n >= 48 && env_flag("VIE_AUTOTUNE", true)) {
-    // measure only where it pays: large grids, unless switched off
+    d.zorder = pt[5] != 0 ? 1 : 0;
+  } else if (nsv != 5 && pl->n >= 48 && env_flag("VIE_AUTOTUNE", true)) {
+    // measure only where it pays: large grids, unless switched off.  Every
+    // pass reads and writes its data in natural order, so each may use its
+    // own split; per pass the fastest (split, tile) over the compiled splits
     const cx<R>* tab;
     if constexpr (std::is_same<R, float>::value)
       tab = c.g.sp->tab32;
     else
       tab = c.g.sp->tab64;
-    rc = pick_tile<R>(pl, P1, P2, true, kPassMaxThreads, P, [&](int T) { return pass_xfwd<R, TV>(c, in, T, s); }, s, &d.tx_fwd);
+    const bool dbg = env_flag("VIE_DEBUG", false);
+    // (variant, tile) with the smallest time of run(ops, T) over the splits
+    auto best_of = [&](const char* name, bool z, bool contig, int maxthreads, int* vout, int* tout,
+                       auto&& run) -> int {
+      float best = 1e30f;
+      for (int v = 0; v < kMaxSplits; ++v) {
+        const LenOps<R>* o = z ? z_ops<R>(Pz, v) : xy_ops<R, TV, TO>(Pxy, v);
+        if (!o) continue;
+        int tv = 0;
+        float ms = 0;
+        const int r = pick_tile<R>(pl, o->P1, o->P2, contig, maxthreads, Pxy, [&](int T) { return run(o, T); }, s,
+                                   &tv, z, &ms, true);
+        if (r) return r;
+        if (dbg && tv)
+          std::fprintf(stderr, "[vie] %s P=%d split %dx%d fp%d nb=%d: T=%d %.3f ms\n", name, o->P, o->P1, o->P2,
+                       int(8 * sizeof(R)), c.nb, tv, double(ms));
+        if (tv && ms < best) {
+          best = ms;
+          *vout = v;
+          *tout = tv;
+        }
+      }
+      return best < 1e30f ? VIE_OK : fail(pl, VIE_E_SIZE, std::string("no launch shape for the ") + name);
+    };
+    rc = best_of("x fwd", false, true, kPassMaxThreads, &d.vx_fwd, &d.tx_fwd,
+                 [&](const LenOps<R>* o, int T) { return pass_xfwd<R, TV>(c, o, in, T, s); });
     if (rc) return rc;
-    rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, P, [&](int T) { return pass_yfwd<R>(c, T, s); }, s, &d.ty_fwd);
+    rc = best_of("y fwd", false, false, kPassMaxThreads, &d.vy_fwd, &d.ty_fwd,
+                 [&](const LenOps<R>* o, int T) { return pass_yfwd<R>(c, o, T, s); });
     if (rc) return rc;
-    rc = pick_tile<R>(pl, Z1, Z2, false, fmax, P, [&](int T) { return pass_z<R>(c, tab, T, s); }, s, &d.tz, true);
-    if (rc) return rc;
-    rc = pick_tile<R>(pl, P1, P2, false, kPassMaxThreads, P, [&](int T) { return pass_yinv<R>(c, T, s); }, s, &d.ty_inv);
+    // the z pass: split, tile width and block order (the paired order needs
+    // the slices in groups of 8: tiles that do not allow it are refused at
+    // launch and skipped)
+    {
+      int vq = 0, tq = 0, vp = 0, tp = 0;
+      rc = best_of("z (mirror groups)", true, false, fmax, &vq, &tq,
+                   [&](const LenOps<R>* o, int T) { return pass_z<R>(c, o, tab, T, 1, s); });
+      if (rc) return rc;
+      float mq = 0, mp = 1e30f;
+      rc = pick_tile<R>(pl, z_ops<R>(Pz, vq)->P1, z_ops<R>(Pz, vq)->P2, false, fmax, Pxy,
+                        [&](int T) { return pass_z<R>(c, z_ops<R>(Pz, vq), tab, T, 1, s); }, s, &tq, true, &mq, true);
+      if (rc) return rc;
+      const int rp = best_of("z (paired)", true, false, fmax, &vp, &tp,
+                             [&](const LenOps<R>* o, int T) { return pass_z<R>(c, o, tab, T, 0, s); });
+      if (rp == VIE_OK && tp) {
+        rc = pick_tile<R>(pl, z_ops<R>(Pz, vp)->P1, z_ops<R>(Pz, vp)->P2, false, fmax, Pxy,
+                          [&](int T) { return pass_z<R>(c, z_ops<R>(Pz, vp), tab, T, 0, s); }, s, &tp, true, &mp,
+                          true);
+        if (rc) return rc;
+      }
+      if (tp && mp < mq) {
+        d.zorder = 0;
+        d.vz = vp;
+        d.tz = tp;
+      } else {
+        d.zorder = 1;
+        d.vz = vq;
+        d.tz = tq;
+      }
+    }
+    rc = best_of("y inv", false, false, kPassMaxThreads, &d.vy_inv, &d.ty_inv,
+                 [&](const LenOps<R>* o, int T) { return pass_yinv<R>(c, o, T, s); });
     if (rc) return rc;
     // the raw convolution for complex128 vectors (any J), the matvec for complex64
     const int xmode = std::is_same<TV, c128>::value && std::is_same<TO, c128>::value ? MODE_CONV : MODE_MATVEC;
-    rc = pick_tile<R>(pl, P1, P2, true, fmax, P,
-                      [&](int T) { return pass_xinv<R, TV, TO>(c, in, nullptr, out, xmode, T, s); }, s,
-                      &d.tx_inv);
+    rc = best_of("x inv", false, true, fmax, &d.vx_inv, &d.tx_inv, [&](const LenOps<R>* o, int T) {
+      return pass_xinv<R, TV, TO>(c, o, in, nullptr, out, xmode, T, s);
+    });
     if (rc) return rc;
   }
   d.tuned = true;
   if (env_flag("VIE_DEBUG", false))
-    std::fprintf(stderr, "[vie] tiles P=%d fp%d nb=%d box %dx%dx%d: xfwd %d yfwd %d z %d yinv %d xinv %d\n", P,
-                 int(8 * sizeof(R)), c.nb, c.g.bx, c.g.by, c.g.bz, d.tx_fwd, d.ty_fwd, d.tz, d.ty_inv, d.tx_inv);
+    std::fprintf(stderr,
+                 "[vie] tiles Pxy=%d Pz=%d fp%d nb=%d box %dx%dx%d: xfwd %d/%d yfwd %d/%d z %d/%d order %d "
+                 "yinv %d/%d xinv %d/%d (split/tile)\n",
+                 Pxy, Pz, int(8 * sizeof(R)), c.nb, c.g.bx, c.g.by, c.g.bz, d.vx_fwd, d.tx_fwd, d.vy_fwd, d.ty_fwd,
+                 d.vz, d.tz, d.zorder, d.vy_inv, d.ty_inv, d.vx_inv, d.tx_inv);
   pl->tune[idx][key] = d;
+  if (!pin && !spin) {
+    std::lock_guard<std::mutex> lk(shared_tunes_mutex());
+    shared_tunes()[skey] = d;
+  }
   *t = d;
   return VIE_OK;
 }
@@ -719,21 +888,28 @@ int apply_typed(vie_plan* pl, const Geom& geom, const TV* in, const TV* addv, co
     const double comb_f = (mode == MODE_CONV) ? 0.0 : 72.0 * vN3 / 3.0;
     // the allocation-free path records no events (creating one may allocate)
     const bool prof = !fw;
+    // the split of each pass (tuned or pinned; variant 0 by default)
+    const LenOps<R>* ox_f = xy_ops<R, TV, TO>(sp.Pxy, t.vx_fwd);
+    const LenOps<R>* oy_f = xy_ops<R, TV, TO>(sp.Pxy, t.vy_fwd);
+    const LenOps<R>* oz = z_ops<R>(sp.Pz, t.vz);
+    const LenOps<R>* oy_i = xy_ops<R, TV, TO>(sp.Pxy, t.vy_inv);
+    const LenOps<R>* ox_i = xy_ops<R, TV, TO>(sp.Pxy, t.vx_inv);
+    if (!ox_f || !oy_f || !oz || !oy_i || !ox_i) return fail(pl, VIE_E_STATE, "tuned split not compiled");
     int tok = prof ? prof_begin(pl, s) : -1;
-    HIPCHK(pl, (pass_xfwd<R, TV>(c, inr, t.tx_fwd, s)));
+    HIPCHK(pl, (pass_xfwd<R, TV>(c, ox_f, inr, t.tx_fwd, s)));
     prof_end(pl, f0 + 0, tok, s, vN3 * c16 + vN2P * cr, rows_x * fft_row);
     tok = prof ? prof_begin(pl, s) : -1;
-    HIPCHK(pl, pass_yfwd<R>(c, t.ty_fwd, s));
+    HIPCHK(pl, pass_yfwd<R>(c, oy_f, t.ty_fwd, s));
     prof_end(pl, f0 + 1, tok, s, (vN2P + vNP2) * cr, rows_y * fft_row);
     tok = prof ? prof_begin(pl, s) : -1;
-    HIPCHK(pl, pass_z<R>(c, tab, t.tz, s));
+    HIPCHK(pl, pass_z<R>(c, oz, tab, t.tz, t.zorder, s));
     prof_end(pl, f0 + 2, tok, s, 2.0 * vNP2 * cr + double(sp.tab_elems) * cr, 2.0 * rows_z * fft_row_z + mul_f);
     tok = prof ? prof_begin(pl, s) : -1;
-    HIPCHK(pl, pass_yinv<R>(c, t.ty_inv, s));
+    HIPCHK(pl, pass_yinv<R>(c, oy_i, t.ty_inv, s));
     prof_end(pl, f0 + 3, tok, s, (vN2P + vNP2) * cr, rows_y * fft_row);
     tok = prof ? prof_begin(pl, s) : -1;
-    HIPCHK(pl, (pass_xinv<R, TV, TO>(c, addv ? addv + off : inr, bvec ? bvec + off : nullptr, outr, mode, t.tx_inv,
-                                     s)));
+    HIPCHK(pl, (pass_xinv<R, TV, TO>(c, ox_i, addv ? addv + off : inr, bvec ? bvec + off : nullptr, outr, mode,
+                                     t.tx_inv, s)));
     prof_end(pl, f0 + 4, tok, s, xinv_b, rows_x * fft_row + comb_f);
   }
   return VIE_OK;

@@ -50,6 +50,8 @@ inline Box box_of(const Geom& g, int n) { return Box{n, g.bx, g.by, g.bz, g.x0, 
 // tile choices of the five apply passes
 struct Tune {
   int tx_fwd = 0, ty_fwd = 0, tz = 0, ty_inv = 0, tx_inv = 0;
+  int vx_fwd = 0, vy_fwd = 0, vz = 0, vy_inv = 0, vx_inv = 0;  // split variant of each pass
+  int zorder = 0;  // block order of the z pass: 0 paired ky slices (plain if not pairable), 1 mirror groups
   bool tuned = false;
 };
 

@@ -234,17 +234,20 @@ def test_short_box_transform_equals_full_length(vie):
     full.close()
 
 
-def test_z_block_order_with_and_without_slice_pairing(vie, monkeypatch):
-    """The z pass runs the mirrored slices (ky, P - ky) of a column tile back
-    to back on one XCD when (P / 2) * tiles is a multiple of 8, and in plain
-    order otherwise.  At P = 120, z tiles of 16 (8 tiles) are paired, tiles of
-    8 (FP64) and 24 (FP32) are not; the solves agree."""
+def test_z_block_orders_give_the_same_solves(vie, monkeypatch):
+    """The z pass's block orders only decide which block computes a column
+    and where: mirror groups (the four slices reading the same folded table
+    rows back to back on one XCD, the default), mirrored ky slices paired
+    (when (P / 2) * tiles is a multiple of 8) and plain order.  At P = 120,
+    z tiles of 16 (8 tiles) can be paired, tiles of 8 (FP64) and 24 (FP32)
+    cannot; all three give bitwise the same FP64 and mixed solves."""
     n = 64
     coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 18)
     inc = plane_waves(n, omega, 2, 40)
     out = {}
-    for name, tiles64, tiles32 in (("paired", "8,8,16,8,8", "8,24,16,24,8"),
-                                   ("plain", "8,8,8,8,8", "8,24,24,24,8")):
+    for name, tiles64, tiles32 in (("groups", "8,8,16,8,8,1", "8,24,16,24,8,1"),
+                                   ("paired", "8,8,16,8,8,0", "8,24,16,24,8,0"),
+                                   ("plain", "8,8,8,8,8,0", "8,24,24,24,8,0")):
         monkeypatch.setenv("VIE_TILES_FP64", tiles64)
         monkeypatch.setenv("VIE_TILES", tiles32)
         plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2)
@@ -255,9 +258,9 @@ def test_z_block_order_with_and_without_slice_pairing(vie, monkeypatch):
             assert rc == 0
             out[name].append(d.cpu().numpy())
         plan.close()
-    for k, err in ((0, 1e-11), (1, 1e-9)):
-        for r in range(2):
-            assert rel(out["paired"][k][r], out["plain"][k][r]) < err
+    for k in range(2):
+        assert np.array_equal(out["groups"][k], out["paired"][k])
+        assert np.array_equal(out["groups"][k], out["plain"][k])
 
 
 def test_x0_outside_support_rows_is_ignored(vie):

@@ -56,11 +56,29 @@ def oracle_solution(A, inc):
     return x
 
 
+class Helmholtz128:
+    """The headline problem, its oracle operator and (computed once) the oracle
+    solution of right-hand side 0."""
+
+    def __init__(self):
+        self.prob = gen.config_problem("helmholtz128", nrhs=8)
+        print("[full-size] oracle setup at 128^3 (Helmholtz)", flush=True)
+        self.A = op.Operator(self.prob.kind, self.prob.coef, self.prob.omega)
+        self._x0 = None
+
+    def __iter__(self):
+        return iter((self.prob, self.A))
+
+    def x0(self):
+        if self._x0 is None:
+            print("[full-size] oracle solve at 128^3 (Helmholtz, right-hand side 0)", flush=True)
+            self._x0 = oracle_solution(self.A, self.prob.inc[0])
+        return self._x0
+
+
 @pytest.fixture(scope="module")
 def helmholtz128():
-    prob = gen.config_problem("helmholtz128", nrhs=8)
-    print("[full-size] oracle setup at 128^3 (Helmholtz)", flush=True)
-    return prob, op.Operator(prob.kind, prob.coef, prob.omega)
+    return Helmholtz128()
 
 
 @pytest.mark.timeout(900)
@@ -91,8 +109,7 @@ def test_batched_mixed_solve_128_matches_oracle(vie, helmholtz128):
     for r in range(8):
         assert st[r]["rel_residual"] <= 1e-9 and st[r]["matvecs_fp32"] > 0
         assert oracle_residual(A, prob.inc[r], d[r]) <= 2e-9
-    print("[full-size] oracle solve at 128^3 (Helmholtz, right-hand side 0)", flush=True)
-    x0 = oracle_solution(A, prob.inc[0])
+    x0 = helmholtz128.x0()
     assert rel(d[0], x0) < 1e-8
     assert rel(d64[0], x0) < 1e-10
     # a right-hand side alone: bitwise the batch's answer
@@ -100,6 +117,31 @@ def test_batched_mixed_solve_128_matches_oracle(vie, helmholtz128):
     assert np.array_equal(d3.cpu().numpy()[0], d[3])
     assert st3[0]["iters"] == st[3]["iters"]
     plan.close()
+
+
+@pytest.mark.timeout(900)
+def test_alternative_splits_128_match_oracle(vie, helmholtz128, monkeypatch):
+    """Every pass on its alternative split (VIE_SPLITS): the whole-grid
+    applies on 256 = 32 x 8 and the solver's 216 = 12 x 18 (x, y) and
+    256 = 32 x 8 (z) against the oracle."""
+    monkeypatch.setenv("VIE_SPLITS", "1,1,1,1,1")
+    prob, A = helmholtz128
+    n = prob.n
+    x = gen.random_density((1, 3, n, n, n), gen.rng_for(gen.CONFIG_IDS["test"], 802))
+    plan = vie.Plan(prob.kind, prob.coef, omega=prob.omega, precision=vie.PREC_MIXED, max_rhs=1)
+    assert plan.info()["box_P"] == 216
+    y64 = plan.apply(x, vie.APPLY_FP64).cpu().numpy()[0]
+    y32 = plan.apply(x, vie.APPLY_FP32).cpu().numpy()[0]
+    d, _, st, rc = plan.solve(prob.inc[:1], tol=1e-9, want_field=False)
+    d64, _, st64, rc64 = plan.solve(prob.inc[:1], tol=1e-12, fp64=True, want_field=False)
+    assert rc == vie.OK and rc64 == vie.OK
+    plan.close()
+    ref = A.apply(x[0])
+    assert rel(y64, ref) < 1e-12
+    assert rel(y32, ref) < 2e-6
+    x0 = helmholtz128.x0()
+    assert rel(d.cpu().numpy()[0], x0) < 1e-8
+    assert rel(d64.cpu().numpy()[0], x0) < 1e-10
 
 
 @pytest.mark.timeout(900)

@@ -12,6 +12,12 @@ Pxy for the solver's support box; Pz = 2n along z):
 * lengths 16-64, 216, 256, 320, 512 and 640 are covered by the operator,
   box and full-size tests.
 
+Splits: the lengths 128, 192, 216 and 256 are compiled with a second
+factorization P1 x P2 (8x16, 12x16, 12x18, 32x8 beside 16x8, 16x12, 18x12,
+16x16) that the autotuner may pick per pass; with every pass pinned to it
+(VIE_SPLITS) the whole-grid applies at n = 64 and 96 match the oracle
+(n = 128: the full-size tests).
+
 Parameters: an apply on the unit box with h = 1/n (origin 0, the paper's
 numerical section) and applies in the static limit omega = 2 pi 1e-50
 (Helmholtz and reduced Maxwell, the first rows of Tables 2-5) against the
@@ -73,6 +79,29 @@ def test_solver_and_grid_lengths_match_oracle(vie, n, pxy, nrhs):
         xs, info = sv.gmres(A.apply, A.rhs(inc[r]), tol=1e-13, restart=100)
         assert rel(d64[r], xs) < 1e-10
         assert rel(dm[r], xs) < 1e-8
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("n", [64, 96])
+def test_alternative_splits_match_oracle(vie, monkeypatch, n):
+    print(f"[lengths] n = {n}: every pass on its alternative split", flush=True)
+    monkeypatch.setenv("VIE_SPLITS", "1,1,1,1,1")
+    omega = 4.0 * math.pi
+    coef = gen.helmholtz_medium(n, gen.rng_for(gen.CONFIG_IDS["test"], 1400 + n))
+    inc = waves(n, omega, 1, 1500 + n)
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED)
+    x = gen.random_density((1, 3, n, n, n), gen.rng_for(gen.CONFIG_IDS["test"], 1600 + n))
+    y64 = plan.apply(x, vie.APPLY_FP64).cpu().numpy()[0]
+    y32 = plan.apply(x, vie.APPLY_FP32).cpu().numpy()[0]
+    d, _, st, rc = plan.solve(inc, tol=1e-9, want_field=False)
+    assert rc == vie.OK
+    plan.close()
+    A = op.Operator(op.KIND_HELMHOLTZ, coef, omega)
+    ref = A.apply(x[0])
+    assert rel(y64, ref) < 1e-12
+    assert rel(y32, ref) < 2e-6
+    b = A.rhs(inc[0])
+    assert np.linalg.norm(b - A.apply(d.cpu().numpy()[0])) <= 2e-9 * np.linalg.norm(b)
 
 
 def test_unit_box_spacing_matches_oracle(vie):
