@@ -102,8 +102,8 @@ def stats_summary(d: str, command: str, top: int = 16, bench: dict = None) -> st
     if bench:
         roof = bench["roofline"]
         lines += [f"The run's own HIP-event timing of its dominant kernel family `{roof['kernel']}`: "
-                  f"{roof['avg_launch_us']:.1f} us per launch over the timed region "
-                  f"(value {bench['value']:.2f} {bench['unit']}).", ""]
+                  f"{roof['avg_launch_us']:.1f} us per launch over its profiled pass "
+                  f"(value {bench['value']:.2f} {bench['unit']}, from the timed steps).", ""]
     lines += [
               "## rocprofv3 --stats (all dispatches of the run)", "",
               "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
