@@ -5,6 +5,7 @@
 // right-hand sides share a launch.
 #include "pointwise.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace vie {
@@ -256,7 +257,10 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const c128* __restrict__ box
 constexpr int kGroup = 8;  // basis vectors per accumulation sweep
 
 // TV, TW: storage of the basis and of w (complex128 or complex64); the
-// products are formed and summed in FP64.
+// products are formed and summed in FP64.  Block (blk, rhs, z) forms the
+// partial sums over chunk blk of the groups z, z + gridDim.z, ... of kGroup
+// vectors: the partial of (blk, vector) is the same sum in the same order
+// whatever gridDim.z is (small launches spread the groups over blocks).
 template <typename TV, typename TW>
 __global__ void __launch_bounds__(kBlock) k_dots(const TV* __restrict__ V, long vstride, long rstride,
                                                  const TW* __restrict__ w, long L, int nv, long chunk,
@@ -272,7 +276,7 @@ __global__ void __launch_bounds__(kBlock) k_dots(const TV* __restrict__ V, long 
   const TV* Vr = V + rhs * rstride;
   const int nv1 = nv + 1;
   c128* out = partials + (long(rhs) * nblk + blk) * nv1;
-  for (int g0 = 0; g0 < nv1; g0 += kGroup) {
+  for (int g0 = int(blockIdx.z) * kGroup; g0 < nv1; g0 += int(gridDim.z) * kGroup) {
     double ar[kGroup], ai[kGroup];
 #pragma unroll
     for (int q = 0; q < kGroup; ++q) ar[q] = ai[q] = 0.0;
@@ -313,34 +317,33 @@ __global__ void __launch_bounds__(kBlock) k_dots(const TV* __restrict__ V, long 
   }
 }
 
+// Block (rhs, i) sums the nblk partials of coefficient i.
 __global__ void __launch_bounds__(kBlock) k_reduce(const c128* __restrict__ partials, int nblk, int nv1,
                                                    c128* __restrict__ out, const int* __restrict__ act) {
   __shared__ double red[kBlock / 64][2];
   const int rhs = blockIdx.x;
   if (act && !act[rhs]) return;
-  for (int i = 0; i < nv1; ++i) {
-    double sr = 0.0, si = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-      const c128 v = partials[(long(rhs) * nblk + b) * nv1 + i];
-      sr += v.re;
-      si += v.im;
+  const int i = blockIdx.y;
+  double sr = 0.0, si = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    const c128 v = partials[(long(rhs) * nblk + b) * nv1 + i];
+    sr += v.re;
+    si += v.im;
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x / 64][0] = sr;
+    red[threadIdx.x / 64][1] = si;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+    for (int k = 0; k < kBlock / 64; ++k) {
+      a += red[k][0];
+      c += red[k][1];
     }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    if ((threadIdx.x & 63) == 0) {
-      red[threadIdx.x / 64][0] = sr;
-      red[threadIdx.x / 64][1] = si;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double a = 0.0, c = 0.0;
-      for (int k = 0; k < kBlock / 64; ++k) {
-        a += red[k][0];
-        c += red[k][1];
-      }
-      out[long(rhs) * nv1 + i] = {a, c};
-    }
-    __syncthreads();
+    out[long(rhs) * nv1 + i] = {a, c};
   }
 }
 
@@ -442,8 +445,15 @@ int grid_for(long n) {
 
 }  // namespace
 
+// Chunks of the two-phase reductions over vectors of length L: about 8
+// elements per thread, at least 64 chunks (of at least one element per
+// thread) for short vectors so that a single right-hand side still spreads
+// over the device, at most 1024.  A function of L alone, so that a
+// right-hand side's sums do not depend on the batch it is in.
 int krylov_blocks(long L) {
   long b = (L + 8 * kBlock - 1) / (8 * kBlock);
+  const long lo = std::min<long>(64, (L + kBlock - 1) / kBlock);
+  if (b < lo) b = lo;
   if (b > 1024) b = 1024;
   if (b < 1) b = 1;
   return int(b);
@@ -480,7 +490,12 @@ template <typename TV, typename TW>
 hipError_t launch_dots(const TV* V, long vstride, long rstride, const TW* w, long L, int nv, int nrhs, int nblk,
                        c128* partials, hipStream_t s, const int* act) {
   const long chunk = (L + nblk - 1) / nblk;
-  k_dots<TV, TW><<<dim3(nblk, nrhs), kBlock, 0, s>>>(V, vstride, rstride, w, L, nv, chunk, partials, act);
+  // groups of kGroup vectors over blocks while the launch is short of ~4
+  // blocks per compute unit
+  const int ngroups = (nv + 1 + kGroup - 1) / kGroup;
+  int gz = 1;
+  while (gz < ngroups && long(nblk) * nrhs * gz < 1024) ++gz;
+  k_dots<TV, TW><<<dim3(nblk, nrhs, gz), kBlock, 0, s>>>(V, vstride, rstride, w, L, nv, chunk, partials, act);
   return hipGetLastError();
 }
 template hipError_t launch_dots<c128, c128>(const c128*, long, long, const c128*, long, int, int, int, c128*,
@@ -491,7 +506,7 @@ template hipError_t launch_dots<c128, c64>(const c128*, long, long, const c64*, 
 
 hipError_t launch_reduce(const c128* partials, int nrhs, int nblk, int nv1, c128* out, hipStream_t s,
                          const int* act) {
-  k_reduce<<<nrhs, kBlock, 0, s>>>(partials, nblk, nv1, out, act);
+  k_reduce<<<dim3(nrhs, nv1), kBlock, 0, s>>>(partials, nblk, nv1, out, act);
   return hipGetLastError();
 }
 
