@@ -282,7 +282,11 @@ long vie_release_cached_memory(void);
  * the solver's applies: the shortest compiled length >= 2 max(bx, by) and
  * <= 2n (2n with VIE_FULL_LENGTH or VIE_WHOLE_GRID; along z always 2n); its
  * kernel tables are the transform of the kernel windowed to
- * |m_a| <= length_a/2 - 1. */
+ * |m_a| <= length_a/2 - 1; out[16], out[17] = right-hand sides the FP32 and
+ * FP64 apply workspaces hold now (each grows on demand, up to max_rhs, by
+ * c (n^2 2n + n (2n)^2) elements of 8 or 16 bytes per right-hand side),
+ * out[18] = solver slots the Krylov workspace holds now.  Entries beyond
+ * nout are not written. */
 int vie_plan_info(const vie_plan *pl, double *out, int nout);
 
 /* Copies the FP64 kernel-transform tables into host memory:

@@ -3,6 +3,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -589,6 +590,21 @@ SharedTuneKey shared_key(const vie_plan* pl, int rsize, int nb, const Geom& g) {
   return SharedTuneKey{rsize, g.sp->Pxy, g.sp->Pz, pl->C, g.mul < 0 ? (pl->full ? MUL_MAX6 : MUL_SYM3) : g.mul,
                        bucket_of(nb), g.bx, g.by, g.bz, g.rows ? 1 : 0};
 }
+// The split of every pass, per shape without the batch bucket: the split
+// sets the rounding of the transforms, so it is measured once per shape and
+// precision and kept for every batch size, and a right-hand side gets
+// bitwise the same applies alone or in any batch of the process (tiles and
+// the z block order leave the arithmetic as it is and are measured per bucket).
+std::map<SharedTuneKey, std::array<int, 5>>& shared_splits() {
+  static std::map<SharedTuneKey, std::array<int, 5>> m;
+  return m;
+}
+// one measurement at a time in the process: timings taken while another
+// thread measures on the same device would be skewed
+std::mutex& tuning_mutex() {
+  static std::mutex m;
+  return m;
+}
 
 // tiles chosen without measuring: about 256 threads per block, whole 128-byte
 // lines where the column count allows
@@ -653,15 +669,16 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStre
   // shared with other plans
   const char* pin = std::getenv(sizeof(R) == 8 ? "VIE_TILES_FP64" : "VIE_TILES");
   const char* spin = std::getenv("VIE_SPLITS");
-  if (!pin && !spin) {
+  auto from_shared = [&]() {
+    if (pin || spin) return false;
     std::lock_guard<std::mutex> lk(shared_tunes_mutex());
     auto sit = shared_tunes().find(skey);
-    if (sit != shared_tunes().end()) {
-      pl->tune[idx][key] = sit->second;
-      *t = sit->second;
-      return VIE_OK;
-    }
-  }
+    if (sit == shared_tunes().end()) return false;
+    pl->tune[idx][key] = sit->second;
+    *t = sit->second;
+    return true;
+  };
+  if (from_shared()) return VIE_OK;
   const int Pxy = c.g.sp->Pxy, Pz = c.g.sp->Pz;
   const int fmax = pl->C == 6 ? fused_max_threads<R, 6>() : fused_max_threads<R, 3>();
   Tune d;
@@ -710,7 +727,21 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStre
   } else if (nsv != 5 && pl->n >= 48 && env_flag("VIE_AUTOTUNE", true)) {
     // measure only where it pays: large grids, unless switched off.  Every
     // pass reads and writes its data in natural order, so each may use its
-    // own split; per pass the fastest (split, tile) over the compiled splits
+    // own split; per pass the fastest (split, tile) over the compiled splits,
+    // or over the tiles of the split this shape already has
+    std::lock_guard<std::mutex> tl(tuning_mutex());
+    if (from_shared()) return VIE_OK;  // measured by another plan meanwhile
+    const SharedTuneKey split_key = shared_key(pl, int(sizeof(R)), 0, c.g);
+    std::array<int, 5> only{-1, -1, -1, -1, -1};
+    bool have_splits = false;
+    {
+      std::lock_guard<std::mutex> lk(shared_tunes_mutex());
+      auto sit = shared_splits().find(split_key);
+      if (sit != shared_splits().end() && !pin && !spin) {
+        only = sit->second;
+        have_splits = true;
+      }
+    }
     const cx<R>* tab;
     if constexpr (std::is_same<R, float>::value)
       tab = c.g.sp->tab32;
@@ -718,10 +749,12 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStre
       tab = c.g.sp->tab64;
     const bool dbg = env_flag("VIE_DEBUG", false);
     // (variant, tile) with the smallest time of run(ops, T) over the splits
-    auto best_of = [&](const char* name, bool z, bool contig, int maxthreads, int* vout, int* tout,
+    auto best_of = [&](const char* name, int pass, bool contig, int maxthreads, int* vout, int* tout,
                        auto&& run) -> int {
       float best = 1e30f;
+      const bool z = pass == 2;
       for (int v = 0; v < kMaxSplits; ++v) {
+        if (only[size_t(pass)] >= 0 && v != only[size_t(pass)]) continue;
         const LenOps<R>* o = z ? z_ops<R>(Pz, v) : xy_ops<R, TV, TO>(Pxy, v);
         if (!o) continue;
         int tv = 0;
@@ -740,10 +773,10 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStre
       }
       return best < 1e30f ? VIE_OK : fail(pl, VIE_E_SIZE, std::string("no launch shape for the ") + name);
     };
-    rc = best_of("x fwd", false, true, kPassMaxThreads, &d.vx_fwd, &d.tx_fwd,
+    rc = best_of("x fwd", 0, true, kPassMaxThreads, &d.vx_fwd, &d.tx_fwd,
                  [&](const LenOps<R>* o, int T) { return pass_xfwd<R, TV>(c, o, in, T, s); });
     if (rc) return rc;
-    rc = best_of("y fwd", false, false, kPassMaxThreads, &d.vy_fwd, &d.ty_fwd,
+    rc = best_of("y fwd", 1, false, kPassMaxThreads, &d.vy_fwd, &d.ty_fwd,
                  [&](const LenOps<R>* o, int T) { return pass_yfwd<R>(c, o, T, s); });
     if (rc) return rc;
     // the z pass: split, tile width and block order (the paired order needs
@@ -751,14 +784,14 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStre
     // launch and skipped)
     {
       int vq = 0, tq = 0, vp = 0, tp = 0;
-      rc = best_of("z (mirror groups)", true, false, fmax, &vq, &tq,
+      rc = best_of("z (mirror groups)", 2, false, fmax, &vq, &tq,
                    [&](const LenOps<R>* o, int T) { return pass_z<R>(c, o, tab, T, 1, s); });
       if (rc) return rc;
       float mq = 0, mp = 1e30f;
       rc = pick_tile<R>(pl, z_ops<R>(Pz, vq)->P1, z_ops<R>(Pz, vq)->P2, false, fmax, Pxy,
                         [&](int T) { return pass_z<R>(c, z_ops<R>(Pz, vq), tab, T, 1, s); }, s, &tq, true, &mq, true);
       if (rc) return rc;
-      const int rp = best_of("z (paired)", true, false, fmax, &vp, &tp,
+      const int rp = best_of("z (paired)", 2, false, fmax, &vp, &tp,
                              [&](const LenOps<R>* o, int T) { return pass_z<R>(c, o, tab, T, 0, s); });
       if (rp == VIE_OK && tp) {
         rc = pick_tile<R>(pl, z_ops<R>(Pz, vp)->P1, z_ops<R>(Pz, vp)->P2, false, fmax, Pxy,
@@ -776,15 +809,19 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStre
         d.tz = tq;
       }
     }
-    rc = best_of("y inv", false, false, kPassMaxThreads, &d.vy_inv, &d.ty_inv,
+    rc = best_of("y inv", 3, false, kPassMaxThreads, &d.vy_inv, &d.ty_inv,
                  [&](const LenOps<R>* o, int T) { return pass_yinv<R>(c, o, T, s); });
     if (rc) return rc;
     // the raw convolution for complex128 vectors (any J), the matvec for complex64
     const int xmode = std::is_same<TV, c128>::value && std::is_same<TO, c128>::value ? MODE_CONV : MODE_MATVEC;
-    rc = best_of("x inv", false, true, fmax, &d.vx_inv, &d.tx_inv, [&](const LenOps<R>* o, int T) {
+    rc = best_of("x inv", 4, true, fmax, &d.vx_inv, &d.tx_inv, [&](const LenOps<R>* o, int T) {
       return pass_xinv<R, TV, TO>(c, o, in, nullptr, out, xmode, T, s);
     });
     if (rc) return rc;
+    if (!have_splits && !pin && !spin) {
+      std::lock_guard<std::mutex> lk(shared_tunes_mutex());
+      shared_splits()[split_key] = {d.vx_fwd, d.vy_fwd, d.vz, d.vy_inv, d.vx_inv};
+    }
   }
   d.tuned = true;
   if (env_flag("VIE_DEBUG", false))
@@ -1610,12 +1647,12 @@ int vie_far_field(vie_plan* pl, const double* density, int nrhs, const double* d
 
 int vie_plan_info(const vie_plan* pl, double* out, int nout) {
   if (!pl || !out) return VIE_E_ARG;
-  const double v[16] = {double(pl->n),         double(pl->C),      double(pl->P),      double(pl->M),
+  const double v[19] = {double(pl->n),         double(pl->C),      double(pl->P),      double(pl->M),
                         pl->hmax,              double(pl->ne),     double(pl->dev_bytes),
                         double(pl->graph_launches), double(pl->box.x0), double(pl->box.y0), double(pl->box.z0),
                         double(pl->box.bx),    double(pl->box.by), double(pl->box.bz), double(pl->box.np),
-                        double(pl->sb.Pxy)};
-  for (int i = 0; i < nout && i < 16; ++i) out[i] = v[i];
+                        double(pl->sb.Pxy),    double(pl->ws_cap[0]), double(pl->ws_cap[1]), double(pl->kr_cap)};
+  for (int i = 0; i < nout && i < 19; ++i) out[i] = v[i];
   return VIE_OK;
 }
 

@@ -620,8 +620,18 @@ struct SolveSession {
 
 namespace {
 
-Batch batch_of(vie_plan* pl, const SolveSession& S, hipStream_t s) {
-  return Batch{pl, s, S.cap, S.L, long(pl->kr_cap) * S.L, krylov_blocks(S.L)};
+// The launches of a session cover slots 0 .. hw - 1, hw = one past the
+// highest slot in use (slots are filled lowest first), not the whole
+// capacity: a batch holding a few right-hand sides launches for those only.
+int high_water(const SolveSession& S) {
+  int hw = 0;
+  for (int r = 0; r < S.cap; ++r)
+    if (S.used[size_t(r)]) hw = r + 1;
+  return hw;
+}
+
+Batch batch_of(vie_plan* pl, const SolveSession& S, hipStream_t s, int nb) {
+  return Batch{pl, s, nb, S.L, long(pl->kr_cap) * S.L, krylov_blocks(S.L)};
 }
 
 bool ends(const RhsState& S) { return S.done; }
@@ -671,8 +681,9 @@ int session_add(vie_plan* pl, const c128* inc, const c128* x0, int k, int* slots
   for (int r = 0; r < S->cap && int(sl.size()) < k; ++r)
     if (!S->used[zu(r)]) sl.push_back(r);
   if (int(sl.size()) < k) return fail(pl, VIE_E_ARG, "not enough free slots in the batch");
-  Batch b = batch_of(pl, *S, s);
-  std::vector<bool> fresh(zu(S->cap), false);
+  const int hw = std::max(high_water(*S), sl.back() + 1);
+  Batch b = batch_of(pl, *S, s, hw);
+  std::vector<bool> fresh(zu(hw), false);
   for (int i = 0; i < k; ++i) {
     const int r = sl[zu(i)];
     fresh[zu(r)] = true;
@@ -692,13 +703,13 @@ int session_add(vie_plan* pl, const c128* inc, const c128* x0, int k, int* slots
   rc = norms(b, pl->bw, bnorm, act, nact);
   if (rc) return rc;
   if (x0) {
-    rc = apply_any(pl, pl->box, true, pl->xw, pl->xw, pl->bw, pl->rw, S->cap, MODE_RESIDUAL, s, act, nact);
+    rc = apply_any(pl, pl->box, true, pl->xw, pl->xw, pl->bw, pl->rw, hw, MODE_RESIDUAL, s, act, nact);
     if (rc) return rc;
   }
   rc = norms(b, pl->rw, rnorm, act, nact);
   if (rc) return rc;
   const auto now = std::chrono::steady_clock::now();
-  std::vector<int> c0(zu(S->cap), -1);
+  std::vector<int> c0(zu(hw), -1);
   for (int i = 0; i < k; ++i) {
     const int r = sl[zu(i)];
     RhsState& T = S->st[zu(r)];
@@ -722,7 +733,7 @@ int session_add(vie_plan* pl, const c128* inc, const c128* x0, int k, int* slots
     if (slots) slots[i] = r;
   }
   // the best iterate so far of every new slot: its initial one
-  std::vector<double> one(zu(S->cap), 1.0);
+  std::vector<double> one(zu(hw), 1.0);
   std::vector<cd> none;
   const c128* nov = nullptr;
   return combine_host(b, nov, pl->xw, pl->xbest, 0, none, one, &c0);
@@ -733,9 +744,9 @@ int session_add(vie_plan* pl, const c128* inc, const c128* x0, int k, int* slots
 int session_step(vie_plan* pl, hipStream_t s, int* nactive) {
   SolveSession* Sx = pl->session;
   const vie_solve_opts& o = Sx->o;
-  const int nb = Sx->cap, m = Sx->m;
+  const int nb = high_water(*Sx), m = Sx->m;
   std::vector<RhsState>& st = Sx->st;
-  Batch b = batch_of(pl, *Sx, s);
+  Batch b = batch_of(pl, *Sx, s, nb);
   int rc = VIE_OK;
   std::vector<double> target(zu(nb)), rnorm(zu(nb));
   std::vector<bool> active(zu(nb));
@@ -810,7 +821,7 @@ int session_step(vie_plan* pl, hipStream_t s, int* nactive) {
     }
   }
   int left = 0;
-  for (int r = 0; r < nb; ++r) left += (Sx->used[zu(r)] && !ends(st[zu(r)])) ? 1 : 0;
+  for (int r = 0; r < Sx->cap; ++r) left += (Sx->used[zu(r)] && !ends(st[zu(r)])) ? 1 : 0;
   if (nactive) *nactive = left;
   return VIE_OK;
 }

@@ -232,6 +232,11 @@ class PlanCache:
         with self.lock:
             return key in self.free
 
+    def peek(self, key: str):
+        """The idle entry of `key` without checking it out (or None)."""
+        with self.lock:
+            return self.free.get(key)
+
     def put(self, key: str, plan, nbytes: int = 0):
         victims = []
         with self.lock:
@@ -268,10 +273,10 @@ class PlanCache:
 
 class Server:
     def __init__(self, budget_bytes: Optional[int] = None, workers: int = 3, restart: int = 20,
-                 max_batch: int = 16, plan_cache: int = 4, precision: Optional[int] = None,
+                 max_batch: int = 16, plan_cache: int = 16, precision: Optional[int] = None,
                  keep_results: bool = True, gen_workers: int = 8, host_budget_bytes: int = 32 * 10 ** 9,
                  pinned_inputs: bool = False, device_inputs: bool = True, progress: int = 0,
-                 tol: float = 1e-9):
+                 tol: float = 1e-9, overtake_s: float = 2.0):
         import torch
         from . import vie
         self.vie = vie
@@ -314,11 +319,42 @@ class Server:
         self.joins_running = 0  # ... while other right-hand sides of the batch were iterating
         self.batches = 0
         self.refused = 0
+        # a younger request may be admitted ahead of an older one that does not
+        # fit yet, until the older one has waited this long since its arrival
+        self.overtake_s = overtake_s
+        self.overtakes = 0
+        self.seen = set()  # keys served before
+        self.returned_bytes = 0  # estimate minus resident bytes, given back after plan creation
 
     # ---- footprint -----------------------------------------------------------
-    def plan_bytes(self, r: Request) -> int:
-        """Device bytes of a plan with a batch of max_batch slots."""
-        return int(self.vie.footprint_bytes(r.kind, r.n, r.full, self.max_batch, self.restart))
+    def plan_bytes(self, r: Request, slots: Optional[int] = None) -> int:
+        """Device bytes of a new plan with a batch of `slots` (default
+        max_batch) slots: an upper estimate from the grid alone."""
+        nb = self.max_batch if slots is None else slots
+        return int(self.vie.footprint_bytes(r.kind, r.n, r.full, nb, self.restart))
+
+    def resident_bytes(self, plan, r: Request, slots: int) -> int:
+        """Device bytes a plan holds at most while it serves a batch of
+        `slots` slots: what it holds after batch_open (contrast, tables, the
+        Krylov slots on the support rows; the precompute buffers are freed)
+        plus the growth of its apply workspaces, which are allocated on
+        demand up to the launches' right-hand sides."""
+        info = plan.info()
+        c, n = (6 if r.full else 3), r.n
+        p = 2 * n
+        per_rhs = c * (n * n * p + n * p * p)
+        grow = (max(0, slots - info["workspace_rhs_fp32"]) * per_rhs * 8 +
+                max(0, slots - info["workspace_rhs_fp64"]) * per_rhs * 16)
+        return int(info["device_bytes"]) + grow
+
+    def _slots_for(self, q: Request, cached) -> int:
+        """Batch capacity for the request's key: the full batch for a key that
+        repeats (a resident plan, served before, or another queued request),
+        else the request's own right-hand sides, so that a one-off medium
+        does not hold Krylov vectors for joiners that never come."""
+        if cached is not None or q.key in self.seen or any(o is not q and o.key == q.key for o in self.queue):
+            return self.max_batch
+        return q.nrhs
 
     @staticmethod
     def io_bytes(r: Request) -> int:
@@ -345,12 +381,15 @@ class Server:
     def _claim(self):
         """The oldest queued request whose key no worker is serving and whose
         plan and arrays fit the device budget (evicting idle cached plans for
-        room): (request, its cached (plan, charged bytes) checked out, or None
-        and the plan bytes charged for a new plan)."""
+        room): (request, its cached (plan, charged bytes) checked out or None,
+        the plan bytes charged now (a new plan, or the growth of a cached one
+        to more slots), the batch capacity).  A request that does not fit is
+        overtaken by younger ones until it has waited overtake_s."""
         with self.qlock:
             while True:
                 if self.closed and not self.queue:
-                    return None, None, 0
+                    return None, None, 0, 0
+                blocked = False
                 for q in list(self.queue):
                     if q.key in self.serving:
                         continue
@@ -358,8 +397,15 @@ class Server:
                         self.queue.remove(q)
                         self._refuse(q, f"{q.nrhs} right-hand sides exceed the batch capacity {self.max_batch}")
                         continue
-                    cached = self.cache.contains(q.key)
-                    need = (0 if cached else self.plan_bytes(q)) + self.io_bytes(q)
+                    peek = self.cache.peek(q.key)
+                    cached = peek is not None
+                    slots = self._slots_for(q, peek)
+                    if cached:
+                        have = peek[0].info()["krylov_slots"]
+                        grow = 0 if have >= slots else self.plan_bytes(q, slots) - self.plan_bytes(q, have)
+                    else:
+                        grow = self.plan_bytes(q, slots)
+                    need = grow + self.io_bytes(q)
                     if not self.admission.can_ever_fit(need):
                         self.queue.remove(q)
                         self._refuse(q, f"footprint {need / 1e9:.1f} GB exceeds the device budget "
@@ -377,8 +423,13 @@ class Server:
                             self.serving.add(q.key)
                             self.inflight += 1
                             self.max_inflight = max(self.max_inflight, self.inflight)
-                            return q, entry, need - self.io_bytes(q)
-                    break  # the oldest admissible key must wait for memory: keep the order
+                            self.seen.add(q.key)
+                            if blocked:
+                                self.overtakes += 1
+                            return q, entry, need - self.io_bytes(q), slots
+                    if self.now() - q.arrival >= self.overtake_s:
+                        break  # it has waited long enough: nothing younger goes first
+                    blocked = True
                 self.qlock.wait(timeout=0.05)
 
     def _joiners(self, key: str, free: int) -> List[Request]:
@@ -410,7 +461,7 @@ class Server:
         vie = self.vie
         stream = torch.cuda.Stream()
         while True:
-            first, entry, plan_charge = self._claim()
+            first, entry, plan_charge, cap = self._claim()
             if first is None:
                 return
             key = first.key
@@ -423,7 +474,7 @@ class Server:
                     self._inputs(first)
                     t_plan = time.perf_counter()
                     if entry is not None:
-                        plan, charged = entry[0], entry[1]
+                        plan, charged = entry[0], entry[1] + plan_charge
                     else:
                         # worker threads allocate and synchronise while others
                         # solve, which stream capture would forbid
@@ -434,7 +485,17 @@ class Server:
                         with self.rlock:
                             self.plans_created += 1
                     t_solve = time.perf_counter()
-                    plan.batch_open(self.max_batch, tol=self.tol, restart=self.restart, stream=stream)
+                    plan.batch_open(cap, tol=self.tol, restart=self.restart, stream=stream)
+                    # the estimate counted whole-grid Krylov vectors and the
+                    # precompute; keep only what the plan can hold from now on
+                    fit = self.resident_bytes(plan, first, cap)
+                    with self.admission.lock:
+                        if fit < charged:
+                            self.returned_bytes += charged - fit
+                        self.admission.take(fit - charged)
+                        if fit < charged:
+                            self.admission.lock.notify_all()
+                    charged = fit
                     with self.rlock:
                         self.plan_s += t_solve - t_plan
                         self.batches += 1
@@ -443,9 +504,9 @@ class Server:
                     while True:
                         for q in pending:
                             self._inputs(q)
-                            slots = plan.batch_add(q.inc, stream=stream)
+                            got = plan.batch_add(q.inc, stream=stream)
                             open_reqs[q.id] = [q, self.now(), [None] * q.nrhs, [None] * q.nrhs, q.nrhs, used > 0]
-                            for i, sl in enumerate(slots):
+                            for i, sl in enumerate(got):
                                 slot_of[sl] = (q.id, i)
                             with self.rlock:
                                 self.joins += q.nrhs
@@ -457,7 +518,7 @@ class Server:
                             # nothing left: release the key atomically with the last
                             # look at the queue, so a late request starts a new batch
                             with self.qlock:
-                                pending = self._joiners(key, self.max_batch)
+                                pending = self._joiners(key, cap)
                                 if not pending:
                                     self.serving.discard(key)
                                     self.inflight -= 1
@@ -476,7 +537,7 @@ class Server:
                             used -= 1
                             if o[4] == 0:
                                 self._finish(open_reqs.pop(rid), stream)
-                        pending = self._joiners(key, self.max_batch - used)
+                        pending = self._joiners(key, cap - used)
                     plan.batch_close()
                     with self.rlock:
                         self.solve_s += time.perf_counter() - t_solve
@@ -597,6 +658,7 @@ class Server:
                 "plans_created": self.plans_created, "batches": self.batches,
                 "joins_rhs": self.joins, "joins_into_running_rhs": self.joins_running,
                 "requests_joined_running": sum(1 for r in results if r.joined_running),
+                "overtakes": self.overtakes, "returned_GB": self.returned_bytes / 1e9,
                 "refused": self.refused, "errors": self.errors[:5]}
 
 
@@ -627,6 +689,7 @@ def main(argv=None):
     ap.add_argument("--grids", type=str, default="32,48,64,96,128,160")
     ap.add_argument("--max-rhs", type=int, default=16)
     ap.add_argument("--workers", type=int, default=3)
+    ap.add_argument("--plan-cache", type=int, default=16, help="idle plans kept resident (evicted for room)")
     ap.add_argument("--budget-gb", type=float, default=0.0)
     ap.add_argument("--host-budget-gb", type=float, default=24.0, help="host memory for generated inputs")
     ap.add_argument("--gen-workers", type=int, default=8, help="threads generating the stream's inputs")
@@ -643,7 +706,7 @@ def main(argv=None):
     srv = Server(int(args.budget_gb * 1e9) if args.budget_gb > 0 else None, workers=args.workers,
                  keep_results=False, gen_workers=args.gen_workers,
                  host_budget_bytes=int(args.host_budget_gb * 1e9), pinned_inputs=not args.pageable,
-                 device_inputs=args.inputs == "device", progress=100)
+                 device_inputs=args.inputs == "device", progress=100, plan_cache=args.plan_cache)
     res = srv.run(lambda: reqs)
     out = srv.summary(res)
     out.update({"rate": args.rate, "grids": list(grids), "workers": args.workers, "media": args.media})

@@ -91,13 +91,13 @@ def test_feeder_keeps_generated_inputs_within_the_host_budget():
     lock = threading.Lock()
 
     class FakeServer(serving.Server):
-        def plan_bytes(self, r):
+        def plan_bytes(self, r, slots=None):
             return 0
 
         def _worker(self):
             import time
             while True:
-                q, entry, charge = self._claim()
+                q, entry, charge, slots = self._claim()
                 if q is None:
                     return
                 time.sleep(0.01)     # the device is slower than the stream
@@ -125,6 +125,73 @@ def test_feeder_keeps_generated_inputs_within_the_host_budget():
     assert [r.id for r in res] == list(range(40))
     assert srv.host.peak <= 3 * one and srv.host.used == 0
     assert all(q.coef is None and q.inc is None for q in held)
+
+
+def test_batch_capacity_follows_key_repetition():
+    """A one-off key opens a batch of its own right-hand sides; a key with a
+    resident plan, one served before, or a second queued request opens the
+    full batch so that later requests can join it."""
+    from paper_1805_04791_amd import serving
+    srv = serving.Server(budget_bytes=10 ** 9, workers=1, max_batch=16, keep_results=False)
+    a = Request(0, 1, 8, 2.0, 3, key="a")
+    b1, b2 = Request(1, 1, 8, 2.0, 5, key="b"), Request(2, 1, 8, 2.0, 2, key="b")
+    srv.queue = [a, b1, b2]
+    assert srv._slots_for(a, None) == 3
+    assert srv._slots_for(b1, None) == 16 and srv._slots_for(b2, None) == 16
+    srv.queue = [a]
+    assert srv._slots_for(a, ("plan", 0)) == 16
+    srv.seen.add("a")
+    assert srv._slots_for(a, None) == 16
+
+
+@pytest.mark.parametrize("overtake_s,order", [(60.0, [0, 2, 1]), (0.0, [0, 1, 2])],
+                         ids=["overtake", "strict-order"])
+def test_younger_requests_overtake_one_that_does_not_fit(overtake_s, order):
+    """Admission order: with a device budget of 100, request 0 (30) runs while
+    request 1 (80) cannot fit; request 2 (30) goes first while request 1 has
+    waited less than overtake_s, and waits behind it once it has waited that
+    long (overtake_s = 0: strict arrival order)."""
+    import time
+    from paper_1805_04791_amd import serving
+
+    started = []
+    lock = threading.Lock()
+
+    class FakeServer(serving.Server):
+        def plan_bytes(self, r, slots=None):
+            return 80 if r.id == 1 else 30
+
+        def io_bytes(self, r):
+            return 0
+
+        def _worker(self):
+            while True:
+                q, entry, charge, slots = self._claim()
+                if q is None:
+                    return
+                with lock:
+                    started.append(q.id)
+                time.sleep(0.3 if q.id == 0 else 0.05)
+                with self.rlock:
+                    self.results.append(serving.Result(q.id, None, [], q.arrival, self.now(), self.now()))
+                q.release()
+                self.host.give(q.host_bytes)
+                self.admission.give(charge + self.io_bytes(q))
+                with self.qlock:
+                    self.serving.discard(q.key)
+                    self.inflight -= 1
+                    self.qlock.notify_all()
+
+    def make():
+        return (np.zeros((9, 2, 2, 2), complex), None, np.zeros((1, 3, 2, 2, 2), complex))
+
+    reqs = [Request(i, 1, 2, 2.0, 1, arrival=0.02 * i, key=f"k{i}", make=make) for i in range(3)]
+    srv = FakeServer(budget_bytes=100, workers=2, keep_results=False, gen_workers=1, overtake_s=overtake_s)
+    res = srv.run(lambda: reqs)
+    assert [r.id for r in res] == [0, 1, 2] and not srv.errors
+    assert started == order
+    assert srv.overtakes == (1 if order[1] == 2 else 0)
+    assert srv.admission.used == 0 and srv.admission.peak <= 100
 
 
 @pytest.mark.gpu
