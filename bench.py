@@ -68,13 +68,22 @@ def make_problem(workload: str, n: int, nrhs: int):
 
 
 def cpu_model():
-    """The host CPU's model name as lscpu reports it (else /proc/cpuinfo)."""
+    """The host CPU as lscpu reports it: model name, then family / model /
+    stepping and the logical CPUs visible (a virtual machine may report only a
+    generic name); else /proc/cpuinfo's model name."""
     import subprocess
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        f = {}
         for line in out.splitlines():
-            if line.startswith("Model name:"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = line.split(":", 1)
+                f.setdefault(k.strip(), v.strip())
+        if "Model name" in f:
+            extra = ", ".join(f"{k.lower()} {f[k]}" for k in ("CPU family", "Model", "Stepping") if k in f)
+            if "CPU(s)" in f:
+                extra += f", {f['CPU(s)']} logical CPUs visible"
+            return f"{f['Model name']} ({extra})" if extra else f["Model name"]
     except (OSError, subprocess.SubprocessError):
         pass
     try:

@@ -284,7 +284,8 @@ long vie_release_cached_memory(void);
  * kernel tables are the transform of the kernel windowed to
  * |m_a| <= length_a/2 - 1; out[16], out[17] = right-hand sides the FP32 and
  * FP64 apply workspaces hold now (each grows on demand, up to max_rhs, by
- * c (n^2 2n + n (2n)^2) elements of 8 or 16 bytes per right-hand side),
+ * c (n^2 2n + n 2n w) elements of 8 or 16 bytes per right-hand side, w = 2n
+ * rounded up to a multiple of 16),
  * out[18] = solver slots the Krylov workspace holds now.  Entries beyond
  * nout are not written. */
 int vie_plan_info(const vie_plan *pl, double *out, int nout);

@@ -44,7 +44,7 @@ struct ZArgs {
   int P;            // z transform length
   int nxp;          // padded octant row length (n + 1 rounded up to 16)
   int ne;           // table entries (6 or 9)
-  long comp_stride; // nz * pxy * pxy
+  long comp_stride; // nz * pxy * pitch
   long rhs_stride;  // C * comp_stride
   int nb;           // right-hand sides in the launch
   int nz;           // z extent of the data (n, or the support box): inputs z < nz, outputs z < nz
@@ -61,6 +61,7 @@ struct ZArgs {
   int quad = 0;
   int ntx = 0;
   long ngroups = 0;
+  long pitch = 0;   // elements from row ky to row ky + 1 of a plane (pitch_y(pxy))
 };
 
 // Minimum waves per SIMD the register allocation of k_zpass must allow: the
@@ -147,8 +148,8 @@ __attribute__((amdgpu_waves_per_eu(zpass_min_waves<R, C>()))) k_zpass(cx<R>* buf
     kx = tile * T + col;
     valid = kx < a.pxy;
   }
-  const long PP = long(a.pxy) * a.pxy;
-  cx<R>* base = buf + rhs * a.rhs_stride + long(ky) * a.pxy + (valid ? kx : 0);
+  const long PP = long(a.pxy) * a.pitch;  // one z plane
+  cx<R>* base = buf + rhs * a.rhs_stride + long(ky) * a.pitch + (valid ? kx : 0);
 
   // kUpfront: all inputs of the block in flight at once
   constexpr int CU = kUpfront<R> ? C : 1;
@@ -266,6 +267,7 @@ struct XArgs {
   long np;          // points per component of the vectors
   const int* rows;  // support rows (xa, len, off) per (z, y) row, or null: dense box
   const int* act = nullptr;  // optional: rows of right-hand side r are skipped when act[r] == 0
+  long pitch = 0;   // elements from one spectral row of A to the next (pitch_x(P))
 };
 
 // Blocks of a k_xinv launch.  With xcd_order the ceil(bz by / T) row tiles of
@@ -331,7 +333,7 @@ __global__ void __launch_bounds__((fused_max_threads<R, C>())) k_xinv(const cx<R
   constexpr int CU = kUpfront<R> ? C : 1;
   cx<R> X[CU][P2];
   auto load_comp = [&](int c, cx<R>(&dst)[P2]) {
-    const cx<R>* src = A + ((rhs * C + c) * NN + zy) * P;
+    const cx<R>* src = A + ((rhs * C + c) * NN + zy) * a.pitch;
     static_for<0, P2>([&](auto k2) { dst[k2] = (need && j < P1) ? src[j + P1 * k2] : czero<R>(); });
   };
   if constexpr (kUpfront<R>) static_for<0, C>([&](auto c) { load_comp(c, X[c]); });

@@ -39,6 +39,16 @@ struct scalar_of<cx<R>> {
 template <typename R>
 constexpr bool kUpfront = sizeof(R) == 4;
 
+// Row pitch of an apply's intermediate arrays: A, the x-transformed rows
+// [..][by][pitch_x(P)], and B, the y-transformed planes [..][P][pitch_y(P)].
+// The rows of B start on 128-byte lines (P rounded up to 16 elements): a
+// z-pass tile of 16 columns of a row is then one line (complex64) instead of
+// straddling two, which the blocks of neighbouring tiles, on other XCDs,
+// would each fetch whole.
+constexpr long kRowAlign = 16;
+__host__ __device__ constexpr long pitch_x(long P) { return P; }
+__host__ __device__ constexpr long pitch_y(long P) { return (P + kRowAlign - 1) / kRowAlign * kRowAlign; }
+
 // largest block of each kernel family (the tile choice keeps T*J within it)
 constexpr int kPassMaxThreads = 512;
 constexpr int kFusedMaxThreads = 512;

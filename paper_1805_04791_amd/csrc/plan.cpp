@@ -415,7 +415,7 @@ hipError_t pass_xfwd(const ApplyCall<R>& c, const LenOps<R>* ops, const TV* in, 
   const long rows = long(c.nb) * pl->C * nr;
   const int P = c.g.sp->Pxy;
   Geo g{T, int((rows + T - 1) / T), rows, c.g.bx, P, c.act, long(pl->C) * nr};
-  MemStore<cx<R>> dst{c.A, 0, P, 1, 1.0, 0};
+  MemStore<cx<R>> dst{c.A, 0, pitch_x(P), 1, 1.0, 0};
   if constexpr (std::is_same<TV, c128>::value) {
     if (c.g.rows) return ops->contig_fwd_rows(RowLoad<c128>{in, c.g.rows, nr, c.g.np}, dst, g, 1, c.tw, s);
     return ops->contig_fwd(MemLoad<c128>{in, 0, c.g.bx, 1}, dst, g, 1, c.tw, s);
@@ -425,14 +425,15 @@ hipError_t pass_xfwd(const ApplyCall<R>& c, const LenOps<R>* ops, const TV* in, 
   }
 }
 
-// y forward: A [rhs][c][bz][by][P] -> B [rhs][c][bz][P][P]
+// y forward: A [rhs][c][bz][by][Wx] -> B [rhs][c][bz][P][Wy], rows of
+// Wx = pitch_x(P) and Wy = pitch_y(P) elements of which the first P are used
 template <typename R>
 hipError_t pass_yfwd(const ApplyCall<R>& c, const LenOps<R>* ops, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long P = c.g.sp->Pxy, by = c.g.by;
+  const long P = c.g.sp->Pxy, by = c.g.by, Wx = pitch_x(P), Wy = pitch_y(P);
   Geo g{T, int(P / T), P, int(by), int(P), c.act, long(pl->C) * c.g.bz * P};
-  MemLoad<cx<R>> src{c.A, by * P, 1, P};
-  MemStore<cx<R>> dst{c.B, P * P, 1, P, 1.0, 0};
+  MemLoad<cx<R>> src{c.A, by * Wx, 1, Wx};
+  MemStore<cx<R>> dst{c.B, P * Wy, 1, Wy, 1.0, 0};
   return ops->strided(false, src, dst, g, long(c.nb) * pl->C * c.g.bz, c.tw, s);
 }
 
@@ -442,10 +443,11 @@ hipError_t pass_yfwd(const ApplyCall<R>& c, const LenOps<R>* ops, int T, hipStre
 template <typename R>
 hipError_t pass_z(const ApplyCall<R>& c, const LenOps<R>* opsz, const cx<R>* tab, int T, int order, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long Pz = c.g.sp->Pz, Q = c.g.sp->Pxy, bz = c.g.bz;
+  const long Pz = c.g.sp->Pz, Q = c.g.sp->Pxy, bz = c.g.bz, W = pitch_y(Q);
   const long ntiles = (Q + T - 1) / T;  // the last tile may be partial
-  ZArgs a{T,      int(ntiles), int(Pz / 2),           int(Pz), c.g.sp->nxp, c.g.sp->ne, bz * Q * Q,
-          long(pl->C) * bz * Q * Q, c.nb, int(bz), int(Q), pl->omega, c.act};
+  ZArgs a{T,      int(ntiles), int(Pz / 2),           int(Pz), c.g.sp->nxp, c.g.sp->ne, bz * Q * W,
+          long(pl->C) * bz * Q * W, c.nb, int(bz), int(Q), pl->omega, c.act};
+  a.pitch = W;
   long nblocks;
   if (order == 1) {
     a.quad = 1;
@@ -464,10 +466,10 @@ hipError_t pass_z(const ApplyCall<R>& c, const LenOps<R>* opsz, const cx<R>* tab
 template <typename R>
 hipError_t pass_yinv(const ApplyCall<R>& c, const LenOps<R>* ops, int T, hipStream_t s) {
   const vie_plan* pl = c.pl;
-  const long P = c.g.sp->Pxy, by = c.g.by;
+  const long P = c.g.sp->Pxy, by = c.g.by, Wx = pitch_x(P), Wy = pitch_y(P);
   Geo g{T, int(P / T), P, int(P), int(by), c.act, long(pl->C) * c.g.bz * P};
-  MemLoad<cx<R>> src{c.B, P * P, 1, P};
-  MemStore<cx<R>> dst{c.A, by * P, 1, P, 1.0, 0};
+  MemLoad<cx<R>> src{c.B, P * Wy, 1, Wy};
+  MemStore<cx<R>> dst{c.A, by * Wx, 1, Wx, 1.0, 0};
   return ops->strided(true, src, dst, g, long(c.nb) * pl->C * c.g.bz, c.tw, s);
 }
 
@@ -481,6 +483,7 @@ hipError_t pass_xinv(const ApplyCall<R>& c, const LenOps<R>* ops, const TV* addv
   const int xcd = 1;  // tiles of all right-hand sides that share H run back to back on one XCD
   XArgs a{T,      long(c.nb) * NN, pl->n,  pl->n3, c.nb,   xcd,  c.g.bx,
           c.g.by, c.g.bz,          c.g.x0, c.g.y0, c.g.z0, c.g.np, c.g.rows, c.act};
+  a.pitch = pitch_x(c.g.sp->Pxy);
   const cx<R>* H;
   const cx<R>* Hmu;
   if constexpr (std::is_same<R, float>::value) {
@@ -510,10 +513,12 @@ int ensure_workspace(vie_plan* pl, int nb) {
   dev_free(pl, pl->wsB[idx]);
   pl->wsA[idx] = pl->wsB[idx] = nullptr;
   pl->ws_cap[idx] = 0;
+  // every transform length is at most P = 2n, and the pitches grow with it
   const size_t N = size_t(pl->n), P = size_t(pl->P), C = size_t(pl->C);
-  int rc = dev_alloc(pl, &pl->wsA[idx], sizeof(cx<R>) * size_t(nb) * C * N * N * P);
+  const size_t Wx = size_t(pitch_x(pl->P)), Wy = size_t(pitch_y(pl->P));
+  int rc = dev_alloc(pl, &pl->wsA[idx], sizeof(cx<R>) * size_t(nb) * C * N * N * Wx);
   if (rc) return rc;
-  rc = dev_alloc(pl, &pl->wsB[idx], sizeof(cx<R>) * size_t(nb) * C * N * P * P);
+  rc = dev_alloc(pl, &pl->wsB[idx], sizeof(cx<R>) * size_t(nb) * C * N * P * Wy);
   if (rc) return rc;
   pl->ws_cap[idx] = nb;
   return VIE_OK;
@@ -574,10 +579,13 @@ int pick_tile(vie_plan* pl, int P1, int P2, bool contig, int maxthreads, int col
 int tune_key(int nb, const Geom& g) { return bucket_of(nb) + (g.id << 20) + ((g.mul + 1) << 24); }
 
 // Tile choices measured by any plan of the process, so that later plans of
-// the same shape (a serving stream's requests on one grid) do not measure
-// again: keyed by precision, transform lengths, components, multiply, batch
-// bucket and the extent of the data box (and whether it holds support rows).
-using SharedTuneKey = std::tuple<int, int, int, int, int, int, int, int, int, int>;
+// the same shape (a serving stream's requests on one grid, whatever their
+// media) do not measure again: keyed by precision, transform lengths,
+// components, multiply, batch bucket and whether the data are support rows.
+// The extent of the support box is left out: it sets the number of pencils
+// of the x and y passes and the z length of the data, not which launch shape
+// is fastest, and boxes of one transform length differ by a few planes.
+using SharedTuneKey = std::tuple<int, int, int, int, int, int, int>;
 std::map<SharedTuneKey, Tune>& shared_tunes() {
   static std::map<SharedTuneKey, Tune> m;
   return m;
@@ -588,7 +596,7 @@ std::mutex& shared_tunes_mutex() {
 }
 SharedTuneKey shared_key(const vie_plan* pl, int rsize, int nb, const Geom& g) {
   return SharedTuneKey{rsize, g.sp->Pxy, g.sp->Pz, pl->C, g.mul < 0 ? (pl->full ? MUL_MAX6 : MUL_SYM3) : g.mul,
-                       bucket_of(nb), g.bx, g.by, g.bz, g.rows ? 1 : 0};
+                       bucket_of(nb), g.rows ? 1 : 0};
 }
 // The split of every pass, per shape without the batch bucket: the split
 // sets the rounding of the transforms, so it is measured once per shape and
@@ -1505,8 +1513,9 @@ int vie_apply_noalloc(vie_plan* pl, const double* x, double* y, int nrhs, unsign
     return fail(pl, VIE_E_ARG, "vie_apply_noalloc: complex64 vectors need the FP32 matvec (no FP64, no CONV)");
   // workspace of one right-hand side (the arrays A and B of the whole grid)
   const size_t N = size_t(pl->n), P = size_t(pl->P), C = size_t(pl->C);
+  const size_t Wx = size_t(pitch_x(pl->P)), Wy = size_t(pitch_y(pl->P));
   const size_t el = fp64 ? sizeof(c128) : sizeof(c64);
-  const size_t a1 = el * C * N * N * P, b1 = el * C * N * P * P;
+  const size_t a1 = el * C * N * N * Wx, b1 = el * C * N * P * Wy;
   const size_t total = size_t(VIE_NOALLOC_SCRATCH_MIB) << 20;
   const size_t cap = (total - 256) / (a1 + b1);
   if (cap < 1)
@@ -1706,13 +1715,14 @@ long vie_footprint_bytes(int kind, int n, int full, int nrhs_batch, int restart)
   const double n3 = double(n) * n * n, P = 2.0 * n, M = 4.0 * n;
   const double C = full ? 6 : 3, ne = full ? 9 : 6;
   const double nxp = double(((n + 1 + 15) / 16) * 16);
+  const double Wx = double(pitch_x(2L * n)), Wy = double(pitch_y(2L * n));  // row pitches of the workspaces
   (void)kind;
   double b = 0;
   b += (full ? 2 : 1) * 9 * n3 * (16 + 8);                       // H in FP64 and FP32
   b += 2 * double(n + 1) * (n + 1) * ne * nxp * (16 + 8);        // octant tables (grid and box lengths)
   const double precompute = (M * M * P + M * P * P + ne * P * P * P) * 16 + 9 * n3 * 16;
   const double nb = nrhs_batch;
-  const double ws = nb * C * (double(n) * n * P + double(n) * P * P);  // apply workspace elements
+  const double ws = nb * C * (double(n) * n * Wx + double(n) * P * Wy);  // apply workspace elements
   b += ws * (8 + 16);                                             // FP32 and FP64 workspaces
   const double L = C * n3;
   b += (double(restart) + 1 + 4) * nb * L * 16;                   // Krylov basis + x, b, r, w

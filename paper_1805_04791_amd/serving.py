@@ -342,7 +342,8 @@ class Server:
         info = plan.info()
         c, n = (6 if r.full else 3), r.n
         p = 2 * n
-        per_rhs = c * (n * n * p + n * p * p)
+        w = (p + 15) // 16 * 16  # row pitch of the y-transformed planes
+        per_rhs = c * (n * n * p + n * p * w)
         grow = (max(0, slots - info["workspace_rhs_fp32"]) * per_rhs * 8 +
                 max(0, slots - info["workspace_rhs_fp64"]) * per_rhs * 16)
         return int(info["device_bytes"]) + grow
