@@ -607,12 +607,6 @@ std::map<SharedTuneKey, std::array<int, 5>>& shared_splits() {
   static std::map<SharedTuneKey, std::array<int, 5>> m;
   return m;
 }
-// one measurement at a time in the process: timings taken while another
-// thread measures on the same device would be skewed
-std::mutex& tuning_mutex() {
-  static std::mutex m;
-  return m;
-}
 
 // tiles chosen without measuring: about 256 threads per block, whole 128-byte
 // lines where the column count allows
@@ -736,9 +730,9 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStre
     // measure only where it pays: large grids, unless switched off.  Every
     // pass reads and writes its data in natural order, so each may use its
     // own split; per pass the fastest (split, tile) over the compiled splits,
-    // or over the tiles of the split this shape already has
-    std::lock_guard<std::mutex> tl(tuning_mutex());
-    if (from_shared()) return VIE_OK;  // measured by another plan meanwhile
+    // or over the tiles of the split this shape already has.  Plans on other
+    // threads may measure at the same time (serving workers: their timings
+    // then share the device); the first splits stored for a shape win.
     const SharedTuneKey split_key = shared_key(pl, int(sizeof(R)), 0, c.g);
     std::array<int, 5> only{-1, -1, -1, -1, -1};
     bool have_splits = false;
@@ -781,54 +775,61 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStre
       }
       return best < 1e30f ? VIE_OK : fail(pl, VIE_E_SIZE, std::string("no launch shape for the ") + name);
     };
-    rc = best_of("x fwd", 0, true, kPassMaxThreads, &d.vx_fwd, &d.tx_fwd,
-                 [&](const LenOps<R>* o, int T) { return pass_xfwd<R, TV>(c, o, in, T, s); });
-    if (rc) return rc;
-    rc = best_of("y fwd", 1, false, kPassMaxThreads, &d.vy_fwd, &d.ty_fwd,
-                 [&](const LenOps<R>* o, int T) { return pass_yfwd<R>(c, o, T, s); });
-    if (rc) return rc;
-    // the z pass: split, tile width and block order (the paired order needs
-    // the slices in groups of 8: tiles that do not allow it are refused at
-    // launch and skipped)
-    {
-      int vq = 0, tq = 0, vp = 0, tp = 0;
-      rc = best_of("z (mirror groups)", 2, false, fmax, &vq, &tq,
-                   [&](const LenOps<R>* o, int T) { return pass_z<R>(c, o, tab, T, 1, s); });
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      rc = best_of("x fwd", 0, true, kPassMaxThreads, &d.vx_fwd, &d.tx_fwd,
+                   [&](const LenOps<R>* o, int T) { return pass_xfwd<R, TV>(c, o, in, T, s); });
       if (rc) return rc;
-      float mq = 0, mp = 1e30f;
-      rc = pick_tile<R>(pl, z_ops<R>(Pz, vq)->P1, z_ops<R>(Pz, vq)->P2, false, fmax, Pxy,
-                        [&](int T) { return pass_z<R>(c, z_ops<R>(Pz, vq), tab, T, 1, s); }, s, &tq, true, &mq, true);
+      rc = best_of("y fwd", 1, false, kPassMaxThreads, &d.vy_fwd, &d.ty_fwd,
+                   [&](const LenOps<R>* o, int T) { return pass_yfwd<R>(c, o, T, s); });
       if (rc) return rc;
-      const int rp = best_of("z (paired)", 2, false, fmax, &vp, &tp,
-                             [&](const LenOps<R>* o, int T) { return pass_z<R>(c, o, tab, T, 0, s); });
-      if (rp == VIE_OK && tp) {
-        rc = pick_tile<R>(pl, z_ops<R>(Pz, vp)->P1, z_ops<R>(Pz, vp)->P2, false, fmax, Pxy,
-                          [&](int T) { return pass_z<R>(c, z_ops<R>(Pz, vp), tab, T, 0, s); }, s, &tp, true, &mp,
-                          true);
+      // the z pass: split, tile width and block order (the paired order needs
+      // the slices in groups of 8: tiles that do not allow it are refused at
+      // launch and skipped)
+      {
+        int vq = 0, tq = 0, vp = 0, tp = 0;
+        rc = best_of("z (mirror groups)", 2, false, fmax, &vq, &tq,
+                     [&](const LenOps<R>* o, int T) { return pass_z<R>(c, o, tab, T, 1, s); });
         if (rc) return rc;
+        float mq = 0, mp = 1e30f;
+        rc = pick_tile<R>(pl, z_ops<R>(Pz, vq)->P1, z_ops<R>(Pz, vq)->P2, false, fmax, Pxy,
+                          [&](int T) { return pass_z<R>(c, z_ops<R>(Pz, vq), tab, T, 1, s); }, s, &tq, true, &mq, true);
+        if (rc) return rc;
+        const int rp = best_of("z (paired)", 2, false, fmax, &vp, &tp,
+                               [&](const LenOps<R>* o, int T) { return pass_z<R>(c, o, tab, T, 0, s); });
+        if (rp == VIE_OK && tp) {
+          rc = pick_tile<R>(pl, z_ops<R>(Pz, vp)->P1, z_ops<R>(Pz, vp)->P2, false, fmax, Pxy,
+                            [&](int T) { return pass_z<R>(c, z_ops<R>(Pz, vp), tab, T, 0, s); }, s, &tp, true, &mp,
+                            true);
+          if (rc) return rc;
+        }
+        if (tp && mp < mq) {
+          d.zorder = 0;
+          d.vz = vp;
+          d.tz = tp;
+        } else {
+          d.zorder = 1;
+          d.vz = vq;
+          d.tz = tq;
+        }
       }
-      if (tp && mp < mq) {
-        d.zorder = 0;
-        d.vz = vp;
-        d.tz = tp;
-      } else {
-        d.zorder = 1;
-        d.vz = vq;
-        d.tz = tq;
-      }
-    }
-    rc = best_of("y inv", 3, false, kPassMaxThreads, &d.vy_inv, &d.ty_inv,
-                 [&](const LenOps<R>* o, int T) { return pass_yinv<R>(c, o, T, s); });
-    if (rc) return rc;
-    // the raw convolution for complex128 vectors (any J), the matvec for complex64
-    const int xmode = std::is_same<TV, c128>::value && std::is_same<TO, c128>::value ? MODE_CONV : MODE_MATVEC;
-    rc = best_of("x inv", 4, true, fmax, &d.vx_inv, &d.tx_inv, [&](const LenOps<R>* o, int T) {
-      return pass_xinv<R, TV, TO>(c, o, in, nullptr, out, xmode, T, s);
-    });
-    if (rc) return rc;
-    if (!have_splits && !pin && !spin) {
+      rc = best_of("y inv", 3, false, kPassMaxThreads, &d.vy_inv, &d.ty_inv,
+                   [&](const LenOps<R>* o, int T) { return pass_yinv<R>(c, o, T, s); });
+      if (rc) return rc;
+      // the raw convolution for complex128 vectors (any J), the matvec for complex64
+      const int xmode = std::is_same<TV, c128>::value && std::is_same<TO, c128>::value ? MODE_CONV : MODE_MATVEC;
+      rc = best_of("x inv", 4, true, fmax, &d.vx_inv, &d.tx_inv, [&](const LenOps<R>* o, int T) {
+        return pass_xinv<R, TV, TO>(c, o, in, nullptr, out, xmode, T, s);
+      });
+      if (rc) return rc;
+      if (have_splits || pin || spin) break;
+      const std::array<int, 5> got{d.vx_fwd, d.vy_fwd, d.vz, d.vy_inv, d.vx_inv};
       std::lock_guard<std::mutex> lk(shared_tunes_mutex());
-      shared_splits()[split_key] = {d.vx_fwd, d.vy_fwd, d.vz, d.vy_inv, d.vx_inv};
+      const auto ins = shared_splits().emplace(split_key, got);
+      if (ins.second || ins.first->second == got) break;
+      // another plan of this shape stored different splits while this one
+      // measured: take those, and measure their tiles
+      only = ins.first->second;
+      have_splits = true;
     }
   }
   d.tuned = true;
