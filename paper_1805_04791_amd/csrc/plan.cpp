@@ -733,6 +733,26 @@ int get_tune(vie_plan* pl, const ApplyCall<R>& c, const TV* in, TO* out, hipStre
     // or over the tiles of the split this shape already has.  Plans on other
     // threads may measure at the same time (serving workers: their timings
     // then share the device); the first splits stored for a shape win.
+    //
+    // A batch bucket within a factor of 4 of one that this shape has already
+    // measured takes that one's choices instead of measuring: a serving
+    // stream meets every batch size from 1 to 16 on every grid, and a
+    // measurement costs more than a small solve.
+    if (!pin && !spin) {
+      std::lock_guard<std::mutex> lk(shared_tunes_mutex());
+      const int b0 = bucket_of(c.nb);
+      for (const int b : {b0 / 2, b0 * 2, b0 / 4, b0 * 4}) {
+        if (b < 1) continue;
+        SharedTuneKey near = skey;
+        std::get<5>(near) = b;
+        const auto it = shared_tunes().find(near);
+        if (it == shared_tunes().end()) continue;
+        // kept by this plan only: the process-wide map holds measured choices
+        pl->tune[idx][key] = it->second;
+        *t = it->second;
+        return VIE_OK;
+      }
+    }
     const SharedTuneKey split_key = shared_key(pl, int(sizeof(R)), 0, c.g);
     std::array<int, 5> only{-1, -1, -1, -1, -1};
     bool have_splits = false;
