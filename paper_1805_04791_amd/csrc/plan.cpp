@@ -184,6 +184,16 @@ void quiesce(vie_plan* pl) {
   if (pl->gstream) (void)hipStreamSynchronize(pl->gstream);
 }
 
+StreamUse::~StreamUse() {
+  if (!pl->done_ev) return;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone) {
+    pl->done_valid = false;
+    return;
+  }
+  pl->done_valid = hipEventRecord(pl->done_ev, s) == hipSuccess;
+}
+
 int dev_alloc(vie_plan* pl, void** p, size_t bytes) {
   std::lock_guard<std::recursive_mutex> lk(hip_mutex());
   *p = nullptr;
@@ -1193,10 +1203,18 @@ bool n_supported(int n) {
 void destroy_plan(vie_plan* pl) {
   if (!pl) return;
   // wait for the plan's own work before taking the library lock: the stream
-  // may be another thread's, still busy, and the lock would stall every
-  // allocation meanwhile
-  quiesce(pl);
+  // may be another thread's, still busy with later work (the event marks the
+  // end of the plan's last call), and the lock would stall every allocation
+  // meanwhile
+  if (pl->done_valid) {
+    (void)hipEventSynchronize(pl->done_ev);
+    if (pl->gstream) (void)hipStreamSynchronize(pl->gstream);
+  } else {
+    quiesce(pl);
+  }
   std::lock_guard<std::recursive_mutex> lk(hip_mutex());
+  if (pl->done_ev) (void)hipEventDestroy(pl->done_ev);
+  pl->done_ev = nullptr;
   vie::close_session(pl);
   vie::clear_graphs(pl);
   if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
@@ -1326,9 +1344,10 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   pl->flags = p->flags;
   pl->n3 = long(p->n) * p->n * p->n;
   pl->use_graphs = !(p->flags & VIE_NO_GRAPHS);
-  pl->last_stream = s;
+  const StreamUse use(pl, s);
   HIPCHK(pl, hipGetDevice(&pl->device));
   if (pl->device < 0 || pl->device >= kMaxDevices) return fail(pl, VIE_E_DEVICE, "device index out of range");
+  HIPCHK(pl, hipEventCreateWithFlags(&pl->done_ev, hipEventDisableTiming));
   {
     // the device address of the scratch of vie_apply_noalloc, once per device
     std::lock_guard<std::recursive_mutex> lk(hip_mutex());
@@ -1499,7 +1518,7 @@ int vie_apply(vie_plan* pl, const double* x, double* y, int nrhs, unsigned flags
   if (!x || !y || nrhs < 1) return fail(pl, VIE_E_ARG, "vie_apply: null pointer or nrhs < 1");
   if ((flags & VIE_APPLY_FP64) && (flags & VIE_APPLY_FP32)) return fail(pl, VIE_E_ARG, "FP64 and FP32 both set");
   if (x == y) return fail(pl, VIE_E_ARG, "vie_apply: x and y must not overlap");
-  pl->last_stream = static_cast<hipStream_t>(hip_stream);
+  const StreamUse use(pl, static_cast<hipStream_t>(hip_stream));
   bool fp64 = pl->precision == VIE_PREC_FP64;
   if (flags & VIE_APPLY_FP64) fp64 = true;
   if (flags & VIE_APPLY_FP32) fp64 = false;
@@ -1546,7 +1565,7 @@ int vie_apply_noalloc(vie_plan* pl, const double* x, double* y, int nrhs, unsign
   const int ncap = int(std::min<size_t>(cap, 4096));
   const FixedWork fw{base, base + (a1 * size_t(ncap) + 255) / 256 * 256, ncap};
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  pl->last_stream = s;
+  const StreamUse use(pl, s);
   if (flags & VIE_APPLY_C64) {
     const c64* in = reinterpret_cast<const c64*>(x);
     return apply_typed<float, c64>(pl, pl->grid, in, in, nullptr, reinterpret_cast<c64*>(y), nrhs, MODE_MATVEC, s,
@@ -1561,7 +1580,7 @@ int vie_apply_noalloc(vie_plan* pl, const double* x, double* y, int nrhs, unsign
 int vie_rhs(vie_plan* pl, const double* inc, double* b, int nrhs, void* hip_stream) {
   if (!pl) return VIE_E_ARG;
   if (!inc || !b || nrhs < 1) return fail(pl, VIE_E_ARG, "vie_rhs: null pointer or nrhs < 1");
-  pl->last_stream = static_cast<hipStream_t>(hip_stream);
+  const StreamUse use(pl, static_cast<hipStream_t>(hip_stream));
   hipError_t e = launch_rhs(pl->H64, pl->Hmu64, reinterpret_cast<const c128*>(inc), reinterpret_cast<c128*>(b),
                             nrhs, pl->C, box_of(pl->grid, pl->n), static_cast<hipStream_t>(hip_stream));
   return e == hipSuccess ? VIE_OK : hip_fail(pl, e, "vie_rhs");
@@ -1570,7 +1589,7 @@ int vie_rhs(vie_plan* pl, const double* inc, double* b, int nrhs, void* hip_stre
 int vie_field(vie_plan* pl, const double* density, const double* inc, double* field, int nrhs, void* hip_stream) {
   if (!pl) return VIE_E_ARG;
   if (!density || !inc || !field || nrhs < 1) return fail(pl, VIE_E_ARG, "vie_field: null pointer or nrhs < 1");
-  pl->last_stream = static_cast<hipStream_t>(hip_stream);
+  const StreamUse use(pl, static_cast<hipStream_t>(hip_stream));
   return apply_any(pl, pl->grid, true, reinterpret_cast<const c128*>(density),
                    reinterpret_cast<const c128*>(inc), nullptr, reinterpret_cast<c128*>(field), nrhs, MODE_FIELD,
                    static_cast<hipStream_t>(hip_stream));
@@ -1581,7 +1600,7 @@ int vie_potential(vie_plan* pl, const double* density, double* phi, int nrhs, vo
   if (!density || !phi || nrhs < 1) return fail(pl, VIE_E_ARG, "vie_potential: null pointer or nrhs < 1");
   if (pl->kind == VIE_MAXWELL) return fail(pl, VIE_E_STATE, "vie_potential: Laplace and Helmholtz plans only");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  pl->last_stream = s;
+  const StreamUse use(pl, s);
   int rc = ensure_div_spec(pl, s);
   if (rc) return rc;
   // (div V J, 0, 0) per right-hand side into the scratch, then its first component
@@ -1608,7 +1627,7 @@ int vie_field_h(vie_plan* pl, const double* density, const double* h_inc, double
   if (pl->kind != VIE_MAXWELL || pl->full)
     return fail(pl, VIE_E_STATE, "vie_field_h: Maxwell plans with mu = I only (vie_field returns E and H otherwise)");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  pl->last_stream = s;
+  const StreamUse use(pl, s);
   const int rc = ensure_div_spec(pl, s);
   if (rc) return rc;
   const c128* d = reinterpret_cast<const c128*>(density);
@@ -1637,7 +1656,7 @@ int vie_fields_at(vie_plan* pl, const double* density, int nrhs, const double* p
       return fail(pl, VIE_E_ARG, "vie_fields_at: point " + std::to_string(p) + " is within 2h of the support box");
   }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  pl->last_stream = s;
+  const StreamUse use(pl, s);
   const bool mx = pl->kind == VIE_MAXWELL;
   const long part = points_partial_doubles(post_grid(pl), mx, npts, nrhs);
   int rc = ensure_post(pl, sizeof(double) * (size_t(3 * npts) + size_t(part)), s);
@@ -1663,7 +1682,7 @@ int vie_far_field(vie_plan* pl, const double* density, int nrhs, const double* d
       return fail(pl, VIE_E_ARG, "vie_far_field: direction " + std::to_string(d) + " is not a unit vector");
   }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  pl->last_stream = s;
+  const StreamUse use(pl, s);
   const bool mx = pl->kind == VIE_MAXWELL;
   const long part = far_partial_doubles(post_grid(pl), pl->C, ndirs, nrhs);
   int rc = ensure_post(pl, sizeof(double) * (size_t(3 * ndirs) + size_t(part)), s);

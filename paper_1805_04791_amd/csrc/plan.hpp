@@ -71,7 +71,12 @@ struct vie_plan {
   vie::Geom grid, box;  // whole grid; the solver's: bounding box of supp(H) (and H_mu), support rows
   bool use_box = true;
   int* rows_d = nullptr;  // device (xa, len, off) per (z, y) row of the box
-  hipStream_t last_stream = nullptr;  // stream of the latest call (synchronised by vie_destroy)
+  hipStream_t last_stream = nullptr;  // stream of the latest call
+  // recorded on last_stream after each call's work (vie_destroy waits for it,
+  // not for later work of other callers on that stream); not valid when the
+  // call's stream was being captured
+  hipEvent_t done_ev = nullptr;
+  bool done_valid = false;
   int device = 0;
   size_t max_lds = 65536;
 
@@ -158,6 +163,17 @@ namespace vie {
   } while (0)
 
 std::string& last_create_error();
+
+// The stream of an entry point's work: sets the plan's last stream and, on
+// leaving the call, records done_ev after the work the call enqueued.
+struct StreamUse {
+  vie_plan* pl;
+  hipStream_t s;
+  StreamUse(vie_plan* p, hipStream_t st) : pl(p), s(st) { pl->last_stream = st; }
+  ~StreamUse();
+  StreamUse(const StreamUse&) = delete;
+  StreamUse& operator=(const StreamUse&) = delete;
+};
 
 // allocation helpers (record bytes on the plan)
 int dev_alloc(vie_plan* pl, void** p, size_t bytes);

@@ -894,7 +894,7 @@ extern "C" int vie_batch_open(vie_plan* pl, int capacity, const vie_solve_opts* 
   if (!(o.tol > 0) || o.max_iters < 1 || o.restart < 1 || o.restart > 1000 ||
       (o.solver != VIE_SOLVER_GMRES && o.solver != VIE_SOLVER_BICGSTAB))
     return vie::fail(pl, VIE_E_ARG, "vie_batch_open: invalid options");
-  pl->last_stream = static_cast<hipStream_t>(hip_stream);
+  const vie::StreamUse use(pl, static_cast<hipStream_t>(hip_stream));
   return vie::open_session(pl, capacity, o, true, static_cast<hipStream_t>(hip_stream));
 }
 
@@ -903,7 +903,7 @@ extern "C" int vie_batch_add(vie_plan* pl, const double* inc, const double* x0, 
   if (!pl) return VIE_E_ARG;
   if (!pl->session || !pl->session->user) return vie::fail(pl, VIE_E_STATE, "vie_batch_add: no open batch");
   if (!inc || nrhs < 1) return vie::fail(pl, VIE_E_ARG, "vie_batch_add: null pointer or nrhs < 1");
-  pl->last_stream = static_cast<hipStream_t>(hip_stream);
+  const vie::StreamUse use(pl, static_cast<hipStream_t>(hip_stream));
   return vie::session_add(pl, reinterpret_cast<const vie::c128*>(inc), reinterpret_cast<const vie::c128*>(x0),
                           nrhs, slots, static_cast<hipStream_t>(hip_stream));
 }
@@ -911,7 +911,7 @@ extern "C" int vie_batch_add(vie_plan* pl, const double* inc, const double* x0, 
 extern "C" int vie_batch_step(vie_plan* pl, int* nactive, void* hip_stream) {
   if (!pl) return VIE_E_ARG;
   if (!pl->session || !pl->session->user) return vie::fail(pl, VIE_E_STATE, "vie_batch_step: no open batch");
-  pl->last_stream = static_cast<hipStream_t>(hip_stream);
+  const vie::StreamUse use(pl, static_cast<hipStream_t>(hip_stream));
   return vie::session_step(pl, static_cast<hipStream_t>(hip_stream), nactive);
 }
 
@@ -942,7 +942,7 @@ extern "C" int vie_batch_take(vie_plan* pl, int slot, double* density, double* f
     return vie::fail(pl, VIE_E_ARG, "vie_batch_take: the slot holds no finished right-hand side");
   if (!density || (field && !inc)) return vie::fail(pl, VIE_E_ARG, "vie_batch_take: null density (or inc with field)");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  pl->last_stream = s;
+  const vie::StreamUse use(pl, s);
   auto* d = reinterpret_cast<vie::c128*>(density);
   HIPCHK(pl, vie::launch_scatter(pl->xw + long(slot) * S->L, d, pl->C, vie::box_of(pl->box, pl->n), s));
   if (field) {
@@ -968,7 +968,7 @@ extern "C" int vie_solve(vie_plan* pl, const double* inc, double* density, doubl
                          const vie_solve_opts* opts, vie_solve_stats* stats, void* hip_stream) {
   if (!pl) return VIE_E_ARG;
   if (!inc || !density || nrhs < 1) return vie::fail(pl, VIE_E_ARG, "vie_solve: null pointer or nrhs < 1");
-  pl->last_stream = static_cast<hipStream_t>(hip_stream);
+  const vie::StreamUse use(pl, static_cast<hipStream_t>(hip_stream));
   vie_solve_opts o{1e-10, 2000, 40, 0.0, VIE_SOLVER_GMRES, 0u};
   if (opts) o = *opts;
   if (!(o.tol > 0) || o.max_iters < 1 || o.restart < 1 || o.restart > 1000 ||

@@ -48,7 +48,7 @@ import os
 import sys
 import threading
 import time
-from collections import OrderedDict
+from collections import Counter, OrderedDict
 from dataclasses import dataclass, field
 from typing import Callable, List, Optional
 
@@ -324,6 +324,8 @@ class Server:
         self.overtake_s = overtake_s
         self.overtakes = 0
         self.seen = set()  # keys served before
+        self.repeats = set()  # keys claimed more than once
+        self.closed_after_use = 0  # plans of one-off keys closed at once instead of cached
         self.returned_bytes = 0  # estimate minus resident bytes, given back after plan creation
 
     # ---- footprint -----------------------------------------------------------
@@ -348,14 +350,33 @@ class Server:
                 max(0, slots - info["workspace_rhs_fp64"]) * per_rhs * 16)
         return int(info["device_bytes"]) + grow
 
-    def _slots_for(self, q: Request, cached) -> int:
+    def _slots_for(self, q: Request, cached, queued: Optional[Counter] = None) -> int:
         """Batch capacity for the request's key: the full batch for a key that
         repeats (a resident plan, served before, or another queued request),
         else the request's own right-hand sides, so that a one-off medium
-        does not hold Krylov vectors for joiners that never come."""
-        if cached is not None or q.key in self.seen or any(o is not q and o.key == q.key for o in self.queue):
+        does not hold Krylov vectors for joiners that never come.  queued:
+        the count of each key in the queue (computed here when not given)."""
+        if queued is None:
+            queued = Counter(o.key for o in self.queue)
+        if cached is not None or q.key in self.seen or queued[q.key] > 1:
             return self.max_batch
         return q.nrhs
+
+    def _plan_bytes_cached(self, q: Request, slots: int) -> int:
+        """plan_bytes, remembered on the request (the claim looks at every
+        queued request on each pass)."""
+        memo = q.__dict__.setdefault("_plan_bytes", {})
+        if slots not in memo:
+            memo[slots] = self.plan_bytes(q, slots)
+        return memo[slots]
+
+    def _keep_plan(self, key: str) -> bool:
+        """Keep an idle plan resident only for a key that has repeated or is
+        queued again."""
+        if key in self.repeats:
+            return True
+        with self.qlock:
+            return any(o.key == key for o in self.queue)
 
     @staticmethod
     def io_bytes(r: Request) -> int:
@@ -391,6 +412,7 @@ class Server:
                 if self.closed and not self.queue:
                     return None, None, 0, 0
                 blocked = False
+                queued = Counter(o.key for o in self.queue)
                 for q in list(self.queue):
                     if q.key in self.serving:
                         continue
@@ -400,12 +422,13 @@ class Server:
                         continue
                     peek = self.cache.peek(q.key)
                     cached = peek is not None
-                    slots = self._slots_for(q, peek)
+                    slots = self._slots_for(q, peek, queued)
                     if cached:
                         have = peek[0].info()["krylov_slots"]
-                        grow = 0 if have >= slots else self.plan_bytes(q, slots) - self.plan_bytes(q, have)
+                        grow = 0 if have >= slots else (self._plan_bytes_cached(q, slots) -
+                                                        self._plan_bytes_cached(q, have))
                     else:
-                        grow = self.plan_bytes(q, slots)
+                        grow = self._plan_bytes_cached(q, slots)
                     need = grow + self.io_bytes(q)
                     if not self.admission.can_ever_fit(need):
                         self.queue.remove(q)
@@ -424,6 +447,8 @@ class Server:
                             self.serving.add(q.key)
                             self.inflight += 1
                             self.max_inflight = max(self.max_inflight, self.inflight)
+                            if q.key in self.seen:
+                                self.repeats.add(q.key)
                             self.seen.add(q.key)
                             if blocked:
                                 self.overtakes += 1
@@ -542,7 +567,15 @@ class Server:
                     plan.batch_close()
                     with self.rlock:
                         self.solve_s += time.perf_counter() - t_solve
-                self.cache.put(key, plan, charged)
+                if self._keep_plan(key):
+                    self.cache.put(key, plan, charged)
+                else:
+                    # a key that has not repeated: its memory serves the next
+                    # plans better in the library's block cache than held idle
+                    plan.close()
+                    self.admission.give(charged)
+                    with self.rlock:
+                        self.closed_after_use += 1
                 plan = None
             except Exception as exc:  # keep serving; report at the end
                 self.errors.append(f"key {key}: {exc}")
@@ -660,6 +693,7 @@ class Server:
                 "joins_rhs": self.joins, "joins_into_running_rhs": self.joins_running,
                 "requests_joined_running": sum(1 for r in results if r.joined_running),
                 "overtakes": self.overtakes, "returned_GB": self.returned_bytes / 1e9,
+                "plans_closed_after_use": self.closed_after_use,
                 "refused": self.refused, "errors": self.errors[:5]}
 
 
