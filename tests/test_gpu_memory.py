@@ -49,3 +49,25 @@ def test_released_blocks_are_cached_and_reused(vie):
     assert np.array_equal(d_fresh, d_again)
     assert np.array_equal(d_fresh, d_reused)
     assert vie.release_cached_memory() >= held
+
+
+def test_destroy_waits_for_the_plans_work_only(vie):
+    """vie_destroy waits for the work of the plan's last call (an event recorded
+    after it), not for later work of other callers on the same stream: after
+    the plan's apply, a bounded spin kernel on that stream is still running
+    when the destroy returns, and the apply's result is complete."""
+    n = 16
+    coef, _, omega = medium(op.KIND_HELMHOLTZ, n, 23)
+    x = torch.from_numpy(gen.random_density((1, 3, n, n, n), gen.rng_for(gen.CONFIG_IDS["test"], 231))).cuda()
+    s = torch.cuda.Stream()
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_FP64, stream=s)
+    with torch.cuda.stream(s):
+        y = plan.apply(x, vie.APPLY_FP64, stream=s)
+        torch.cuda._sleep(int(5e7))  # bounded spin: tens of milliseconds
+    plan.close()
+    busy = not s.query()
+    s.synchronize()
+    assert busy, "the destroy waited for work queued after the plan's last call"
+    ref = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_FP64)
+    assert torch.equal(y, ref.apply(x, vie.APPLY_FP64))
+    ref.close()
