@@ -230,20 +230,21 @@ def test_results_alone_equal_results_in_the_mix(device_inputs):
 
 @pytest.mark.gpu
 def test_joins_into_running_batches_equal_solves_alone():
-    """Continuous batching: a stream over a pool of two scatterers (32^3 and
-    48^3 grids) queued at once, served with batches of 4 slots, so that later
-    requests join solves already running as slots free up.  Every result is
-    bitwise the solve of that request alone (vie_solve on its own plan, same
-    options), plans are reused, and the summary counts the joins."""
+    """Continuous batching: a stream over a pool of two scatterers (the seeded
+    pool draws two Helmholtz media on the 64^3 grid) queued at once, served
+    with batches of 4 slots, so that later requests join solves already
+    running as slots free up.  Every result is bitwise the solve of that
+    request alone (vie_solve on its own plan, same options), plans are
+    reused, and the summary counts the joins."""
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1805_04791_amd import vie
     from paper_1805_04791_amd.serving import Server, device_inputs, requests_from_generator
     from vie_inputs import generators as gen
-    reqs = requests_from_generator(14, rate=1e6, grids=(32, 48), max_rhs=3, media=2)
-    assert len({r.key for r in reqs}) == 2
-    rqs = {rq["id"]: rq for rq in gen.serving_requests(14, 1e6, (32, 48), 3, media=2)}
+    reqs = requests_from_generator(14, rate=1e6, grids=(48, 64), max_rhs=3, media=2)
+    assert len({r.key for r in reqs}) == 2 and {r.n for r in reqs} == {64}
+    rqs = {rq["id"]: rq for rq in gen.serving_requests(14, 1e6, (48, 64), 3, media=2)}
     srv = Server(workers=2, max_batch=4, device_inputs=True)
     res = srv.run(lambda: reqs, realtime=False)
     assert not srv.errors, srv.errors
