@@ -252,12 +252,14 @@ int vie_batch_take(vie_plan *pl, int slot, double *density, double *field, const
                    vie_solve_stats *stats, void *hip_stream);
 int vie_batch_close(vie_plan *pl);
 
-/* Synchronises the stream of the plan's latest call, then frees the plan.
- * Work on other streams that uses the plan must have completed.  Its device
- * blocks (and small pinned host buffers) go to a process-wide cache from
- * which later plans of about the same sizes take their memory (at most
- * 48 GiB kept; a hipFree would wait for the whole device); an allocation
- * that cannot be met frees the cache of its device and retries.
+/* Waits for the work of the plan's latest call (an event recorded after it on
+ * its stream, not later work of other callers on that stream), then frees
+ * the plan.  Work on other streams that uses the plan must have completed.
+ * Its device blocks (and small pinned host buffers) go to a process-wide
+ * cache from which later plans take their memory (blocks above 64 MiB come
+ * in size classes 2^(1/4) apart, so plans of nearby sizes share them; at most
+ * 64 GiB kept; a hipFree would wait for the whole device); an allocation that
+ * cannot be met frees the cache of its device and retries.
  * vie_destroy(NULL) is a no-op. */
 int vie_destroy(vie_plan *pl);
 
