@@ -324,6 +324,7 @@ class Server:
         self.overtake_s = overtake_s
         self.overtakes = 0
         self.seen = set()  # keys served before
+        self.running = 0   # workers with an open batch
         self.repeats = set()  # keys claimed more than once
         self.closed_after_use = 0  # plans of one-off keys closed at once instead of cached
         self.returned_bytes = 0  # estimate minus resident bytes, given back after plan creation
@@ -334,6 +335,39 @@ class Server:
         max_batch) slots: an upper estimate from the grid alone."""
         nb = self.max_batch if slots is None else slots
         return int(self.vie.footprint_bytes(r.kind, r.n, r.full, nb, self.restart))
+
+    def creation_bytes(self, r: Request) -> int:
+        """Device bytes of creating a plan (the kernel-table precompute at its
+        peak, or the plan with one solver slot): charged before the plan
+        exists; its batch is charged once the plan knows its support."""
+        return int(self.vie.footprint_bytes(r.kind, r.n, r.full, 1, 1))
+
+    def batch_bytes(self, plan, r: Request, slots: int) -> int:
+        """Device bytes that opening a batch of `slots` slots adds to a new
+        plan: the Krylov vectors on the plan's support rows (basis of restart
+        + 1 vectors, iterate, right-hand side, residual, work vector and best
+        iterate per slot; blocks up to 1.2x larger in the library's size
+        classes) and the apply workspaces for the batch."""
+        info = plan.info()
+        L = info["ncomp"] * info["unknown_points"]
+        krylov = int(1.2 * (max(self.restart, 5) + 6) * 16 * L * slots)
+        return krylov + self.resident_bytes(plan, r, slots) - int(info["device_bytes"])
+
+    def _admit_batch(self, key: str, nbytes: int):
+        """Charge a new plan's batch, waiting while it does not fit and other
+        batches (which will release memory) are running; idle plans are
+        evicted for room.  With nothing running it goes ahead: waiting would
+        not make room."""
+        with self.admission.lock:
+            while not self.admission.fits(nbytes):
+                if self.cache.evict_one(keep=key):
+                    continue
+                with self.rlock:
+                    running = self.running
+                if running == 0:
+                    break
+                self.admission.lock.wait(timeout=0.05)
+            self.admission.take(nbytes)
 
     def resident_bytes(self, plan, r: Request, slots: int) -> int:
         """Device bytes a plan holds at most while it serves a batch of
@@ -367,7 +401,7 @@ class Server:
         queued request on each pass)."""
         memo = q.__dict__.setdefault("_plan_bytes", {})
         if slots not in memo:
-            memo[slots] = self.plan_bytes(q, slots)
+            memo[slots] = self.creation_bytes(q) if slots == 0 else self.plan_bytes(q, slots)
         return memo[slots]
 
     def _keep_plan(self, key: str) -> bool:
@@ -428,7 +462,9 @@ class Server:
                         grow = 0 if have >= slots else (self._plan_bytes_cached(q, slots) -
                                                         self._plan_bytes_cached(q, have))
                     else:
-                        grow = self._plan_bytes_cached(q, slots)
+                        # the plan's creation; its batch is charged from its own
+                        # support once it exists (_admit_batch)
+                        grow = self._plan_bytes_cached(q, 0)
                     need = grow + self.io_bytes(q)
                     if not self.admission.can_ever_fit(need):
                         self.queue.remove(q)
@@ -492,6 +528,7 @@ class Server:
                 return
             key = first.key
             plan, charged = None, plan_charge
+            opened = False  # this worker's batch counts in self.running
             # request id -> [request, admitted time, densities, stats, slots left, joined while running]
             open_reqs = {}
             slot_of = {}    # slot -> (request id, index within the request)
@@ -511,9 +548,17 @@ class Server:
                         with self.rlock:
                             self.plans_created += 1
                     t_solve = time.perf_counter()
+                    if entry is None:
+                        extra = self.batch_bytes(plan, first, cap)
+                        self._admit_batch(key, extra)
+                        charged += extra
                     plan.batch_open(cap, tol=self.tol, restart=self.restart, stream=stream)
-                    # the estimate counted whole-grid Krylov vectors and the
-                    # precompute; keep only what the plan can hold from now on
+                    with self.rlock:
+                        self.running += 1
+                        opened = True
+                    # the charges were estimates (a cached plan's growth from
+                    # the grid alone, a new plan's batch in the largest block
+                    # sizes); keep only what the plan can hold from now on
                     fit = self.resident_bytes(plan, first, cap)
                     with self.admission.lock:
                         if fit < charged:
@@ -567,6 +612,8 @@ class Server:
                     plan.batch_close()
                     with self.rlock:
                         self.solve_s += time.perf_counter() - t_solve
+                        self.running -= 1
+                        opened = False
                 if self._keep_plan(key):
                     self.cache.put(key, plan, charged)
                 else:
@@ -579,6 +626,9 @@ class Server:
                 plan = None
             except Exception as exc:  # keep serving; report at the end
                 self.errors.append(f"key {key}: {exc}")
+                if opened:
+                    with self.rlock:
+                        self.running -= 1
                 for o in open_reqs.values():
                     self.admission.give(self.io_bytes(o[0]))
                     o[0].release()

@@ -94,6 +94,9 @@ def test_feeder_keeps_generated_inputs_within_the_host_budget():
         def plan_bytes(self, r, slots=None):
             return 0
 
+        def creation_bytes(self, r):
+            return 0
+
         def _worker(self):
             import time
             while True:
@@ -144,6 +147,29 @@ def test_batch_capacity_follows_key_repetition():
     assert srv._slots_for(a, None) == 16
 
 
+def test_batch_admission_waits_only_while_batches_run():
+    """A new plan's batch is charged once the plan exists: it waits while it
+    does not fit and another batch (which will release memory) is running,
+    and goes ahead at once when nothing is running (waiting would not make
+    room)."""
+    import time
+    from paper_1805_04791_amd import serving
+    srv = serving.Server(budget_bytes=100, workers=1, keep_results=False)
+    srv.admission.take(90)
+    srv.running = 1
+    done = []
+    t = threading.Thread(target=lambda: (srv._admit_batch("k", 20), done.append(True)))
+    t.start()
+    time.sleep(0.2)
+    assert not done                      # 90 + 20 > 100 while a batch runs
+    srv.admission.give(50)
+    t.join(timeout=5)
+    assert done and srv.admission.used == 60
+    srv.running = 0
+    srv._admit_batch("k", 80)            # does not fit, but nothing runs
+    assert srv.admission.used == 140
+
+
 @pytest.mark.parametrize("overtake_s,order", [(60.0, [0, 2, 1]), (0.0, [0, 1, 2])],
                          ids=["overtake", "strict-order"])
 def test_younger_requests_overtake_one_that_does_not_fit(overtake_s, order):
@@ -160,6 +186,9 @@ def test_younger_requests_overtake_one_that_does_not_fit(overtake_s, order):
     class FakeServer(serving.Server):
         def plan_bytes(self, r, slots=None):
             return 80 if r.id == 1 else 30
+
+        def creation_bytes(self, r):
+            return self.plan_bytes(r)
 
         def io_bytes(self, r):
             return 0
