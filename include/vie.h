@@ -282,14 +282,17 @@ long vie_release_cached_memory(void);
  * H_mu) is non-zero (the whole box with VIE_DENSE_BOX, the whole grid with
  * VIE_WHOLE_GRID), out[15] = the periodic transform length along x and y of
  * the solver's applies: the shortest compiled length >= 2 max(bx, by) and
- * <= 2n (2n with VIE_FULL_LENGTH or VIE_WHOLE_GRID; along z always 2n); its
- * kernel tables are the transform of the kernel windowed to
- * |m_a| <= length_a/2 - 1; out[16], out[17] = right-hand sides the FP32 and
+ * <= 2n (2n with VIE_FULL_LENGTH or VIE_WHOLE_GRID); its kernel tables are
+ * the transform of the kernel windowed to |m_a| <= length_a/2 - 1;
+ * out[16], out[17] = right-hand sides the FP32 and
  * FP64 apply workspaces hold now (each grows on demand, up to max_rhs, by
  * c (n^2 2n + n 2n w) elements of 8 or 16 bytes per right-hand side, w = 2n
  * rounded up to a multiple of 16),
- * out[18] = solver slots the Krylov workspace holds now.  Entries beyond
- * nout are not written. */
+ * out[18] = solver slots the Krylov workspace holds now, out[19] = the
+ * periodic transform length along z of the solver's applies: 64 or 256 when
+ * it is >= 2 bz and >= out[15] and < 2n (their square pencil splits keep the
+ * fused z pass's lanes busy), else 2n (always 2n with VIE_FULL_LENGTH or
+ * VIE_WHOLE_GRID).  Entries beyond nout are not written. */
 int vie_plan_info(const vie_plan *pl, double *out, int nout);
 
 /* Copies the FP64 kernel-transform tables into host memory:

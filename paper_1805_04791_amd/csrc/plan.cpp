@@ -1286,8 +1286,7 @@ namespace {
 
 // The shortest compiled transform length L <= 2n with L >= 2 max(bx, by)
 // (so that the cyclic convolution of box data has no wrap-around along x and
-// y) whose apply and precompute kernels exist.  Along z the fused pass keeps
-// 2n, whose balanced split suits it best.
+// y) whose apply and precompute kernels exist (along z: z_length).
 int box_length(const vie_plan* pl) {
   const int need = 2 * std::max(pl->box.bx, pl->box.by);
   for (int L = need + (need & 1); L < pl->P; L += 2) {
@@ -1296,6 +1295,24 @@ int box_length(const vie_plan* pl) {
     if (L % 8 == 0 && o32 && o64 && o32->contig_fwd && o32->strided && o32->xinv && o64->contig_fwd &&
         o64->strided && o64->xinv)
       return L;
+  }
+  return pl->P;
+}
+
+// The z length of the box's transforms: at least 2 bz (no wrap-around along
+// z), at least the x/y length (the table octant holds qx, qy <= Pxy/2 <=
+// Pz/2) and at most 2n.  A length with a square split (64 = 8 x 8,
+// 256 = 16 x 16) is taken when it fits: its fused z pass keeps every lane
+// busy in all four DFT steps, in blocks of whole waves, where the other
+// splits idle lanes (the 20 x 16 split of 320 ran at about half its issue
+// rate); else 2n, as before.
+int z_length(const vie_plan* pl, int pxy) {
+  const int need = std::max(2 * pl->box.bz, pxy);
+  for (const int L : {64, 256}) {
+    if (L < need || L >= pl->P) continue;
+    const LenOps<float>* o32 = len_ops<float>(L);
+    const LenOps<double>* o64 = len_ops<double>(L);
+    if (o32 && o64 && o32->zpass && o64->zpass && o64->strided) return L;
   }
   return pl->P;
 }
@@ -1452,10 +1469,12 @@ int create_impl(const vie_problem* p, hipStream_t s, vie_plan* pl) {
   // twiddles and kernel tables: the whole grid's, and the box's when shorter
   // (the whole grid's are built at its first use when they differ: a solve
   // without field output never needs them)
-  const int pb = pl->use_box && !(p->flags & VIE_FULL_LENGTH) ? box_length(pl) : pl->P;
-  rc = make_spec(pl, pl->P, pb, pl->sym_set, pl->ne, pl->sb, s);
+  const bool shorter = pl->use_box && !(p->flags & VIE_FULL_LENGTH);
+  const int pb = shorter ? box_length(pl) : pl->P;
+  const int pz = shorter ? z_length(pl, pb) : pl->P;
+  rc = make_spec(pl, pz, pb, pl->sym_set, pl->ne, pl->sb, s);
   if (rc) return rc;
-  if (pb == pl->P) pl->sg = pl->sb;
+  if (pb == pl->P && pz == pl->P) pl->sg = pl->sb;
   if (p->flags & VIE_GRID_TABLES) {
     rc = ensure_grid_spec(pl, s);
     if (rc) return rc;
@@ -1710,12 +1729,13 @@ int vie_far_field(vie_plan* pl, const double* density, int nrhs, const double* d
 
 int vie_plan_info(const vie_plan* pl, double* out, int nout) {
   if (!pl || !out) return VIE_E_ARG;
-  const double v[19] = {double(pl->n),         double(pl->C),      double(pl->P),      double(pl->M),
+  const double v[20] = {double(pl->n),         double(pl->C),      double(pl->P),      double(pl->M),
                         pl->hmax,              double(pl->ne),     double(pl->dev_bytes),
                         double(pl->graph_launches), double(pl->box.x0), double(pl->box.y0), double(pl->box.z0),
                         double(pl->box.bx),    double(pl->box.by), double(pl->box.bz), double(pl->box.np),
-                        double(pl->sb.Pxy),    double(pl->ws_cap[0]), double(pl->ws_cap[1]), double(pl->kr_cap)};
-  for (int i = 0; i < nout && i < 19; ++i) out[i] = v[i];
+                        double(pl->sb.Pxy),    double(pl->ws_cap[0]), double(pl->ws_cap[1]), double(pl->kr_cap),
+                        double(pl->sb.Pz)};
+  for (int i = 0; i < nout && i < 20; ++i) out[i] = v[i];
   return VIE_OK;
 }
 

@@ -369,14 +369,14 @@ class Plan:
         self._check(self.lib.vie_batch_close(self._h), "vie_batch_close")
 
     def info(self) -> dict:
-        out = (ctypes.c_double * 19)()
-        self._check(self.lib.vie_plan_info(self._h, out, 19), "vie_plan_info")
+        out = (ctypes.c_double * 20)()
+        self._check(self.lib.vie_plan_info(self._h, out, 20), "vie_plan_info")
         keys = ["n", "ncomp", "P", "M", "max_contrast_norm", "table_entries", "device_bytes", "graph_launches",
                 "box_x0", "box_y0", "box_z0", "box_nx", "box_ny", "box_nz", "unknown_points", "box_P",
-                "workspace_rhs_fp32", "workspace_rhs_fp64", "krylov_slots"]
+                "workspace_rhs_fp32", "workspace_rhs_fp64", "krylov_slots", "box_Pz"]
         d = dict(zip(keys, list(out)))
         d["box"] = tuple(int(d.pop(k)) for k in keys[8:14])
-        for k in ("unknown_points", "box_P", "workspace_rhs_fp32", "workspace_rhs_fp64", "krylov_slots"):
+        for k in ("unknown_points", "box_P", "workspace_rhs_fp32", "workspace_rhs_fp64", "krylov_slots", "box_Pz"):
             d[k] = int(d[k])
         return d
 

@@ -213,6 +213,30 @@ def test_short_box_transform_matches_oracle(vie, n, radius):
     plan.close()
 
 
+def test_square_z_length_matches_oracle(vie):
+    """n = 96, a ball of radius 0.3 (a support box of 29 points): the solver's
+    transforms are 64 long along x and y and, since 64 >= 2 bz and its 8 x 8
+    split is square, along z as well (not 2n = 192); the solution is the
+    oracle's (whole grid, window of the whole grid) to FP64 and mixed
+    accuracy."""
+    n = 96
+    coef, omega = ball_medium(n, 0.3, 19)
+    inc = plane_waves(n, omega, 2, 50)
+    A = op.Operator(op.KIND_HELMHOLTZ, coef, omega)
+    ref = [sv.gmres(A.apply, A.rhs(inc[r]), tol=1e-13)[0] for r in range(2)]
+    plan = vie.Plan(op.KIND_HELMHOLTZ, coef, omega=omega, precision=vie.PREC_MIXED, max_rhs=2)
+    info = plan.info()
+    assert info["box_P"] == 64 and info["box_Pz"] == 64 and info["box"][5] <= 32
+    for fp64, tol, err in ((True, 1e-12, 1e-10), (False, 1e-9, 1e-8)):
+        d, _, st, rc = plan.solve(inc, tol=tol, fp64=fp64, want_field=False)
+        assert rc == vie.OK
+        d = d.cpu().numpy()
+        for r in range(2):
+            assert st[r]["rel_residual"] <= tol
+            assert rel(d[r], ref[r]) < err
+    plan.close()
+
+
 def test_short_box_transform_equals_full_length(vie):
     """n = 64, bump of radius 0.8: the solver's transform length along x and y
     is 120 (not 128); solves agree with those on the 2n grid."""

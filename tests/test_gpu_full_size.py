@@ -194,13 +194,14 @@ def test_largest_grid_160(vie):
     """The largest supported grid (160^3, the top of the serving mix): the
     Helmholtz recipe at omega = 10 pi.  The whole-grid apply runs on length
     320 along every axis with tables from the 640-point precompute, the solver
-    on the support box (length 256 along x and y, 320 along z).  FP64 and FP32
+    on the support box (length 256 along every axis: the box is 128 points
+    along z, and 256 has a square split).  FP64 and FP32
     applies against the oracle on the whole grid, and the oracle residual of a
     mixed solve of 2 right-hand sides."""
     n = 160
     prob = gen.helmholtz_problem(n, 10 * math.pi, "helmholtz128", nrhs=2)
     plan = vie.Plan(prob.kind, prob.coef, omega=prob.omega, precision=vie.PREC_MIXED, max_rhs=2)
-    assert plan.info()["box_P"] == 256
+    assert plan.info()["box_P"] == 256 and plan.info()["box_Pz"] == 256
     x = gen.random_density((1, 3, n, n, n), gen.rng_for(gen.CONFIG_IDS["test"], 801))
     y64 = plan.apply(x, vie.APPLY_FP64).cpu().numpy()[0]
     y32 = plan.apply(x).cpu().numpy()[0]
