@@ -75,7 +75,8 @@ std::vector<FreeBlock>& free_blocks() {
   return v;
 }
 size_t g_cached_bytes = 0;
-constexpr size_t kCacheLimit = size_t(64) << 30;  // bytes kept for reuse at most
+constexpr size_t kCacheLimit = size_t(96) << 30;  // bytes kept for reuse at most
+constexpr size_t kCacheFloor = size_t(32) << 30;  // device memory left free for other allocators
 std::vector<std::pair<void*, size_t>>& free_host_blocks() {
   static std::vector<std::pair<void*, size_t>> v;
   return v;
@@ -182,9 +183,19 @@ void release_cached(int device) {
   }
 }
 
-// a block no queued work uses any more: cached, or freed beyond the limit
+// a block no queued work uses any more: cached, or freed beyond the limit or
+// when the device would keep less than kCacheFloor free for other allocators
 void give_block(void* p, size_t bytes, int device) {
-  if (g_cached_bytes + bytes > kCacheLimit) {
+  bool keep = g_cached_bytes + bytes <= kCacheLimit;
+  if (keep) {
+    size_t free_b = 0, total_b = 0;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != device) (void)hipSetDevice(device);
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) keep = free_b >= kCacheFloor;
+    if (cur != device && cur >= 0) (void)hipSetDevice(cur);
+  }
+  if (!keep) {
     (void)hipFree(p);
     return;
   }
