@@ -257,9 +257,10 @@ int vie_batch_close(vie_plan *pl);
  * the plan.  Work on other streams that uses the plan must have completed.
  * Its device blocks (and small pinned host buffers) go to a process-wide
  * cache from which later plans take their memory (blocks above 64 MiB come
- * in size classes 2^(1/4) apart, so plans of nearby sizes share them; at most
- * 64 GiB kept; a hipFree would wait for the whole device); an allocation that
- * cannot be met frees the cache of its device and retries.
+ * in size classes 2^(1/4) apart, so plans of nearby sizes share them; up to
+ * 96 GiB kept while 32 GiB of the device stay free; a hipFree would wait for
+ * the whole device); an allocation that cannot be met frees the cache of its
+ * device and retries.
  * vie_destroy(NULL) is a no-op. */
 int vie_destroy(vie_plan *pl);
 
