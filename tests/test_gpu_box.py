@@ -237,6 +237,27 @@ def test_square_z_length_matches_oracle(vie):
     plan.close()
 
 
+def test_square_z_length_full_maxwell_matches_oracle(vie):
+    """The 64-long z transform with the 6 x 6 Maxwell multiply (eps and mu,
+    9 tables): n = 96, both media restricted to a ball of radius 0.3; the
+    FP64 solve is the oracle's to 1e-10."""
+    n = 96
+    eps, mu, omega = medium(op.KIND_MAXWELL, n, 24, full=True)
+    X, Y, Z = gen.grid_coords(n)
+    ball = (X * X + Y * Y + Z * Z < 0.09).astype(float)
+    eps, mu = masked(eps, ball), masked(mu, ball)
+    inc = em_waves(n, omega, 1, 60, True)
+    A = op.Operator(op.KIND_MAXWELL, eps, omega, mu=mu)
+    ref = sv.gmres(A.apply, A.rhs(inc[0]), tol=1e-13)[0]
+    plan = vie.Plan(op.KIND_MAXWELL, eps, omega=omega, mu=mu, precision=vie.PREC_MIXED, max_rhs=1)
+    info = plan.info()
+    assert info["box_Pz"] == 64 and info["box_P"] == 64
+    d, _, st, rc = plan.solve(inc, tol=1e-12, fp64=True, want_field=False)
+    assert rc == vie.OK and st[0]["rel_residual"] <= 1e-12
+    assert rel(d.cpu().numpy()[0], ref) < 1e-10
+    plan.close()
+
+
 def test_short_box_transform_equals_full_length(vie):
     """n = 64, bump of radius 0.8: the solver's transform length along x and y
     is 120 (not 128); solves agree with those on the 2n grid."""
