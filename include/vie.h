@@ -219,7 +219,10 @@ int vie_solve(vie_plan *pl, const double *inc, double *density, double *field, i
  * soon as they are done.  One batch per plan; vie_solve returns VIE_E_STATE
  * while it is open.  Each slot's arithmetic is independent of the other
  * slots, of its position and of when it joined: a right-hand side gets
- * bitwise the result vie_solve gives it alone with the same options.
+ * bitwise the result vie_solve gives it alone with the same options (within
+ * one process: the pencil splits of a shape are measured once per process).
+ * Slots are filled lowest first, and the launches of a step cover the slots
+ * up to the highest one in use.
  *
  * vie_batch_open:  opens the batch with the options of vie_solve (opts may be
  *                  NULL: its defaults); sizes the Krylov workspace for it.
